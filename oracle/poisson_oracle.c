@@ -1,0 +1,551 @@
+/*
+ * poisson_oracle.c -- plain, slow, single-threaded FP64 reference ("the oracle")
+ * for the periodic variable-coefficient pressure Poisson solve
+ *
+ *        div( (1/rho) grad p ) = f                      (section "Poisson equation")
+ *
+ * of Pouransari, Mortazavi & Mani, "Parallel variable-density particle-laden
+ * turbulence simulation" (arXiv:1601.05448).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the checker against which the GPU
+ * library is judged.  Only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it.  It shares no code, header, table or
+ * constant with the GPU path and includes nothing from it.
+ *
+ * Conventions (all readings of the paper are listed in the design notes):
+ *   - Grid (nx, ny, nz), uniform spacing h_d = L_d / N_d, triply periodic
+ *     (section "Boundary and initial conditions", configuration 1).
+ *   - Scalars (rho, p, f) live at cell centres, fluxes on faces (section
+ *     "Spatial discretization", staggered-grid figure).  Storage is
+ *     [nz][ny][nx], x fastest: idx = (k*ny + j)*nx + i.
+ *   - Discrete operator, second order (section "Spatial discretization"):
+ *        (A p)_c = sum_d [ beta_{c+1/2} (p_{c+e_d} - p_c)
+ *                        - beta_{c-1/2} (p_c - p_{c-e_d}) ] / h_d^2
+ *     with the face coefficient beta (the paper never writes it out):
+ *        coef 0: beta = 2 / (rho_a + rho_b)      1/rho of the face-averaged rho
+ *        coef 1: beta = (1/rho_a + 1/rho_b) / 2  face average of 1/rho
+ *   - Compatibility: the right-hand side is made zero-mean by subtracting its
+ *     domain mean (the constant chi of Appendix A); p is returned zero-mean.
+ *   - The paper's iteration (section "Poisson equation", eq. (Pois)): with
+ *     p = p_g + dp, drop the term rho grad(1/rho).grad dp, solve the remaining
+ *     constant-coefficient Poisson problem by Fourier transform in the periodic
+ *     directions, set p_g <- p_g + dp, and repeat until convergence.  In
+ *     residual form one step is
+ *        r  = f~ - A p_g,     q = w * r,     L dp = q,     p_g += dp
+ *     with w = rho (weight 0, the multiplier of eq. (Pois)) or w = 1/mean of the
+ *     six face coefficients (weight 1).  L is the constant-coefficient 7-point
+ *     Laplacian, inverted on zero-mean fields through its discrete Fourier
+ *     symbol  sum_d -4 sin^2(pi k_d / N_d) / h_d^2.
+ *
+ * Compiled with -O2 -ffp-contract=off: IEEE double, round to nearest, no FMA
+ * contraction, no fast-math.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stddef.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ENOMEM (-2)
+#define OR_EDOMAIN (-3)
+#define OR_ENOCONV (-4)
+#define OR_EDIVERGED (-5)
+
+typedef double complex cplx;
+
+static const double OR_PI = 3.14159265358979323846264338327950288;
+
+/* ------------------------------------------------------------------------ */
+/* grid helpers                                                             */
+/* ------------------------------------------------------------------------ */
+
+static size_t cell(int nx, int ny, int i, int j, int k) {
+    return ((size_t)k * (size_t)ny + (size_t)j) * (size_t)nx + (size_t)i;
+}
+
+static int wrap(int i, int n) { return (i % n + n) % n; }
+
+static int is_2a3b(int n) {
+    if (n < 1) return 0;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+static int check_grid(int nx, int ny, int nz, double hx, double hy, double hz) {
+    if (nx < 2 || ny < 2 || nz < 2) return OR_EINVAL;
+    if (!(hx > 0.0) || !(hy > 0.0) || !(hz > 0.0)) return OR_EINVAL;
+    return OR_OK;
+}
+
+/* Face coefficient between two cells with densities ra and rb. */
+static double face_beta(int coef, double ra, double rb) {
+    if (coef == 0) return 2.0 / (ra + rb);
+    return 0.5 * (1.0 / ra + 1.0 / rb);
+}
+
+/* ------------------------------------------------------------------------ */
+/* operator                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* out = A p : the second-order flux-form discretisation of div((1/rho) grad p)
+ * on the periodic staggered grid.  rho may be NULL, meaning rho = 1 (then A is
+ * the constant-coefficient 7-point Laplacian L). */
+int oracle_apply(int nx, int ny, int nz, double hx, double hy, double hz, int coef,
+                 const double* rho, const double* p, double* out) {
+    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || (coef != 0 && coef != 1) || !p || !out)
+        return OR_EINVAL;
+    const int n3[3] = {nx, ny, nz};
+    const double h2[3] = {hx * hx, hy * hy, hz * hz};
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const size_t c = cell(nx, ny, i, j, k);
+                double acc = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    int ip = i, jp = j, kp = k, im = i, jm = j, km = k;
+                    if (d == 0) { ip = wrap(i + 1, n3[0]); im = wrap(i - 1, n3[0]); }
+                    if (d == 1) { jp = wrap(j + 1, n3[1]); jm = wrap(j - 1, n3[1]); }
+                    if (d == 2) { kp = wrap(k + 1, n3[2]); km = wrap(k - 1, n3[2]); }
+                    const size_t cp = cell(nx, ny, ip, jp, kp);
+                    const size_t cm = cell(nx, ny, im, jm, km);
+                    const double bp = rho ? face_beta(coef, rho[c], rho[cp]) : 1.0;
+                    const double bm = rho ? face_beta(coef, rho[cm], rho[c]) : 1.0;
+                    acc += (bp * (p[cp] - p[c]) - bm * (p[c] - p[cm])) / h2[d];
+                }
+                out[c] = acc;
+            }
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* textbook complex FFT, lengths 2^a 3^b (recursive Cooley-Tukey, DIT)       */
+/* ------------------------------------------------------------------------ */
+
+/* X[K] = sum_j x[j*stride] * tw[(j*K*tstep) mod N], with tw[t] = exp(sign*2*pi*i*t/N)
+ * and n = N/tstep.  Split j = r*j' + q (r = 2 or 3): X[K] = sum_q w^{qK} Y_q[K mod m]. */
+static void fft_rec(const cplx* x, size_t stride, cplx* X, int n, const cplx* tw, int N,
+                    int tstep, cplx* scratch) {
+    if (n == 1) {
+        X[0] = x[0];
+        return;
+    }
+    const int r = (n % 2 == 0) ? 2 : 3;
+    const int m = n / r;
+    for (int q = 0; q < r; ++q)
+        fft_rec(x + (size_t)q * stride, stride * (size_t)r, X + (size_t)q * m, m, tw, N,
+                tstep * r, scratch);
+    for (int K = 0; K < n; ++K) {
+        cplx acc = 0.0;
+        for (int q = 0; q < r; ++q) {
+            const long t = ((long)q * (long)K) % n;
+            acc += tw[(size_t)t * (size_t)tstep % (size_t)N] * X[(size_t)q * m + (size_t)(K % m)];
+        }
+        scratch[K] = acc;
+    }
+    memcpy(X, scratch, (size_t)n * sizeof(cplx));
+}
+
+static cplx* make_twiddles(int n, int sign) {
+    cplx* tw = (cplx*)malloc((size_t)n * sizeof(cplx));
+    if (!tw) return NULL;
+    for (int t = 0; t < n; ++t) {
+        const double a = 2.0 * OR_PI * (double)t / (double)n;
+        tw[t] = cos(a) + (double)sign * sin(a) * I;
+    }
+    return tw;
+}
+
+/* In-place 1-D DFT of a line of length n (2^a 3^b), elements at stride. */
+static int fft_line(cplx* data, size_t stride, int n, const cplx* tw, cplx* in, cplx* out,
+                    cplx* scratch) {
+    for (int j = 0; j < n; ++j) in[j] = data[(size_t)j * stride];
+    fft_rec(in, 1, out, n, tw, n, 1, scratch);
+    for (int j = 0; j < n; ++j) data[(size_t)j * stride] = out[j];
+    return OR_OK;
+}
+
+/* Exported for pinning: in-place complex DFT of length n, sign -1 forward
+ * (exp(-2 pi i jk/n)), +1 backward (unnormalised). */
+int oracle_fft1d(int n, double* re, double* im, int sign) {
+    if (!is_2a3b(n) || (sign != 1 && sign != -1) || !re || !im) return OR_EINVAL;
+    cplx* buf = (cplx*)malloc(4 * (size_t)n * sizeof(cplx));
+    cplx* tw = make_twiddles(n, sign);
+    if (!buf || !tw) {
+        free(buf);
+        free(tw);
+        return OR_ENOMEM;
+    }
+    cplx* line = buf;
+    for (int j = 0; j < n; ++j) line[j] = re[j] + im[j] * I;
+    fft_line(line, 1, n, tw, buf + n, buf + 2 * (size_t)n, buf + 3 * (size_t)n);
+    for (int j = 0; j < n; ++j) {
+        re[j] = creal(line[j]);
+        im[j] = cimag(line[j]);
+    }
+    free(buf);
+    free(tw);
+    return OR_OK;
+}
+
+/* 3-D DFT of a complex [nz][ny][nx] array along x, then y, then z. */
+static int fft3(cplx* a, int nx, int ny, int nz, int sign) {
+    const int nmax = nx > ny ? (nx > nz ? nx : nz) : (ny > nz ? ny : nz);
+    cplx* buf = (cplx*)malloc(3 * (size_t)nmax * sizeof(cplx));
+    cplx* twx = make_twiddles(nx, sign);
+    cplx* twy = make_twiddles(ny, sign);
+    cplx* twz = make_twiddles(nz, sign);
+    if (!buf || !twx || !twy || !twz) {
+        free(buf); free(twx); free(twy); free(twz);
+        return OR_ENOMEM;
+    }
+    cplx *in = buf, *out = buf + nmax, *scr = buf + 2 * (size_t)nmax;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j) fft_line(a + cell(nx, ny, 0, j, k), 1, nx, twx, in, out, scr);
+    for (int k = 0; k < nz; ++k)
+        for (int i = 0; i < nx; ++i) fft_line(a + cell(nx, ny, i, 0, k), (size_t)nx, ny, twy, in, out, scr);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i)
+            fft_line(a + cell(nx, ny, i, j, 0), (size_t)nx * (size_t)ny, nz, twz, in, out, scr);
+    free(buf); free(twx); free(twy); free(twz);
+    return OR_OK;
+}
+
+/* Discrete symbol of the 1-D periodic second difference: -4 sin^2(pi k/N)/h^2. */
+static double symbol_1d(int k, int n, double h) {
+    const double s = sin(OR_PI * (double)k / (double)n);
+    return -4.0 * s * s / (h * h);
+}
+
+/* delta = L^+ q : the zero-mean solution of L delta = q - mean(q), where L is the
+ * constant-coefficient periodic 7-point Laplacian (the inner solve of eq. (Pois)
+ * "by Fourier transform in the periodic directions").  Forward 3-D DFT, divide by
+ * the discrete symbol, zero the k = 0 mode, backward 3-D DFT, scale 1/n. */
+int oracle_lap_pinv(int nx, int ny, int nz, double hx, double hy, double hz, const double* q,
+                    double* delta) {
+    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || !q || !delta) return OR_EINVAL;
+    if (!is_2a3b(nx) || !is_2a3b(ny) || !is_2a3b(nz)) return OR_EINVAL;
+    const size_t n = (size_t)nx * ny * nz;
+    cplx* F = (cplx*)malloc(n * sizeof(cplx));
+    if (!F) return OR_ENOMEM;
+    for (size_t c = 0; c < n; ++c) F[c] = q[c];
+    int rc = fft3(F, nx, ny, nz, -1);
+    if (rc != OR_OK) { free(F); return rc; }
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const size_t c = cell(nx, ny, i, j, k);
+                if (i == 0 && j == 0 && k == 0) {
+                    F[c] = 0.0;
+                    continue;
+                }
+                const double lam = symbol_1d(i, nx, hx) + symbol_1d(j, ny, hy) + symbol_1d(k, nz, hz);
+                F[c] /= lam;
+            }
+    rc = fft3(F, nx, ny, nz, +1);
+    if (rc != OR_OK) { free(F); return rc; }
+    for (size_t c = 0; c < n; ++c) delta[c] = creal(F[c]) / (double)n;
+    free(F);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* reductions                                                               */
+/* ------------------------------------------------------------------------ */
+
+static double mean_of(const double* a, size_t n) {
+    double s = 0.0;
+    for (size_t c = 0; c < n; ++c) s += a[c];
+    return s / (double)n;
+}
+
+static double norm2_of(const double* a, size_t n) {
+    double s = 0.0;
+    for (size_t c = 0; c < n; ++c) s += a[c] * a[c];
+    return sqrt(s);
+}
+
+static int check_fields(const double* rho, const double* b, size_t n) {
+    for (size_t c = 0; c < n; ++c) {
+        if (!isfinite(rho[c]) || !(rho[c] > 0.0)) return OR_EDOMAIN;
+        if (!isfinite(b[c])) return OR_EDOMAIN;
+    }
+    return OR_OK;
+}
+
+/* r = (b - mean(b)) - A p.  Returns through the pointers the removed mean of b,
+ * ||b - mean(b)||_2 and ||r||_2.  r may be NULL.  This is the O(n) verifier
+ * used on any solution, including ones the full oracle solve would take too
+ * long to produce. */
+int oracle_residual(int nx, int ny, int nz, double hx, double hy, double hz, int coef,
+                    const double* rho, const double* b, const double* p, double* r,
+                    double* b_mean, double* b_norm, double* r_norm) {
+    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || (coef != 0 && coef != 1) || !rho || !b || !p)
+        return OR_EINVAL;
+    const size_t n = (size_t)nx * ny * nz;
+    double* Ap = (double*)malloc(n * sizeof(double));
+    if (!Ap) return OR_ENOMEM;
+    oracle_apply(nx, ny, nz, hx, hy, hz, coef, rho, p, Ap);
+    const double bm = mean_of(b, n);
+    double sb = 0.0, sr = 0.0;
+    for (size_t c = 0; c < n; ++c) {
+        const double bt = b[c] - bm;
+        const double rc = bt - Ap[c];
+        sb += bt * bt;
+        sr += rc * rc;
+        if (r) r[c] = rc;
+    }
+    free(Ap);
+    if (b_mean) *b_mean = bm;
+    if (b_norm) *b_norm = sqrt(sb);
+    if (r_norm) *r_norm = sqrt(sr);
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* the paper's iteration                                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Weight multiplying the residual before the constant-coefficient solve.
+ * weight 0: w = rho (the multiplier in eq. (Pois)); weight 1: w = 1 / (mean of
+ * the six face coefficients around the cell). */
+static void make_weight(int nx, int ny, int nz, int coef, int weight, const double* rho,
+                        double* w) {
+    const int n3[3] = {nx, ny, nz};
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const size_t c = cell(nx, ny, i, j, k);
+                if (weight == 0) {
+                    w[c] = rho[c];
+                    continue;
+                }
+                double s = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    int ip = i, jp = j, kp = k, im = i, jm = j, km = k;
+                    if (d == 0) { ip = wrap(i + 1, n3[0]); im = wrap(i - 1, n3[0]); }
+                    if (d == 1) { jp = wrap(j + 1, n3[1]); jm = wrap(j - 1, n3[1]); }
+                    if (d == 2) { kp = wrap(k + 1, n3[2]); km = wrap(k - 1, n3[2]); }
+                    s += face_beta(coef, rho[c], rho[cell(nx, ny, ip, jp, kp)]);
+                    s += face_beta(coef, rho[cell(nx, ny, im, jm, km)], rho[c]);
+                }
+                w[c] = 6.0 / s;
+            }
+}
+
+/* The paper's solver.  p is in/out: on entry the estimate p_g, on exit the
+ * zero-mean iterate whose relative residual ||r||/||b~|| is <= tol.
+ * Iterates: r = b~ - A p; stop if small; p += L^+ (w r).
+ * history (may be NULL, length max_iter+1) receives ||r_k|| / ||b~||.
+ * Returns OR_OK, OR_ENOCONV (p = last iterate), OR_EDIVERGED (relative residual
+ * above 1e8 or not finite), OR_EDOMAIN, OR_EINVAL, OR_ENOMEM. */
+int oracle_solve(int nx, int ny, int nz, double hx, double hy, double hz, int coef, int weight,
+                 const double* rho, const double* b, double* p, double tol, int max_iter,
+                 int* iters_out, double* rel_out, double* b_mean_out, double* history) {
+    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK) return OR_EINVAL;
+    if (!is_2a3b(nx) || !is_2a3b(ny) || !is_2a3b(nz)) return OR_EINVAL;
+    if ((coef != 0 && coef != 1) || (weight != 0 && weight != 1)) return OR_EINVAL;
+    if (!rho || !b || !p || !(tol > 0.0) || max_iter < 0) return OR_EINVAL;
+    const size_t n = (size_t)nx * ny * nz;
+    if (check_fields(rho, b, n) != OR_OK) return OR_EDOMAIN;
+
+    double* bt = (double*)malloc(n * sizeof(double));
+    double* r = (double*)malloc(n * sizeof(double));
+    double* w = (double*)malloc(n * sizeof(double));
+    double* dp = (double*)malloc(n * sizeof(double));
+    if (!bt || !r || !w || !dp) {
+        free(bt); free(r); free(w); free(dp);
+        return OR_ENOMEM;
+    }
+    /* compatibility: remove the domain mean of the right-hand side */
+    const double bm = mean_of(b, n);
+    for (size_t c = 0; c < n; ++c) bt[c] = b[c] - bm;
+    const double bn = norm2_of(bt, n);
+    if (b_mean_out) *b_mean_out = bm;
+
+    int rc = OR_OK, it = 0;
+    double rel = 0.0;
+    if (bn == 0.0) {
+        for (size_t c = 0; c < n; ++c) p[c] = 0.0;
+        if (history) history[0] = 0.0;
+        goto done;
+    }
+    /* gauge: the solution is the zero-mean one */
+    {
+        const double pm = mean_of(p, n);
+        for (size_t c = 0; c < n; ++c) p[c] -= pm;
+    }
+    make_weight(nx, ny, nz, coef, weight, rho, w);
+    for (it = 0;; ++it) {
+        oracle_apply(nx, ny, nz, hx, hy, hz, coef, rho, p, r);
+        for (size_t c = 0; c < n; ++c) r[c] = bt[c] - r[c];
+        rel = norm2_of(r, n) / bn;
+        if (history) history[it] = rel;
+        if (rel <= tol) break;
+        if (!isfinite(rel) || rel > 1e8) { /* the iteration is not contracting */
+            rc = OR_EDIVERGED;
+            break;
+        }
+        if (it == max_iter) {
+            rc = OR_ENOCONV;
+            break;
+        }
+        for (size_t c = 0; c < n; ++c) r[c] *= w[c];
+        rc = oracle_lap_pinv(nx, ny, nz, hx, hy, hz, r, dp);
+        if (rc != OR_OK) break;
+        for (size_t c = 0; c < n; ++c) p[c] += dp[c];
+    }
+done:
+    if (iters_out) *iters_out = it;
+    if (rel_out) *rel_out = rel;
+    free(bt); free(r); free(w); free(dp);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* independent cross-checks                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Conjugate gradients on the symmetric positive semi-definite -A, restricted
+ * to zero-mean vectors: solves -A p = -(b - mean b) from p = 0.  An algorithm
+ * unrelated to the paper's iteration, used to cross-check it. */
+int oracle_cg(int nx, int ny, int nz, double hx, double hy, double hz, int coef,
+              const double* rho, const double* b, double* p, double tol, int max_iter,
+              int* iters_out, double* rel_out) {
+    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || (coef != 0 && coef != 1)) return OR_EINVAL;
+    if (!rho || !b || !p || !(tol > 0.0) || max_iter < 0) return OR_EINVAL;
+    const size_t n = (size_t)nx * ny * nz;
+    if (check_fields(rho, b, n) != OR_OK) return OR_EDOMAIN;
+    double* r = (double*)malloc(n * sizeof(double));
+    double* d = (double*)malloc(n * sizeof(double));
+    double* Ad = (double*)malloc(n * sizeof(double));
+    if (!r || !d || !Ad) {
+        free(r); free(d); free(Ad);
+        return OR_ENOMEM;
+    }
+    const double bm = mean_of(b, n);
+    for (size_t c = 0; c < n; ++c) {
+        p[c] = 0.0;
+        r[c] = -(b[c] - bm); /* residual of -A p = -b~ at p = 0 */
+        d[c] = r[c];
+    }
+    const double bn = norm2_of(r, n);
+    double rr = bn * bn;
+    int it = 0, rc = OR_OK;
+    double rel = bn > 0.0 ? 1.0 : 0.0;
+    while (bn > 0.0 && rel > tol) {
+        if (it == max_iter) {
+            rc = OR_ENOCONV;
+            break;
+        }
+        oracle_apply(nx, ny, nz, hx, hy, hz, coef, rho, d, Ad);
+        double dAd = 0.0;
+        for (size_t c = 0; c < n; ++c) dAd += d[c] * (-Ad[c]);
+        const double alpha = rr / dAd;
+        double rr_new = 0.0;
+        for (size_t c = 0; c < n; ++c) {
+            p[c] += alpha * d[c];
+            r[c] -= alpha * (-Ad[c]);
+            rr_new += r[c] * r[c];
+        }
+        const double beta = rr_new / rr;
+        rr = rr_new;
+        for (size_t c = 0; c < n; ++c) d[c] = r[c] + beta * d[c];
+        rel = sqrt(rr) / bn;
+        ++it;
+    }
+    const double pm = mean_of(p, n);
+    for (size_t c = 0; c < n; ++c) p[c] -= pm;
+    if (iters_out) *iters_out = it;
+    if (rel_out) *rel_out = rel;
+    free(r); free(d); free(Ad);
+    return rc;
+}
+
+/* Brute force for tiny grids: assemble the n x n matrix of A column by column
+ * from oracle_apply, border it with the constraint sum(p) = 0,
+ *      [ A   1 ] [p]   [b - mean b]
+ *      [ 1^T 0 ] [c] = [    0     ]
+ * and solve by Gaussian elimination with partial pivoting. */
+int oracle_dense(int nx, int ny, int nz, double hx, double hy, double hz, int coef,
+                 const double* rho, const double* b, double* p) {
+    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || (coef != 0 && coef != 1)) return OR_EINVAL;
+    if (!rho || !b || !p) return OR_EINVAL;
+    const size_t n = (size_t)nx * ny * nz;
+    if (n > 4096) return OR_EINVAL;
+    const size_t m = n + 1;
+    double* M = (double*)calloc(m * m, sizeof(double));
+    double* e = (double*)calloc(n, sizeof(double));
+    double* col = (double*)malloc(n * sizeof(double));
+    double* rhs = (double*)malloc(m * sizeof(double));
+    if (!M || !e || !col || !rhs) {
+        free(M); free(e); free(col); free(rhs);
+        return OR_ENOMEM;
+    }
+    for (size_t jc = 0; jc < n; ++jc) {
+        e[jc] = 1.0;
+        oracle_apply(nx, ny, nz, hx, hy, hz, coef, rho, e, col);
+        e[jc] = 0.0;
+        for (size_t ir = 0; ir < n; ++ir) M[ir * m + jc] = col[ir];
+    }
+    for (size_t t = 0; t < n; ++t) {
+        M[t * m + n] = 1.0;
+        M[n * m + t] = 1.0;
+    }
+    const double bm = mean_of(b, n);
+    for (size_t t = 0; t < n; ++t) rhs[t] = b[t] - bm;
+    rhs[n] = 0.0;
+    int rc = OR_OK;
+    for (size_t piv = 0; piv < m; ++piv) {
+        size_t best = piv;
+        for (size_t ir = piv + 1; ir < m; ++ir)
+            if (fabs(M[ir * m + piv]) > fabs(M[best * m + piv])) best = ir;
+        if (M[best * m + piv] == 0.0) {
+            rc = OR_EDOMAIN;
+            break;
+        }
+        if (best != piv) {
+            for (size_t jc = 0; jc < m; ++jc) {
+                const double tmp = M[piv * m + jc];
+                M[piv * m + jc] = M[best * m + jc];
+                M[best * m + jc] = tmp;
+            }
+            const double tmp = rhs[piv];
+            rhs[piv] = rhs[best];
+            rhs[best] = tmp;
+        }
+        for (size_t ir = piv + 1; ir < m; ++ir) {
+            const double f = M[ir * m + piv] / M[piv * m + piv];
+            if (f == 0.0) continue;
+            for (size_t jc = piv; jc < m; ++jc) M[ir * m + jc] -= f * M[piv * m + jc];
+            rhs[ir] -= f * rhs[piv];
+        }
+    }
+    if (rc == OR_OK) {
+        for (size_t ir = m; ir-- > 0;) {
+            double s = rhs[ir];
+            for (size_t jc = ir + 1; jc < m; ++jc) s -= M[ir * m + jc] * rhs[jc];
+            rhs[ir] = s / M[ir * m + ir];
+        }
+        for (size_t t = 0; t < n; ++t) p[t] = rhs[t];
+    }
+    free(M); free(e); free(col); free(rhs);
+    return rc;
+}
+
+/* A-posteriori error bound.  Every face coefficient is >= 1/rho_max in both
+ * coefficient modes, so -A >= (-L)/rho_max on zero-mean fields and
+ *     ||p - p*||_2 <= rho_max ||r||_2 / min_d (4 sin^2(pi/N_d) / h_d^2).
+ * Returns the bound on the absolute 2-norm error given ||r||_2. */
+double oracle_error_bound(int nx, int ny, int nz, double hx, double hy, double hz,
+                          double rho_max, double r_norm) {
+    double lmin = -symbol_1d(1, nx, hx);
+    const double ly = -symbol_1d(1, ny, hy), lz = -symbol_1d(1, nz, hz);
+    if (ly < lmin) lmin = ly;
+    if (lz < lmin) lmin = lz;
+    return rho_max * r_norm / lmin;
+}
+
+int oracle_abi_version(void) { return 1; }

@@ -1,0 +1,270 @@
+"""Seeded synthetic inputs for the variable-density Poisson solve.
+
+This module only draws and shapes input fields (density rho, right-hand side b,
+request streams).  It holds none of the solver's arithmetic, imports nothing
+from the GPU library or from the oracle, and is the one piece that both sides
+share, so that they consume identical bytes.
+
+All fields are float64 numpy arrays of shape (nz, ny, nx), x fastest, sampled at
+cell centres x_i = (i + 1/2) h (scalars live at cell centres on the paper's
+staggered grid, section "Spatial discretization").  Randomness comes from
+numpy's PCG64 ``default_rng``; base seed 1601, workload c uses 1601*100 + c and
+served request r uses 1601*1000 + r.
+
+Workloads (the density contrasts follow the paper's motivation: particles heat
+the gas, hot gas is light, section "Motivation and objectives"):
+  1  32^3, [0,2pi)^3, rho = 1 + sin x sin y sin z / 2, b = discrete divergence
+     of Gaussian face velocities.
+  2  256^3, rho = exp(s), s band-limited |k| <= 8 and scaled to max/min = 4,
+     b band-limited |k| <= 8.
+  3  512^3, rho = 1/(1 + 9 d/max d), d = cloud-in-cell deposit of 10^6 uniform
+     particles (the paper's linear particle-to-grid projection); b band-limited.
+  4  served stream: 512 requests, Poisson arrivals, N in {64,96,128,192}, rho
+     lognormal band-limited with contrast R ~ U[2,8], b band-limited.
+  5  1024x512x512 on [0,4pi)x[0,2pi)^2, rho = 1/(1 + 19 f/max f), f = sum of
+     10^5 periodic Gaussian blobs of width 2 cells; b band-limited.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import Iterator, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+BASE_SEED = 1601
+TWO_PI = 2.0 * math.pi
+
+
+def workload_seed(c: int) -> int:
+    return BASE_SEED * 100 + c
+
+
+def request_seed(r: int) -> int:
+    return BASE_SEED * 1000 + r
+
+
+def centres(n: int, length: float) -> np.ndarray:
+    """Cell-centre coordinates (i + 1/2) h, h = length / n."""
+    return (np.arange(n, dtype=np.float64) + 0.5) * (length / n)
+
+
+def bandlim(shape: Sequence[int], lengths: Sequence[float], kmax: float,
+            rng: np.random.Generator, z_chunk: int = 64) -> np.ndarray:
+    """Gaussian random field band-limited to physical wavenumbers 0 < |k| <= kmax.
+
+    Independent complex N(0,1) coefficients on every integer wavevector m with
+    |2 pi m / L| <= kmax (m != 0); the field is the real part of their Fourier
+    synthesis at cell centres, shifted to zero mean and scaled to unit RMS.
+    The synthesis is separable (x, then y, then z) so it is independent of the
+    grid resolution and cheap at any size.
+    """
+    nz, ny, nx = shape
+    lx, ly, lz = lengths
+    mx = int(math.floor(kmax * lx / TWO_PI))
+    my = int(math.floor(kmax * ly / TWO_PI))
+    mz = int(math.floor(kmax * lz / TWO_PI))
+    ax = np.arange(-mx, mx + 1)
+    ay = np.arange(-my, my + 1)
+    az = np.arange(-mz, mz + 1)
+    kz, ky, kx = np.meshgrid(TWO_PI * az / lz, TWO_PI * ay / ly, TWO_PI * ax / lx, indexing="ij")
+    kk = kx * kx + ky * ky + kz * kz
+    mask = (kk <= kmax * kmax * (1 + 1e-12)) & (kk > 0)
+    coef = (rng.standard_normal(mask.shape) + 1j * rng.standard_normal(mask.shape)) * mask
+    ex = np.exp(1j * np.outer(TWO_PI * ax / lx, centres(nx, lx)))  # (2mx+1, nx)
+    ey = np.exp(1j * np.outer(TWO_PI * ay / ly, centres(ny, ly)))  # (2my+1, ny)
+    ez = np.exp(1j * np.outer(TWO_PI * az / lz, centres(nz, lz)))  # (2mz+1, nz)
+    t1 = coef @ ex  # (mz, my, nx)
+    t2 = np.einsum("zyi,yj->zji", t1, ey).reshape(len(az), ny * nx)  # (mz, ny*nx)
+    t2r, t2i = np.ascontiguousarray(t2.real), np.ascontiguousarray(t2.imag)
+    out = np.empty((nz, ny * nx))
+    ezr, ezi = ez.real.T.copy(), ez.imag.T.copy()  # (nz, mz)
+    for k0 in range(0, nz, z_chunk):
+        k1 = min(nz, k0 + z_chunk)
+        out[k0:k1] = ezr[k0:k1] @ t2r - ezi[k0:k1] @ t2i
+    out = out.reshape(nz, ny, nx)
+    out -= out.mean()
+    rms = math.sqrt(float(np.mean(out * out)))
+    if rms > 0:
+        out /= rms
+    return out
+
+
+def contrast_exp(s: np.ndarray, ratio: float) -> np.ndarray:
+    """rho = exp(c s) with c chosen so that max(rho)/min(rho) = ratio."""
+    span = float(s.max() - s.min())
+    return np.exp(s * (math.log(ratio) / span))
+
+
+def face_divergence(shape: Sequence[int], lengths: Sequence[float],
+                    rng: np.random.Generator) -> np.ndarray:
+    """Divergence at cell centres of independent N(0,1) face velocities.
+
+    u_d is stored on the face between cells i and i + e_d; the divergence is
+    sum_d (u_d[i+1/2] - u_d[i-1/2]) / h_d, which sums to zero over the periodic
+    box (telescoping)."""
+    nz, ny, nx = shape
+    hs = (lengths[0] / nx, lengths[1] / ny, lengths[2] / nz)
+    out = np.zeros(shape)
+    for d, axis in enumerate((2, 1, 0)):
+        u = rng.standard_normal(shape)
+        out += (u - np.roll(u, 1, axis=axis)) / hs[d]
+    return out
+
+
+def cic_deposit(shape: Sequence[int], lengths: Sequence[float], pos: np.ndarray) -> np.ndarray:
+    """Cloud-in-cell (trilinear) deposit of unit-weight particles onto cell
+    centres, periodic: the linear particle-to-grid projection the paper uses
+    for two-way coupling (section "Physical model")."""
+    nz, ny, nx = shape
+    ns = (nx, ny, nz)
+    idx = []
+    wts = []
+    for d in range(3):
+        s = pos[:, d] * (ns[d] / lengths[d]) - 0.5
+        i0 = np.floor(s)
+        f = s - i0
+        i0 = i0.astype(np.int64) % ns[d]
+        idx.append((i0, (i0 + 1) % ns[d]))
+        wts.append((1.0 - f, f))
+    n = nx * ny * nz
+    dep = np.zeros(n)
+    for a in (0, 1):
+        for bb in (0, 1):
+            for c in (0, 1):
+                flat = (idx[2][c] * ny + idx[1][bb]) * nx + idx[0][a]
+                dep += np.bincount(flat, weights=wts[0][a] * wts[1][bb] * wts[2][c], minlength=n)
+    return dep.reshape(shape)
+
+
+def gaussian_blobs(shape: Sequence[int], lengths: Sequence[float], centres_xyz: np.ndarray,
+                   sigma_cells: float, cut_sigmas: float = 4.0) -> np.ndarray:
+    """Sum of unit-amplitude periodic Gaussian blobs of width sigma_cells (in
+    cells), truncated at cut_sigmas widths, evaluated at cell centres.  Each blob
+    is separable, exp(-|x-c|^2 / (2 s^2)) = gx * gy * gz, so it is laid down as
+    an outer product over its (2R+1)^3 support."""
+    nz, ny, nx = shape
+    ns = (nx, ny, nz)
+    hs = [lengths[d] / ns[d] for d in range(3)]
+    R = int(math.ceil(cut_sigmas * sigma_cells))
+    offs = np.arange(-R, R + 1)
+    out = np.zeros(shape)
+    for c in centres_xyz:
+        gs = []
+        ids = []
+        for d in range(3):
+            s = c[d] / hs[d] - 0.5  # position in cell-centre index units
+            i0 = int(math.floor(s))
+            cells = i0 + offs
+            dist = cells - s
+            g = np.exp(-0.5 * (dist / sigma_cells) ** 2)
+            g[np.abs(dist) > cut_sigmas * sigma_cells] = 0.0
+            gs.append(g)
+            ids.append(cells % ns[d])
+        block = gs[2][:, None, None] * gs[1][None, :, None] * gs[0][None, None, :]
+        out[np.ix_(ids[2], ids[1], ids[0])] += block
+    return out
+
+
+@dataclass
+class Problem:
+    """One solve: grid shape (nz, ny, nx), box lengths (lx, ly, lz), fields."""
+    name: str
+    shape: Tuple[int, int, int]
+    lengths: Tuple[float, float, float]
+    rho: np.ndarray
+    b: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(np.prod(self.shape))
+
+
+def workload1(n: int = 32) -> Problem:
+    rng = np.random.default_rng(workload_seed(1))
+    L = (TWO_PI,) * 3
+    x = centres(n, TWO_PI)
+    sz, sy, sx = np.sin(x)[:, None, None], np.sin(x)[None, :, None], np.sin(x)[None, None, :]
+    rho = 1.0 + 0.5 * sz * sy * sx
+    b = face_divergence((n, n, n), L, rng)
+    return Problem(f"sinusoidal-rho {n}^3", (n, n, n), L, np.ascontiguousarray(rho), b)
+
+
+def workload2(n: int = 256, ratio: float = 4.0, kmax: float = 8.0) -> Problem:
+    rng = np.random.default_rng(workload_seed(2))
+    L = (TWO_PI,) * 3
+    s = bandlim((n, n, n), L, kmax, rng)
+    rho = contrast_exp(s, ratio)
+    b = bandlim((n, n, n), L, kmax, rng)
+    return Problem(f"lognormal-rho {n}^3 ratio {ratio:g}", (n, n, n), L, rho, b)
+
+
+def workload3(n: int = 512, particles: int = 10**6, ratio: float = 10.0,
+              kmax: float = 8.0) -> Problem:
+    rng = np.random.default_rng(workload_seed(3))
+    L = (TWO_PI,) * 3
+    pos = rng.uniform(0.0, TWO_PI, size=(particles, 3))
+    d = cic_deposit((n, n, n), L, pos)
+    rho = 1.0 / (1.0 + (ratio - 1.0) * d / d.max())
+    b = bandlim((n, n, n), L, kmax, rng)
+    return Problem(f"particle-deposit-rho {n}^3 ratio {ratio:g}", (n, n, n), L, rho, b)
+
+
+def workload5(shape=(512, 512, 1024), blobs: int = 10**5, ratio: float = 20.0,
+              sigma_cells: float = 2.0, kmax: float = 8.0) -> Problem:
+    rng = np.random.default_rng(workload_seed(5))
+    nz, ny, nx = shape
+    h = TWO_PI / ny
+    L = (nx * h, ny * h, nz * h)
+    cen = rng.uniform(0.0, 1.0, size=(blobs, 3)) * np.asarray(L)
+    f = gaussian_blobs(shape, L, cen, sigma_cells)
+    rho = 1.0 / (1.0 + (ratio - 1.0) * f / f.max())
+    b = bandlim(shape, L, kmax, rng)
+    return Problem(f"hot-blob-rho {nx}x{ny}x{nz} ratio {ratio:g}", tuple(shape), L, rho, b)
+
+
+SERVE_SIZES = (64, 96, 128, 192)
+
+
+@dataclass
+class Request:
+    rid: int
+    arrival_s: float
+    n: int
+    ratio: float
+
+
+def request_stream(count: int = 512, rate_hz: float = 100.0,
+                   sizes: Sequence[int] = SERVE_SIZES) -> List[Request]:
+    """Poisson arrivals at a fixed rate; grid size uniform over `sizes`;
+    density contrast uniform in [2, 8]."""
+    rng = np.random.default_rng(workload_seed(4))
+    gaps = rng.exponential(1.0 / rate_hz, size=count)
+    t = np.cumsum(gaps) - gaps[0]
+    ns = rng.choice(np.asarray(sizes), size=count)
+    ratios = rng.uniform(2.0, 8.0, size=count)
+    return [Request(r, float(t[r]), int(ns[r]), float(ratios[r])) for r in range(count)]
+
+
+def request_problem(req: Request, kmax: float = 8.0) -> Problem:
+    """Fields of one served request: lognormal band-limited rho with the
+    request's contrast, band-limited zero-mean b."""
+    rng = np.random.default_rng(request_seed(req.rid))
+    n = req.n
+    L = (TWO_PI,) * 3
+    s = bandlim((n, n, n), L, kmax, rng)
+    rho = contrast_exp(s, req.ratio)
+    b = bandlim((n, n, n), L, kmax, rng)
+    return Problem(f"request {req.rid} {n}^3 ratio {req.ratio:.2f}", (n, n, n), L, rho, b)
+
+
+def small_problem(shape=(16, 12, 24), lengths=(TWO_PI, 3.0, 5.0), ratio: float = 3.0,
+                  seed: int = 7, kmax: float = 3.0) -> Problem:
+    """A small anisotropic problem (distinct nx, ny, nz and lx, ly, lz) for
+    parity tests that must catch transposed axes."""
+    rng = np.random.default_rng(seed)
+    L3 = (lengths[0], lengths[1], lengths[2])
+    s = bandlim(shape, L3, kmax, rng)
+    rho = contrast_exp(s, ratio)
+    b = bandlim(shape, L3, kmax, rng) + 0.3 * rng.standard_normal(shape)
+    return Problem(f"small {shape}", tuple(shape), L3, rho, b)

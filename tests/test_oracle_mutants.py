@@ -1,0 +1,74 @@
+"""Planted mistakes in the oracle must each fail at least one pin.
+
+Each case copies the oracle's C source, makes one plausible mistake in it (a
+wrong coefficient, a flipped sign, a wrong neighbour index, swapped spacings, a
+dropped mean removal, a wrong FFT twiddle ...), builds the copy with gcc into a
+temporary directory and runs the pins of test_oracle_pins against it.  The real
+oracle is untouched; everything happens on the CPU.
+"""
+import os
+import subprocess
+
+import pytest
+
+import oracle
+import test_oracle_pins as pins
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "poisson_oracle.c")
+
+MUTANTS = {
+    "face coefficient halved": ("return 2.0 / (ra + rb);", "return 1.0 / (ra + rb);"),
+    "flux difference sign": ("acc += (bp * (p[cp] - p[c]) - bm * (p[c] - p[cm])) / h2[d];",
+                             "acc += (bp * (p[cp] - p[c]) + bm * (p[c] - p[cm])) / h2[d];"),
+    "minus-face uses plus neighbour": ("const double bm = rho ? face_beta(coef, rho[cm], rho[c]) : 1.0;",
+                                       "const double bm = rho ? face_beta(coef, rho[cp], rho[c]) : 1.0;"),
+    "spacings swapped y<->z": ("const double h2[3] = {hx * hx, hy * hy, hz * hz};",
+                               "const double h2[3] = {hx * hx, hz * hz, hy * hy};"),
+    "x minus neighbour wrong": ("if (d == 0) { ip = wrap(i + 1, n3[0]); im = wrap(i - 1, n3[0]); }\n"
+                                "                    if (d == 1) { jp = wrap(j + 1, n3[1]); jm = wrap(j - 1, n3[1]); }\n"
+                                "                    if (d == 2) { kp = wrap(k + 1, n3[2]); km = wrap(k - 1, n3[2]); }\n"
+                                "                    const size_t cp",
+                                "if (d == 0) { ip = wrap(i + 1, n3[0]); im = wrap(i - 2, n3[0]); }\n"
+                                "                    if (d == 1) { jp = wrap(j + 1, n3[1]); jm = wrap(j - 1, n3[1]); }\n"
+                                "                    if (d == 2) { kp = wrap(k + 1, n3[2]); km = wrap(k - 1, n3[2]); }\n"
+                                "                    const size_t cp"),
+    "symbol factor": ("return -4.0 * s * s / (h * h);", "return -2.0 * s * s / (h * h);"),
+    "symbol axes transposed": ("symbol_1d(j, ny, hy)", "symbol_1d(j, ny, hx)"),
+    "zero mode kept": ("                    F[c] = 0.0;\n                    continue;",
+                       "                    continue;"),
+    "weight inverted": ("w[c] = rho[c];", "w[c] = 1.0 / rho[c];"),
+    "update sign": ("p[c] += dp[c];\n    }\ndone:", "p[c] -= 0.5 * dp[c];\n    }\ndone:"),
+    "mean of b not removed": ("for (size_t c = 0; c < n; ++c) bt[c] = b[c] - bm;",
+                              "for (size_t c = 0; c < n; ++c) bt[c] = b[c];"),
+    "twiddle sign ignored": ("tw[t] = cos(a) + (double)sign * sin(a) * I;", "tw[t] = cos(a) - sin(a) * I;"),
+    "radix-3 combine index": ("const long t = ((long)q * (long)K) % n;", "const long t = ((long)q * (long)(K % m)) % n;"),
+    "gauge not fixed": ("for (size_t c = 0; c < n; ++c) p[c] -= pm;\n    }\n    make_weight",
+                        "(void)pm;\n    }\n    make_weight"),
+}
+
+
+def _caught(lib_path):
+    with oracle.use_library(lib_path):
+        for pin in pins.ALL_PINS:
+            try:
+                pin()
+            except (AssertionError, oracle.OracleError, FloatingPointError):
+                return pin.__name__
+    return None
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name!r} not unique in the oracle source"
+    mut = tmp_path / "mutant.c"
+    mut.write_text(src.replace(old, new))
+    lib = tmp_path / "libmutant.so"
+    subprocess.run(["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o",
+                    str(lib), str(mut), "-lm"], check=True)
+    import numpy as np
+    with np.errstate(all="ignore"):
+        who = _caught(str(lib))
+    assert who is not None, f"no pin caught the planted mistake {name!r}"

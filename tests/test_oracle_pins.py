@@ -1,0 +1,478 @@
+"""Pins of the FP64 CPU oracle against facts fixed by the paper and by the
+mathematics, never against the oracle itself.
+
+Paper: Pouransari, Mortazavi & Mani, arXiv:1601.05448.  The problem is
+div((1/rho) grad p) = f on the periodic staggered grid (section "Poisson
+equation"; section "Spatial discretization"); f is made zero-mean by the
+compatibility constant chi (Appendix A); the solver is the split p = p_g + dp
+with the cross term rho grad(1/rho).grad dp dropped and p_g <- p_g + dp iterated
+(eq. (Pois)).  The paper prints no numerical worked example for this solve, so
+every pin below is a closed form, an invariant, a library routine or brute
+force:
+
+  fft       oracle DFT == numpy.fft and == the O(n^2) definition
+  symbol    constant rho: A cos(m.x) = -(1/rho0) sum_d 4 sin^2(pi m_d/N_d)/h_d^2 cos(m.x)
+  order2    manufactured smooth p, rho: A p -> div(rho^-1 grad p) at O(h^2)
+  flux1d    rho, b varying along one axis only: exact prefix-sum solution
+  matrix    A = A^T, A 1 = 0, -A positive semi-definite with a 1-D kernel
+  pinv      L(L^+ q) = q - mean q, mean(L^+ q) = 0
+  const     constant rho, one Fourier mode: exact answer after ONE iteration
+  discrete  b = A p*  ->  p* recovered
+  dense     8^3 brute force (numpy lstsq on the assembled matrix) == iteration
+  cg        conjugate gradients == iteration
+  equivar   scaling rho -> c rho gives p -> c p; shifts; axis permutation
+  bound     ||p - p*|| <= rho_max ||r|| / min_d 4 sin^2(pi/N_d)/h_d^2
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1601_05448_amd import inputs
+
+TWO_PI = 2.0 * math.pi
+
+
+def _coords(shape, lengths):
+    nz, ny, nx = shape
+    lx, ly, lz = lengths
+    x = inputs.centres(nx, lx)[None, None, :]
+    y = inputs.centres(ny, ly)[None, :, None]
+    z = inputs.centres(nz, lz)[:, None, None]
+    return x, y, z
+
+
+def _lengths_h(shape, lengths):
+    nz, ny, nx = shape
+    return (lengths[0] / nx, lengths[1] / ny, lengths[2] / nz)
+
+
+# --------------------------------------------------------------------------
+# FFT
+# --------------------------------------------------------------------------
+
+LENGTHS_2A3B = [n for n in range(1, 1025) if (lambda m: (m // (m & -m)) in (1, 3, 9, 27, 81, 243, 729))(n)]
+
+
+def pin_fft():
+    rng = np.random.default_rng(1)
+    for n in LENGTHS_2A3B:
+        x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        ref = np.fft.fft(x)
+        got = oracle.fft1d(x, -1)
+        assert np.max(np.abs(got - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref))), n
+        back = oracle.fft1d(got, +1) / n
+        assert np.max(np.abs(back - x)) <= 1e-13 * max(1.0, np.max(np.abs(x))), n
+    for n in (2, 3, 4, 6, 12, 18):  # the definition, written out
+        x = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        jk = np.outer(np.arange(n), np.arange(n))
+        ref = np.exp(-2j * np.pi * jk / n) @ x
+        assert np.allclose(oracle.fft1d(x, -1), ref, atol=1e-12, rtol=0)
+
+
+def test_fft_matches_numpy_and_definition():
+    pin_fft()
+
+
+# --------------------------------------------------------------------------
+# operator
+# --------------------------------------------------------------------------
+
+
+def pin_symbol():
+    """Constant rho: every Fourier mode is an eigenvector of A with the discrete
+    symbol; checked for modes along each axis separately on an anisotropic grid
+    (catches a wrong sign, a dropped axis and swapped spacings)."""
+    shape, L = (12, 8, 16), (TWO_PI, 3.0, 5.5)
+    x, y, z = _coords(shape, L)
+    hx, hy, hz = _lengths_h(shape, L)
+    rho0 = 1.7
+    rho = np.full(shape, rho0)
+    for coef in (0, 1):
+        for m in ((1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 3, 1), (3, 0, 2)):
+            ph = TWO_PI * (m[0] * x / L[0] + m[1] * y / L[1] + m[2] * z / L[2])
+            for f in (np.cos(ph), np.sin(ph)):
+                f = np.broadcast_to(f, shape)
+                lam = sum(4 * math.sin(math.pi * m[d] / shape[2 - d]) ** 2 / h ** 2
+                          for d, h in enumerate((hx, hy, hz)))
+                got = oracle.apply(rho, f, L, coef)
+                assert np.max(np.abs(got + (lam / rho0) * f)) <= 1e-11 * max(1.0, lam), (coef, m)
+
+
+def test_constant_rho_symbol():
+    pin_symbol()
+
+
+def _manufactured(shape, L):
+    x, y, z = _coords(shape, L)
+    ax, ay, az = TWO_PI / L[0], TWO_PI / L[1], TWO_PI / L[2]
+    p = np.cos(ax * x) * np.sin(2 * ay * y) * np.cos(az * z)
+    rho = 1.0 + 0.5 * np.sin(ax * x) * np.sin(ay * y) * np.sin(az * z)
+    px = -ax * np.sin(ax * x) * np.sin(2 * ay * y) * np.cos(az * z)
+    py = 2 * ay * np.cos(ax * x) * np.cos(2 * ay * y) * np.cos(az * z)
+    pz = -az * np.cos(ax * x) * np.sin(2 * ay * y) * np.sin(az * z)
+    lap = -(ax * ax + 4 * ay * ay + az * az) * p
+    rx = 0.5 * ax * np.cos(ax * x) * np.sin(ay * y) * np.sin(az * z)
+    ry = 0.5 * ay * np.sin(ax * x) * np.cos(ay * y) * np.sin(az * z)
+    rz = 0.5 * az * np.sin(ax * x) * np.sin(ay * y) * np.cos(az * z)
+    f = lap / rho - (rx * px + ry * py + rz * pz) / rho ** 2
+    b = lambda a: np.ascontiguousarray(np.broadcast_to(a, shape))  # noqa: E731
+    return b(p), b(rho), b(f)
+
+
+def pin_order2():
+    """The discrete operator converges to div(rho^-1 grad p) at second order (the
+    paper's discretisation is second order, section "Spatial discretization"):
+    error ratio ~4 per halving of h, on an anisotropic box with distinct N."""
+    L = (TWO_PI, 4.0, 9.0)
+    for coef in (0, 1):
+        errs = []
+        for s in (1, 2, 4):
+            shape = (8 * s, 12 * s, 16 * s)
+            p, rho, f = _manufactured(shape, L)
+            errs.append(np.max(np.abs(oracle.apply(rho, p, L, coef) - f)) / np.max(np.abs(f)))
+        r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+        assert 3.6 < r1 < 4.4 and 3.8 < r2 < 4.2, (coef, errs)
+        assert errs[2] < 1e-2
+
+
+def test_second_order_manufactured():
+    pin_order2()
+
+
+def _flux1d_solution(rho1, b1, h, coef):
+    """Exact solution of the 1-D periodic flux problem
+    (g_{i+1/2} - g_{i-1/2})/h = b_i - mean(b), g_{i+1/2} = beta_{i+1/2} (p_{i+1} - p_i)/h,
+    by prefix sums: g = G + h cumsum(b~), periodicity sum h g / beta = 0 fixes G."""
+    rn = np.roll(rho1, -1)
+    beta = 2.0 / (rho1 + rn) if coef == 0 else 0.5 * (1.0 / rho1 + 1.0 / rn)
+    bt = b1 - b1.mean()
+    S = h * np.cumsum(bt)
+    G = -np.sum(S / beta) / np.sum(1.0 / beta)
+    g = G + S
+    dp = h * g / beta  # p_{i+1} - p_i
+    p = np.concatenate([[0.0], np.cumsum(dp)[:-1]])
+    return p - p.mean()
+
+
+def pin_flux1d():
+    rng = np.random.default_rng(3)
+    shape, L = (12, 8, 16), (TWO_PI, 5.0, 3.0)
+    hx, hy, hz = _lengths_h(shape, L)
+    for coef in (0, 1):
+        for axis, n, h in ((2, 16, hx), (1, 8, hy), (0, 12, hz)):
+            rho1 = np.exp(rng.uniform(-1.2, 1.2, n))
+            b1 = rng.standard_normal(n)
+            want1 = _flux1d_solution(rho1, b1, h, coef)
+            sh = [1, 1, 1]
+            sh[axis] = n
+            rho = np.ascontiguousarray(np.broadcast_to(rho1.reshape(sh), shape))
+            b = np.ascontiguousarray(np.broadcast_to(b1.reshape(sh), shape))
+            want = np.broadcast_to(want1.reshape(sh), shape)
+            for weight in _weights(coef):
+                got = oracle.solve(rho, b, lengths=L, coef=coef, weight=weight, tol=1e-13)["p"]
+                assert np.max(np.abs(got - want)) <= 1e-11 * max(1.0, np.max(np.abs(want))), (coef, axis)
+
+
+def test_flux_form_1d_closed_form():
+    pin_flux1d()
+
+
+def _weights(coef):
+    """Weights under which the iteration contracts on cell-scale rough density:
+    with the face-averaged 1/rho coefficient the paper's multiplier rho can give
+    rho_c * beta > 2 and diverge (see test_rough_density_divergence), so that
+    combination is exercised on smooth fields only."""
+    return (0, 1) if coef == 0 else (1,)
+
+
+def _matrix(rho, L, coef):
+    shape = rho.shape
+    n = rho.size
+    M = np.empty((n, n))
+    e = np.zeros(n)
+    for j in range(n):
+        e[j] = 1.0
+        M[:, j] = oracle.apply(rho, e.reshape(shape), L, coef).ravel()
+        e[j] = 0.0
+    return M
+
+
+def pin_matrix():
+    rng = np.random.default_rng(4)
+    shape, L = (4, 6, 5), (TWO_PI, 2.0, 3.0)
+    rho = np.exp(rng.uniform(-1, 1, shape))
+    for coef in (0, 1):
+        M = _matrix(rho, L, coef)
+        scale = np.max(np.abs(M))
+        assert np.max(np.abs(M - M.T)) <= 1e-14 * scale
+        assert np.max(np.abs(M.sum(axis=1))) <= 1e-12 * scale
+        ev = np.linalg.eigvalsh(-0.5 * (M + M.T))
+        assert ev[0] > -1e-12 * scale
+        assert ev[1] > 1e-6 * scale  # kernel is exactly the constants
+
+
+def test_operator_matrix_invariants():
+    pin_matrix()
+
+
+# --------------------------------------------------------------------------
+# constant-coefficient inverse (the inner solve of eq. (Pois))
+# --------------------------------------------------------------------------
+
+
+def pin_pinv():
+    rng = np.random.default_rng(5)
+    for shape, L in (((8, 12, 6), (TWO_PI, 3.0, 7.0)), ((16, 16, 16), (TWO_PI,) * 3),
+                     ((9, 4, 18), (1.0, 2.0, 3.0))):
+        q = rng.standard_normal(shape) + 3.0
+        d = oracle.lap_pinv(q, L)
+        assert abs(d.mean()) <= 1e-12 * np.max(np.abs(d))
+        back = oracle.apply(None, d, L)
+        assert np.max(np.abs(back - (q - q.mean()))) <= 1e-11 * np.max(np.abs(q))
+        # library route: numpy FFT with the discrete symbol
+        nz, ny, nx = shape
+        hx, hy, hz = _lengths_h(shape, L)
+        sym = lambda n, h: -4 * np.sin(np.pi * np.arange(n) / n) ** 2 / h ** 2  # noqa: E731
+        lam = sym(nz, hz)[:, None, None] + sym(ny, hy)[None, :, None] + sym(nx, hx)[None, None, :]
+        lam[0, 0, 0] = 1.0
+        F = np.fft.fftn(q) / lam
+        F[0, 0, 0] = 0.0
+        ref = np.fft.ifftn(F).real
+        assert np.max(np.abs(d - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_constant_coefficient_inverse():
+    pin_pinv()
+
+
+# --------------------------------------------------------------------------
+# the paper's iteration
+# --------------------------------------------------------------------------
+
+
+def pin_const_one_iteration():
+    """With constant rho the dropped term rho grad(1/rho).grad dp vanishes, so the
+    split of eq. (Pois) is exact: one iteration gives the answer, and for a single
+    Fourier mode that answer is closed-form."""
+    shape, L = (12, 16, 8), (TWO_PI, 4.0, 3.0)
+    x, y, z = _coords(shape, L)
+    hx, hy, hz = _lengths_h(shape, L)
+    for coef in (0, 1):
+        for weight in (0, 1):
+            for rho0, m in ((2.5, (1, 2, 1)), (0.4, (3, 0, 2))):
+                ph = TWO_PI * (m[0] * x / L[0] + m[1] * y / L[1] + m[2] * z / L[2])
+                b = np.ascontiguousarray(np.broadcast_to(np.cos(ph) + 0.25, shape))
+                lam = sum(4 * math.sin(math.pi * m[d] / shape[2 - d]) ** 2 / h ** 2
+                          for d, h in enumerate((hx, hy, hz)))
+                want = -rho0 * (b - 0.25) / lam
+                res = oracle.solve(np.full(shape, rho0), b, lengths=L, coef=coef, weight=weight,
+                                   tol=1e-13)
+                assert res["iters"] == 1, res["history"]
+                assert abs(res["b_mean"] - 0.25) < 1e-14
+                assert np.max(np.abs(res["p"] - want)) <= 1e-13 * np.max(np.abs(want))
+
+
+def test_constant_rho_exact_in_one_iteration():
+    pin_const_one_iteration()
+
+
+def pin_discrete_manufactured():
+    shape, L = (16, 16, 16), (TWO_PI,) * 3
+    p, rho, _ = _manufactured(shape, L)
+    p = p - p.mean()
+    for coef in (0, 1):
+        b = oracle.apply(rho, p, L, coef)
+        got = oracle.solve(rho, b, lengths=L, coef=coef, tol=1e-13)
+        assert np.max(np.abs(got["p"] - p)) <= 1e-12
+
+
+def test_discrete_manufactured_recovered():
+    pin_discrete_manufactured()
+
+
+def pin_dense():
+    rng = np.random.default_rng(6)
+    shape, L = (8, 8, 8), (TWO_PI,) * 3
+    rho = np.exp(rng.uniform(-0.8, 0.8, shape))
+    b = rng.standard_normal(shape)
+    for coef in (0, 1):
+        M = _matrix(rho, L, coef)
+        ref = np.linalg.lstsq(M, (b - b.mean()).ravel(), rcond=None)[0].reshape(shape)
+        de = oracle.dense(rho, b, lengths=L, coef=coef)
+        scale = np.max(np.abs(ref))
+        assert np.max(np.abs(de - ref)) <= 1e-12 * scale
+        for weight in _weights(coef):
+            it = oracle.solve(rho, b, lengths=L, coef=coef, weight=weight, tol=1e-13)["p"]
+            assert np.max(np.abs(it - ref)) <= 1e-12 * scale
+
+
+def test_dense_brute_force_8cubed():
+    pin_dense()
+
+
+def pin_cg():
+    prob = inputs.small_problem()
+    for coef in (0, 1):
+        it = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, coef=coef, tol=1e-13)["p"]
+        cg = oracle.cg(prob.rho, prob.b, lengths=prob.lengths, coef=coef, tol=1e-13)["p"]
+        assert np.linalg.norm(it - cg) <= 1e-11 * np.linalg.norm(cg)
+
+
+def test_cg_cross_check():
+    pin_cg()
+
+
+def pin_equivariance():
+    prob = inputs.small_problem(shape=(12, 8, 16), lengths=(TWO_PI, 3.0, 5.0))
+    rho, b, L = prob.rho, prob.b, prob.lengths
+    base = oracle.solve(rho, b, lengths=L, tol=1e-13)["p"]
+    scale = np.max(np.abs(base))
+    # rho -> c rho scales p by c; b -> c b scales p by c
+    assert np.max(np.abs(oracle.solve(3.0 * rho, b, lengths=L, tol=1e-13)["p"] - 3.0 * base)) <= 1e-12 * scale * 3
+    assert np.max(np.abs(oracle.solve(rho, -2.0 * b, lengths=L, tol=1e-13)["p"] + 2.0 * base)) <= 1e-12 * scale * 2
+    # periodic shift
+    sh = (3, -2, 5)
+    got = oracle.solve(np.roll(rho, sh, axis=(0, 1, 2)), np.roll(b, sh, axis=(0, 1, 2)), lengths=L,
+                       tol=1e-13)["p"]
+    assert np.max(np.abs(got - np.roll(base, sh, axis=(0, 1, 2)))) <= 1e-12 * scale
+    # axis permutation (x <-> z): transpose the arrays and swap the lengths
+    got = oracle.solve(np.ascontiguousarray(rho.transpose(2, 1, 0)),
+                       np.ascontiguousarray(b.transpose(2, 1, 0)), lengths=(L[2], L[1], L[0]),
+                       tol=1e-13)["p"]
+    assert np.max(np.abs(got - base.transpose(2, 1, 0))) <= 1e-12 * scale
+
+
+def test_equivariance():
+    pin_equivariance()
+
+
+def pin_bound():
+    prob = inputs.small_problem()
+    exact = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, tol=1e-13)["p"]
+    for k in (1, 2, 4):
+        early = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, tol=1e-13, max_iter=k,
+                             allow_noconv=True)
+        assert early["code"] == oracle.ENOCONV
+        res = oracle.residual(prob.rho, prob.b, early["p"], prob.lengths)
+        bound = oracle.error_bound(prob.shape, prob.lengths, prob.rho.max(), res["r_norm"])
+        err = np.linalg.norm(early["p"] - exact)
+        assert err <= bound
+        assert err >= bound * 1e-6  # the bound is not vacuous
+
+
+def test_a_posteriori_bound():
+    pin_bound()
+
+
+# --------------------------------------------------------------------------
+# solver semantics
+# --------------------------------------------------------------------------
+
+
+def test_weight_does_not_change_the_answer():
+    prob = inputs.small_problem()
+    a = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, weight=0, tol=1e-13)
+    b = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, weight=1, tol=1e-13)
+    assert np.linalg.norm(a["p"] - b["p"]) <= 1e-11 * np.linalg.norm(a["p"])
+
+
+def test_coefficient_modes_differ():
+    """The two face-coefficient readings are different discretisations: the
+    answers differ well above rounding (so a parity test must name its mode)."""
+    prob = inputs.small_problem(ratio=8.0)
+    a = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, coef=0, tol=1e-13)["p"]
+    b = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, coef=1, tol=1e-13)["p"]
+    assert np.linalg.norm(a - b) > 1e-4 * np.linalg.norm(a)
+
+
+def test_convergence_slows_with_density_contrast():
+    """The paper notes that the convergence rate depends on the variation of the
+    density field; iterations must not decrease as the contrast grows."""
+    its = []
+    for ratio in (1.0, 2.0, 8.0, 32.0):
+        prob = inputs.small_problem(shape=(16, 16, 16), lengths=(TWO_PI,) * 3, ratio=ratio)
+        its.append(oracle.solve(prob.rho, prob.b, lengths=prob.lengths, tol=1e-10)["iters"])
+    assert its[0] == 1
+    assert its == sorted(its) and its[-1] > its[1]
+
+
+def pin_mean_removal():
+    prob = inputs.small_problem()
+    a = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, tol=1e-13)
+    b = oracle.solve(prob.rho, prob.b + 5.0, lengths=prob.lengths, tol=1e-13)
+    assert abs(b["b_mean"] - a["b_mean"] - 5.0) < 1e-12
+    assert abs(a["p"].mean()) < 1e-13 * np.max(np.abs(a["p"]))
+    assert np.max(np.abs(a["p"] - b["p"])) <= 1e-12 * np.max(np.abs(a["p"]))
+
+
+def test_mean_of_b_removed_and_p_zero_mean():
+    pin_mean_removal()
+
+
+def pin_gauge():
+    """Warm start (p_g is the previous estimate, section "Poisson equation"): from
+    the answer plus a constant, zero iterations and the zero-mean answer."""
+    prob = inputs.small_problem()
+    a = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, tol=1e-12)
+    again = oracle.solve(prob.rho, prob.b, p0=a["p"] + 4.0, lengths=prob.lengths, tol=1e-12)
+    assert again["iters"] == 0
+    assert abs(again["p"].mean()) < 1e-12
+    assert np.max(np.abs(again["p"] - a["p"])) <= 1e-12 * np.max(np.abs(a["p"]))
+
+
+def test_warm_start_and_gauge():
+    pin_gauge()
+
+
+def test_degenerate_and_invalid_inputs():
+    prob = inputs.small_problem()
+    flat = oracle.solve(prob.rho, np.full(prob.shape, 2.0), p0=np.ones(prob.shape), lengths=prob.lengths)
+    assert flat["iters"] == 0 and np.all(flat["p"] == 0.0)
+    bad = prob.rho.copy()
+    bad[1, 2, 3] = -1.0
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.solve(bad, prob.b, lengths=prob.lengths)
+    assert e.value.code == oracle.EDOMAIN
+    nanb = prob.b.copy()
+    nanb[0, 0, 0] = np.nan
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.solve(prob.rho, nanb, lengths=prob.lengths)
+    assert e.value.code == oracle.EDOMAIN
+    res = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, tol=1e-30, max_iter=3, allow_noconv=True)
+    assert res["code"] == oracle.ENOCONV and res["iters"] == 3
+    with pytest.raises(oracle.OracleError):
+        oracle.solve(np.ones((5, 4, 4)), np.ones((5, 4, 4)))  # 5 is not 2^a 3^b
+
+
+def test_rough_density_divergence():
+    """With beta = (1/rho_a + 1/rho_b)/2 and w = rho, rho_c * beta = (1 + rho_c/rho_nb)/2
+    is unbounded, and on cell-to-cell rough rho the iteration diverges; with
+    beta = 2/(rho_a + rho_b) it is below 2 and the iteration converges.  The
+    oracle reports the divergence instead of looping."""
+    rng = np.random.default_rng(6)
+    shape, L = (8, 8, 8), (TWO_PI,) * 3
+    rho = np.exp(rng.uniform(-0.8, 0.8, shape))
+    b = rng.standard_normal(shape)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.solve(rho, b, lengths=L, coef=1, weight=0, tol=1e-12)
+    assert e.value.code == oracle.EDIVERGED
+    assert oracle.solve(rho, b, lengths=L, coef=0, weight=0, tol=1e-12)["rel"] <= 1e-12
+
+
+def test_residual_verifier_definition():
+    """The O(n) verifier returns b - mean(b) - A p with the documented norms."""
+    prob = inputs.small_problem()
+    p = np.random.default_rng(8).standard_normal(prob.shape)
+    res = oracle.residual(prob.rho, prob.b, p, prob.lengths, want_field=True)
+    Ap = oracle.apply(prob.rho, p, prob.lengths)
+    want = prob.b - prob.b.mean() - Ap
+    assert np.max(np.abs(res["r"] - want)) <= 1e-13 * np.max(np.abs(want))
+    assert abs(res["r_norm"] - np.linalg.norm(want)) <= 1e-12 * np.linalg.norm(want)
+    assert abs(res["b_norm"] - np.linalg.norm(prob.b - prob.b.mean())) <= 1e-12 * res["b_norm"]
+
+
+ALL_PINS = [pin_fft, pin_symbol, pin_order2, pin_flux1d, pin_matrix, pin_pinv,
+            pin_const_one_iteration, pin_discrete_manufactured, pin_dense, pin_cg,
+            pin_equivariance, pin_bound, pin_mean_removal, pin_gauge]
