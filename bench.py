@@ -1,0 +1,153 @@
+"""Throughput of the variable-density Poisson solve on one MI355X.
+
+Workload: 256^3 periodic cube [0, 2pi)^3, rho = exp(s) with s a seeded Gaussian
+field band-limited to |k| <= 8 scaled to max/min rho = 4, b band-limited
+|k| <= 8; tolerance 1e-10 on ||b~ - A p|| / ||b~||.  One step = one complete
+solve from p = 0 (the zeroing of p included), inputs resident in HBM.  Both
+arithmetic paths are timed (FP64, and FP32 sweeps with FP64 refinement); the
+headline value is the faster path.  Prints one JSON line.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Poisson solves/s at 256^3 to 1e-10 resid (FP64 vs FP32+refine); p50/p99 ms"
+HBM_PEAK_GBS = 8000.0
+# algorithmic HBM bytes per cell of each sweep (FP64, FP32): read inputs once,
+# write outputs once
+SWEEP_BYTES = {1: (32, 16), 2: (16, 8), 3: (16, 8), 5: (24, 12)}
+SWEEP_NAMES = {1: "k_resid_dhtx", 2: "k_dht_cols (y)", 3: "k_dht_z_solve", 5: "k_dhtx_update"}
+
+
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q
+    f, c = math.floor(k), math.ceil(k)
+    return xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def time_path(P, torch, prob, precision, steps, warmup, tol):
+    rho = torch.from_numpy(prob.rho).cuda()
+    b = torch.from_numpy(prob.b).cuda()
+    p = torch.zeros(prob.shape, dtype=torch.float64, device="cuda")
+    s = P.Solver(prob.shape, prob.lengths, precision=precision)
+    stats = None
+    for _ in range(warmup):
+        p.zero_()
+        stats = s.solve(rho, b, p, tol)
+    torch.cuda.synchronize()
+    lat = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        p.zero_()
+        stats = s.solve(rho, b, p, tol)
+        lat.append((time.perf_counter() - a) * 1e3)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if stats["status"] != 0:
+        raise RuntimeError(f"solve failed: {stats}")
+    out = dict(solves_per_s=steps / (t1 - t0), ms_per_solve=(t1 - t0) * 1e3 / steps,
+               p50_ms=percentile(lat, 0.5), p99_ms=percentile(lat, 0.99), iters=stats["iters"],
+               outer_iters=stats["outer_iters"], rel_resid=stats["rel_resid"],
+               err_bound_rel=stats["err_bound_rel"], device_ms=stats["ms"])
+    # per-sweep device time with HIP events on the solver's stream
+    sweeps = {}
+    for sw in (1, 2, 3, 5):
+        for fp32 in ((False, True) if precision == P.POISSON_FP32_REFINE else (False,)):
+            ms = P.poisson_time_sweep(s.h, sw, fp32, rho, b, p, 20)
+            nbytes = SWEEP_BYTES[sw][1 if fp32 else 0] * prob.n
+            sweeps[f"{'f32' if fp32 else 'f64'}:{SWEEP_NAMES[sw]}"] = dict(
+                ms=ms, bytes=nbytes, gbs=nbytes / ms / 1e6)
+    s.close()
+    out["sweeps"] = sweeps
+    return out
+
+
+def cpu_baseline(prob, fp64_iters):
+    """The oracle (single-threaded C, FP64) on a bounded sample of the same
+    workload: one residual evaluation plus one iteration, scaled to the
+    iteration count the method needs on this workload."""
+    import numpy as np
+
+    import oracle
+
+    t0 = time.perf_counter()
+    oracle.residual(prob.rho, prob.b, np.zeros(prob.shape), prob.lengths)
+    t_res = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.solve(prob.rho, prob.b, lengths=prob.lengths, tol=1e-10, max_iter=1, allow_noconv=True)
+    t_one = time.perf_counter() - t0
+    t_iter = max(t_one - t_res, 1e-9)
+    t_solve = t_res + fp64_iters * t_iter
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"one oracle iteration on the {prob.shape[0]}^3 workload ({t_one:.1f} s incl. setup), "
+                      f"scaled to {fp64_iters} iterations + 1 residual"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see the design notes on "
+              "sharding); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1601_05448_amd import inputs
+    from paper_1601_05448_amd import poisson as P
+
+    torch.cuda.set_device(0)
+    prob = inputs.workload2(args.size)
+    fp64 = time_path(P, torch, prob, P.POISSON_FP64, args.steps, args.warmup, args.tol)
+    fp32 = time_path(P, torch, prob, P.POISSON_FP32_REFINE, args.steps, args.warmup, args.tol)
+    best_name, best = ("fp32_refine", fp32) if fp32["solves_per_s"] > fp64["solves_per_s"] else ("fp64", fp64)
+
+    # dominant kernel of the headline path: the sweep with the largest share of an iteration
+    sw = best["sweeps"]
+    key = max(sw, key=lambda k: sw[k]["ms"] * (2 if "k_dht_cols" in k else 1))
+    dom = sw[key]
+    roofline = {"bound": "hbm", "kernel": key, "achieved": dom["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dom["gbs"] / HBM_PEAK_GBS, "traffic": None}
+
+    line = {
+        "metric": METRIC,
+        "value": best["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": best["ms_per_solve"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 sweeps + f64 refinement" if best_name == "fp32_refine" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.size}^3 lognormal rho (max/min 4), band-limited b, tol {args.tol:g}",
+                   "path": best_name, "p50_ms": best["p50_ms"], "p99_ms": best["p99_ms"]},
+        "paths": {"fp64": fp64, "fp32_refine": fp32},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(prob, fp64["iters"])
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

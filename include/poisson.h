@@ -1,0 +1,187 @@
+/*
+ * poisson.h -- C ABI of libpoisson, an MI355X (gfx950) solver for the
+ * variable-coefficient pressure Poisson equation
+ *
+ *        div( (1/rho) grad p ) = b
+ *
+ * on a uniform, triply periodic, staggered grid, by the iteration of
+ * Pouransari, Mortazavi & Mani, "Parallel variable-density particle-laden
+ * turbulence simulation" (arXiv:1601.05448), section "Poisson equation",
+ * eq. (Pois): write p = p_g + dp, drop the term rho grad(1/rho).grad dp, solve
+ * the remaining constant-coefficient Poisson equation by Fourier transform in
+ * the periodic directions, set p_g <- p_g + dp and repeat until convergence.
+ *
+ * Discretisation (section "Spatial discretization"; staggered-grid figure):
+ * rho, b and p live at cell centres, fluxes on faces, second order:
+ *     (A p)_c = sum_d [ beta_{c+1/2}(p_{c+e_d} - p_c) - beta_{c-1/2}(p_c - p_{c-e_d}) ] / h_d^2
+ * with h_d = L_d / N_d and the face coefficient chosen by `coef` below.
+ * Compatibility (Appendix A, the constant chi): the mean of b is removed
+ * before solving, and p is returned with zero mean.
+ *
+ * Fields: contiguous arrays of n = nx*ny*nz values laid out [nz][ny][nx]
+ * (x fastest), index (k*ny + j)*nx + i, cell centre ((i+1/2)hx, (j+1/2)hy,
+ * (k+1/2)hz).  Every field pointer is a DEVICE pointer (hipMalloc'd memory,
+ * e.g. torch.Tensor.data_ptr()) on the current HIP device.  Callers own rho,
+ * b and p; the library owns its workspace.  rho, b and p must not overlap.
+ *
+ * Grid sizes: each of nx, ny, nz must be 2^a or 3*2^a with 4 <= N <= 1024.
+ *
+ * Threading: a handle is used by one host thread at a time.  Calls enqueue
+ * work on the handle's stream and, unless stated otherwise, block until that
+ * work has finished.  No C++ exception crosses this interface.
+ */
+#ifndef PAPER_1601_05448_AMD_POISSON_H
+#define PAPER_1601_05448_AMD_POISSON_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define POISSON_OK 0
+#define POISSON_EINVAL (-1)    /* bad size, NULL or overlapping pointer, tol <= 0, bad enum */
+#define POISSON_ENOMEM (-2)    /* device or host allocation failed                         */
+#define POISSON_EDOMAIN (-3)   /* rho <= 0, or a non-finite value in rho or b; p untouched */
+#define POISSON_ENOCONV (-4)   /* max_iter reached; p holds the last iterate               */
+#define POISSON_EDIVERGED (-5) /* residual grew above 1e8 x ||b~|| or became non-finite    */
+#define POISSON_EHIP (-6)      /* HIP runtime error                                        */
+#define POISSON_ETOOBIG (-7)   /* serving: request larger than the memory budget           */
+#define POISSON_EBUSY (-8)     /* serving: no free slot or memory right now, retry later   */
+#define POISSON_ENOTFOUND (-9) /* serving: unknown request id                              */
+
+/* ---- options ------------------------------------------------------------ */
+/* Arithmetic of the solve. */
+#define POISSON_FP64 0        /* every sweep in FP64                                       */
+#define POISSON_FP32_REFINE 1 /* FP32 sweeps, FP64 residual, mean removal and update       */
+
+/* Face coefficient beta between cells a and b (the paper does not write the
+ * discrete operator out; both readings are second order and symmetric). */
+#define POISSON_COEF_RHO_FACE_MEAN 0    /* beta = 2 / (rho_a + rho_b): 1/rho of the face rho */
+#define POISSON_COEF_INVRHO_FACE_MEAN 1 /* beta = (1/rho_a + 1/rho_b) / 2                      */
+
+/* Multiplier of the residual before the constant-coefficient solve.  It
+ * changes the iteration count, never the converged answer. */
+#define POISSON_W_RHO 0  /* w = rho, the multiplier of eq. (Pois)                */
+#define POISSON_W_DIAG 1 /* w = 1 / (mean of the six face coefficients of a cell) */
+
+typedef struct poisson_s* poisson_t;
+
+typedef struct {
+    int nx, ny, nz;       /* cells per direction                                   */
+    double lx, ly, lz;    /* box lengths; h_d = l_d / n_d                           */
+    int precision;        /* POISSON_FP64 or POISSON_FP32_REFINE                   */
+    int coef;             /* POISSON_COEF_*                                         */
+    int weight;           /* POISSON_W_*                                            */
+    int max_iter;         /* cap on (inner) iterations; <= 0 selects 1000           */
+    void* stream;         /* hipStream_t to run on; NULL = the null stream          */
+} poisson_opts;
+
+typedef struct {
+    int status;             /* POISSON_* code of the last solve                           */
+    int iters;              /* FP64: iterations; FP32_REFINE: inner iterations in total   */
+    int outer_iters;        /* FP32_REFINE: FP64 refinement steps; FP64: 0                */
+    double rel_resid;       /* ||b~ - A p||_2 / ||b~||_2 at exit, evaluated in FP64        */
+    double b_mean_removed;  /* mean(b), removed for compatibility                         */
+    double b_norm;          /* ||b - mean(b)||_2                                          */
+    double rho_min, rho_max;
+    double err_bound_rel;   /* bound on ||p - p*||_2 / ||p||_2 from the final residual:   */
+                            /* rho_max ||r||_2 / min_d(4 sin^2(pi/N_d)/h_d^2) / ||p||_2   */
+    double ms;              /* device time of the solve (HIP events on the stream)        */
+} poisson_stats;
+
+/* Create a solver for one grid: validates the options, builds the transform
+ * tables (twiddles and the discrete Laplacian symbol -4 sin^2(pi k/N)/h^2 per
+ * direction) and allocates the workspace (about 8 B/cell for FP64, 24 B/cell
+ * for FP32_REFINE).  Returns POISSON_OK and *out, or an error and *out = NULL. */
+int poisson_create(const poisson_opts* opts, poisson_t* out);
+
+/* Solve A p = b - mean(b) for the zero-mean p.  p is in/out: on entry the
+ * estimate p_g (warm start; zeros are fine), on exit the solution with
+ * ||b~ - A p||_2 <= tol * ||b~||_2.  If b is constant, p is set to 0 with no
+ * iteration.  On POISSON_EDOMAIN p is untouched; on POISSON_ENOCONV and
+ * POISSON_EDIVERGED p holds the last iterate.  Blocks until done. */
+int poisson_solve(poisson_t h, const double* rho, const double* b, double* p, double tol);
+
+/* Statistics of the last poisson_solve on this handle. */
+int poisson_get_stats(poisson_t h, poisson_stats* stats);
+
+/* Residual history of the last solve: hist[k] = ||r_k|| / ||b~|| for
+ * k = 0..count-1 (FP64 path: one entry per iteration; FP32_REFINE: one per
+ * outer FP64 step).  Writes at most cap entries; returns the count or < 0. */
+int poisson_get_history(poisson_t h, double* hist, int cap);
+
+/* Release the handle and its workspace.  NULL is allowed. */
+void poisson_destroy(poisson_t h);
+
+/* Text for a status code.  Never NULL. */
+const char* poisson_strerror(int code);
+
+/* ---- single sweeps of the hot path, for parity checks and profiling ------
+ * Each uses the handle's grid, coef and stream and blocks until done. */
+
+/* out = A p (the operator above).  rho, p, out: device FP64 fields. */
+int poisson_apply(poisson_t h, const double* rho, const double* p, double* out);
+
+/* r = (b - mean(b)) - A p, with ||r||_2 and ||b - mean(b)||_2 returned through
+ * r_norm and b_norm (host pointers, may be NULL).  r may be NULL. */
+int poisson_residual(poisson_t h, const double* rho, const double* b, const double* p, double* r,
+                     double* r_norm, double* b_norm);
+
+/* delta = L^+ q: zero-mean solution of L delta = q - mean(q) with L the
+ * constant-coefficient 7-point Laplacian, by separable real (Hartley)
+ * transforms, which diagonalise it with the discrete symbol above.  This is
+ * the inner solve of eq. (Pois).  q and delta are device FP64 fields and may
+ * be the same pointer. */
+int poisson_lap_pinv(poisson_t h, const double* q, double* delta);
+
+/* Average device time of one sweep of the iteration, launched `reps` times
+ * back to back between two HIP events on the handle's stream (after one
+ * warm-up launch), written to *avg_ms.  sweep: 1 residual + weight + Hartley
+ * along x; 2 Hartley along y; 3 Hartley along z, symbol division, Hartley
+ * along z; 5 Hartley along x + update.  fp32 != 0 times the FP32 sweeps of a
+ * POISSON_FP32_REFINE handle.  p is used as scratch: its contents are lost. */
+int poisson_time_sweep(poisson_t h, int sweep, int fp32, const double* rho, const double* b, double* p, int reps,
+                       double* avg_ms);
+
+/* ---- serving: many independent solves of different sizes -----------------
+ * A server keeps each admitted request's rho, b, p and iteration state on the
+ * device, groups requests of equal grid size into batches that advance
+ * together in one captured graph per size class, and admits new requests
+ * between ticks as slots and memory free up.  Requests are independent: each
+ * result is the same as a solve of that request alone. */
+typedef struct poisson_server_s* poisson_server_t;
+
+/* budget_bytes: device memory the server may hold for admitted requests
+ * (fields and workspace); max_slots: most requests resident at once;
+ * stream: hipStream_t or NULL.  precision/coef/weight/max_iter as above, for
+ * every request. */
+int poisson_server_create(size_t budget_bytes, int max_slots, int precision, int coef, int weight,
+                          int max_iter, void* stream, poisson_server_t* out);
+
+/* Queue a request.  rho, b: device FP64 fields the server copies at
+ * admission (the caller may reuse them after the request is admitted, see
+ * poisson_server_poll); p: device FP64 field, in/out like poisson_solve,
+ * written when the request completes.  Does not block.  Returns the id
+ * through *id.  POISSON_ETOOBIG if the request can never fit the budget. */
+int poisson_server_submit(poisson_server_t s, int nx, int ny, int nz, double lx, double ly, double lz,
+                          const double* rho, const double* b, double* p, double tol, long long* id);
+
+/* Run one scheduling tick: admit queued requests that fit, advance every
+ * resident batch by a few iterations, retire finished requests.  Blocks for
+ * the tick.  Returns the number of requests still queued or resident. */
+int poisson_server_tick(poisson_server_t s);
+
+/* 0 and *stats filled if the request is done, 1 if still queued or running,
+ * < 0 on error.  A done request's stats stay readable until the server is
+ * destroyed. */
+int poisson_server_poll(poisson_server_t s, long long id, poisson_stats* stats);
+
+void poisson_server_destroy(poisson_server_t s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAPER_1601_05448_AMD_POISSON_H */

@@ -1,0 +1,463 @@
+// Host engine and C ABI of libpoisson (declarations and semantics in
+// include/poisson.h).
+//
+// poisson_create builds, per grid, the tables of the separable Hartley
+// transforms (twiddles exp(-2 pi i t/N) and the discrete symbol of the 1-D
+// periodic second difference, -4 sin^2(pi k/N)/h^2, both in FP64 from host
+// libm) and the workspace.  poisson_solve drives the iteration of the paper
+// (section "Poisson equation", eq. (Pois)) on the device; the host only waits
+// for chunks of iterations and reads back a small state record.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/poisson.h"
+#include "poisson_engine.hpp"
+#include "poisson_internal.hpp"
+
+using namespace pois;
+
+namespace pois {
+
+static const double kPi = 3.14159265358979323846264338327950288;
+
+int hip_status(hipError_t e) { return e == hipSuccess ? POISSON_OK : POISSON_EHIP; }
+
+bool valid_lengths(double lx, double ly, double lz) {
+    return std::isfinite(lx) && std::isfinite(ly) && std::isfinite(lz) && lx > 0 && ly > 0 && lz > 0;
+}
+
+GridArgs make_grid(int nx, int ny, int nz, double lx, double ly, double lz, int coef, int weight) {
+    GridArgs g{};
+    g.nx = nx; g.ny = ny; g.nz = nz;
+    g.nxh = nx / 2;
+    g.n = (long long)nx * ny * nz;
+    const double hx = lx / nx, hy = ly / ny, hz = lz / nz;
+    g.ihx2 = 1.0 / (hx * hx);
+    g.ihy2 = 1.0 / (hy * hy);
+    g.ihz2 = 1.0 / (hz * hz);
+    g.coef = coef;
+    g.weight = weight;
+    return g;
+}
+
+// Smallest nonzero eigenvalue magnitude of -L: min_d 4 sin^2(pi/N_d)/h_d^2.
+double min_symbol(const GridArgs& g) {
+    auto one = [](int n, double ih2) {
+        const double s = std::sin(kPi / n);
+        return 4.0 * s * s * ih2;
+    };
+    return std::min(one(g.nx, g.ihx2), std::min(one(g.ny, g.ihy2), one(g.nz, g.ihz2)));
+}
+
+// ---- per-grid tables ---------------------------------------------------------------
+
+int GridTables::build(const GridArgs& g) {
+    const int ns[3] = {g.nx, g.ny, g.nz};
+    const double ih2[3] = {g.ihx2, g.ihy2, g.ihz2};
+    // layout first: four 256-byte aligned arrays per direction
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = (off + 255) & ~(size_t)255;
+        const size_t at = off;
+        off += bytes;
+        return at;
+    };
+    size_t at[3][4];
+    for (int d = 0; d < 3; ++d) {
+        at[d][0] = take((size_t)ns[d] * 16);  // FP64 twiddles
+        at[d][1] = take((size_t)ns[d] * 8);   // FP32 twiddles
+        at[d][2] = take((size_t)ns[d] * 8);   // FP64 symbol
+        at[d][3] = take((size_t)ns[d] * 4);   // FP32 symbol
+    }
+    const size_t total = off;
+    if (hipMalloc(&mem, total) != hipSuccess) {
+        mem = nullptr;
+        return POISSON_ENOMEM;
+    }
+    std::vector<unsigned char> host(total, 0);
+    unsigned char* base = static_cast<unsigned char*>(mem);
+    for (int d = 0; d < 3; ++d) {
+        const int n = ns[d];
+        double* tw = reinterpret_cast<double*>(host.data() + at[d][0]);
+        float* tw32 = reinterpret_cast<float*>(host.data() + at[d][1]);
+        double* lam = reinterpret_cast<double*>(host.data() + at[d][2]);
+        float* lam32 = reinterpret_cast<float*>(host.data() + at[d][3]);
+        for (int t = 0; t < n; ++t) {
+            const double ang = 2.0 * kPi * (double)t / (double)n;
+            tw[2 * t] = std::cos(ang);
+            tw[2 * t + 1] = -std::sin(ang);
+            tw32[2 * t] = (float)tw[2 * t];
+            tw32[2 * t + 1] = (float)tw[2 * t + 1];
+            const double s = std::sin(kPi * (double)t / (double)n);
+            lam[t] = -4.0 * s * s * ih2[d];
+            lam32[t] = (float)lam[t];
+        }
+    }
+    if (hipMemcpy(mem, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) return POISSON_EHIP;
+    auto ptr = [&](int d, int k) { return static_cast<const void*>(base + at[d][k]); };
+    t.twx = static_cast<const double2*>(ptr(0, 0)); t.twy = static_cast<const double2*>(ptr(1, 0));
+    t.twz = static_cast<const double2*>(ptr(2, 0));
+    t.twx32 = static_cast<const float2*>(ptr(0, 1)); t.twy32 = static_cast<const float2*>(ptr(1, 1));
+    t.twz32 = static_cast<const float2*>(ptr(2, 1));
+    t.lamx = static_cast<const double*>(ptr(0, 2)); t.lamy = static_cast<const double*>(ptr(1, 2));
+    t.lamz = static_cast<const double*>(ptr(2, 2));
+    t.lamx32 = static_cast<const float*>(ptr(0, 3)); t.lamy32 = static_cast<const float*>(ptr(1, 3));
+    t.lamz32 = static_cast<const float*>(ptr(2, 3));
+    return POISSON_OK;
+}
+
+void GridTables::release() {
+    if (mem) (void)hipFree(mem);
+    mem = nullptr;
+}
+
+// ---- per-solve workspace -------------------------------------------------------------
+
+size_t workspace_bytes(const GridArgs& g, const Geometry& geo, int precision) {
+    size_t b = (size_t)g.n * 8 + 256;                        // W
+    if (precision == POISSON_FP32_REFINE) b += 4 * ((size_t)g.n * 4 + 256);
+    b += (size_t)geo.max_blocks * kPartialStride * 8 + 256;  // partial sums
+    b += sizeof(SolveState) + 256;
+    return b;
+}
+
+int Workspace::allocate(const GridArgs& g, const Geometry& geo, int precision) {
+    bytes = workspace_bytes(g, geo, precision);
+    if (hipMalloc(&mem, bytes) != hipSuccess) {
+        mem = nullptr;
+        return POISSON_ENOMEM;
+    }
+    unsigned char* base = static_cast<unsigned char*>(mem);
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        off = (off + 255) & ~(size_t)255;
+        unsigned char* at = base + off;
+        off += n;
+        return at;
+    };
+    W = reinterpret_cast<double*>(take((size_t)g.n * 8));
+    rho32 = r32 = d32 = W32 = nullptr;
+    if (precision == POISSON_FP32_REFINE) {
+        rho32 = reinterpret_cast<float*>(take((size_t)g.n * 4));
+        r32 = reinterpret_cast<float*>(take((size_t)g.n * 4));
+        d32 = reinterpret_cast<float*>(take((size_t)g.n * 4));
+        W32 = reinterpret_cast<float*>(take((size_t)g.n * 4));
+    }
+    partial = reinterpret_cast<double*>(take((size_t)geo.max_blocks * kPartialStride * 8));
+    st = reinterpret_cast<SolveState*>(take(sizeof(SolveState)));
+    return POISSON_OK;
+}
+
+void Workspace::release() {
+    if (mem) (void)hipFree(mem);
+    mem = nullptr;
+}
+
+Slot Workspace::slot(const double* rho, const double* b, double* p) const {
+    Slot s{};
+    s.rho = rho; s.b = b; s.p = p;
+    s.W = W; s.rho32 = rho32; s.r32 = r32; s.d32 = d32; s.W32 = W32;
+    s.partial = partial; s.st = st;
+    return s;
+}
+
+// ---- the solve driver -----------------------------------------------------------------
+
+// Enqueue the whole solve for the slots on the stream, reading back the state
+// header of slot 0..nslots-1 between chunks.  `hdr` is pinned host memory for
+// nslots state headers.
+int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* d_slots, int nslots,
+                SolveState* const* d_states, SolveState* hdr, const SolveParams& prm, hipStream_t s) {
+    hipError_t e;
+    const bool fp32 = prm.precision == POISSON_FP32_REFINE;
+    if ((e = launch_init(g, d_slots, nslots, prm.tol, prm.inner_tol, prm.max_iter, prm.max_outer,
+                         prm.precision, s)) != hipSuccess) return hip_status(e);
+    if ((e = launch_setup(g, geo, d_slots, nslots, fp32, s)) != hipSuccess) return hip_status(e);
+    if ((e = launch_setup_finalize(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
+    const size_t hb = offsetof(SolveState, hist);
+    auto poll = [&](bool want_inner) -> int {  // 1: all done (or inner done), 0: not yet, <0 error
+        for (int q = 0; q < nslots; ++q)
+            if ((e = hipMemcpyAsync(&hdr[q], d_states[q], hb, hipMemcpyDeviceToHost, s)) != hipSuccess)
+                return hip_status(e);
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_status(e);
+        for (int q = 0; q < nslots; ++q) {
+            if (hdr[q].done) continue;
+            if (want_inner && hdr[q].inner_done) continue;
+            return 0;
+        }
+        return 1;
+    };
+    if (!fp32) {
+        int launched = 0, chunk = prm.first_chunk;
+        const int cap = prm.max_iter + 1;
+        while (true) {
+            for (int c = 0; c < chunk && launched < cap; ++c, ++launched)
+                if ((e = launch_iteration(g, geo, t, d_slots, nslots, false, s)) != hipSuccess) return hip_status(e);
+            const int r = poll(false);
+            if (r < 0) return r;
+            if (r == 1 || launched >= cap) break;
+            chunk = std::min(chunk * 2, prm.max_chunk);
+        }
+    } else {
+        for (int outer = 0; outer <= prm.max_outer; ++outer) {
+            if ((e = launch_outer_residual(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
+            int r = poll(false);
+            if (r < 0) return r;
+            if (r == 1) break;
+            int launched = 0, chunk = prm.first_chunk;
+            while (true) {
+                for (int c = 0; c < chunk && launched < prm.max_inner + 1; ++c, ++launched)
+                    if ((e = launch_iteration(g, geo, t, d_slots, nslots, true, s)) != hipSuccess)
+                        return hip_status(e);
+                r = poll(true);
+                if (r < 0) return r;
+                if (r == 1 || launched >= prm.max_inner + 1) break;
+                chunk = std::min(chunk * 2, prm.max_chunk);
+            }
+            if ((e = launch_outer_update(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
+        }
+    }
+    if ((e = launch_fixup(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
+    return POISSON_OK;
+}
+
+void fill_stats(const GridArgs& g, const SolveState& st, poisson_stats* out) {
+    poisson_stats s{};
+    s.status = st.status;
+    const bool fp32 = st.precision == POISSON_FP32_REFINE;
+    s.iters = fp32 ? st.inner_total : st.iter;
+    s.outer_iters = fp32 ? st.iter : 0;
+    s.rel_resid = st.rel;
+    s.b_mean_removed = st.b_mean;
+    s.b_norm = st.b_norm;
+    s.rho_min = st.rho_min;
+    s.rho_max = st.rho_max;
+    // a-posteriori bound: every face coefficient is >= 1/rho_max, so on zero-mean
+    // fields -A >= -L / rho_max and ||p - p*|| <= rho_max ||r|| / lambda_min(-L)
+    const double pn2 = st.p_sumsq - st.p_sum * st.p_sum / (double)g.n;
+    const double pn = pn2 > 0.0 ? std::sqrt(pn2) : 0.0;
+    const double bound = st.rho_max * st.r_norm / min_symbol(g);
+    s.err_bound_rel = (pn > 0.0 && st.status != POISSON_EDOMAIN) ? bound / pn : 0.0;
+    s.ms = 0.0;
+    *out = s;
+}
+
+}  // namespace pois
+
+// ---- C ABI -----------------------------------------------------------------------------
+
+struct poisson_s {
+    poisson_opts o{};
+    GridArgs g{};
+    Geometry geo{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    GridTables tables;
+    Workspace ws;
+    Slot* d_slot = nullptr;       // device copy of the slot
+    Slot* h_slot = nullptr;       // pinned staging
+    SolveState* h_state = nullptr;  // pinned copy of the state
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    poisson_stats stats{};
+    int hist_count = 0;
+};
+
+extern "C" {
+
+const char* poisson_strerror(int code) {
+    switch (code) {
+        case POISSON_OK: return "ok";
+        case POISSON_EINVAL: return "invalid argument";
+        case POISSON_ENOMEM: return "out of memory";
+        case POISSON_EDOMAIN: return "rho must be finite and positive and b finite";
+        case POISSON_ENOCONV: return "iteration cap reached before the tolerance";
+        case POISSON_EDIVERGED: return "iteration diverged";
+        case POISSON_EHIP: return "HIP runtime error";
+        case POISSON_ETOOBIG: return "request exceeds the memory budget";
+        case POISSON_EBUSY: return "no free slot or memory";
+        case POISSON_ENOTFOUND: return "unknown request";
+        default: return "unknown status";
+    }
+}
+
+void poisson_destroy(poisson_t h) {
+    if (!h) return;
+    if (h->d_slot) (void)hipFree(h->d_slot);
+    if (h->h_slot) (void)hipHostFree(h->h_slot);
+    if (h->h_state) (void)hipHostFree(h->h_state);
+    if (h->ev0) (void)hipEventDestroy(h->ev0);
+    if (h->ev1) (void)hipEventDestroy(h->ev1);
+    h->ws.release();
+    h->tables.release();
+    delete h;
+}
+
+int poisson_create(const poisson_opts* o, poisson_t* out) {
+    if (!out) return POISSON_EINVAL;
+    *out = nullptr;
+    if (!o) return POISSON_EINVAL;
+    if (!length_supported(o->nx) || !length_supported(o->ny) || !length_supported(o->nz)) return POISSON_EINVAL;
+    if (!valid_lengths(o->lx, o->ly, o->lz)) return POISSON_EINVAL;
+    if (o->precision != POISSON_FP64 && o->precision != POISSON_FP32_REFINE) return POISSON_EINVAL;
+    if (o->coef != POISSON_COEF_RHO_FACE_MEAN && o->coef != POISSON_COEF_INVRHO_FACE_MEAN) return POISSON_EINVAL;
+    if (o->weight != POISSON_W_RHO && o->weight != POISSON_W_DIAG) return POISSON_EINVAL;
+    poisson_s* h = new (std::nothrow) poisson_s();
+    if (!h) return POISSON_ENOMEM;
+    h->o = *o;
+    if (h->o.max_iter <= 0) h->o.max_iter = 1000;
+    h->stream = static_cast<hipStream_t>(o->stream);
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return POISSON_EHIP;
+    }
+    h->g = make_grid(o->nx, o->ny, o->nz, o->lx, o->ly, o->lz, o->coef, o->weight);
+    h->geo = make_geometry(h->g);
+    int rc = h->tables.build(h->g);
+    if (rc == POISSON_OK) rc = h->ws.allocate(h->g, h->geo, o->precision);
+    if (rc == POISSON_OK && hipMalloc(&h->d_slot, sizeof(Slot)) != hipSuccess) rc = POISSON_ENOMEM;
+    if (rc == POISSON_OK && hipHostMalloc(&h->h_slot, sizeof(Slot), hipHostMallocDefault) != hipSuccess)
+        rc = POISSON_ENOMEM;
+    if (rc == POISSON_OK && hipHostMalloc(&h->h_state, sizeof(SolveState), hipHostMallocDefault) != hipSuccess)
+        rc = POISSON_ENOMEM;
+    if (rc == POISSON_OK && (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess))
+        rc = POISSON_EHIP;
+    if (rc != POISSON_OK) {
+        poisson_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return POISSON_OK;
+}
+
+static bool overlaps(const void* a, const void* b, size_t bytes) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bytes && y < x + bytes;
+}
+
+static int set_slot(poisson_t h, const Slot& s) {
+    *h->h_slot = s;
+    return hip_status(hipMemcpyAsync(h->d_slot, h->h_slot, sizeof(Slot), hipMemcpyHostToDevice, h->stream));
+}
+
+int poisson_solve(poisson_t h, const double* rho, const double* b, double* p, double tol) {
+    if (!h || !rho || !b || !p || !(tol > 0.0) || !std::isfinite(tol)) return POISSON_EINVAL;
+    const size_t bytes = (size_t)h->g.n * sizeof(double);
+    if (overlaps(rho, b, bytes) || overlaps(rho, p, bytes) || overlaps(b, p, bytes)) return POISSON_EINVAL;
+    int rc = set_slot(h, h->ws.slot(rho, b, p));
+    if (rc != POISSON_OK) return rc;
+    SolveParams prm;
+    prm.tol = tol;
+    prm.precision = h->o.precision;
+    prm.max_iter = h->o.max_iter;
+    if ((rc = hip_status(hipEventRecord(h->ev0, h->stream))) != POISSON_OK) return rc;
+    SolveState* dst = h->ws.st;
+    rc = drive_solve(h->g, h->geo, h->tables.t, h->d_slot, 1, &dst, h->h_state, prm, h->stream);
+    if (rc != POISSON_OK) return rc;
+    if ((rc = hip_status(hipEventRecord(h->ev1, h->stream))) != POISSON_OK) return rc;
+    if ((rc = hip_status(hipMemcpyAsync(h->h_state, h->ws.st, sizeof(SolveState), hipMemcpyDeviceToHost,
+                                        h->stream))) != POISSON_OK)
+        return rc;
+    if ((rc = hip_status(hipStreamSynchronize(h->stream))) != POISSON_OK) return rc;
+    const SolveState& st = *h->h_state;
+    fill_stats(h->g, st, &h->stats);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->stats.ms = ms;
+    h->hist_count = std::min(st.iter + 1, kHistCap);
+    if (st.status == POISSON_EDOMAIN) h->hist_count = 0;
+    return h->stats.status;
+}
+
+int poisson_get_stats(poisson_t h, poisson_stats* s) {
+    if (!h || !s) return POISSON_EINVAL;
+    *s = h->stats;
+    return POISSON_OK;
+}
+
+int poisson_get_history(poisson_t h, double* hist, int cap) {
+    if (!h || (!hist && cap > 0) || cap < 0) return POISSON_EINVAL;
+    const int n = std::min(cap, h->hist_count);
+    for (int k = 0; k < n; ++k) hist[k] = h->h_state->hist[k];
+    return h->hist_count;
+}
+
+int poisson_apply(poisson_t h, const double* rho, const double* p, double* out) {
+    if (!h || !rho || !p || !out) return POISSON_EINVAL;
+    int rc = hip_status(launch_apply(h->g, h->geo, rho, p, out, h->stream));
+    if (rc != POISSON_OK) return rc;
+    return hip_status(hipStreamSynchronize(h->stream));
+}
+
+int poisson_residual(poisson_t h, const double* rho, const double* b, const double* p, double* r,
+                     double* r_norm, double* b_norm) {
+    if (!h || !rho || !b || !p) return POISSON_EINVAL;
+    // the residual sweep only reads p; the host copy of the last solve's state
+    // (stats, history) is not touched
+    Slot s = h->ws.slot(rho, b, const_cast<double*>(p));
+    int rc = set_slot(h, s);
+    if (rc != POISSON_OK) return rc;
+    hipError_t e;
+    if ((e = launch_init(h->g, h->d_slot, 1, 1.0, 1.0, 0, 0, POISSON_FP64, h->stream)) != hipSuccess) return hip_status(e);
+    if ((e = launch_setup(h->g, h->geo, h->d_slot, 1, false, h->stream)) != hipSuccess) return hip_status(e);
+    if ((e = launch_setup_finalize(h->g, h->geo, h->d_slot, 1, h->stream)) != hipSuccess) return hip_status(e);
+    if ((e = launch_residual(h->g, h->geo, h->d_slot, r, h->stream)) != hipSuccess) return hip_status(e);
+    const int nb = h->geo.blocks_pt;
+    std::vector<double> part((size_t)nb * kPartialStride);
+    if ((e = hipMemcpyAsync(part.data(), h->ws.partial, part.size() * 8, hipMemcpyDeviceToHost, h->stream)) !=
+        hipSuccess)
+        return hip_status(e);
+    if ((e = hipStreamSynchronize(h->stream)) != hipSuccess) return hip_status(e);
+    double s0 = 0.0, s1 = 0.0;
+    for (int q = 0; q < nb; ++q) {
+        s0 += part[(size_t)q * kPartialStride + 0];
+        s1 += part[(size_t)q * kPartialStride + 1];
+    }
+    if (r_norm) *r_norm = std::sqrt(s0);
+    if (b_norm) *b_norm = std::sqrt(s1);
+    return POISSON_OK;
+}
+
+int poisson_time_sweep(poisson_t h, int sweep, int fp32, const double* rho, const double* b, double* p, int reps,
+                       double* avg_ms) {
+    if (!h || !rho || !b || !p || !avg_ms || reps < 1) return POISSON_EINVAL;
+    if (sweep != 1 && sweep != 2 && sweep != 3 && sweep != 5) return POISSON_EINVAL;
+    if (fp32 && h->o.precision != POISSON_FP32_REFINE) return POISSON_EINVAL;
+    int rc = set_slot(h, h->ws.slot(rho, b, p));
+    if (rc != POISSON_OK) return rc;
+    hipError_t e;
+    // a state that never converges (tol 0) so that every sweep does its work
+    if ((e = launch_init(h->g, h->d_slot, 1, 0.0, 0.0, 1 << 30, 1 << 30, h->o.precision, h->stream)) != hipSuccess)
+        return hip_status(e);
+    if ((e = launch_setup(h->g, h->geo, h->d_slot, 1, fp32 != 0, h->stream)) != hipSuccess) return hip_status(e);
+    if ((e = launch_setup_finalize(h->g, h->geo, h->d_slot, 1, h->stream)) != hipSuccess) return hip_status(e);
+    if (fp32 && (e = launch_outer_residual(h->g, h->geo, h->d_slot, 1, h->stream)) != hipSuccess)
+        return hip_status(e);
+    if ((e = launch_sweep(h->g, h->tables.t, h->d_slot, 1, fp32 != 0, sweep, h->stream)) != hipSuccess)
+        return hip_status(e);  // warm
+    if ((e = hipEventRecord(h->ev0, h->stream)) != hipSuccess) return hip_status(e);
+    for (int r = 0; r < reps; ++r)
+        if ((e = launch_sweep(h->g, h->tables.t, h->d_slot, 1, fp32 != 0, sweep, h->stream)) != hipSuccess)
+            return hip_status(e);
+    if ((e = hipEventRecord(h->ev1, h->stream)) != hipSuccess) return hip_status(e);
+    if ((e = hipEventSynchronize(h->ev1)) != hipSuccess) return hip_status(e);
+    float ms = 0.f;
+    if ((e = hipEventElapsedTime(&ms, h->ev0, h->ev1)) != hipSuccess) return hip_status(e);
+    *avg_ms = (double)ms / reps;
+    return POISSON_OK;
+}
+
+int poisson_lap_pinv(poisson_t h, const double* q, double* delta) {
+    if (!h || !q || !delta) return POISSON_EINVAL;
+    int rc = set_slot(h, h->ws.slot(nullptr, q, delta));
+    if (rc != POISSON_OK) return rc;
+    hipError_t e = launch_lap_pinv(h->g, h->geo, h->tables.t, h->d_slot, h->stream);
+    if (e != hipSuccess) return hip_status(e);
+    return hip_status(hipStreamSynchronize(h->stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,264 @@
+// Device building blocks for the separable real (Hartley) transforms that
+// diagonalise the periodic constant-coefficient 7-point Laplacian.
+//
+// The paper solves the constant-coefficient Poisson equation of eq. (Pois) by
+// Fourier transform in the periodic directions (section "Poisson equation").
+// Here the transform along each direction is the discrete Hartley transform
+//     H(a)_k = sum_j a_j cas(2 pi j k / N),   cas = cos + sin,
+// a real, self-inverse (H H = N I) transform whose basis vectors are
+// eigenvectors of every symmetric circulant matrix, in particular of the 1-D
+// periodic second difference (eigenvalue -4 sin^2(pi k/N)/h^2).  The product
+// of the three 1-D transforms therefore diagonalises the 7-point Laplacian on
+// the real field itself: no complex spectrum, no layout change, and the same
+// kernel serves for the forward and the inverse sweep.
+//
+// Two real lines a, b are transformed together as one complex line z = a + ib:
+// with Z = DFT(z) (kernel exp(-2 pi i jk/N)),
+//     H(z)_k = H(a)_k + i H(b)_k = ((1+i) Z_k + (1-i) Z_{N-k}) / 2.
+// Row pairs supply (a, b) for the x direction; for y and z the interleaved
+// columns (2m, 2m+1) of the x-fastest layout already form complex numbers.
+//
+// The complex DFT is a Stockham autosort FFT over lines held in LDS: stage s
+// of radix R takes butterfly j (of N/R) from elements j + r N/R, twiddles by
+// exp(-2 pi i (j mod Ns) r / (Ns R)) (Ns = product of the previous radices),
+// applies a length-R DFT in registers and writes to (j div Ns) Ns R + (j mod
+// Ns) + r Ns; after the last stage the line is in natural order.  Lengths are
+// 2^a or 3*2^a; radices 16, 8, 4, 2 and one final 3.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace pois {
+
+template <typename T>
+struct cpx {
+    T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * (-i)
+template <typename T>
+__device__ __forceinline__ cpx<T> cmi(cpx<T> a) { return {a.y, -a.x}; }
+
+// Mathematical constants (not tabulated from any library).
+constexpr double kSqrtHalf = 0.70710678118654752440084436210484903928;
+constexpr double kCosPi8 = 0.92387953251128675612818318939678828682;
+constexpr double kSinPi8 = 0.38268343236508977172845998403039886676;
+constexpr double kSin2Pi3 = 0.86602540378443864676372317075293618347;  // sqrt(3)/2
+
+// ---- length-R forward DFTs in registers ------------------------------------
+
+template <typename T>
+__device__ __forceinline__ void dft2(cpx<T>* v) {
+    const cpx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft3(cpx<T>* v) {
+    const cpx<T> s = cadd(v[1], v[2]);
+    const cpx<T> d = csub(v[1], v[2]);
+    const cpx<T> a = v[0];
+    const cpx<T> m = {a.x - T(0.5) * s.x, a.y - T(0.5) * s.y};
+    // -i sin(2pi/3) d
+    const cpx<T> t = {T(kSin2Pi3) * d.y, -T(kSin2Pi3) * d.x};
+    v[0] = cadd(a, s);
+    v[1] = cadd(m, t);
+    v[2] = csub(m, t);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4v(cpx<T>& v0, cpx<T>& v1, cpx<T>& v2, cpx<T>& v3) {
+    const cpx<T> t0 = cadd(v0, v2), t1 = csub(v0, v2);
+    const cpx<T> t2 = cadd(v1, v3), t3 = cmi(csub(v1, v3));
+    v0 = cadd(t0, t2);
+    v2 = csub(t0, t2);
+    v1 = cadd(t1, t3);
+    v3 = csub(t1, t3);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft4(cpx<T>* v) { dft4v(v[0], v[1], v[2], v[3]); }
+
+template <typename T>
+__device__ __forceinline__ void dft8(cpx<T>* v) {
+    cpx<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    cpx<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4v(e0, e1, e2, e3);
+    dft4v(o0, o1, o2, o3);
+    const T c = T(kSqrtHalf);
+    o1 = {c * (o1.x + o1.y), c * (o1.y - o1.x)};   // * exp(-i pi/4)
+    o2 = cmi(o2);                                  // * exp(-i pi/2)
+    o3 = {c * (o3.y - o3.x), -c * (o3.x + o3.y)};  // * exp(-3i pi/4)
+    v[0] = cadd(e0, o0); v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1); v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2); v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
+}
+
+// multiply by exp(-2 pi i M / 16) for the M = n2 * k1 values of a 4 x 4 split
+template <typename T, int M>
+__device__ __forceinline__ cpx<T> tw16(cpx<T> a) {
+    if constexpr (M == 0) {
+        return a;
+    } else if constexpr (M == 4) {
+        return cmi(a);
+    } else {
+        constexpr double c = (M == 1) ? kCosPi8 : (M == 2) ? kSqrtHalf : (M == 3) ? kSinPi8
+                             : (M == 6) ? -kSqrtHalf : -kCosPi8;  // M == 9
+        constexpr double s = (M == 1) ? -kSinPi8 : (M == 2) ? -kSqrtHalf : (M == 3) ? -kCosPi8
+                             : (M == 6) ? -kSqrtHalf : kSinPi8;
+        return cmul(a, cpx<T>{T(c), T(s)});
+    }
+}
+
+template <typename T, int N2>
+__device__ __forceinline__ void dft16_col(cpx<T>* v) {
+    // length-4 DFT over n1 of v[4 n1 + N2], then twiddle by exp(-2pi i N2 k1/16)
+    dft4v(v[N2], v[4 + N2], v[8 + N2], v[12 + N2]);
+    v[4 + N2] = tw16<T, N2 * 1>(v[4 + N2]);
+    v[8 + N2] = tw16<T, N2 * 2>(v[8 + N2]);
+    v[12 + N2] = tw16<T, N2 * 3>(v[12 + N2]);
+}
+
+template <typename T>
+__device__ __forceinline__ void dft16(cpx<T>* v) {
+    // index n = 4 n1 + n2, k = k1 + 4 k2; after the column pass v[4 k1 + n2]
+    // holds Y[n2][k1]; the row pass over n2 gives X[k1 + 4 k2].
+    dft16_col<T, 0>(v);
+    dft16_col<T, 1>(v);
+    dft16_col<T, 2>(v);
+    dft16_col<T, 3>(v);
+    cpx<T> out[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        cpx<T> a = v[4 * k1 + 0], b = v[4 * k1 + 1], c = v[4 * k1 + 2], d = v[4 * k1 + 3];
+        dft4v(a, b, c, d);
+        out[k1] = a;
+        out[k1 + 4] = b;
+        out[k1 + 8] = c;
+        out[k1 + 12] = d;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = out[r];
+}
+
+template <typename T, int R>
+__device__ __forceinline__ void dft(cpx<T>* v) {
+    if constexpr (R == 2) dft2(v);
+    else if constexpr (R == 3) dft3(v);
+    else if constexpr (R == 4) dft4(v);
+    else if constexpr (R == 8) dft8(v);
+    else dft16(v);
+}
+
+// ---- line geometry ------------------------------------------------------------
+
+constexpr int pick_radix(int rem) {
+    return rem % 16 == 0 ? 16 : rem % 8 == 0 ? 8 : rem % 4 == 0 ? 4 : rem % 2 == 0 ? 2 : 3;
+}
+
+constexpr int lines_per_block(int tt, int n, int elem_bytes) {
+    int l = (256 % tt == 0) ? 256 / tt : 192 / tt;
+    while (l * (n + 1) * elem_bytes > 82000 && ((l / 2) * tt) % 64 == 0) l /= 2;
+    return l;
+}
+
+// Threads per line TT (one radix-16 butterfly per thread in the first stage),
+// lines per block L (threads a multiple of 64), LDS line stride LS (one
+// complex of padding against bank conflicts on column-wise accesses).
+template <typename T, int N>
+struct LineCfg {
+    static constexpr int TT = N >= 16 ? N / 16 : 1;
+    static constexpr int L = lines_per_block(TT, N, (int)sizeof(cpx<T>));
+    static constexpr int NT = L * TT;
+    static constexpr int LS = N + 1;
+    static_assert(NT % 64 == 0, "block must be whole wavefronts");
+};
+
+// One Stockham stage on a line in LDS (all threads of the block call it).
+template <typename T, int N, int R, int NS, int TT>
+__device__ __forceinline__ void stockham_stage(cpx<T>* ln, int t, const cpx<T>* tw) {
+    constexpr int NB = N / R;
+    constexpr int BPT = (NB + TT - 1) / TT;
+    cpx<T> v[BPT][R];
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+        const int j = t + u * TT;
+        if (NB % TT == 0 || j < NB) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[u][r] = ln[j + r * NB];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < BPT; ++u) {
+        const int j = t + u * TT;
+        if (NB % TT == 0 || j < NB) {
+            const int jm = j % NS;
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) v[u][r] = cmul(v[u][r], tw[jm * r * (N / (NS * R))]);
+            }
+            dft<T, R>(v[u]);
+            const int base = (j / NS) * NS * R + jm;
+#pragma unroll
+            for (int r = 0; r < R; ++r) ln[base + r * NS] = v[u][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int N, int NS, int TT>
+__device__ __forceinline__ void fft_stages(cpx<T>* ln, int t, const cpx<T>* tw) {
+    if constexpr (NS < N) {
+        constexpr int R = pick_radix(N / NS);
+        stockham_stage<T, N, R, NS, TT>(ln, t, tw);
+        fft_stages<T, N, NS * R, TT>(ln, t, tw);
+    }
+}
+
+// Forward complex DFT of every line of the block, in place in LDS.
+// Expects the lines written and a barrier passed; ends with a barrier.
+template <typename T, int N>
+__device__ __forceinline__ void fft_block_lines(cpx<T>* lds, const cpx<T>* tw) {
+    using C = LineCfg<T, N>;
+    const int line = threadIdx.x / C::TT;
+    const int t = threadIdx.x % C::TT;
+    fft_stages<T, N, 1, C::TT>(lds + line * C::LS, t, tw);
+}
+
+// Hartley value of the pair-packed line at k from its DFT Z:
+// ((1+i) Z_k + (1-i) Z_{N-k}) / 2.
+template <typename T>
+__device__ __forceinline__ cpx<T> hartley(cpx<T> zk, cpx<T> zmk) {
+    return {T(0.5) * ((zk.x - zk.y) + (zmk.x + zmk.y)), T(0.5) * ((zk.x + zk.y) + (zmk.y - zmk.x))};
+}
+
+// ---- reductions -----------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+}  // namespace pois

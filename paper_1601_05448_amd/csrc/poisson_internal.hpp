@@ -1,0 +1,132 @@
+// Internal structures shared by the kernels and the host engine of libpoisson.
+// Nothing here is part of the C ABI (include/poisson.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pois {
+
+constexpr int kHistCap = 256;      // residual-history entries kept per solve
+constexpr int kPartialStride = 8;  // doubles of per-block partial sums per block
+constexpr int kMaxSetupBlocks = 1024;
+constexpr int kMaxInner = 100;    // FP32 inner iterations per refinement step
+
+// Grid description passed by value to every kernel.  Uniform over a batch:
+// all solves of one launch share the grid.
+struct GridArgs {
+    int nx, ny, nz;
+    int nxh;           // nx / 2 (complex columns of a row pair view)
+    long long n;       // cells
+    double ihx2, ihy2, ihz2;  // 1 / h_d^2
+    int coef;          // face-coefficient mode
+    int weight;        // residual multiplier mode
+};
+
+// Per-solve state, resident in device memory.  Written only by the one-block
+// finalize kernels (and zeroed by the init kernel); every sweep kernel reads
+// `done` first and returns at once when the solve is over, so that unrolled
+// iteration sequences stop doing work after convergence.
+struct SolveState {
+    // parameters (init kernel)
+    double tol;
+    double inner_tol;
+    int max_iter;
+    int max_outer;
+    int precision;
+    int pad0;
+    // setup results
+    double b_mean;
+    double b_sumsq;     // sum b^2 (for the FP32 scale only)
+    double rho_min, rho_max;
+    int bad;            // non-finite or non-positive input seen
+    // outer (FP64) iteration
+    int iter;           // FP64 path: current iteration; FP32 path: current outer step
+    int done;           // solve finished (any status)
+    int status;         // POISSON_* code
+    double b_norm;      // ||b - mean b||
+    double r_norm;      // last FP64 residual norm
+    double rel;         // last relative residual
+    double p_shift;     // mean of the incoming p, removed by the first update
+    double p_sum;       // sum p and sum p^2 of the last iterate whose residual was taken
+    double p_sumsq;
+    int p_fixed;        // p_shift already removed
+    // FP32 inner iteration
+    int inner_iter;     // inner iteration within the current outer step
+    int inner_done;
+    int inner_total;
+    int since_best;
+    double inv_s;       // r32 = r * inv_s (a power of two)
+    double rhs_mean32;  // mean of r32, removed inside the inner sweeps
+    double rhs_norm32;  // ||r32 - mean||
+    double rel_in;
+    double best_in;
+    double hist[kHistCap];
+};
+
+// Per-solve device pointers (a batch launch indexes these by blockIdx.y).
+struct Slot {
+    const double* rho;
+    const double* b;
+    double* p;
+    double* W;        // FP64 spectral workspace, n values
+    float* rho32;     // FP32 copies / workspace (FP32_REFINE only)
+    float* r32;
+    float* d32;
+    float* W32;
+    double* partial;  // per-block partial sums, kPartialStride per block
+    SolveState* st;
+};
+
+// Device tables for one grid, shared by every solve of that grid.
+struct Tables {
+    const double2* twx; const double2* twy; const double2* twz;  // exp(-2 pi i t/N), FP64
+    const float2* twx32; const float2* twy32; const float2* twz32;
+    const double* lamx; const double* lamy; const double* lamz;  // -4 sin^2(pi k/N)/h^2
+    const float* lamx32; const float* lamy32; const float* lamz32;
+};
+
+// Launch geometry of the sweeps of one grid (host side).
+struct Geometry {
+    int blocks_x;      // row-pair line groups (x transforms)
+    int blocks_y;      // column line groups for the y transform
+    int blocks_z;      // column line groups for the z transform
+    int blocks_pt;     // pointwise kernels
+    int max_blocks;    // partial-sum capacity needed
+};
+
+// ---- launchers (poisson_kernels.hip) ----------------------------------------
+// Every launcher enqueues on `stream` for `nslots` solves described by the
+// device array `slots`.  They return hipSuccess or the launch error.
+Geometry make_geometry(const GridArgs& g);
+bool length_supported(int n);
+
+hipError_t launch_init(const GridArgs& g, const Slot* slots, int nslots, double tol, double inner_tol,
+                       int max_iter, int max_outer, int precision, hipStream_t s);
+hipError_t launch_setup(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,
+                        bool write_rho32, hipStream_t s);
+hipError_t launch_setup_finalize(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,
+                                 hipStream_t s);
+// One iteration of the paper's method on all slots (FP64 fields) or one inner
+// iteration (FP32 fields).
+hipError_t launch_iteration(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slots,
+                            int nslots, bool fp32, hipStream_t s);
+// One sweep alone (1: P1, 2: P2 and P4, 3: P3, 5: P5), for timing.
+hipError_t launch_sweep(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32, int which,
+                        hipStream_t s);
+// FP32_REFINE outer step pieces.
+hipError_t launch_outer_residual(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,
+                                 hipStream_t s);
+hipError_t launch_outer_update(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,
+                               hipStream_t s);
+hipError_t launch_fixup(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots, hipStream_t s);
+
+// Single sweeps for parity checks (one slot).
+hipError_t launch_apply(const GridArgs& g, const Geometry& geo, const double* rho, const double* p, double* out,
+                        hipStream_t s);
+hipError_t launch_residual(const GridArgs& g, const Geometry& geo, const Slot* slot, double* r,
+                           hipStream_t s);
+hipError_t launch_lap_pinv(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slot,
+                           hipStream_t s);
+
+}  // namespace pois
