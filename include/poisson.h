@@ -160,11 +160,13 @@ typedef struct poisson_server_s* poisson_server_t;
 int poisson_server_create(size_t budget_bytes, int max_slots, int precision, int coef, int weight,
                           int max_iter, void* stream, poisson_server_t* out);
 
-/* Queue a request.  rho, b: device FP64 fields the server copies at
- * admission (the caller may reuse them after the request is admitted, see
- * poisson_server_poll); p: device FP64 field, in/out like poisson_solve,
- * written when the request completes.  Does not block.  Returns the id
- * through *id.  POISSON_ETOOBIG if the request can never fit the budget. */
+/* Queue a request.  rho, b, p: device FP64 fields of the request's grid that
+ * the server uses in place: rho and b must stay valid and unchanged, and p
+ * must not be touched, until poisson_server_poll reports the request done.  p
+ * is in/out like in poisson_solve.  The request's resident footprint (its
+ * three fields plus the solver workspace) counts against the budget while it
+ * is admitted.  Does not block.  Returns the id through *id.
+ * POISSON_ETOOBIG if the request could never fit the budget. */
 int poisson_server_submit(poisson_server_t s, int nx, int ny, int nz, double lx, double ly, double lz,
                           const double* rho, const double* b, double* p, double tol, long long* id);
 
@@ -174,8 +176,9 @@ int poisson_server_submit(poisson_server_t s, int nx, int ny, int nz, double lx,
 int poisson_server_tick(poisson_server_t s);
 
 /* 0 and *stats filled if the request is done, 1 if still queued or running,
- * < 0 on error.  A done request's stats stay readable until the server is
- * destroyed. */
+ * < 0 on error.  For a served request stats->ms is the latency from submit to
+ * completion (host clock).  A done request's stats stay readable until the
+ * server is destroyed.  A server is driven by one host thread. */
 int poisson_server_poll(poisson_server_t s, long long id, poisson_stats* stats);
 
 void poisson_server_destroy(poisson_server_t s);

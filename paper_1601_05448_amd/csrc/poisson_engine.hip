@@ -159,8 +159,9 @@ void Workspace::release() {
     mem = nullptr;
 }
 
-Slot Workspace::slot(const double* rho, const double* b, double* p) const {
+Slot Workspace::slot(const double* rho, const double* b, double* p, double tol) const {
     Slot s{};
+    s.tol = tol;
     s.rho = rho; s.b = b; s.p = p;
     s.W = W; s.rho32 = rho32; s.r32 = r32; s.d32 = d32; s.W32 = W32;
     s.partial = partial; s.st = st;
@@ -176,8 +177,9 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
                 SolveState* const* d_states, SolveState* hdr, const SolveParams& prm, hipStream_t s) {
     hipError_t e;
     const bool fp32 = prm.precision == POISSON_FP32_REFINE;
-    if ((e = launch_init(g, d_slots, nslots, prm.tol, prm.inner_tol, prm.max_iter, prm.max_outer,
-                         prm.precision, s)) != hipSuccess) return hip_status(e);
+    if ((e = launch_init(g, d_slots, nslots, prm.inner_tol, prm.max_iter, prm.max_outer, prm.precision, s)) !=
+        hipSuccess)
+        return hip_status(e);
     if ((e = launch_setup(g, geo, d_slots, nslots, fp32, s)) != hipSuccess) return hip_status(e);
     if ((e = launch_setup_finalize(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
     const size_t hb = offsetof(SolveState, hist);
@@ -349,7 +351,7 @@ int poisson_solve(poisson_t h, const double* rho, const double* b, double* p, do
     if (!h || !rho || !b || !p || !(tol > 0.0) || !std::isfinite(tol)) return POISSON_EINVAL;
     const size_t bytes = (size_t)h->g.n * sizeof(double);
     if (overlaps(rho, b, bytes) || overlaps(rho, p, bytes) || overlaps(b, p, bytes)) return POISSON_EINVAL;
-    int rc = set_slot(h, h->ws.slot(rho, b, p));
+    int rc = set_slot(h, h->ws.slot(rho, b, p, tol));
     if (rc != POISSON_OK) return rc;
     SolveParams prm;
     prm.tol = tol;
@@ -398,11 +400,11 @@ int poisson_residual(poisson_t h, const double* rho, const double* b, const doub
     if (!h || !rho || !b || !p) return POISSON_EINVAL;
     // the residual sweep only reads p; the host copy of the last solve's state
     // (stats, history) is not touched
-    Slot s = h->ws.slot(rho, b, const_cast<double*>(p));
+    Slot s = h->ws.slot(rho, b, const_cast<double*>(p), 1.0);
     int rc = set_slot(h, s);
     if (rc != POISSON_OK) return rc;
     hipError_t e;
-    if ((e = launch_init(h->g, h->d_slot, 1, 1.0, 1.0, 0, 0, POISSON_FP64, h->stream)) != hipSuccess) return hip_status(e);
+    if ((e = launch_init(h->g, h->d_slot, 1, 1.0, 0, 0, POISSON_FP64, h->stream)) != hipSuccess) return hip_status(e);
     if ((e = launch_setup(h->g, h->geo, h->d_slot, 1, false, h->stream)) != hipSuccess) return hip_status(e);
     if ((e = launch_setup_finalize(h->g, h->geo, h->d_slot, 1, h->stream)) != hipSuccess) return hip_status(e);
     if ((e = launch_residual(h->g, h->geo, h->d_slot, r, h->stream)) != hipSuccess) return hip_status(e);
@@ -427,11 +429,11 @@ int poisson_time_sweep(poisson_t h, int sweep, int fp32, const double* rho, cons
     if (!h || !rho || !b || !p || !avg_ms || reps < 1) return POISSON_EINVAL;
     if (sweep != 1 && sweep != 2 && sweep != 3 && sweep != 5) return POISSON_EINVAL;
     if (fp32 && h->o.precision != POISSON_FP32_REFINE) return POISSON_EINVAL;
-    int rc = set_slot(h, h->ws.slot(rho, b, p));
+    // a state that never converges (tol 0) so that every sweep does its work
+    int rc = set_slot(h, h->ws.slot(rho, b, p, 0.0));
     if (rc != POISSON_OK) return rc;
     hipError_t e;
-    // a state that never converges (tol 0) so that every sweep does its work
-    if ((e = launch_init(h->g, h->d_slot, 1, 0.0, 0.0, 1 << 30, 1 << 30, h->o.precision, h->stream)) != hipSuccess)
+    if ((e = launch_init(h->g, h->d_slot, 1, 0.0, 1 << 30, 1 << 30, h->o.precision, h->stream)) != hipSuccess)
         return hip_status(e);
     if ((e = launch_setup(h->g, h->geo, h->d_slot, 1, fp32 != 0, h->stream)) != hipSuccess) return hip_status(e);
     if ((e = launch_setup_finalize(h->g, h->geo, h->d_slot, 1, h->stream)) != hipSuccess) return hip_status(e);
@@ -453,7 +455,7 @@ int poisson_time_sweep(poisson_t h, int sweep, int fp32, const double* rho, cons
 
 int poisson_lap_pinv(poisson_t h, const double* q, double* delta) {
     if (!h || !q || !delta) return POISSON_EINVAL;
-    int rc = set_slot(h, h->ws.slot(nullptr, q, delta));
+    int rc = set_slot(h, h->ws.slot(nullptr, q, delta, 1.0));
     if (rc != POISSON_OK) return rc;
     hipError_t e = launch_lap_pinv(h->g, h->geo, h->tables.t, h->d_slot, h->stream);
     if (e != hipSuccess) return hip_status(e);

@@ -40,7 +40,7 @@ struct Workspace {
     SolveState* st = nullptr;
     int allocate(const GridArgs& g, const Geometry& geo, int precision);
     void release();
-    Slot slot(const double* rho, const double* b, double* p) const;
+    Slot slot(const double* rho, const double* b, double* p, double tol) const;
 };
 
 int hip_status(hipError_t e);

@@ -51,7 +51,10 @@ struct SolveState {
     double p_sum;       // sum p and sum p^2 of the last iterate whose residual was taken
     double p_sumsq;
     int p_fixed;        // p_shift already removed
-    // FP32 inner iteration
+    // FP32 inner iteration.  stage: 0 the next FP64 outer residual is due, 1 inner
+    // FP32 sweeps run, 2 the FP64 update is due; each kernel acts only on the
+    // solves in its stage, so solves at different stages share one launch sequence
+    int stage;
     int inner_iter;     // inner iteration within the current outer step
     int inner_done;
     int inner_total;
@@ -66,6 +69,7 @@ struct SolveState {
 
 // Per-solve device pointers (a batch launch indexes these by blockIdx.y).
 struct Slot {
+    double tol;       // relative-residual target of this solve
     const double* rho;
     const double* b;
     double* p;
@@ -101,8 +105,9 @@ struct Geometry {
 Geometry make_geometry(const GridArgs& g);
 bool length_supported(int n);
 
-hipError_t launch_init(const GridArgs& g, const Slot* slots, int nslots, double tol, double inner_tol,
-                       int max_iter, int max_outer, int precision, hipStream_t s);
+// Initialises the state of each slot (tolerance from Slot::tol).
+hipError_t launch_init(const GridArgs& g, const Slot* slots, int nslots, double inner_tol, int max_iter,
+                       int max_outer, int precision, hipStream_t s);
 hipError_t launch_setup(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,
                         bool write_rho32, hipStream_t s);
 hipError_t launch_setup_finalize(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,

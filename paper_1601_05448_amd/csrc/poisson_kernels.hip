@@ -229,7 +229,9 @@ struct IterView<float> {
     const float* p; const float* rhs; const float* rho; float* W; float rhs_mean;
     __device__ IterView(const Slot& s)
         : p(s.d32), rhs(s.r32), rho(s.rho32), W(s.W32), rhs_mean((float)s.st->rhs_mean32) {}
-    static __device__ bool skip(const SolveState* st) { return st->done != 0 || st->inner_done != 0; }
+    static __device__ bool skip(const SolveState* st) {
+        return st->done != 0 || st->stage != 1 || st->inner_done != 0;
+    }
 };
 
 template <typename T>
@@ -487,11 +489,11 @@ k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
 
 constexpr int kPtThreads = 256;
 
-__global__ void __launch_bounds__(1) k_init(const Slot* __restrict__ slots, double tol, double inner_tol,
-                                           int max_iter, int max_outer, int precision) {
+__global__ void __launch_bounds__(1) k_init(const Slot* __restrict__ slots, double inner_tol, int max_iter,
+                                           int max_outer, int precision) {
     SolveState* st = slots[blockIdx.x].st;
     SolveState z = {};
-    z.tol = tol;
+    z.tol = slots[blockIdx.x].tol;
     z.inner_tol = inner_tol;
     z.max_iter = max_iter;
     z.max_outer = max_outer;
@@ -652,7 +654,7 @@ __global__ void __launch_bounds__(256) k_finalize_outer(GridArgs g, const Slot* 
     __shared__ double red[20];
     const Slot& s = slots[blockIdx.x];
     SolveState* st = s.st;
-    if (st->done) return;
+    if (st->done || st->stage != 0) return;
     double sums[5];  // sum r^2, sum bt^2, sum p, sum p^2, sum r
     sum_partials<5>(s.partial, nblk, sums, red);
     if (threadIdx.x != 0) return;
@@ -688,6 +690,7 @@ __global__ void __launch_bounds__(256) k_finalize_outer(GridArgs g, const Slot* 
         st->status = POISSON_ENOCONV;
     } else {
         st->rhs_mean32 = sums[4] * st->inv_s / (double)g.n;
+        st->stage = 1;
         st->inner_iter = 0;
         st->inner_done = 0;
         st->since_best = 0;
@@ -702,7 +705,7 @@ __global__ void __launch_bounds__(256) k_finalize_inner(GridArgs g, const Slot* 
     __shared__ double red[16];
     const Slot& s = slots[blockIdx.x];
     SolveState* st = s.st;
-    if (st->done || st->inner_done) return;
+    if (st->done || st->stage != 1 || st->inner_done) return;
     double sums[2];
     sum_partials<2>(s.partial, nblk, sums, red);
     if (threadIdx.x != 0) return;
@@ -722,6 +725,7 @@ __global__ void __launch_bounds__(256) k_finalize_inner(GridArgs g, const Slot* 
     if (t >= max_inner || st->inner_total >= st->max_iter) stop = true;
     if (stop) {
         st->inner_done = 1;
+        st->stage = 2;
     } else {
         st->inner_iter = t + 1;
         st->inner_total += 1;
@@ -738,7 +742,7 @@ k_stencil(GridArgs g, const Slot* __restrict__ slots, const double* __restrict__
           const double* __restrict__ p_in, double* __restrict__ out) {
     __shared__ double red[(kPtThreads / 64) * 5];
     const Slot* sp = slots ? &slots[blockIdx.y] : nullptr;
-    if (MODE == 2 && sp->st->done) return;
+    if (MODE == 2 && (sp->st->done || sp->st->stage != 0)) return;
     const double* rho = (MODE == 0) ? rho_in : sp->rho;
     const double* p = (MODE == 0) ? p_in : sp->p;
     const double* b = (MODE == 0) ? nullptr : sp->b;
@@ -788,7 +792,7 @@ k_stencil(GridArgs g, const Slot* __restrict__ slots, const double* __restrict__
 __global__ void __launch_bounds__(kPtThreads) k_outer_update(GridArgs g, const Slot* __restrict__ slots) {
     const Slot& s = slots[blockIdx.y];
     const SolveState* st = s.st;
-    if (st->done) return;
+    if (st->done || st->stage != 2) return;
     const double scale = 1.0 / st->inv_s;
     // mean of the current p (FP64 sum of the outer residual sweep): removing it
     // here keeps p zero-mean although the FP32 correction is not exactly so
@@ -801,7 +805,8 @@ __global__ void __launch_bounds__(kPtThreads) k_outer_update(GridArgs g, const S
 // One block per slot: between the outer update and the next outer residual.
 __global__ void __launch_bounds__(64) k_outer_advance(GridArgs g, const Slot* __restrict__ slots) {
     SolveState* st = slots[blockIdx.x].st;
-    if (st->done || threadIdx.x != 0) return;
+    if (st->done || st->stage != 2 || threadIdx.x != 0) return;
+    st->stage = 0;
     // predicted size of the next FP64 residual: ||r|| times the inner reduction
     const double est = st->r_norm * fmax(st->rel_in, 1e-30);
     st->inv_s = 1.0 / pow2_near(est / sqrt((double)g.n));
@@ -894,10 +899,10 @@ Geometry make_geometry(const GridArgs& g) {
     return geo;
 }
 
-hipError_t launch_init(const GridArgs& g, const Slot* slots, int nslots, double tol, double inner_tol,
-                       int max_iter, int max_outer, int precision, hipStream_t s) {
+hipError_t launch_init(const GridArgs& g, const Slot* slots, int nslots, double inner_tol, int max_iter,
+                       int max_outer, int precision, hipStream_t s) {
     (void)g;
-    k_init<<<nslots, 1, 0, s>>>(slots, tol, inner_tol, max_iter, max_outer, precision);
+    k_init<<<nslots, 1, 0, s>>>(slots, inner_tol, max_iter, max_outer, precision);
     return hipGetLastError();
 }
 

@@ -49,16 +49,9 @@ def centres(n: int, length: float) -> np.ndarray:
     return (np.arange(n, dtype=np.float64) + 0.5) * (length / n)
 
 
-def bandlim(shape: Sequence[int], lengths: Sequence[float], kmax: float,
-            rng: np.random.Generator, z_chunk: int = 64) -> np.ndarray:
-    """Gaussian random field band-limited to physical wavenumbers 0 < |k| <= kmax.
-
-    Independent complex N(0,1) coefficients on every integer wavevector m with
-    |2 pi m / L| <= kmax (m != 0); the field is the real part of their Fourier
-    synthesis at cell centres, shifted to zero mean and scaled to unit RMS.
-    The synthesis is separable (x, then y, then z) so it is independent of the
-    grid resolution and cheap at any size.
-    """
+def _bandlim_spectrum(shape: Sequence[int], lengths: Sequence[float], kmax: float,
+                      rng: np.random.Generator):
+    """Random coefficients and 1-D synthesis factors of a band-limited field."""
     nz, ny, nx = shape
     lx, ly, lz = lengths
     mx = int(math.floor(kmax * lx / TWO_PI))
@@ -76,6 +69,21 @@ def bandlim(shape: Sequence[int], lengths: Sequence[float], kmax: float,
     ez = np.exp(1j * np.outer(TWO_PI * az / lz, centres(nz, lz)))  # (2mz+1, nz)
     t1 = coef @ ex  # (mz, my, nx)
     t2 = np.einsum("zyi,yj->zji", t1, ey).reshape(len(az), ny * nx)  # (mz, ny*nx)
+    return t2, ez
+
+
+def bandlim(shape: Sequence[int], lengths: Sequence[float], kmax: float,
+            rng: np.random.Generator, z_chunk: int = 64) -> np.ndarray:
+    """Gaussian random field band-limited to physical wavenumbers 0 < |k| <= kmax.
+
+    Independent complex N(0,1) coefficients on every integer wavevector m with
+    |2 pi m / L| <= kmax (m != 0); the field is the real part of their Fourier
+    synthesis at cell centres, shifted to zero mean and scaled to unit RMS.
+    The synthesis is separable (x, then y, then z) so it is independent of the
+    grid resolution and cheap at any size.
+    """
+    nz, ny, nx = shape
+    t2, ez = _bandlim_spectrum(shape, lengths, kmax, rng)
     t2r, t2i = np.ascontiguousarray(t2.real), np.ascontiguousarray(t2.imag)
     out = np.empty((nz, ny * nx))
     ezr, ezi = ez.real.T.copy(), ez.imag.T.copy()  # (nz, mz)
@@ -88,6 +96,28 @@ def bandlim(shape: Sequence[int], lengths: Sequence[float], kmax: float,
     if rms > 0:
         out /= rms
     return out
+
+
+def bandlim_device(shape: Sequence[int], lengths: Sequence[float], kmax: float,
+                   rng: np.random.Generator, device="cuda"):
+    """bandlim with the same random draws, its last synthesis step (the z
+    contraction, the only large one) done as a float64 torch matmul on
+    `device`; returns a torch tensor.  Values agree with bandlim up to the
+    rounding order of the two matrix products."""
+    import torch
+
+    nz, ny, nx = shape
+    t2, ez = _bandlim_spectrum(shape, lengths, kmax, rng)
+    t2r = torch.from_numpy(np.ascontiguousarray(t2.real)).to(device)
+    t2i = torch.from_numpy(np.ascontiguousarray(t2.imag)).to(device)
+    ezr = torch.from_numpy(ez.real.T.copy()).to(device)
+    ezi = torch.from_numpy(ez.imag.T.copy()).to(device)
+    out = (ezr @ t2r - ezi @ t2i).reshape(nz, ny, nx)
+    out -= out.mean()
+    rms = torch.sqrt(torch.mean(out * out))
+    if float(rms) > 0:
+        out /= rms
+    return out.contiguous()
 
 
 def contrast_exp(s: np.ndarray, ratio: float) -> np.ndarray:
@@ -256,6 +286,21 @@ def request_problem(req: Request, kmax: float = 8.0) -> Problem:
     rho = contrast_exp(s, req.ratio)
     b = bandlim((n, n, n), L, kmax, rng)
     return Problem(f"request {req.rid} {n}^3 ratio {req.ratio:.2f}", (n, n, n), L, rho, b)
+
+
+def request_fields_device(req: Request, kmax: float = 8.0, device="cuda"):
+    """Fields (rho, b) of one served request generated on `device` (torch
+    tensors), from the same seeded draws as request_problem."""
+    import torch
+
+    rng = np.random.default_rng(request_seed(req.rid))
+    n = req.n
+    L = (TWO_PI,) * 3
+    s = bandlim_device((n, n, n), L, kmax, rng, device)
+    span = float(s.max() - s.min())
+    rho = torch.exp(s * (math.log(req.ratio) / span))
+    b = bandlim_device((n, n, n), L, kmax, rng, device)
+    return rho.contiguous(), b
 
 
 def small_problem(shape=(16, 12, 24), lengths=(TWO_PI, 3.0, 5.0), ratio: float = 3.0,

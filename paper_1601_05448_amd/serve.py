@@ -1,0 +1,118 @@
+"""Serving driver: replays a stream of solve requests against the C server.
+
+The scheduling itself (admission by footprint, batching per grid size,
+retirement) is in the library (``poisson_server_*`` in include/poisson.h);
+this module only submits requests when their arrival time has come, calls the
+tick, and collects per-request latencies from arrival to completion.
+"""
+from __future__ import annotations
+
+import time
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional, Sequence
+
+from . import poisson as P
+
+
+class Server:
+    """Owning wrapper of a poisson_server_t."""
+
+    def __init__(self, budget_bytes: int, max_slots: int, precision: int = P.POISSON_FP64,
+                 coef: int = P.POISSON_COEF_RHO_FACE_MEAN, weight: int = P.POISSON_W_RHO,
+                 max_iter: int = 0, stream=None):
+        self.h = P.poisson_server_create(budget_bytes, max_slots, precision, coef, weight, max_iter, stream)
+
+    def submit(self, shape, lengths, rho, b, p, tol: float) -> int:
+        return P.poisson_server_submit(self.h, shape, lengths, rho, b, p, tol)
+
+    def tick(self) -> int:
+        return P.poisson_server_tick(self.h)
+
+    def poll(self, rid: int) -> Optional[dict]:
+        return P.poisson_server_poll(self.h, rid)
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            P.poisson_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Job:
+    """One request of a replayed stream: arrival time (s, from the start of the
+    replay), grid, box and device fields."""
+    arrival_s: float
+    shape: Sequence[int]
+    lengths: Sequence[float]
+    rho: object
+    b: object
+    p: object
+    tol: float = 1e-10
+    tag: object = None
+
+
+@dataclass
+class Outcome:
+    job: Job
+    stats: dict
+    latency_ms: float  # arrival to completion
+
+
+@dataclass
+class ReplayResult:
+    outcomes: List[Outcome] = field(default_factory=list)
+    wall_s: float = 0.0
+    ticks: int = 0
+
+    def latencies(self) -> List[float]:
+        return [o.latency_ms for o in self.outcomes]
+
+
+def replay(server: Server, jobs: Sequence[Job], realtime: bool = True,
+           on_done: Optional[Callable[[Outcome], None]] = None) -> ReplayResult:
+    """Submit each job at its arrival time (or all at once if not realtime),
+    tick until every job is done.  Latency = completion - arrival."""
+    order = sorted(range(len(jobs)), key=lambda k: jobs[k].arrival_s)
+    res = ReplayResult()
+    t0 = time.perf_counter()
+    nxt = 0
+    inflight: Dict[int, tuple] = {}
+    while nxt < len(order) or inflight:
+        now = time.perf_counter() - t0
+        while nxt < len(order) and (not realtime or jobs[order[nxt]].arrival_s <= now):
+            j = jobs[order[nxt]]
+            rid = server.submit(j.shape, j.lengths, j.rho, j.b, j.p, j.tol)
+            inflight[rid] = (j, time.perf_counter() - t0)
+            nxt += 1
+        if not inflight:
+            wait = jobs[order[nxt]].arrival_s - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(min(wait, 0.001))
+            continue
+        server.tick()
+        res.ticks += 1
+        for rid in list(inflight):
+            st = server.poll(rid)
+            if st is None:
+                continue
+            j, t_sub = inflight.pop(rid)
+            arrival = j.arrival_s if realtime else 0.0
+            lat = (t_sub - arrival) * 1e3 + st["ms"]
+            out = Outcome(j, st, lat)
+            res.outcomes.append(out)
+            if on_done:
+                on_done(out)
+    res.wall_s = time.perf_counter() - t0
+    return res

@@ -46,3 +46,12 @@ def test_null_arguments_rejected():
     assert lib.poisson_solve(None, None, None, None, 1e-10) == P.POISSON_EINVAL
     assert lib.poisson_get_stats(None, None) == P.POISSON_EINVAL
     lib.poisson_destroy(None)  # NULL is allowed
+
+
+@pytest.mark.parametrize("args", [(0, 4, 0, 0, 0), (1 << 30, 0, 0, 0, 0), (1 << 30, 4, 7, 0, 0),
+                                  (1 << 30, 4, 0, 3, 0), (1 << 30, 4, 0, 0, 9)])
+def test_server_create_rejects_invalid_options(args):
+    budget, slots, prec, coef, weight = args
+    h = ctypes.c_void_p()
+    rc = P.load().poisson_server_create(budget, slots, prec, coef, weight, 0, None, ctypes.byref(h))
+    assert rc == P.POISSON_EINVAL and h.value is None

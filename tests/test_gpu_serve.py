@@ -1,0 +1,145 @@
+"""GPU tests of the serving engine (continuous batching of many solves).
+
+Each request's result must be the same alone and in the mix: the batched
+kernels give every request its own fields, workspace, state and fixed-order
+reductions, so the stated tolerance is 0 (bitwise identical p and identical
+iteration counts).  This is the solver-level analogue of the paper's check that
+results do not depend on the domain decomposition (section "Effect of domain
+partitioning").
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import announce, dev, host
+from paper_1601_05448_amd import inputs
+from paper_1601_05448_amd import poisson as P
+from paper_1601_05448_amd import serve
+
+pytestmark = pytest.mark.gpu
+TWO_PI = 2.0 * math.pi
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    P.load()
+    yield
+
+
+def _mix(count=12):
+    shapes = [(16, 16, 16), (24, 24, 24), (32, 32, 32), (12, 16, 24)]
+    lens = [(TWO_PI,) * 3, (TWO_PI,) * 3, (TWO_PI,) * 3, (TWO_PI, 3.0, 5.0)]
+    probs = []
+    for k in range(count):
+        sh, L = shapes[k % 4], lens[k % 4]
+        probs.append(inputs.small_problem(shape=sh, lengths=L, ratio=2.0 + (k % 5), seed=100 + k))
+    return probs
+
+
+def _alone(prob, precision):
+    h = P.poisson_create(prob.shape, prob.lengths, precision=precision)
+    try:
+        p = dev(np.zeros(prob.shape))
+        P.poisson_solve(h, dev(prob.rho), dev(prob.b), p, 1e-10)
+        st = P.poisson_get_stats(h)
+    finally:
+        P.poisson_destroy(h)
+    return host(p), st
+
+
+def _served(probs, precision, budget=1 << 33, slots=64, tols=None):
+    jobs = []
+    for k, pr in enumerate(probs):
+        jobs.append(serve.Job(0.0, pr.shape, pr.lengths, dev(pr.rho), dev(pr.b), dev(np.zeros(pr.shape)),
+                              tol=1e-10 if tols is None else tols[k], tag=k))
+    with serve.Server(budget, slots, precision=precision) as s:
+        res = serve.replay(s, jobs, realtime=False)
+    out = [None] * len(probs)
+    for o in res.outcomes:
+        out[o.job.tag] = (host(o.job.p), o.stats)
+    return out, res
+
+
+@pytest.mark.parametrize("precision", [P.POISSON_FP64, P.POISSON_FP32_REFINE])
+def test_each_result_same_alone_and_in_the_mix(precision):
+    announce("serve mix invariance", precision)
+    probs = _mix()
+    mixed, res = _served(probs, precision)
+    assert len(res.outcomes) == len(probs)
+    for k, pr in enumerate(probs):
+        p_alone, st_alone = _alone(pr, precision)
+        p_mix, st_mix = mixed[k]
+        assert st_mix["status"] == 0 and st_alone["status"] == 0
+        assert st_mix["iters"] == st_alone["iters"] and st_mix["outer_iters"] == st_alone["outer_iters"]
+        assert np.array_equal(p_mix, p_alone), k
+        assert oracle.residual(pr.rho, pr.b, p_mix, pr.lengths)["rel"] <= 1e-10
+
+
+def test_budget_admits_one_at_a_time_and_all_finish():
+    announce("serve tight budget")
+    probs = _mix(6)
+    # footprint of the largest request (32^3): three fields plus about 8 B/cell of
+    # workspace; the budget holds one such request, not two
+    one = 32 ** 3 * 8 * 4 + (1 << 20)
+    mixed, res = _served(probs, P.POISSON_FP64, budget=int(1.5 * one))
+    for k, pr in enumerate(probs):
+        p_alone, _ = _alone(pr, P.POISSON_FP64)
+        assert np.array_equal(mixed[k][0], p_alone)
+
+
+def test_request_too_big_for_budget():
+    announce("serve etoobig")
+    pr = _mix(1)[0]
+    with serve.Server(1024, 4) as s:
+        with pytest.raises(P.PoissonError) as e:
+            s.submit(pr.shape, pr.lengths, dev(pr.rho), dev(pr.b), dev(np.zeros(pr.shape)), 1e-10)
+        assert e.value.code == P.POISSON_ETOOBIG
+
+
+def test_bad_request_does_not_disturb_the_mix():
+    announce("serve edomain in mix")
+    probs = _mix(8)
+    probs[3].rho[1, 2, 3] = -1.0
+    mixed, _ = _served(probs, P.POISSON_FP64)
+    assert mixed[3][1]["status"] == P.POISSON_EDOMAIN
+    for k in (0, 1, 2, 4, 5, 6, 7):
+        p_alone, _ = _alone(probs[k], P.POISSON_FP64)
+        assert mixed[k][1]["status"] == 0
+        assert np.array_equal(mixed[k][0], p_alone)
+
+
+def test_per_request_tolerance():
+    announce("serve per-request tol")
+    probs = _mix(4)
+    mixed, _ = _served(probs, P.POISSON_FP64, tols=[1e-4, 1e-6, 1e-8, 1e-10])
+    for k, tol in enumerate([1e-4, 1e-6, 1e-8, 1e-10]):
+        st = mixed[k][1]
+        assert st["rel_resid"] <= tol
+        assert oracle.residual(probs[k].rho, probs[k].b, mixed[k][0], probs[k].lengths)["rel"] <= tol
+
+
+def test_poisson_arrival_stream_of_served_sizes():
+    """A short real-time stream with the served grid sizes (64^3, 96^3), fields
+    generated on the device; every request reaches 1e-10."""
+    announce("serve realtime stream")
+    import torch
+
+    reqs = [r for r in inputs.request_stream(48, rate_hz=400.0) if r.n in (64, 96)][:16]
+    jobs = []
+    for r in reqs:
+        rho, b = inputs.request_fields_device(r)
+        jobs.append(serve.Job(r.arrival_s, (r.n,) * 3, (TWO_PI,) * 3, rho, b,
+                              torch.zeros((r.n,) * 3, dtype=torch.float64, device="cuda"), tag=r))
+    with serve.Server(1 << 33, 32) as s:
+        res = serve.replay(s, jobs, realtime=True)
+    assert len(res.outcomes) == len(jobs)
+    for o in res.outcomes:
+        assert o.stats["status"] == 0 and o.stats["rel_resid"] <= 1e-10 and o.latency_ms > 0
+    o = res.outcomes[0]
+    chk = oracle.residual(host(o.job.rho), host(o.job.b), host(o.job.p), o.job.lengths)
+    assert chk["rel"] <= 1e-10
