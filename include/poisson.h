@@ -43,7 +43,8 @@ extern "C" {
 #define POISSON_OK 0
 #define POISSON_EINVAL (-1)    /* bad size, NULL or overlapping pointer, tol <= 0, bad enum */
 #define POISSON_ENOMEM (-2)    /* device or host allocation failed                         */
-#define POISSON_EDOMAIN (-3)   /* rho <= 0, or a non-finite value in rho or b; p untouched */
+#define POISSON_EDOMAIN (-3)   /* rho <= 0, non-finite rho or b, or max/min rho above the   */
+                               /* supported ratio (1e20 FP64, 1e8 FP32_REFINE); p untouched */
 #define POISSON_ENOCONV (-4)   /* max_iter reached; p holds the last iterate               */
 #define POISSON_EDIVERGED (-5) /* residual grew above 1e8 x ||b~|| or became non-finite    */
 #define POISSON_EHIP (-6)      /* HIP runtime error                                        */

@@ -212,14 +212,16 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
             int r = poll(false);
             if (r < 0) return r;
             if (r == 1) break;
+            // the device stops the inner sweeps (tolerance, stagnation, or the
+            // max_iter budget, so at most max_iter + 1 launches are ever needed)
             int launched = 0, chunk = prm.first_chunk;
             while (true) {
-                for (int c = 0; c < chunk && launched < prm.max_inner + 1; ++c, ++launched)
+                for (int c = 0; c < chunk && launched < prm.max_iter + 1; ++c, ++launched)
                     if ((e = launch_iteration(g, geo, t, d_slots, nslots, true, s)) != hipSuccess)
                         return hip_status(e);
                 r = poll(true);
                 if (r < 0) return r;
-                if (r == 1 || launched >= prm.max_inner + 1) break;
+                if (r == 1 || launched >= prm.max_iter + 1) break;
                 chunk = std::min(chunk * 2, prm.max_chunk);
             }
             if ((e = launch_outer_update(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);

@@ -17,7 +17,6 @@ struct SolveParams {
     int precision = POISSON_FP64;
     int max_iter = 1000;      // ... or after this many inner (or FP64) iterations in total
     int max_outer = 30;
-    int max_inner = 100;      // per refinement step
     int first_chunk = 4;      // iterations enqueued before the first poll
     int max_chunk = 16;
 };

@@ -180,6 +180,7 @@ struct LineCfg {
     static constexpr int TT = N >= 16 ? N / 16 : 1;
     static constexpr int L = lines_per_block(TT, N, (int)sizeof(cpx<T>));
     static constexpr int NT = L * TT;
+    static constexpr int IT = N / TT;  // elements per thread when a block walks its L lines
     static constexpr int LS = N + 1;
     static_assert(NT % 64 == 0, "block must be whole wavefronts");
 };

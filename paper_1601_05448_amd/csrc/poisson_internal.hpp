@@ -9,8 +9,8 @@ namespace pois {
 
 constexpr int kHistCap = 256;      // residual-history entries kept per solve
 constexpr int kPartialStride = 8;  // doubles of per-block partial sums per block
-constexpr int kMaxSetupBlocks = 1024;
-constexpr int kMaxInner = 100;    // FP32 inner iterations per refinement step
+constexpr int kMaxSetupBlocks = 4096;
+constexpr int kMaxInnerPerStep = 1 << 20;  // FP32 inner sweeps per refinement step: bounded by max_iter
 
 // Grid description passed by value to every kernel.  Uniform over a batch:
 // all solves of one launch share the grid.

@@ -28,13 +28,54 @@
 
 namespace pois {
 
+// Field pointers reach the kernels through the slot records, so the compiler
+// sees them as generic (flat) pointers that might alias LDS, which stops it from
+// hoisting global loads above LDS stores.  Every field access goes through the
+// global address space instead.
+#define POIS_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ POIS_GLOBAL T* gptr(T* p) {
+    return (POIS_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const POIS_GLOBAL T* gptr(const T* p) {
+    return (const POIS_GLOBAL T*)p;
+}
+
+// Complex values in global memory as native two-element vectors (one 8- or
+// 16-byte access each).
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec2<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+template <typename T>
+__device__ __forceinline__ cpx<T> gload_c(const POIS_GLOBAL T* base, unsigned idx) {
+    const typename Vec2<T>::type v = ((const POIS_GLOBAL typename Vec2<T>::type*)base)[idx];
+    return {v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void gstore_c(POIS_GLOBAL T* base, unsigned idx, cpx<T> c) {
+    typename Vec2<T>::type v;
+    v.x = c.x;
+    v.y = c.y;
+    ((POIS_GLOBAL typename Vec2<T>::type*)base)[idx] = v;
+}
+
 // ---- stencil ------------------------------------------------------------------
 // Face coefficients (the paper does not write the discrete operator out):
-//   coef 0: beta = 2 / (rho_a + rho_b)      1/rho with rho averaged to the face
-//   coef 1: beta = (1/rho_a + 1/rho_b) / 2  face average of 1/rho
-// All reciprocals of a cell (pair) come from one hardware reciprocal refined by
-// Newton steps (Montgomery's batch trick); entries whose running product leaves
-// the normal range fall back to plain divisions.
+//   COEF 0: beta = 2 / (rho_a + rho_b)      1/rho with rho averaged to the face
+//   COEF 1: beta = (1/rho_a + 1/rho_b) / 2  face average of 1/rho
+// The reciprocals of a cell pair come from one hardware reciprocal refined by
+// Newton steps (Montgomery's batch trick), branch-free: the values are first
+// scaled by 1/rho_max into (0, 2], so that the running products stay normal
+// (FP64: one batch, density ratio up to 1e20; FP32: batches of at most four,
+// ratio up to 1e8; the set-up rejects larger ratios).
 
 __device__ __forceinline__ double recip(double x) {
     double y = __builtin_amdgcn_rcp(x);
@@ -49,110 +90,56 @@ __device__ __forceinline__ float recip(float x) {
     return fmaf(y, e, y);
 }
 
-template <typename T>
-struct RecipRange;
-template <>
-struct RecipRange<double> {
-    static constexpr double lo = 1e-290, hi = 1e290;
-};
-template <>
-struct RecipRange<float> {
-    static constexpr float lo = 1e-30f, hi = 1e30f;
-};
-
-// d[k] <- 1 / d[k] for positive d
+// d[k] <- 1 / d[k], k < K, with one reciprocal
 template <typename T, int K>
-__device__ __forceinline__ void batch_recip(T (&d)[K]) {
+__device__ __forceinline__ void batch_recip(T* d) {
     T pre[K];
     pre[0] = d[0];
 #pragma unroll
     for (int k = 1; k < K; ++k) pre[k] = pre[k - 1] * d[k];
-    const T tot = pre[K - 1];
-    if (tot > RecipRange<T>::lo && tot < RecipRange<T>::hi) {
-        T inv = recip(tot);
+    T inv = recip(pre[K - 1]);
 #pragma unroll
-        for (int k = K - 1; k > 0; --k) {
-            const T r = inv * pre[k - 1];
-            inv = inv * d[k];
-            d[k] = r;
-        }
-        d[0] = inv;
-    } else {
-#pragma unroll
-        for (int k = 0; k < K; ++k) d[k] = T(1) / d[k];
+    for (int k = K - 1; k > 0; --k) {
+        const T r = inv * pre[k - 1];
+        inv = inv * d[k];
+        d[k] = r;
+    }
+    d[0] = inv;
+}
+
+template <typename T, int K, int OFF>
+__device__ __forceinline__ void recip_groups(T* d) {
+    if constexpr (OFF < K) {
+        constexpr int G = (sizeof(T) == 8) ? K : ((K - OFF) < 4 ? (K - OFF) : 4);
+        batch_recip<T, G>(d + OFF);
+        recip_groups<T, K, OFF + G>(d);
     }
 }
 
-// Face coefficients of F faces given the densities on their two sides.
-template <typename T, int F>
-__device__ __forceinline__ void face_coefs(int coef, const T (&r1)[F], const T (&r2)[F], T (&beta)[F]) {
-    if (coef == 0) {
-#pragma unroll
-        for (int f = 0; f < F; ++f) beta[f] = r1[f] + r2[f];
-        batch_recip(beta);
-#pragma unroll
-        for (int f = 0; f < F; ++f) beta[f] = T(2) * beta[f];
-    } else {
-        T i1[F], i2[F];
-#pragma unroll
-        for (int f = 0; f < F; ++f) {
-            i1[f] = r1[f];
-            i2[f] = r2[f];
-        }
-        batch_recip(i1);
-        batch_recip(i2);
-#pragma unroll
-        for (int f = 0; f < F; ++f) beta[f] = T(0.5) * (i1[f] + i2[f]);
-    }
+// reciprocals of K values that the caller scaled into (0, 2]
+template <typename T, int K>
+__device__ __forceinline__ void scaled_recips(T (&d)[K]) {
+    recip_groups<T, K, 0>(d);
 }
 
-// Residual b~ - A p of one cell and its weight w; 32-bit indices (grids up to
-// 2^31 cells), periodic neighbours.
 template <typename T>
 struct CellOut {
     T r, w, bt, pc;
 };
-
-template <typename T>
-__device__ __forceinline__ CellOut<T> cell_residual(const GridArgs& g, const T* __restrict__ p,
-                                                    const T* __restrict__ rho, const T* __restrict__ rhs,
-                                                    T rhs_mean, int i, int j, int k) {
-    const unsigned nx = g.nx, ny = g.ny, nz = g.nz, sz = nx * ny;
-    const unsigned c = ((unsigned)k * ny + j) * nx + i;
-    const unsigned cxm = (i == 0) ? c + (nx - 1) : c - 1;
-    const unsigned cxp = (i + 1 == g.nx) ? c - (nx - 1) : c + 1;
-    const unsigned cym = (j == 0) ? c + (ny - 1) * nx : c - nx;
-    const unsigned cyp = (j + 1 == g.ny) ? c - (ny - 1) * nx : c + nx;
-    const unsigned czm = (k == 0) ? c + (nz - 1) * sz : c - sz;
-    const unsigned czp = (k + 1 == g.nz) ? c - (nz - 1) * sz : c + sz;
-    const T rc = rho[c];
-    const T rn[6] = {rho[cxm], rho[cxp], rho[cym], rho[cyp], rho[czm], rho[czp]};
-    const T rcc[6] = {rc, rc, rc, rc, rc, rc};
-    T be[6];  // x-, x+, y-, y+, z-, z+
-    face_coefs<T, 6>(g.coef, rn, rcc, be);
-    CellOut<T> o;
-    o.bt = rhs ? rhs[c] - rhs_mean : T(0);
-    const T pc = p[c];
-    o.pc = pc;
-    const T ap = (be[1] * (p[cxp] - pc) - be[0] * (pc - p[cxm])) * T(g.ihx2) +
-                 (be[3] * (p[cyp] - pc) - be[2] * (pc - p[cym])) * T(g.ihy2) +
-                 (be[5] * (p[czp] - pc) - be[4] * (pc - p[czm])) * T(g.ihz2);
-    o.r = o.bt - ap;
-    o.w = (g.weight == 0) ? rc : T(6) * recip(be[0] + be[1] + be[2] + be[3] + be[4] + be[5]);
-    return o;
-}
-
-// The same for the two cells (i, j0, k0) and (i, j0 + 1, k0) of a row pair (j0
-// even), sharing their common y face: 11 faces, one batched reciprocal.
 template <typename T>
 struct PairOut {
     CellOut<T> a, b;
 };
 
-template <typename T>
-__device__ __forceinline__ PairOut<T> pair_residual(const GridArgs& g, const T* __restrict__ p,
-                                                    const T* __restrict__ rho, const T* __restrict__ rhs,
-                                                    T rhs_mean, int i, int j0, int k0) {
+// Residual b~ - A p and weight w of the two cells (i, j0, k0) and (i, j0 + 1, k0)
+// of a row pair (j0 even), which share their common y face: 11 faces.  32-bit
+// indices (grids up to 2^31 cells), periodic neighbours.  All loads first, then
+// the arithmetic.  rmax = max rho, rinv = 1 / rmax.
+template <typename T, int COEF, int WEIGHT>
+__device__ __forceinline__ PairOut<T> pair_residual(const GridArgs& g, const POIS_GLOBAL T* __restrict__ p,
+                                                    const POIS_GLOBAL T* __restrict__ rho,
+                                                    const POIS_GLOBAL T* __restrict__ rhs, T rhs_mean, T rmax,
+                                                    T rinv, int i, int j0, int k0) {
     const unsigned nx = g.nx, ny = g.ny, nz = g.nz, sz = nx * ny;
     const unsigned a = ((unsigned)k0 * ny + j0) * nx + i, b = a + nx;
     const unsigned axm = (i == 0) ? a + (nx - 1) : a - 1;
@@ -162,35 +149,95 @@ __device__ __forceinline__ PairOut<T> pair_residual(const GridArgs& g, const T* 
     const unsigned byp = (j0 + 2 == g.ny) ? b - (ny - 1) * nx : b + nx;
     const unsigned azm = (k0 == 0) ? a + (nz - 1) * sz : a - sz, bzm = azm + nx;
     const unsigned azp = (k0 + 1 == g.nz) ? a - (nz - 1) * sz : a + sz, bzp = azp + nx;
-    const T ra = rho[a], rb = rho[b];
+    // densities: a, b, a x-, a x+, b x-, b x+, a y-, b y+, a z-, a z+, b z-, b z+
+    const T r[12] = {rho[a], rho[b], rho[axm], rho[axp], rho[bxm], rho[bxp],
+                     rho[aym], rho[byp], rho[azm], rho[azp], rho[bzm], rho[bzp]};
+    const T q[12] = {p[a], p[b], p[axm], p[axp], p[bxm], p[bxp], p[aym], p[byp], p[azm], p[azp], p[bzm], p[bzp]};
+    const T ba = rhs[a], bb = rhs[b];
     // faces: a x-, a x+, a y-, a|b, a z-, a z+, b x-, b x+, b y+, b z-, b z+
-    const T r1[11] = {rho[axm], ra, rho[aym], ra, rho[azm], ra, rho[bxm], rb, rb, rho[bzm], rb};
-    const T r2[11] = {ra, rho[axp], ra, rb, ra, rho[azp], rb, rho[bxp], rho[byp], rb, rho[bzp]};
     T be[11];
-    face_coefs<T, 11>(g.coef, r1, r2, be);
-    const T pa = p[a], pb = p[b];
+    if constexpr (COEF == 0) {
+        T d[11] = {r[2] + r[0], r[0] + r[3], r[6] + r[0], r[0] + r[1], r[8] + r[0], r[0] + r[9],
+                   r[4] + r[1], r[1] + r[5], r[1] + r[7], r[10] + r[1], r[1] + r[11]};
+#pragma unroll
+        for (int f = 0; f < 11; ++f) d[f] *= rinv;
+        scaled_recips(d);
+        const T c = T(2) * rinv;
+#pragma unroll
+        for (int f = 0; f < 11; ++f) be[f] = c * d[f];
+    } else {
+        T v[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = r[k] * rinv;
+        scaled_recips(v);  // rmax / rho
+        const T c = T(0.5) * rinv;
+        be[0] = c * (v[2] + v[0]);  be[1] = c * (v[0] + v[3]);  be[2] = c * (v[6] + v[0]);
+        be[3] = c * (v[0] + v[1]);  be[4] = c * (v[8] + v[0]);  be[5] = c * (v[0] + v[9]);
+        be[6] = c * (v[4] + v[1]);  be[7] = c * (v[1] + v[5]);  be[8] = c * (v[1] + v[7]);
+        be[9] = c * (v[10] + v[1]); be[10] = c * (v[1] + v[11]);
+    }
+    const T pa = q[0], pb = q[1];
     const T hx = T(g.ihx2), hy = T(g.ihy2), hz = T(g.ihz2);
     const T gy = be[3] * (pb - pa);  // flux through the shared face
-    const T apa = (be[1] * (p[axp] - pa) - be[0] * (pa - p[axm])) * hx + (gy - be[2] * (pa - p[aym])) * hy +
-                  (be[5] * (p[azp] - pa) - be[4] * (pa - p[azm])) * hz;
-    const T apb = (be[7] * (p[bxp] - pb) - be[6] * (pb - p[bxm])) * hx + (be[8] * (p[byp] - pb) - gy) * hy +
-                  (be[10] * (p[bzp] - pb) - be[9] * (pb - p[bzm])) * hz;
+    const T apa = (be[1] * (q[3] - pa) - be[0] * (pa - q[2])) * hx + (gy - be[2] * (pa - q[6])) * hy +
+                  (be[5] * (q[9] - pa) - be[4] * (pa - q[8])) * hz;
+    const T apb = (be[7] * (q[5] - pb) - be[6] * (pb - q[4])) * hx + (be[8] * (q[7] - pb) - gy) * hy +
+                  (be[10] * (q[11] - pb) - be[9] * (pb - q[10])) * hz;
     PairOut<T> o;
-    o.a.bt = rhs[a] - rhs_mean;
-    o.b.bt = rhs[b] - rhs_mean;
+    o.a.bt = ba - rhs_mean;
+    o.b.bt = bb - rhs_mean;
     o.a.pc = pa;
     o.b.pc = pb;
     o.a.r = o.a.bt - apa;
     o.b.r = o.b.bt - apb;
-    if (g.weight == 0) {
-        o.a.w = ra;
-        o.b.w = rb;
+    if constexpr (WEIGHT == 0) {
+        o.a.w = r[0];
+        o.b.w = r[1];
     } else {
-        T s[2] = {be[0] + be[1] + be[2] + be[3] + be[4] + be[5], be[6] + be[7] + be[3] + be[8] + be[9] + be[10]};
-        batch_recip(s);
-        o.a.w = T(6) * s[0];
-        o.b.w = T(6) * s[1];
+        // w = 6 / (sum of the six face coefficients); sum * rmax / 6 lies in [1, rmax/rmin]
+        const T c = rmax * T(1.0 / 6.0);
+        T sw[2] = {(be[0] + be[1] + be[2] + be[3] + be[4] + be[5]) * c,
+                   (be[6] + be[7] + be[3] + be[8] + be[9] + be[10]) * c};
+        batch_recip<T, 2>(sw);
+        o.a.w = rmax * sw[0];
+        o.b.w = rmax * sw[1];
     }
+    return o;
+}
+
+// One cell, plain IEEE divisions: the stand-alone operator and residual sweeps
+// (parity checks), which need no state and are off the iteration's path.
+template <typename T>
+__device__ __forceinline__ T face_beta(int coef, T ra, T rb) {
+    return coef == 0 ? T(2) / (ra + rb) : (ra + rb) / (T(2) * ra * rb);
+}
+
+template <typename T>
+__device__ __forceinline__ CellOut<T> cell_residual(const GridArgs& g, const POIS_GLOBAL T* __restrict__ p,
+                                                    const POIS_GLOBAL T* __restrict__ rho,
+                                                    const POIS_GLOBAL T* __restrict__ rhs, T rhs_mean, int i,
+                                                    int j, int k) {
+    const unsigned nx = g.nx, ny = g.ny, nz = g.nz, sz = nx * ny;
+    const unsigned c = ((unsigned)k * ny + j) * nx + i;
+    const unsigned cxm = (i == 0) ? c + (nx - 1) : c - 1;
+    const unsigned cxp = (i + 1 == g.nx) ? c - (nx - 1) : c + 1;
+    const unsigned cym = (j == 0) ? c + (ny - 1) * nx : c - nx;
+    const unsigned cyp = (j + 1 == g.ny) ? c - (ny - 1) * nx : c + nx;
+    const unsigned czm = (k == 0) ? c + (nz - 1) * sz : c - sz;
+    const unsigned czp = (k + 1 == g.nz) ? c - (nz - 1) * sz : c + sz;
+    const T rc = rho[c];
+    const T bxm = face_beta<T>(g.coef, rho[cxm], rc), bxp = face_beta<T>(g.coef, rc, rho[cxp]);
+    const T bym = face_beta<T>(g.coef, rho[cym], rc), byp = face_beta<T>(g.coef, rc, rho[cyp]);
+    const T bzm = face_beta<T>(g.coef, rho[czm], rc), bzp = face_beta<T>(g.coef, rc, rho[czp]);
+    CellOut<T> o;
+    o.bt = rhs ? rhs[c] - rhs_mean : T(0);
+    const T pc = p[c];
+    o.pc = pc;
+    const T ap = (bxp * (p[cxp] - pc) - bxm * (pc - p[cxm])) * T(g.ihx2) +
+                 (byp * (p[cyp] - pc) - bym * (pc - p[cym])) * T(g.ihy2) +
+                 (bzp * (p[czp] - pc) - bzm * (pc - p[czm])) * T(g.ihz2);
+    o.r = o.bt - ap;
+    o.w = (g.weight == 0) ? rc : T(6) / (bxm + bxp + bym + byp + bzm + bzp);
     return o;
 }
 
@@ -219,16 +266,21 @@ struct IterView;
 
 template <>
 struct IterView<double> {
-    const double* p; const double* rhs; const double* rho; double* W; double rhs_mean;
-    __device__ IterView(const Slot& s) : p(s.p), rhs(s.b), rho(s.rho), W(s.W), rhs_mean(s.st->b_mean) {}
+    const POIS_GLOBAL double* p; const POIS_GLOBAL double* rhs; const POIS_GLOBAL double* rho;
+    POIS_GLOBAL double* W; double rhs_mean, rmax, rinv;
+    __device__ IterView(const Slot& s)
+        : p(gptr(s.p)), rhs(gptr(s.b)), rho(gptr(s.rho)), W(gptr(s.W)), rhs_mean(s.st->b_mean),
+          rmax(s.st->rho_max), rinv(recip(s.st->rho_max)) {}
     static __device__ bool skip(const SolveState* st) { return st->done != 0; }
 };
 
 template <>
 struct IterView<float> {
-    const float* p; const float* rhs; const float* rho; float* W; float rhs_mean;
+    const POIS_GLOBAL float* p; const POIS_GLOBAL float* rhs; const POIS_GLOBAL float* rho;
+    POIS_GLOBAL float* W; float rhs_mean, rmax, rinv;
     __device__ IterView(const Slot& s)
-        : p(s.d32), rhs(s.r32), rho(s.rho32), W(s.W32), rhs_mean((float)s.st->rhs_mean32) {}
+        : p(gptr(s.d32)), rhs(gptr(s.r32)), rho(gptr(s.rho32)), W(gptr(s.W32)),
+          rhs_mean((float)s.st->rhs_mean32), rmax((float)s.st->rho_max), rinv(recip((float)s.st->rho_max)) {}
     static __device__ bool skip(const SolveState* st) {
         return st->done != 0 || st->stage != 1 || st->inner_done != 0;
     }
@@ -248,7 +300,7 @@ __device__ __forceinline__ const cpx<float>* twiddles<float>(const Tables& t, in
 // ---- P1: residual, weight, Hartley along x --------------------------------------
 // MODE 0: stencil residual from the iteration view; MODE 1: q = b (copy, for the
 // stand-alone L^+ sweep).
-template <typename T, int N, int MODE>
+template <typename T, int N, int MODE, int COEF, int WEIGHT>
 __global__ void __launch_bounds__((LineCfg<T, N>::NT))
 k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb, int nblk) {
     using C = LineCfg<T, N>;
@@ -271,14 +323,17 @@ k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb, int nblk) {
     __syncthreads();
     double acc[4] = {0.0, 0.0, 0.0, 0.0};  // sum r^2, sum bt^2, sum p, sum p^2
     const IterView<T> v(s);
-    for (int e = threadIdx.x; e < C::L * N; e += C::NT) {
+#pragma unroll 2
+    for (int it = 0; it < C::IT; ++it) {
+        const int e = threadIdx.x + it * C::NT;
         const int l = e / N, i = e % N;
         const unsigned P = line0 + l;
         cpx<T> q = {T(0), T(0)};
         if (P < nlines) {
             const unsigned r0 = 2u * P;
             if (MODE == 0) {
-                const PairOut<T> pr = pair_residual<T>(g, v.p, v.rho, v.rhs, v.rhs_mean, i, s_j0[l], s_k0[l]);
+                const PairOut<T> pr = pair_residual<T, COEF, WEIGHT>(g, v.p, v.rho, v.rhs, v.rhs_mean, v.rmax, v.rinv,
+                                                                     i, s_j0[l], s_k0[l]);
                 const CellOut<T>& a = pr.a;
                 const CellOut<T>& b = pr.b;
                 q = {a.w * a.r, b.w * b.r};
@@ -287,15 +342,17 @@ k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb, int nblk) {
                 acc[2] += (double)a.pc + (double)b.pc;
                 acc[3] += (double)a.pc * a.pc + (double)b.pc * b.pc;
             } else {
-                q = {T(s.b[r0 * N + i]), T(s.b[(r0 + 1) * N + i])};
+                q = {T(gptr(s.b)[r0 * N + i]), T(gptr(s.b)[(r0 + 1) * N + i])};
             }
         }
         lds[l * C::LS + i] = q;
     }
     __syncthreads();
     fft_block_lines<T, N>(lds, tw);
-    T* W = (MODE == 0) ? v.W : reinterpret_cast<T*>(s.W);
-    for (int e = threadIdx.x; e < C::L * N; e += C::NT) {
+    POIS_GLOBAL T* W = (MODE == 0) ? v.W : (POIS_GLOBAL T*)gptr(s.W);
+#pragma unroll
+    for (int it = 0; it < C::IT; ++it) {
+        const int e = threadIdx.x + it * C::NT;
         const int l = e / N, k = e % N;
         const unsigned P = line0 + l;
         if (P < nlines) {
@@ -338,24 +395,28 @@ k_dht_cols(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     if (MODE == 0 && IterView<T>::skip(s.st)) return;
     const cpx<T>* twg = twiddles<T>(tb, AX);
     for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
-    cpx<T>* Wc = reinterpret_cast<cpx<T>*>(MODE == 0 ? IterView<T>(s).W : reinterpret_cast<T*>(s.W));
+    POIS_GLOBAL T* Wc = MODE == 0 ? IterView<T>(s).W : (POIS_GLOBAL T*)gptr(s.W);  // complex-indexed
     const unsigned nlines = (AX == 1) ? (unsigned)(g.nxh * g.nz) : (unsigned)(g.nxh * g.ny);
     const unsigned se = (AX == 1) ? (unsigned)g.nxh : (unsigned)(g.nxh * g.ny);
     const unsigned line0 = blockIdx.x * C::L;
     line_bases<AX>(g, line0, C::L, base);
     __syncthreads();
-    for (int e = threadIdx.x; e < C::L * N; e += C::NT) {
+#pragma unroll
+    for (int it = 0; it < C::IT; ++it) {
+        const int e = threadIdx.x + it * C::NT;
         const int l = e % C::L, idx = e / C::L;
         cpx<T> q = {T(0), T(0)};
-        if (line0 + l < nlines) q = Wc[base[l] + idx * se];
+        if (line0 + l < nlines) q = gload_c(Wc, base[l] + idx * se);
         lds[l * C::LS + idx] = q;
     }
     __syncthreads();
     fft_block_lines<T, N>(lds, tw);
-    for (int e = threadIdx.x; e < C::L * N; e += C::NT) {
+#pragma unroll
+    for (int it = 0; it < C::IT; ++it) {
+        const int e = threadIdx.x + it * C::NT;
         const int l = e % C::L, idx = e / C::L;
         if (line0 + l < nlines)
-            Wc[base[l] + idx * se] = hartley(lds[l * C::LS + idx], lds[l * C::LS + (idx == 0 ? 0 : N - idx)]);
+            gstore_c(Wc, base[l] + idx * se, hartley(lds[l * C::LS + idx], lds[l * C::LS + (idx == 0 ? 0 : N - idx)]));
     }
 }
 
@@ -390,7 +451,7 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     if (MODE == 0 && IterView<T>::skip(s.st)) return;
     const cpx<T>* twg = twiddles<T>(tb, 2);
     for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
-    cpx<T>* Wc = reinterpret_cast<cpx<T>*>(MODE == 0 ? IterView<T>(s).W : reinterpret_cast<T*>(s.W));
+    POIS_GLOBAL T* Wc = MODE == 0 ? IterView<T>(s).W : (POIS_GLOBAL T*)gptr(s.W);  // complex-indexed
     const unsigned nlines = (unsigned)(g.nxh * g.ny);
     const unsigned se = (unsigned)(g.nxh * g.ny);
     const unsigned line0 = blockIdx.x * C::L;
@@ -407,10 +468,12 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
         lyj[threadIdx.x] = in ? ly[j] : T(0);
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < C::L * N; e += C::NT) {
+#pragma unroll
+    for (int it = 0; it < C::IT; ++it) {
+        const int e = threadIdx.x + it * C::NT;
         const int l = e % C::L, idx = e / C::L;
         cpx<T> q = {T(0), T(0)};
-        if (line0 + l < nlines) q = Wc[base[l] + idx * se];
+        if (line0 + l < nlines) q = gload_c(Wc, base[l] + idx * se);
         lds[l * C::LS + idx] = q;
     }
     __syncthreads();
@@ -433,10 +496,12 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     }
     __syncthreads();
     fft_block_lines<T, N>(lds, tw);
-    for (int e = threadIdx.x; e < C::L * N; e += C::NT) {
+#pragma unroll
+    for (int it = 0; it < C::IT; ++it) {
+        const int e = threadIdx.x + it * C::NT;
         const int l = e % C::L, idx = e / C::L;
         if (line0 + l < nlines)
-            Wc[base[l] + idx * se] = hartley(lds[l * C::LS + idx], lds[l * C::LS + (idx == 0 ? 0 : N - idx)]);
+            gstore_c(Wc, base[l] + idx * se, hartley(lds[l * C::LS + idx], lds[l * C::LS + (idx == 0 ? 0 : N - idx)]));
     }
 }
 
@@ -452,10 +517,12 @@ k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     if (MODE == 0 && IterView<T>::skip(s.st)) return;
     const cpx<T>* twg = twiddles<T>(tb, 0);
     for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
-    const T* W = (MODE == 0) ? IterView<T>(s).W : reinterpret_cast<const T*>(s.W);
+    const POIS_GLOBAL T* W = (MODE == 0) ? IterView<T>(s).W : (const POIS_GLOBAL T*)gptr(s.W);
     const unsigned nlines = (unsigned)(g.ny * g.nz / 2);
     const unsigned line0 = blockIdx.x * C::L;
-    for (int e = threadIdx.x; e < C::L * N; e += C::NT) {
+#pragma unroll
+    for (int it = 0; it < C::IT; ++it) {
+        const int e = threadIdx.x + it * C::NT;
         const int l = e / N, i = e % N;
         const unsigned P = line0 + l;
         cpx<T> q = {T(0), T(0)};
@@ -464,11 +531,13 @@ k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     }
     __syncthreads();
     fft_block_lines<T, N>(lds, tw);
-    T* out;
-    if constexpr (sizeof(T) == 8) out = reinterpret_cast<T*>(s.p);
-    else out = reinterpret_cast<T*>(s.d32);
+    POIS_GLOBAL T* out;
+    if constexpr (sizeof(T) == 8) out = (POIS_GLOBAL T*)gptr(s.p);
+    else out = (POIS_GLOBAL T*)gptr(s.d32);
     const T shift = (MODE == 0 && sizeof(T) == 8) ? T(s.st->p_shift) : T(0);
-    for (int e = threadIdx.x; e < C::L * N; e += C::NT) {
+#pragma unroll
+    for (int it = 0; it < C::IT; ++it) {
+        const int e = threadIdx.x + it * C::NT;
         const int l = e / N, k = e % N;
         const unsigned P = line0 + l;
         if (P < nlines) {
@@ -489,20 +558,22 @@ k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
 
 constexpr int kPtThreads = 256;
 
-__global__ void __launch_bounds__(1) k_init(const Slot* __restrict__ slots, double inner_tol, int max_iter,
-                                           int max_outer, int precision) {
+__global__ void __launch_bounds__(256) k_init(const Slot* __restrict__ slots, double inner_tol, int max_iter,
+                                             int max_outer, int precision) {
     SolveState* st = slots[blockIdx.x].st;
-    SolveState z = {};
-    z.tol = slots[blockIdx.x].tol;
-    z.inner_tol = inner_tol;
-    z.max_iter = max_iter;
-    z.max_outer = max_outer;
-    z.precision = precision;
-    z.rho_min = 0.0;
-    z.rho_max = 0.0;
-    z.status = POISSON_OK;
-    z.inv_s = 1.0;
-    *st = z;
+    // zero the whole record with vector stores, then set the parameters
+    unsigned long long* w = reinterpret_cast<unsigned long long*>(st);
+    constexpr int words = (int)(sizeof(SolveState) / sizeof(unsigned long long));
+    for (int q = threadIdx.x; q < words; q += 256) w[q] = 0ull;
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    st->tol = slots[blockIdx.x].tol;
+    st->inner_tol = inner_tol;
+    st->max_iter = max_iter;
+    st->max_outer = max_outer;
+    st->precision = precision;
+    st->status = POISSON_OK;
+    st->inv_s = 1.0;
 }
 
 // rho: min, max, validity; b: sum, sum of squares, validity; optional FP32 copy of rho.
@@ -513,13 +584,13 @@ k_setup(GridArgs g, const Slot* __restrict__ slots, int write_rho32) {
     double sb = 0.0, sb2 = 0.0, mn = INFINITY, mx = -INFINITY, bad = 0.0;
     const long long stride = (long long)gridDim.x * kPtThreads;
     for (long long c = (long long)blockIdx.x * kPtThreads + threadIdx.x; c < g.n; c += stride) {
-        const double r = s.rho[c], b = s.b[c];
+        const double r = gptr(s.rho)[c], b = gptr(s.b)[c];
         if (!(r > 0.0) || !isfinite(r) || !isfinite(b)) bad += 1.0;
         mn = fmin(mn, r);
         mx = fmax(mx, r);
         sb += b;
         sb2 += b * b;
-        if (write_rho32) s.rho32[c] = (float)r;
+        if (write_rho32) gptr(s.rho32)[c] = (float)r;
     }
     const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
     sb = wave_sum(sb); sb2 = wave_sum(sb2); bad = wave_sum(bad);
@@ -574,6 +645,9 @@ __global__ void __launch_bounds__(256) k_setup_finalize(GridArgs g, const Slot* 
         st->bad = bad > 0.0;
         // scale of the first FP32 right-hand side: near the RMS of b
         st->inv_s = 1.0 / pow2_near(sqrt(sb2 / (double)g.n));
+        // density ratio the scaled batched reciprocals of the sweeps support
+        const double max_ratio = (st->precision == POISSON_FP32_REFINE) ? 1e8 : 1e20;
+        if (!(mx <= max_ratio * mn)) bad += 1.0;
         if (bad > 0.0) {
             st->done = 1;
             st->status = POISSON_EDOMAIN;
@@ -719,9 +793,14 @@ __global__ void __launch_bounds__(256) k_finalize_inner(GridArgs g, const Slot* 
     if (rel < 0.9 * st->best_in) {
         st->best_in = rel;
         st->since_best = 0;
-    } else if (++st->since_best >= 5) {
-        stop = true;  // no 10% gain in 5 sweeps: stagnation at the FP32 rounding floor
+    } else {
+        ++st->since_best;
     }
+    // Stagnation at the FP32 rounding floor: no 10% gain in 8 sweeps after the
+    // residual has come down.  The iteration can first grow by orders of
+    // magnitude on rough density before it contracts, so no stop counts before
+    // the best residual is below half its start.
+    if (st->best_in < 0.5 && st->since_best >= 8) stop = true;
     if (t >= max_inner || st->inner_total >= st->max_iter) stop = true;
     if (stop) {
         st->inner_done = 1;
@@ -734,20 +813,18 @@ __global__ void __launch_bounds__(256) k_finalize_inner(GridArgs g, const Slot* 
 
 // ---- pointwise FP64 stencil sweeps -------------------------------------------------
 // MODE 0: out = A p (apply).  MODE 1: r = b~ - A p into a FP64 field with partial
-// norms (stand-alone residual).  MODE 2: FP32_REFINE outer residual: r32 = r inv_s,
-// d32 = 0.  Partials: sum r^2, sum bt^2, sum p, sum p^2, sum r.
+// norms (stand-alone residual).  Partials: sum r^2, sum bt^2, sum p, sum p^2, sum r.
 template <int MODE>
 __global__ void __launch_bounds__(kPtThreads)
 k_stencil(GridArgs g, const Slot* __restrict__ slots, const double* __restrict__ rho_in,
           const double* __restrict__ p_in, double* __restrict__ out) {
     __shared__ double red[(kPtThreads / 64) * 5];
     const Slot* sp = slots ? &slots[blockIdx.y] : nullptr;
-    if (MODE == 2 && (sp->st->done || sp->st->stage != 0)) return;
-    const double* rho = (MODE == 0) ? rho_in : sp->rho;
-    const double* p = (MODE == 0) ? p_in : sp->p;
-    const double* b = (MODE == 0) ? nullptr : sp->b;
+    const POIS_GLOBAL double* rho = gptr((MODE == 0) ? rho_in : sp->rho);
+    const POIS_GLOBAL double* p = gptr((MODE == 0) ? p_in : sp->p);
+    const POIS_GLOBAL double* b = (MODE == 0) ? nullptr : gptr(sp->b);
+    POIS_GLOBAL double* og = out ? gptr(out) : nullptr;
     const double bm = (MODE == 0) ? 0.0 : sp->st->b_mean;
-    const double inv_s = (MODE == 2) ? sp->st->inv_s : 1.0;
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     // rows of x: a block pass covers rpp rows (several short rows, or one long row
     // that each thread strides over); row -> (j, k) is decoded once per row
@@ -763,7 +840,7 @@ k_stencil(GridArgs g, const Slot* __restrict__ slots, const double* __restrict__
         if (MODE == 0) {
             // with no right-hand side the residual is -A p
             const CellOut<double> o = cell_residual<double>(g, p, rho, nullptr, 0.0, i, j, k);
-            out[c] = -o.r;
+            og[c] = -o.r;
         } else {
             const CellOut<double> o = cell_residual<double>(g, p, rho, b, bm, i, j, k);
             acc[0] += o.r * o.r;
@@ -771,12 +848,7 @@ k_stencil(GridArgs g, const Slot* __restrict__ slots, const double* __restrict__
             acc[2] += o.pc;
             acc[3] += o.pc * o.pc;
             acc[4] += o.r;
-            if (MODE == 1) {
-                if (out) out[c] = o.r;
-            } else {
-                sp->r32[c] = (float)(o.r * inv_s);
-                sp->d32[c] = 0.0f;
-            }
+            if (og) og[c] = o.r;
         }
     }
     if (MODE != 0) {
@@ -786,6 +858,63 @@ k_stencil(GridArgs g, const Slot* __restrict__ slots, const double* __restrict__
             o[0] = acc[0]; o[1] = acc[1]; o[2] = acc[2]; o[3] = acc[3]; o[4] = acc[4];
         }
     }
+}
+
+// FP32_REFINE outer residual in FP64 on row pairs (the layout of P1, so that the
+// neighbour rows of a block are read once from HBM): r = b~ - A p, r32 = r inv_s,
+// d32 = 0.  Partials: sum r^2, sum bt^2, sum p, sum p^2, sum r.
+constexpr int kOuterElems = 2048;  // (pair, column) elements per block
+
+template <int N, int COEF, int WEIGHT>
+__global__ void __launch_bounds__(kPtThreads) k_outer_resid(GridArgs g, const Slot* __restrict__ slots) {
+    constexpr int RPB = N >= kOuterElems ? 1 : kOuterElems / N;  // row pairs per block
+    __shared__ double red[(kPtThreads / 64) * 5];
+    __shared__ int s_j0[RPB], s_k0[RPB];
+    const Slot& s = slots[blockIdx.y];
+    SolveState* st = s.st;
+    if (st->done || st->stage != 0) return;
+    const unsigned npairs = (unsigned)(g.ny * g.nz / 2);
+    const unsigned pair0 = blockIdx.x * RPB;
+    for (int l = threadIdx.x; l < RPB; l += kPtThreads) {
+        const unsigned r0 = 2u * (pair0 + l);
+        s_j0[l] = (int)(r0 % (unsigned)g.ny);
+        s_k0[l] = (int)(r0 / (unsigned)g.ny);
+    }
+    __syncthreads();
+    const double bm = st->b_mean, inv_s = st->inv_s, rmax = st->rho_max, rinv = recip(st->rho_max);
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+    for (int e = threadIdx.x; e < RPB * N; e += kPtThreads) {
+        const int l = e / N, i = e % N;
+        const unsigned P = pair0 + l;
+        if (P >= npairs) continue;
+        const PairOut<double> pr = pair_residual<double, COEF, WEIGHT>(g, gptr(s.p), gptr(s.rho), gptr(s.b), bm, rmax,
+                                                                       rinv, i, s_j0[l], s_k0[l]);
+        const unsigned a = (2 * P) * N + i, b = a + N;
+        acc[0] += pr.a.r * pr.a.r + pr.b.r * pr.b.r;
+        acc[1] += pr.a.bt * pr.a.bt + pr.b.bt * pr.b.bt;
+        acc[2] += pr.a.pc + pr.b.pc;
+        acc[3] += pr.a.pc * pr.a.pc + pr.b.pc * pr.b.pc;
+        acc[4] += pr.a.r + pr.b.r;
+        POIS_GLOBAL float* r32 = gptr(s.r32);
+        POIS_GLOBAL float* d32 = gptr(s.d32);
+        r32[a] = (float)(pr.a.r * inv_s);
+        r32[b] = (float)(pr.b.r * inv_s);
+        d32[a] = 0.0f;
+        d32[b] = 0.0f;
+    }
+    block_sums<kPtThreads, 5>(acc, red);
+    if (threadIdx.x == 0) {
+        double* o = s.partial + (unsigned long long)blockIdx.x * kPartialStride;
+        o[0] = acc[0]; o[1] = acc[1]; o[2] = acc[2]; o[3] = acc[3]; o[4] = acc[4];
+    }
+}
+
+template <int N>
+static int blocks_outer(const GridArgs& g) {
+    constexpr int RPB = N >= kOuterElems ? 1 : kOuterElems / N;
+    const long long np = (long long)g.ny * g.nz / 2;
+    return (int)((np + RPB - 1) / RPB);
 }
 
 // FP32_REFINE outer update: p += d32 / inv_s - p_shift (FP64), then the next scale.
@@ -799,7 +928,7 @@ __global__ void __launch_bounds__(kPtThreads) k_outer_update(GridArgs g, const S
     const double shift = st->p_sum / (double)g.n;
     const unsigned n = (unsigned)g.n, stride = gridDim.x * kPtThreads;
     for (unsigned c = blockIdx.x * kPtThreads + threadIdx.x; c < n; c += stride)
-        s.p[c] = s.p[c] + (double)s.d32[c] * scale - shift;
+        gptr(s.p)[c] = gptr(s.p)[c] + (double)gptr(s.d32)[c] * scale - shift;
 }
 
 // One block per slot: between the outer update and the next outer residual.
@@ -826,7 +955,7 @@ __global__ void __launch_bounds__(kPtThreads) k_fixup(GridArgs g, const Slot* __
     const double sh = st->p_shift;
     const long long stride = (long long)gridDim.x * kPtThreads;
     for (long long c = (long long)blockIdx.x * kPtThreads + threadIdx.x; c < g.n; c += stride)
-        s.p[c] = zero ? 0.0 : s.p[c] - sh;
+        gptr(s.p)[c] = zero ? 0.0 : gptr(s.p)[c] - sh;
 }
 
 // ---- launch helpers ------------------------------------------------------------------
@@ -874,6 +1003,13 @@ static hipError_t dispatch_len(int n, F&& f) {
     }
 }
 
+// Calls f.template operator()<COEF, WEIGHT>() for the runtime modes.
+template <typename F>
+static hipError_t dispatch_op(int coef, int weight, F&& f) {
+    if (coef == 0) return weight == 0 ? f.template operator()<0, 0>() : f.template operator()<0, 1>();
+    return weight == 0 ? f.template operator()<1, 0>() : f.template operator()<1, 1>();
+}
+
 static int pt_blocks(const GridArgs& g) {
     const long long b = (g.n + kPtThreads - 1) / kPtThreads;
     return (int)(b < 4096 ? b : 4096);
@@ -895,14 +1031,19 @@ Geometry make_geometry(const GridArgs& g) {
         return hipSuccess;
     });
     geo.blocks_pt = pt_blocks(g);
-    geo.max_blocks = std::max(std::max(geo.blocks_x, geo.blocks_pt), kMaxSetupBlocks);
+    int nbo = 0;
+    (void)dispatch_len(g.nx, [&]<int N>() {
+        nbo = blocks_outer<N>(g);
+        return hipSuccess;
+    });
+    geo.max_blocks = std::max(std::max(std::max(geo.blocks_x, geo.blocks_pt), nbo), kMaxSetupBlocks);
     return geo;
 }
 
 hipError_t launch_init(const GridArgs& g, const Slot* slots, int nslots, double inner_tol, int max_iter,
                        int max_outer, int precision, hipStream_t s) {
     (void)g;
-    k_init<<<nslots, 1, 0, s>>>(slots, inner_tol, max_iter, max_outer, precision);
+    k_init<<<nslots, 256, 0, s>>>(slots, inner_tol, max_iter, max_outer, precision);
     return hipGetLastError();
 }
 
@@ -931,8 +1072,15 @@ static hipError_t sweeps(const GridArgs& g, const Tables& t, const Slot* slots, 
     int nbx = 0;
     e = dispatch_len(g.nx, [&]<int N>() {
         nbx = blocks_rows<T, N>(g);
-        k_resid_dhtx<T, N, MODE><<<dim3(nbx, nslots), LineCfg<T, N>::NT, 0, s>>>(g, slots, t, nbx);
-        return hipGetLastError();
+        if constexpr (MODE == 1) {
+            k_resid_dhtx<T, N, 1, 0, 0><<<dim3(nbx, nslots), LineCfg<T, N>::NT, 0, s>>>(g, slots, t, nbx);
+            return hipGetLastError();
+        } else {
+            return dispatch_op(g.coef, g.weight, [&]<int C, int W>() {
+                k_resid_dhtx<T, N, 0, C, W><<<dim3(nbx, nslots), LineCfg<T, N>::NT, 0, s>>>(g, slots, t, nbx);
+                return hipGetLastError();
+            });
+        }
     });
     if (e != hipSuccess) return e;
     if (MODE == 0) {
@@ -965,8 +1113,10 @@ static hipError_t one_sweep(const GridArgs& g, const Tables& t, const Slot* slot
         case 1:
             return dispatch_len(g.nx, [&]<int N>() {
                 const int nb = blocks_rows<T, N>(g);
-                k_resid_dhtx<T, N, 0><<<dim3(nb, nslots), LineCfg<T, N>::NT, 0, s>>>(g, slots, t, nb);
-                return hipGetLastError();
+                return dispatch_op(g.coef, g.weight, [&]<int C, int W>() {
+                    k_resid_dhtx<T, N, 0, C, W><<<dim3(nb, nslots), LineCfg<T, N>::NT, 0, s>>>(g, slots, t, nb);
+                    return hipGetLastError();
+                });
             });
         case 2:
             return dispatch_len(g.ny, [&]<int N>() {
@@ -998,16 +1148,23 @@ hipError_t launch_sweep(const GridArgs& g, const Tables& t, const Slot* slots, i
 hipError_t launch_iteration(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slots,
                             int nslots, bool fp32, hipStream_t s) {
     (void)geo;
-    return fp32 ? sweeps<float, 0>(g, t, slots, nslots, s, kMaxInner)
-                : sweeps<double, 0>(g, t, slots, nslots, s, kMaxInner);
+    return fp32 ? sweeps<float, 0>(g, t, slots, nslots, s, kMaxInnerPerStep)
+                : sweeps<double, 0>(g, t, slots, nslots, s, kMaxInnerPerStep);
 }
 
 hipError_t launch_outer_residual(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,
                                  hipStream_t s) {
-    k_stencil<2><<<dim3(geo.blocks_pt, nslots), kPtThreads, 0, s>>>(g, slots, nullptr, nullptr, nullptr);
-    hipError_t e = hipGetLastError();
+    (void)geo;
+    int nb = 0;
+    hipError_t e = dispatch_len(g.nx, [&]<int N>() {
+        nb = blocks_outer<N>(g);
+        return dispatch_op(g.coef, g.weight, [&]<int C, int W>() {
+            k_outer_resid<N, C, W><<<dim3(nb, nslots), kPtThreads, 0, s>>>(g, slots);
+            return hipGetLastError();
+        });
+    });
     if (e != hipSuccess) return e;
-    k_finalize_outer<<<nslots, 256, 0, s>>>(g, slots, geo.blocks_pt);
+    k_finalize_outer<<<nslots, 256, 0, s>>>(g, slots, nb);
     return hipGetLastError();
 }
 
@@ -1039,7 +1196,7 @@ hipError_t launch_residual(const GridArgs& g, const Geometry& geo, const Slot* s
 hipError_t launch_lap_pinv(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slot,
                            hipStream_t s) {
     (void)geo;
-    return sweeps<double, 1>(g, t, slot, 1, s, kMaxInner);
+    return sweeps<double, 1>(g, t, slot, 1, s, kMaxInnerPerStep);
 }
 
 }  // namespace pois

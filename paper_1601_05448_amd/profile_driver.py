@@ -1,0 +1,53 @@
+"""Launches for profiling under rocprofv3: every sweep of the iteration alone
+(FP64 and FP32), one full solve per path, and a device copy of known size that
+calibrates the HBM byte counters.
+
+    python -m paper_1601_05448_amd.profile_driver --size 256 --reps 5
+"""
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--paths", default="fp64,fp32")
+    args = ap.parse_args()
+
+    import torch
+
+    from paper_1601_05448_amd import inputs
+    from paper_1601_05448_amd import poisson as P
+
+    torch.cuda.set_device(0)
+    prob = inputs.workload2(args.size)
+    rho = torch.from_numpy(prob.rho).cuda()
+    b = torch.from_numpy(prob.b).cuda()
+    p = torch.zeros(prob.shape, dtype=torch.float64, device="cuda")
+    for name in args.paths.split(","):
+        prec = P.POISSON_FP64 if name == "fp64" else P.POISSON_FP32_REFINE
+        with P.Solver(prob.shape, prob.lengths, precision=prec) as s:
+            for sw in (1, 2, 3, 5):
+                ms = P.poisson_time_sweep(s.h, sw, prec == P.POISSON_FP32_REFINE, rho, b, p, args.reps)
+                print(f"{name} sweep {sw}: {ms * 1e3:.1f} us", flush=True)
+            p.zero_()
+            st = s.solve(rho, b, p, 1e-10)
+            print(f"{name} solve: {st['ms']:.3f} ms iters {st['iters']} outer {st['outer_iters']}", flush=True)
+    n = args.copy_mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"copy: {args.copy_mib} MiB read + {args.copy_mib} MiB written per launch", flush=True)
+
+
+if __name__ == "__main__":
+    main()

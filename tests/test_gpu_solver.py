@@ -183,7 +183,7 @@ def test_constant_b_gives_zero():
     assert np.all(p == 0.0)
 
 
-@pytest.mark.parametrize("bad", ["rho_negative", "rho_zero", "rho_nan", "b_inf"])
+@pytest.mark.parametrize("bad", ["rho_negative", "rho_zero", "rho_nan", "b_inf", "ratio"])
 def test_invalid_fields_edomain_and_p_untouched(bad):
     announce("edomain", bad)
     prob = inputs.small_problem()
@@ -193,13 +193,26 @@ def test_invalid_fields_edomain_and_p_untouched(bad):
         prob.rho[0, 0, 0] = 0.0
     elif bad == "rho_nan":
         prob.rho[1, 1, 1] = np.nan
-    else:
+    elif bad == "b_inf":
         prob.b[2, 2, 2] = np.inf
+    else:  # density ratio beyond what the scaled reciprocals of the sweeps support
+        prob.rho[4, 4, 4] = prob.rho.max() * 1e21
     p0 = np.random.default_rng(1).standard_normal(prob.shape)
     for prec in (P.POISSON_FP64, P.POISSON_FP32_REFINE):
         p, st, _ = _solve_gpu(prob, precision=prec, p0=p0)
         assert st["code"] == P.POISSON_EDOMAIN
         assert np.array_equal(p, p0)
+
+
+def test_large_density_ratio_within_limits():
+    """Ratios up to the documented limits solve (1e6 FP64 with the face average
+    of rho; 1e6 FP32_REFINE with the diagonal weight)."""
+    announce("large ratio")
+    prob = inputs.small_problem(shape=(16, 16, 16), lengths=(TWO_PI,) * 3, ratio=1e6)
+    ref = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, weight=1, tol=1e-13)
+    for prec in (P.POISSON_FP64, P.POISSON_FP32_REFINE):
+        p, st, _ = _solve_gpu(prob, precision=prec, weight=1, max_iter=5000)
+        _check_solution(prob, p, st, ref["p"])
 
 
 def test_iteration_cap_returns_last_iterate():
