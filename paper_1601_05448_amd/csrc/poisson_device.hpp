@@ -1,0 +1,353 @@
+// Device-side helpers shared by the sweep kernels (poisson_sweeps.hip) and the
+// control and pointwise kernels (poisson_kernels.hip) of libpoisson.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "../../include/poisson.h"
+#include "poisson_fft.hpp"
+#include "poisson_internal.hpp"
+
+namespace pois {
+
+// Field pointers reach the kernels through the slot records, so the compiler
+// sees them as generic (flat) pointers that might alias LDS, which stops it from
+// hoisting global loads above LDS stores.  Every field access goes through the
+// global address space instead.
+#define POIS_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ POIS_GLOBAL T* gptr(T* p) {
+    return (POIS_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ const POIS_GLOBAL T* gptr(const T* p) {
+    return (const POIS_GLOBAL T*)p;
+}
+
+// Complex values in global memory as native two-element vectors (one 8- or
+// 16-byte access each).
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec2<float> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+template <typename T>
+__device__ __forceinline__ cpx<T> gload_c(const POIS_GLOBAL T* base, unsigned idx) {
+    const typename Vec2<T>::type v = ((const POIS_GLOBAL typename Vec2<T>::type*)base)[idx];
+    return {v.x, v.y};
+}
+template <typename T>
+__device__ __forceinline__ void gstore_c(POIS_GLOBAL T* base, unsigned idx, cpx<T> c) {
+    typename Vec2<T>::type v;
+    v.x = c.x;
+    v.y = c.y;
+    ((POIS_GLOBAL typename Vec2<T>::type*)base)[idx] = v;
+}
+
+// ---- stencil ------------------------------------------------------------------
+// Face coefficients (the paper does not write the discrete operator out):
+//   COEF 0: beta = 2 / (rho_a + rho_b)      1/rho with rho averaged to the face
+//   COEF 1: beta = (1/rho_a + 1/rho_b) / 2  face average of 1/rho
+// The reciprocals of a cell pair come from one hardware reciprocal refined by
+// Newton steps (Montgomery's batch trick), branch-free: the values are first
+// scaled by 1/rho_max into (0, 2], so that the running products stay normal
+// (FP64: one batch, density ratio up to 1e20; FP32: batches of at most four,
+// ratio up to 1e8; the set-up rejects larger ratios).
+
+__device__ __forceinline__ double recip(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+__device__ __forceinline__ float recip(float x) {
+    float y = __builtin_amdgcn_rcpf(x);
+    const float e = fmaf(-x, y, 1.0f);
+    return fmaf(y, e, y);
+}
+
+// d[k] <- 1 / d[k], k < K, with one reciprocal
+template <typename T, int K>
+__device__ __forceinline__ void batch_recip(T* d) {
+    T pre[K];
+    pre[0] = d[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k) pre[k] = pre[k - 1] * d[k];
+    T inv = recip(pre[K - 1]);
+#pragma unroll
+    for (int k = K - 1; k > 0; --k) {
+        const T r = inv * pre[k - 1];
+        inv = inv * d[k];
+        d[k] = r;
+    }
+    d[0] = inv;
+}
+
+template <typename T, int K, int OFF>
+__device__ __forceinline__ void recip_groups(T* d) {
+    if constexpr (OFF < K) {
+        constexpr int G = (sizeof(T) == 8) ? K : ((K - OFF) < 4 ? (K - OFF) : 4);
+        batch_recip<T, G>(d + OFF);
+        recip_groups<T, K, OFF + G>(d);
+    }
+}
+
+// reciprocals of K values that the caller scaled into (0, 2]
+template <typename T, int K>
+__device__ __forceinline__ void scaled_recips(T (&d)[K]) {
+    recip_groups<T, K, 0>(d);
+}
+
+template <typename T>
+struct CellOut {
+    T r, w, bt, pc;
+};
+template <typename T>
+struct PairOut {
+    CellOut<T> a, b;
+};
+
+// The 26 inputs of a row pair: the two cells (i, j0, k0) and (i, j0 + 1, k0)
+// (j0 even) and their neighbours.  Fetching them is separate from evaluating
+// them so that a sweep can keep one pair's loads in flight while it evaluates
+// the previous pair.
+template <typename T>
+struct PairIn {
+    // densities and pressures at: a, b, a x-, a x+, b x-, b x+, a y-, b y+, a z-, a z+, b z-, b z+
+    T r[12], q[12];
+    T ba, bb;  // right-hand side at a, b
+};
+
+// 32-bit indices (grids up to 2^31 cells), periodic neighbours.
+template <typename T>
+__device__ __forceinline__ void pair_fetch(const GridArgs& g, const POIS_GLOBAL T* __restrict__ p,
+                                           const POIS_GLOBAL T* __restrict__ rho,
+                                           const POIS_GLOBAL T* __restrict__ rhs, int i, int j0, int k0,
+                                           PairIn<T>& in) {
+    const unsigned nx = g.nx, ny = g.ny, nz = g.nz, sz = nx * ny;
+    const unsigned a = ((unsigned)k0 * ny + j0) * nx + i, b = a + nx;
+    const unsigned axm = (i == 0) ? a + (nx - 1) : a - 1;
+    const unsigned axp = (i + 1 == g.nx) ? a - (nx - 1) : a + 1;
+    const unsigned bxm = axm + nx, bxp = axp + nx;
+    const unsigned aym = (j0 == 0) ? a + (ny - 1) * nx : a - nx;
+    const unsigned byp = (j0 + 2 == g.ny) ? b - (ny - 1) * nx : b + nx;
+    const unsigned azm = (k0 == 0) ? a + (nz - 1) * sz : a - sz, bzm = azm + nx;
+    const unsigned azp = (k0 + 1 == g.nz) ? a - (nz - 1) * sz : a + sz, bzp = azp + nx;
+    const unsigned at[12] = {a, b, axm, axp, bxm, bxp, aym, byp, azm, azp, bzm, bzp};
+#pragma unroll
+    for (int k = 0; k < 12; ++k) in.r[k] = rho[at[k]];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) in.q[k] = p[at[k]];
+    in.ba = rhs[a];
+    in.bb = rhs[b];
+}
+
+// Residual b~ - A p and weight w of the pair; its 11 faces (a x-, a x+, a y-,
+// a|b, a z-, a z+, b x-, b x+, b y+, b z-, b z+) share one batched reciprocal.
+// rmax = max rho, rinv = 1 / rmax.
+template <typename T, int COEF, int WEIGHT>
+__device__ __forceinline__ PairOut<T> pair_eval(const GridArgs& g, const PairIn<T>& in, T rhs_mean, T rmax,
+                                                T rinv) {
+    const T* r = in.r;
+    const T* q = in.q;
+    T be[11];
+    if constexpr (COEF == 0) {
+        T d[11] = {r[2] + r[0], r[0] + r[3], r[6] + r[0], r[0] + r[1], r[8] + r[0], r[0] + r[9],
+                   r[4] + r[1], r[1] + r[5], r[1] + r[7], r[10] + r[1], r[1] + r[11]};
+#pragma unroll
+        for (int f = 0; f < 11; ++f) d[f] *= rinv;
+        scaled_recips(d);
+        const T c = T(2) * rinv;
+#pragma unroll
+        for (int f = 0; f < 11; ++f) be[f] = c * d[f];
+    } else {
+        T v[12];
+#pragma unroll
+        for (int k = 0; k < 12; ++k) v[k] = r[k] * rinv;
+        scaled_recips(v);  // rmax / rho
+        const T c = T(0.5) * rinv;
+        be[0] = c * (v[2] + v[0]);  be[1] = c * (v[0] + v[3]);  be[2] = c * (v[6] + v[0]);
+        be[3] = c * (v[0] + v[1]);  be[4] = c * (v[8] + v[0]);  be[5] = c * (v[0] + v[9]);
+        be[6] = c * (v[4] + v[1]);  be[7] = c * (v[1] + v[5]);  be[8] = c * (v[1] + v[7]);
+        be[9] = c * (v[10] + v[1]); be[10] = c * (v[1] + v[11]);
+    }
+    const T pa = q[0], pb = q[1];
+    const T hx = T(g.ihx2), hy = T(g.ihy2), hz = T(g.ihz2);
+    const T gy = be[3] * (pb - pa);  // flux through the shared face
+    const T apa = (be[1] * (q[3] - pa) - be[0] * (pa - q[2])) * hx + (gy - be[2] * (pa - q[6])) * hy +
+                  (be[5] * (q[9] - pa) - be[4] * (pa - q[8])) * hz;
+    const T apb = (be[7] * (q[5] - pb) - be[6] * (pb - q[4])) * hx + (be[8] * (q[7] - pb) - gy) * hy +
+                  (be[10] * (q[11] - pb) - be[9] * (pb - q[10])) * hz;
+    PairOut<T> o;
+    o.a.bt = in.ba - rhs_mean;
+    o.b.bt = in.bb - rhs_mean;
+    o.a.pc = pa;
+    o.b.pc = pb;
+    o.a.r = o.a.bt - apa;
+    o.b.r = o.b.bt - apb;
+    if constexpr (WEIGHT == 0) {
+        o.a.w = r[0];
+        o.b.w = r[1];
+    } else {
+        // w = 6 / (sum of the six face coefficients); sum * rmax / 6 lies in [1, rmax/rmin]
+        const T c = rmax * T(1.0 / 6.0);
+        T sw[2] = {(be[0] + be[1] + be[2] + be[3] + be[4] + be[5]) * c,
+                   (be[6] + be[7] + be[3] + be[8] + be[9] + be[10]) * c};
+        batch_recip<T, 2>(sw);
+        o.a.w = rmax * sw[0];
+        o.b.w = rmax * sw[1];
+    }
+    return o;
+}
+
+// One cell, plain IEEE divisions: the stand-alone operator and residual sweeps
+// (parity checks), which need no state and are off the iteration's path.
+template <typename T>
+__device__ __forceinline__ T face_beta(int coef, T ra, T rb) {
+    return coef == 0 ? T(2) / (ra + rb) : (ra + rb) / (T(2) * ra * rb);
+}
+
+template <typename T>
+__device__ __forceinline__ CellOut<T> cell_residual(const GridArgs& g, const POIS_GLOBAL T* __restrict__ p,
+                                                    const POIS_GLOBAL T* __restrict__ rho,
+                                                    const POIS_GLOBAL T* __restrict__ rhs, T rhs_mean, int i,
+                                                    int j, int k) {
+    const unsigned nx = g.nx, ny = g.ny, nz = g.nz, sz = nx * ny;
+    const unsigned c = ((unsigned)k * ny + j) * nx + i;
+    const unsigned cxm = (i == 0) ? c + (nx - 1) : c - 1;
+    const unsigned cxp = (i + 1 == g.nx) ? c - (nx - 1) : c + 1;
+    const unsigned cym = (j == 0) ? c + (ny - 1) * nx : c - nx;
+    const unsigned cyp = (j + 1 == g.ny) ? c - (ny - 1) * nx : c + nx;
+    const unsigned czm = (k == 0) ? c + (nz - 1) * sz : c - sz;
+    const unsigned czp = (k + 1 == g.nz) ? c - (nz - 1) * sz : c + sz;
+    const T rc = rho[c];
+    const T bxm = face_beta<T>(g.coef, rho[cxm], rc), bxp = face_beta<T>(g.coef, rc, rho[cxp]);
+    const T bym = face_beta<T>(g.coef, rho[cym], rc), byp = face_beta<T>(g.coef, rc, rho[cyp]);
+    const T bzm = face_beta<T>(g.coef, rho[czm], rc), bzp = face_beta<T>(g.coef, rc, rho[czp]);
+    CellOut<T> o;
+    o.bt = rhs ? rhs[c] - rhs_mean : T(0);
+    const T pc = p[c];
+    o.pc = pc;
+    const T ap = (bxp * (p[cxp] - pc) - bxm * (pc - p[cxm])) * T(g.ihx2) +
+                 (byp * (p[cyp] - pc) - bym * (pc - p[cym])) * T(g.ihy2) +
+                 (bzp * (p[czp] - pc) - bzm * (pc - p[czm])) * T(g.ihz2);
+    o.r = o.bt - ap;
+    o.w = (g.weight == 0) ? rc : T(6) / (bxm + bxp + bym + byp + bzm + bzp);
+    return o;
+}
+
+// Block-wide deterministic sum of K values; result valid in thread 0.
+template <int NT, int K>
+__device__ __forceinline__ void block_sums(double (&v)[K], double* red) {
+    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const double s = wave_sum(v[q]);
+        if (lane == 0) red[w * K + q] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            double s = 0.0;
+            for (int u = 0; u < NT / 64; ++u) s += red[u * K + q];
+            v[q] = s;
+        }
+    }
+}
+
+template <typename T>
+struct IterView;
+
+template <>
+struct IterView<double> {
+    const POIS_GLOBAL double* p; const POIS_GLOBAL double* rhs; const POIS_GLOBAL double* rho;
+    POIS_GLOBAL double* W; double rhs_mean, rmax, rinv;
+    __device__ IterView(const Slot& s)
+        : p(gptr(s.p)), rhs(gptr(s.b)), rho(gptr(s.rho)), W(gptr(s.W)), rhs_mean(s.st->b_mean),
+          rmax(s.st->rho_max), rinv(recip(s.st->rho_max)) {}
+    static __device__ bool skip(const SolveState* st) { return st->done != 0; }
+};
+
+template <>
+struct IterView<float> {
+    const POIS_GLOBAL float* p; const POIS_GLOBAL float* rhs; const POIS_GLOBAL float* rho;
+    POIS_GLOBAL float* W; float rhs_mean, rmax, rinv;
+    __device__ IterView(const Slot& s)
+        : p(gptr(s.d32)), rhs(gptr(s.r32)), rho(gptr(s.rho32)), W(gptr(s.W32)),
+          rhs_mean((float)s.st->rhs_mean32), rmax((float)s.st->rho_max), rinv(recip((float)s.st->rho_max)) {}
+    static __device__ bool skip(const SolveState* st) {
+        return st->done != 0 || st->stage != 1 || st->inner_done != 0;
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ const cpx<T>* twiddles(const Tables& t, int axis);
+template <>
+__device__ __forceinline__ const cpx<double>* twiddles<double>(const Tables& t, int axis) {
+    return reinterpret_cast<const cpx<double>*>(axis == 0 ? t.twx : axis == 1 ? t.twy : t.twz);
+}
+template <>
+__device__ __forceinline__ const cpx<float>* twiddles<float>(const Tables& t, int axis) {
+    return reinterpret_cast<const cpx<float>*>(axis == 0 ? t.twx32 : axis == 1 ? t.twy32 : t.twz32);
+}
+
+template <typename T>
+__device__ __forceinline__ const T* symbol(const Tables& t, int axis);
+template <>
+__device__ __forceinline__ const double* symbol<double>(const Tables& t, int axis) {
+    return axis == 0 ? t.lamx : axis == 1 ? t.lamy : t.lamz;
+}
+template <>
+__device__ __forceinline__ const float* symbol<float>(const Tables& t, int axis) {
+    return axis == 0 ? t.lamx32 : axis == 1 ? t.lamy32 : t.lamz32;
+}
+
+// 1 / (n (lx + ly + lz)), 0 for the constant mode (the zero-mean gauge)
+template <typename T>
+__device__ __forceinline__ T inv_symbol(T lx, T ly, T lz, T n) {
+    const T lam = lx + ly + lz;
+    return lam == T(0) ? T(0) : recip(n * lam);
+}
+
+// Calls f.template operator()<N>() for the runtime length n.
+template <typename F>
+inline hipError_t dispatch_len(int n, F&& f) {
+    switch (n) {
+        case 4: return f.template operator()<4>();
+        case 6: return f.template operator()<6>();
+        case 8: return f.template operator()<8>();
+        case 12: return f.template operator()<12>();
+        case 16: return f.template operator()<16>();
+        case 24: return f.template operator()<24>();
+        case 32: return f.template operator()<32>();
+        case 48: return f.template operator()<48>();
+        case 64: return f.template operator()<64>();
+        case 96: return f.template operator()<96>();
+        case 128: return f.template operator()<128>();
+        case 192: return f.template operator()<192>();
+        case 256: return f.template operator()<256>();
+        case 384: return f.template operator()<384>();
+        case 512: return f.template operator()<512>();
+        case 768: return f.template operator()<768>();
+        case 1024: return f.template operator()<1024>();
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Calls f.template operator()<COEF, WEIGHT>() for the runtime modes.
+template <typename F>
+inline hipError_t dispatch_op(int coef, int weight, F&& f) {
+    if (coef == 0) return weight == 0 ? f.template operator()<0, 0>() : f.template operator()<0, 1>();
+    return weight == 0 ? f.template operator()<1, 0>() : f.template operator()<1, 1>();
+}
+
+
+}  // namespace pois

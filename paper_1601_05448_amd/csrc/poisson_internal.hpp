@@ -92,10 +92,9 @@ struct Tables {
 
 // Launch geometry of the sweeps of one grid (host side).
 struct Geometry {
-    int blocks_x;      // row-pair line groups (x transforms)
-    int blocks_y;      // column line groups for the y transform
-    int blocks_z;      // column line groups for the z transform
+    int blocks_x;      // row-pair line groups of the x sweep (most blocks P1 can use)
     int blocks_pt;     // pointwise kernels
+    int blocks_outer;  // FP64 outer residual
     int max_blocks;    // partial-sum capacity needed
 };
 
@@ -119,6 +118,12 @@ hipError_t launch_iteration(const GridArgs& g, const Geometry& geo, const Tables
 // One sweep alone (1: P1, 2: P2 and P4, 3: P3, 5: P5), for timing.
 hipError_t launch_sweep(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32, int which,
                         hipStream_t s);
+// poisson_sweeps.hip: one sweep; mode 0 iteration, mode 1 the stand-alone L^+ q
+// sweep (FP64).  *nblocks (may be NULL) receives the grid width, i.e. the
+// number of partial sums P1 wrote.
+hipError_t launch_sweep_mode(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32, int which,
+                             int mode, hipStream_t s, int* nblocks);
+unsigned sweep_groups_x(const GridArgs& g);
 // FP32_REFINE outer step pieces.
 hipError_t launch_outer_residual(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,
                                  hipStream_t s);

@@ -1,0 +1,448 @@
+// The four field sweeps of one iteration of the paper's method (section
+// "Poisson equation", eq. (Pois)), written for gfx950:
+//   P1 k_resid_dhtx   r = b~ - A p, q = w r, partial norms, Hartley along x -> W
+//   P2 k_dht_cols     Hartley along y of W (also P4: the transform is self-inverse)
+//   P3 k_dht_z_solve  Hartley along z, divide by n * symbol, Hartley along z
+//   P5 k_dhtx_update  Hartley along x, p += dp (minus the mean of p)
+//
+// Each block holds L whole lines of its transform direction in LDS.  The LDS a
+// line group needs limits an FP64 sweep to two blocks per CU, too few waves to
+// hide HBM latency by occupancy alone, so the blocks are persistent and
+// software-pipelined: a block loops over line groups, and the global loads of
+// the next group (and, in the FP32 P5, the loads of the values to update) are
+// issued before the FFT of the current group, so that they are in flight while
+// the block works in LDS.  P1 evaluates its stencil one row pair behind its loads for the
+// same reason.
+//
+// blockIdx.y selects the solve (slot) of a batch of equal-size grids; every sweep
+// returns at once for solves that are done.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <unordered_map>
+
+#include "poisson_device.hpp"
+
+namespace pois {
+
+// ---- P1: residual, weight, Hartley along x --------------------------------------
+// MODE 0: stencil residual of the iteration view; MODE 1: q = b (copy, for the
+// stand-alone L^+ sweep).
+template <typename T, int N, int MODE, int COEF, int WEIGHT>
+__global__ void __launch_bounds__((LineCfg<T, N>::NT))
+k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
+    using C = LineCfg<T, N>;
+    __shared__ cpx<T> lds[C::L * C::LS];
+    __shared__ cpx<T> tw[N];
+    __shared__ double red[(C::NT / 64) * 4];
+    const Slot& s = slots[blockIdx.y];
+    if (MODE == 0 && IterView<T>::skip(s.st)) return;
+    const cpx<T>* twg = twiddles<T>(tb, 0);
+    for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
+
+    const unsigned nlines = (unsigned)(g.ny * g.nz / 2);
+    const unsigned ngroups = (nlines + C::L - 1) / C::L;
+    const IterView<T> v(s);
+    POIS_GLOBAL T* W = (MODE == 0) ? v.W : (POIS_GLOBAL T*)gptr(s.W);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};  // sum r^2, sum bt^2, sum p, sum p^2
+
+    // element `it` of this thread in a group: line (tid + it NT) / N, column (tid + it NT) % N
+    auto fetch = [&](unsigned grp, int it, PairIn<T>& in) {
+        const int e = threadIdx.x + it * C::NT;
+        const unsigned P = grp * C::L + e / N;
+        if (P < nlines) {
+            const unsigned r0 = 2u * P;  // first row of the pair, k*ny + j
+            pair_fetch<T>(g, v.p, v.rho, v.rhs, e % N, (int)(r0 % (unsigned)g.ny), (int)(r0 / (unsigned)g.ny), in);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 12; ++k) {
+                in.r[k] = T(1);
+                in.q[k] = T(0);
+            }
+            in.ba = in.bb = T(0);
+        }
+    };
+    auto evaluate = [&](unsigned grp, int it, const PairIn<T>& in) {
+        const int e = threadIdx.x + it * C::NT;
+        const int l = e / N, i = e % N;
+        cpx<T> qv = {T(0), T(0)};
+        if (grp * C::L + l < nlines) {
+            const PairOut<T> o = pair_eval<T, COEF, WEIGHT>(g, in, v.rhs_mean, v.rmax, v.rinv);
+            qv = {o.a.w * o.a.r, o.b.w * o.b.r};
+            acc[0] += (double)o.a.r * o.a.r + (double)o.b.r * o.b.r;
+            acc[1] += (double)o.a.bt * o.a.bt + (double)o.b.bt * o.b.bt;
+            acc[2] += (double)o.a.pc + (double)o.b.pc;
+            acc[3] += (double)o.a.pc * o.a.pc + (double)o.b.pc * o.b.pc;
+        }
+        lds[l * C::LS + i] = qv;
+    };
+
+    unsigned grp = blockIdx.x;
+    PairIn<T> A, B;
+    if (MODE == 0) fetch(grp, 0, A);
+    while (true) {
+        if (MODE == 0) {
+            // two row pairs per step, each evaluated while the next one's loads fly
+            for (int it = 0; it < C::IT; it += 2) {
+                fetch(grp, it + 1, B);
+                evaluate(grp, it, A);
+                const bool last = it + 2 >= C::IT;
+                const unsigned ng = last ? grp + gridDim.x : grp;
+                if (ng < ngroups) fetch(ng, last ? 0 : it + 2, A);
+                evaluate(grp, it + 1, B);
+            }
+        } else {
+#pragma unroll
+            for (int it = 0; it < C::IT; ++it) {
+                const int e = threadIdx.x + it * C::NT;
+                const int l = e / N, i = e % N;
+                const unsigned P = grp * C::L + l;
+                const POIS_GLOBAL double* q = gptr(s.b);
+                lds[l * C::LS + i] = (P < nlines) ? cpx<T>{T(q[(2 * P) * N + i]), T(q[(2 * P + 1) * N + i])}
+                                                  : cpx<T>{T(0), T(0)};
+            }
+        }
+        __syncthreads();
+        fft_block_lines<T, N>(lds, tw);
+#pragma unroll
+        for (int it = 0; it < C::IT; ++it) {
+            const int e = threadIdx.x + it * C::NT;
+            const int l = e / N, k = e % N;
+            const unsigned P = grp * C::L + l;
+            if (P < nlines) {
+                const cpx<T> h = hartley(lds[l * C::LS + k], lds[l * C::LS + (k == 0 ? 0 : N - k)]);
+                W[(2 * P) * N + k] = h.x;
+                W[(2 * P + 1) * N + k] = h.y;
+            }
+        }
+        grp += gridDim.x;
+        if (grp >= ngroups) break;
+        __syncthreads();  // the next group overwrites the lines
+    }
+    if (MODE == 0) {
+        block_sums<C::NT, 4>(acc, red);
+        if (threadIdx.x == 0) {
+            double* out = s.partial + (unsigned long long)blockIdx.x * kPartialStride;
+            out[0] = acc[0]; out[1] = acc[1]; out[2] = acc[2]; out[3] = acc[3];
+        }
+    }
+}
+
+// ---- P2 / P4: Hartley along y (AX = 1) of the pair-packed columns -------------
+// Line = (o, m): complex column m (real columns 2m, 2m+1) at outer index o;
+// element e along the axis.  y: address (o*ny + e)*nxh + m; z: (e*ny + o)*nxh + m.
+// Thread t of a block always works on line t % L of the group, elements
+// t / L + it TT.
+template <int AX>
+__device__ __forceinline__ unsigned col_base(const GridArgs& g, unsigned line) {
+    const unsigned nxh = g.nxh, o = line / nxh, m = line - o * nxh;
+    return (AX == 1) ? o * (unsigned)g.ny * nxh + m : o * nxh + m;
+}
+
+template <typename T, int N, int AX, int MODE>
+__global__ void __launch_bounds__((LineCfg<T, N>::NT))
+k_dht_cols(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
+    using C = LineCfg<T, N>;
+    __shared__ cpx<T> lds[C::L * C::LS];
+    __shared__ cpx<T> tw[N];
+    const Slot& s = slots[blockIdx.y];
+    if (MODE == 0 && IterView<T>::skip(s.st)) return;
+    const cpx<T>* twg = twiddles<T>(tb, AX);
+    for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
+    POIS_GLOBAL T* Wc = MODE == 0 ? IterView<T>(s).W : (POIS_GLOBAL T*)gptr(s.W);  // complex-indexed
+    const unsigned nlines = (AX == 1) ? (unsigned)(g.nxh * g.nz) : (unsigned)(g.nxh * g.ny);
+    const unsigned ngroups = (nlines + C::L - 1) / C::L;
+    const unsigned se = (AX == 1) ? (unsigned)g.nxh : (unsigned)(g.nxh * g.ny);
+    const int l = threadIdx.x % C::L, e0 = threadIdx.x / C::L;
+
+    cpx<T> buf[C::IT];
+    auto load = [&](unsigned grp, bool& valid, unsigned& base) {
+        const unsigned line = grp * C::L + l;
+        valid = line < nlines;
+        base = valid ? col_base<AX>(g, line) : 0u;
+#pragma unroll
+        for (int it = 0; it < C::IT; ++it)
+            buf[it] = valid ? gload_c(Wc, base + (unsigned)(e0 + it * C::TT) * se) : cpx<T>{T(0), T(0)};
+    };
+    unsigned grp = blockIdx.x, base;
+    bool valid;
+    load(grp, valid, base);
+    while (true) {
+#pragma unroll
+        for (int it = 0; it < C::IT; ++it) lds[l * C::LS + e0 + it * C::TT] = buf[it];
+        const bool cur_valid = valid;
+        const unsigned cur_base = base;
+        const unsigned ng = grp + gridDim.x;
+        if (ng < ngroups) load(ng, valid, base);  // in flight during the FFT
+        __syncthreads();
+        fft_block_lines<T, N>(lds, tw);
+        if (cur_valid) {
+#pragma unroll
+            for (int it = 0; it < C::IT; ++it) {
+                const int idx = e0 + it * C::TT;
+                gstore_c(Wc, cur_base + (unsigned)idx * se,
+                         hartley(lds[l * C::LS + idx], lds[l * C::LS + (idx == 0 ? 0 : N - idx)]));
+            }
+        }
+        grp = ng;
+        if (grp >= ngroups) break;
+        __syncthreads();
+    }
+}
+
+// ---- P3: Hartley along z, divide by n * symbol, Hartley along z ----------------
+template <typename T, int N, int MODE>
+__global__ void __launch_bounds__((LineCfg<T, N>::NT))
+k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
+    using C = LineCfg<T, N>;
+    __shared__ cpx<T> lds[C::L * C::LS];
+    __shared__ cpx<T> tw[N];
+    const Slot& s = slots[blockIdx.y];
+    if (MODE == 0 && IterView<T>::skip(s.st)) return;
+    const cpx<T>* twg = twiddles<T>(tb, 2);
+    for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
+    POIS_GLOBAL T* Wc = MODE == 0 ? IterView<T>(s).W : (POIS_GLOBAL T*)gptr(s.W);  // complex-indexed
+    const unsigned nlines = (unsigned)(g.nxh * g.ny);
+    const unsigned ngroups = (nlines + C::L - 1) / C::L;
+    const unsigned se = (unsigned)(g.nxh * g.ny);
+    const int l = threadIdx.x % C::L, e0 = threadIdx.x / C::L;
+    const T* lamx = symbol<T>(tb, 0);
+    const T* lamy = symbol<T>(tb, 1);
+    const T* lamz = symbol<T>(tb, 2);
+    const T nn = T(g.n);
+
+    cpx<T> buf[C::IT];
+    auto load = [&](unsigned grp, bool& valid, unsigned& base) {
+        const unsigned line = grp * C::L + l;
+        valid = line < nlines;
+        base = valid ? col_base<2>(g, line) : 0u;
+#pragma unroll
+        for (int it = 0; it < C::IT; ++it)
+            buf[it] = valid ? gload_c(Wc, base + (unsigned)(e0 + it * C::TT) * se) : cpx<T>{T(0), T(0)};
+    };
+    unsigned grp = blockIdx.x, base;
+    bool valid;
+    load(grp, valid, base);
+    while (true) {
+#pragma unroll
+        for (int it = 0; it < C::IT; ++it) lds[l * C::LS + e0 + it * C::TT] = buf[it];
+        const bool cur_valid = valid;
+        const unsigned cur_base = base;
+        // symbol of this thread's line: x wavenumbers 2m, 2m+1 (the pair), y wavenumber j
+        const unsigned line = grp * C::L + l;
+        const unsigned j = cur_valid ? line / (unsigned)g.nxh : 0u, m = cur_valid ? line - j * (unsigned)g.nxh : 0u;
+        const T lxe = lamx[2 * m], lxo = lamx[2 * m + 1], lyj = lamy[j];
+        const unsigned ng = grp + gridDim.x;
+        if (ng < ngroups) load(ng, valid, base);  // in flight during the two FFTs
+        __syncthreads();
+        fft_block_lines<T, N>(lds, tw);
+        // Hartley coefficients of the pairs (k, N-k) of this thread's line, scaled by 1/(n lambda)
+        for (int k = e0; k <= N / 2; k += C::TT) {
+            const int km = (k == 0) ? 0 : N - k;
+            const cpx<T> zk = lds[l * C::LS + k], zm = lds[l * C::LS + km];
+            cpx<T> hk = hartley(zk, zm), hm = hartley(zm, zk);
+            const T lzk = lamz[k], lzm = lamz[km];
+            hk.x *= inv_symbol(lxe, lyj, lzk, nn);
+            hk.y *= inv_symbol(lxo, lyj, lzk, nn);
+            hm.x *= inv_symbol(lxe, lyj, lzm, nn);
+            hm.y *= inv_symbol(lxo, lyj, lzm, nn);
+            lds[l * C::LS + k] = hk;
+            lds[l * C::LS + km] = hm;
+        }
+        __syncthreads();
+        fft_block_lines<T, N>(lds, tw);
+        if (cur_valid) {
+#pragma unroll
+            for (int it = 0; it < C::IT; ++it) {
+                const int idx = e0 + it * C::TT;
+                gstore_c(Wc, cur_base + (unsigned)idx * se,
+                         hartley(lds[l * C::LS + idx], lds[l * C::LS + (idx == 0 ? 0 : N - idx)]));
+            }
+        }
+        grp = ng;
+        if (grp >= ngroups) break;
+        __syncthreads();
+    }
+}
+
+// ---- P5: Hartley along x, update -----------------------------------------------
+// MODE 0: FP64 p += dp - mean(p) (or FP32 d32 += dp); MODE 1: assign to p (L^+ sweep).
+template <typename T, int N, int MODE>
+__global__ void __launch_bounds__((LineCfg<T, N>::NT))
+k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
+    using C = LineCfg<T, N>;
+    __shared__ cpx<T> lds[C::L * C::LS];
+    __shared__ cpx<T> tw[N];
+    const Slot& s = slots[blockIdx.y];
+    if (MODE == 0 && IterView<T>::skip(s.st)) return;
+    const cpx<T>* twg = twiddles<T>(tb, 0);
+    for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
+    const POIS_GLOBAL T* W = (MODE == 0) ? IterView<T>(s).W : (const POIS_GLOBAL T*)gptr(s.W);
+    POIS_GLOBAL T* out;
+    if constexpr (sizeof(T) == 8) out = (POIS_GLOBAL T*)gptr(s.p);
+    else out = (POIS_GLOBAL T*)gptr(s.d32);
+    const T shift = (MODE == 0 && sizeof(T) == 8) ? T(s.st->p_shift) : T(0);
+    const unsigned nlines = (unsigned)(g.ny * g.nz / 2);
+    const unsigned ngroups = (nlines + C::L - 1) / C::L;
+
+    cpx<T> wb[C::IT], pb[C::IT];
+    auto load_w = [&](unsigned grp) {
+#pragma unroll
+        for (int it = 0; it < C::IT; ++it) {
+            const int e = threadIdx.x + it * C::NT;
+            const unsigned P = grp * C::L + e / N;
+            const int i = e % N;
+            wb[it] = (P < nlines) ? cpx<T>{W[(2 * P) * N + i], W[(2 * P + 1) * N + i]} : cpx<T>{T(0), T(0)};
+        }
+    };
+    unsigned grp = blockIdx.x;
+    load_w(grp);
+    while (true) {
+#pragma unroll
+        for (int it = 0; it < C::IT; ++it) {
+            const int e = threadIdx.x + it * C::NT;
+            lds[(e / N) * C::LS + e % N] = wb[it];
+        }
+        // FP32: the values to update are loaded now and are in flight during the
+        // FFT; FP64 has no registers to spare for them and loads them after it
+        if (MODE == 0 && sizeof(T) == 4) {
+#pragma unroll
+            for (int it = 0; it < C::IT; ++it) {
+                const int e = threadIdx.x + it * C::NT;
+                const unsigned P = grp * C::L + e / N;
+                const int k = e % N;
+                pb[it] = (P < nlines) ? cpx<T>{out[(2 * P) * N + k], out[(2 * P + 1) * N + k]} : cpx<T>{T(0), T(0)};
+            }
+        }
+        const unsigned ng = grp + gridDim.x;
+        if (ng < ngroups) load_w(ng);
+        __syncthreads();
+        fft_block_lines<T, N>(lds, tw);
+        if (MODE == 0 && sizeof(T) == 8) {
+#pragma unroll
+            for (int it = 0; it < C::IT; ++it) {
+                const int e = threadIdx.x + it * C::NT;
+                const unsigned P = grp * C::L + e / N;
+                const int k = e % N;
+                pb[it] = (P < nlines) ? cpx<T>{out[(2 * P) * N + k], out[(2 * P + 1) * N + k]} : cpx<T>{T(0), T(0)};
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < C::IT; ++it) {
+            const int e = threadIdx.x + it * C::NT;
+            const int l = e / N, k = e % N;
+            const unsigned P = grp * C::L + l;
+            if (P < nlines) {
+                const cpx<T> h = hartley(lds[l * C::LS + k], lds[l * C::LS + (k == 0 ? 0 : N - k)]);
+                const unsigned a = (2 * P) * N + k, b = a + N;
+                if (MODE == 0) {
+                    out[a] = pb[it].x + h.x - shift;
+                    out[b] = pb[it].y + h.y - shift;
+                } else {
+                    out[a] = h.x;
+                    out[b] = h.y;
+                }
+            }
+        }
+        grp = ng;
+        if (grp >= ngroups) break;
+        __syncthreads();
+    }
+}
+
+// ---- launch ---------------------------------------------------------------------
+
+// Blocks of a persistent sweep: every resident block of the device, shared by
+// the slots of the batch, never more than there are line groups.
+static int resident_blocks(const void* kernel, int threads) {
+    static std::mutex mu;
+    static std::unordered_map<const void*, int> per_cu;
+    static int cus = 0;
+    std::lock_guard<std::mutex> lock(mu);
+    if (cus == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+            cus = 256;
+    }
+    auto it = per_cu.find(kernel);
+    if (it == per_cu.end()) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb < 1) nb = 1;
+        it = per_cu.emplace(kernel, nb).first;
+    }
+    return it->second * cus;
+}
+
+static int persistent_grid(const void* kernel, int threads, unsigned ngroups, int nslots) {
+    const int cap = std::max(1, resident_blocks(kernel, threads) / std::max(1, nslots));
+    return (int)std::min<unsigned>(ngroups, (unsigned)cap);
+}
+
+template <typename T, int MODE>
+static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, int which,
+                          hipStream_t s, int* nblocks) {
+    const unsigned rows = (unsigned)(g.ny * g.nz / 2);
+    switch (which) {
+        case 1:
+            return dispatch_len(g.nx, [&]<int N>() {
+                using C = LineCfg<T, N>;
+                const unsigned ng = (rows + C::L - 1) / C::L;
+                return dispatch_op(MODE == 1 ? 0 : g.coef, MODE == 1 ? 0 : g.weight, [&]<int CO, int WE>() {
+                    const void* k = (const void*)&k_resid_dhtx<T, N, MODE, CO, WE>;
+                    const int nb = persistent_grid(k, C::NT, ng, nslots);
+                    if (nblocks) *nblocks = nb;
+                    k_resid_dhtx<T, N, MODE, CO, WE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
+                    return hipGetLastError();
+                });
+            });
+        case 2:
+            return dispatch_len(g.ny, [&]<int N>() {
+                using C = LineCfg<T, N>;
+                const unsigned ng = ((unsigned)(g.nxh * g.nz) + C::L - 1) / C::L;
+                const int nb = persistent_grid((const void*)&k_dht_cols<T, N, 1, MODE>, C::NT, ng, nslots);
+                k_dht_cols<T, N, 1, MODE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
+                return hipGetLastError();
+            });
+        case 3:
+            return dispatch_len(g.nz, [&]<int N>() {
+                using C = LineCfg<T, N>;
+                const unsigned ng = ((unsigned)(g.nxh * g.ny) + C::L - 1) / C::L;
+                const int nb = persistent_grid((const void*)&k_dht_z_solve<T, N, MODE>, C::NT, ng, nslots);
+                k_dht_z_solve<T, N, MODE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
+                return hipGetLastError();
+            });
+        case 5:
+            return dispatch_len(g.nx, [&]<int N>() {
+                using C = LineCfg<T, N>;
+                const unsigned ng = (rows + C::L - 1) / C::L;
+                const int nb = persistent_grid((const void*)&k_dhtx_update<T, N, MODE>, C::NT, ng, nslots);
+                k_dhtx_update<T, N, MODE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
+                return hipGetLastError();
+            });
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sweep_mode(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32, int which,
+                             int mode, hipStream_t s, int* nblocks) {
+    if (mode == 1) return sweep_t<double, 1>(g, t, slots, nslots, which, s, nblocks);
+    return fp32 ? sweep_t<float, 0>(g, t, slots, nslots, which, s, nblocks)
+                : sweep_t<double, 0>(g, t, slots, nslots, which, s, nblocks);
+}
+
+unsigned sweep_groups_x(const GridArgs& g) {
+    // line groups of P1 at the FP64 and FP32 configurations (the larger)
+    unsigned out = 0;
+    (void)dispatch_len(g.nx, [&]<int N>() {
+        const unsigned rows = (unsigned)(g.ny * g.nz / 2);
+        out = std::max((rows + LineCfg<double, N>::L - 1) / LineCfg<double, N>::L,
+                       (rows + LineCfg<float, N>::L - 1) / LineCfg<float, N>::L);
+        return hipSuccess;
+    });
+    return out;
+}
+
+}  // namespace pois
