@@ -207,6 +207,140 @@ __device__ __forceinline__ PairOut<T> pair_eval(const GridArgs& g, const PairIn<
     return o;
 }
 
+// ---- z-marching stencil ---------------------------------------------------------
+// The stencil sweeps would otherwise fetch each value of p and rho about four
+// times through the vector memory path (x, y and z neighbours of every cell),
+// which on gfx950 makes them bound by the texture-address rate, not by HBM.  A
+// thread instead owns one column i of a row pair (rows 2jp, 2jp+1) and marches
+// along z through a tile of planes, keeping the rows of planes k-1, k, k+1 in
+// registers: every plane is loaded once, the x neighbours come from the
+// neighbouring lanes by DPP wave shifts (the two edge lanes of a wave get the
+// column beyond from the neighbouring wave through LDS), and the two y halo rows
+// are loaded once per plane.  Columns are spread over whole waves (N a multiple
+// of 64).
+
+// v from the neighbouring lane; the lane without a source (lane 0 for a right
+// shift, lane 63 for a left shift) receives `edge`.  No select around the DPP:
+// a select may be compiled into a branch that masks the source lanes off.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v, float edge) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                                 __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v, double edge) {
+    const long long b = __builtin_bit_cast(long long, v), o = __builtin_bit_cast(long long, edge);
+    const int lo = __builtin_amdgcn_update_dpp((int)o, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+constexpr int kDppWaveShr1 = 0x138;  // lane l receives lane l-1
+constexpr int kDppWaveShl1 = 0x130;  // lane l receives lane l+1
+
+// p and rho of the pair's rows a (2jp) and b (2jp+1) at one plane, one column
+template <typename T>
+struct PlaneRows {
+    T pa, pb, ra, rb;
+};
+
+// Per plane and column, what the stencil needs besides the z column: the y halo
+// rows (2jp-1 of a, 2jp+2 of b) and the right-hand side.
+template <typename T>
+struct PlaneSide {
+    T pym, rym, pyp, ryp;
+    T ba, bb;
+};
+
+template <typename T>
+struct ZMarch {
+    const POIS_GLOBAL T* p;
+    const POIS_GLOBAL T* rho;
+    const POIS_GLOBAL T* rhs;
+    unsigned nx, nz, sz;
+    unsigned ra, rb, rm, rp;  // row offsets (row * nx) of a, b and the two halo rows
+    int lane;
+
+    __device__ void rows_of(unsigned jp, unsigned ny) {
+        const unsigned ja = 2 * jp, jb = ja + 1;
+        ra = ja * nx;
+        rb = jb * nx;
+        rm = (ja == 0 ? ny - 1 : ja - 1) * nx;
+        rp = (jb + 1 == ny ? 0 : jb + 1) * nx;
+    }
+    __device__ unsigned plane(int k) const {  // periodic plane index -> offset (k >= -1)
+        return ((unsigned)(k + (int)nz) % nz) * sz;
+    }
+    // No load sits under divergent control flow: the compiler's wait counts stay
+    // exact, so the loads of the next plane really overlap this plane's work.
+    __device__ void load_rows(unsigned po, unsigned i, PlaneRows<T>& r) const {
+        r.pa = p[po + ra + i];
+        r.pb = p[po + rb + i];
+        r.ra = rho[po + ra + i];
+        r.rb = rho[po + rb + i];
+    }
+    __device__ void load_side(unsigned po, unsigned i, PlaneSide<T>& s) const {
+        s.pym = p[po + rm + i];
+        s.rym = rho[po + rm + i];
+        s.pyp = p[po + rp + i];
+        s.ryp = rho[po + rp + i];
+        s.ba = rhs[po + ra + i];
+        s.bb = rhs[po + rb + i];
+    }
+    // The columns beyond a wave's edges come from the neighbouring waves through
+    // LDS: `edge` holds, per strip, two slots (lane 0, lane 63) of 4 values for
+    // each group of 64 columns.  put: edge lanes publish their values; get (after
+    // a barrier): lane 0 reads the left neighbour group's lane 63, lane 63 the
+    // right neighbour group's lane 0 (periodic in x).
+    __device__ void edge_put(T* edge, unsigned col, const PlaneRows<T>& c) const {
+        if (lane == 0 || lane == 63) {
+            T* e = edge + ((col / 64) * 2 + (lane == 63 ? 1 : 0)) * 4;
+            e[0] = c.pa;
+            e[1] = c.pb;
+            e[2] = c.ra;
+            e[3] = c.rb;
+        }
+    }
+    __device__ PlaneRows<T> edge_get(const T* edge, unsigned col) const {
+        const unsigned grp = nx / 64, g = col / 64;
+        const unsigned slot = (lane == 0) ? ((g + grp - 1) % grp) * 2 + 1 : ((g + 1) % grp) * 2;
+        const T* e = edge + slot * 4;
+        return PlaneRows<T>{e[0], e[1], e[2], e[3]};
+    }
+    // the 26 stencil inputs of the pair at plane k from planes k-1 (zm), k (c), k+1
+    // (zp); x neighbours by DPP, the edge lanes taking `ex` (from edge_get)
+    __device__ void pair(const PlaneRows<T>& zm, const PlaneRows<T>& c, const PlaneRows<T>& zp,
+                         const PlaneSide<T>& s, const PlaneRows<T>& ex, PairIn<T>& in) const {
+        const T pa_xm = dpp_move<kDppWaveShr1>(c.pa, ex.pa);
+        const T pa_xp = dpp_move<kDppWaveShl1>(c.pa, ex.pa);
+        const T pb_xm = dpp_move<kDppWaveShr1>(c.pb, ex.pb);
+        const T pb_xp = dpp_move<kDppWaveShl1>(c.pb, ex.pb);
+        const T ra_xm = dpp_move<kDppWaveShr1>(c.ra, ex.ra);
+        const T ra_xp = dpp_move<kDppWaveShl1>(c.ra, ex.ra);
+        const T rb_xm = dpp_move<kDppWaveShr1>(c.rb, ex.rb);
+        const T rb_xp = dpp_move<kDppWaveShl1>(c.rb, ex.rb);
+        // order of PairIn: a, b, a x-, a x+, b x-, b x+, a y-, b y+, a z-, a z+, b z-, b z+
+        in.r[0] = c.ra;  in.r[1] = c.rb;  in.r[2] = ra_xm; in.r[3] = ra_xp; in.r[4] = rb_xm; in.r[5] = rb_xp;
+        in.r[6] = s.rym; in.r[7] = s.ryp; in.r[8] = zm.ra; in.r[9] = zp.ra; in.r[10] = zm.rb; in.r[11] = zp.rb;
+        in.q[0] = c.pa;  in.q[1] = c.pb;  in.q[2] = pa_xm; in.q[3] = pa_xp; in.q[4] = pb_xm; in.q[5] = pb_xp;
+        in.q[6] = s.pym; in.q[7] = s.pyp; in.q[8] = zm.pa; in.q[9] = zp.pa; in.q[10] = zm.pb; in.q[11] = zp.pb;
+        in.ba = s.ba;
+        in.bb = s.bb;
+    }
+};
+
+// Thread layout of a z-marching tile for rows of length N handled by NT
+// threads: SUB strips (row pairs) of N threads each when N < NT, or CPT columns
+// per thread when N >= NT; KC planes per tile so that a tile has L row pairs.
+template <int N, int NT, int L>
+struct ZTile {
+    static constexpr int CPT = N >= NT ? N / NT : 1;
+    static constexpr int SUB = N >= NT ? 1 : NT / N;
+    static constexpr int KC = L / SUB;
+    static constexpr int EDGE = (N / 64) * 2 * 4;  // edge values per strip and buffer
+    static_assert(N % 64 == 0, "columns must fill whole waves");
+    static_assert(SUB * KC == L && (N >= NT ? N % NT == 0 : NT % N == 0), "tile shape");
+};
+
 // One cell, plain IEEE divisions: the stand-alone operator and residual sweeps
 // (parity checks), which need no state and are off the iteration's path.
 template <typename T>

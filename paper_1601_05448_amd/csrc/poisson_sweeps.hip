@@ -129,6 +129,133 @@ k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     }
 }
 
+// P1 for rows whose length is a multiple of the wave size: the residual of a tile
+// of KC planes x SUB row pairs is computed by z-marching columns (see ZMarch),
+// then the tile's L lines are transformed along x.  The tile's line l = s KC + kk
+// is row pair jp = tj SUB + s of plane k = tk KC + kk.
+template <typename T, int N, int COEF, int WEIGHT>
+__global__ void __launch_bounds__((LineCfg<T, N>::NT))
+k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
+    using C = LineCfg<T, N>;
+    using Z = ZTile<N, C::NT, C::L>;
+    __shared__ cpx<T> lds[C::L * C::LS];
+    __shared__ cpx<T> tw[N];
+    __shared__ double red[(C::NT / 64) * 4];
+    __shared__ T edge[2 * Z::SUB * Z::EDGE];  // wave-edge columns, double-buffered by step parity
+    const Slot& s = slots[blockIdx.y];
+    if (IterView<T>::skip(s.st)) return;
+    const cpx<T>* twg = twiddles<T>(tb, 0);
+    for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
+    const IterView<T> v(s);
+
+    const unsigned nyh = (unsigned)g.ny / 2, nz = (unsigned)g.nz;
+    const unsigned ngj = (nyh + Z::SUB - 1) / Z::SUB, ngk = (nz + Z::KC - 1) / Z::KC;
+    const unsigned ntiles = ngj * ngk;
+    const int sidx = (N >= C::NT) ? 0 : (int)threadIdx.x / N;
+    const unsigned col0 = (N >= C::NT) ? threadIdx.x : threadIdx.x % N;
+    ZMarch<T> zm;
+    zm.p = v.p;
+    zm.rho = v.rho;
+    zm.rhs = v.rhs;
+    zm.nx = (unsigned)g.nx;
+    zm.nz = nz;
+    zm.sz = (unsigned)g.nx * (unsigned)g.ny;
+    zm.lane = (int)(threadIdx.x & 63);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};  // sum r^2, sum bt^2, sum p, sum p^2
+
+    for (unsigned tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const unsigned tj = tile % ngj, tk = tile / ngj;
+        const unsigned jp = tj * Z::SUB + sidx;
+        const bool jvalid = jp < nyh;
+        zm.rows_of(jvalid ? jp : 0u, (unsigned)g.ny);
+        const int k0 = (int)(tk * Z::KC);
+        PlaneRows<T> pl[Z::CPT][3];
+        PlaneSide<T> sd[Z::CPT];
+#pragma unroll
+        for (int c = 0; c < Z::CPT; ++c) {
+            const unsigned i = col0 + c * C::NT;
+            zm.load_rows(zm.plane(k0 - 1), i, pl[c][0]);
+            zm.load_rows(zm.plane(k0), i, pl[c][1]);
+            zm.load_rows(zm.plane(k0 + 1), i, pl[c][2]);
+            zm.load_side(zm.plane(k0), i, sd[c]);
+        }
+        // fully unrolled, so that the rotation of the plane registers below is a
+        // renaming and not a copy that would wait for the prefetched loads
+#pragma unroll
+        for (int kk = 0; kk < Z::KC; ++kk) {
+            const int k = k0 + kk;
+            const bool valid = jvalid && k < (int)nz;
+            // the next step's plane and side fly while this step computes (also on
+            // the last step, wrapped in z and unused, so that the wait counts are
+            // the same every step)
+            PlaneRows<T> nn[Z::CPT];
+            PlaneSide<T> ns[Z::CPT];
+#pragma unroll
+            for (int c = 0; c < Z::CPT; ++c) {
+                const unsigned i = col0 + c * C::NT;
+                zm.load_rows(zm.plane(k + 2), i, nn[c]);
+                zm.load_side(zm.plane(k + 1), i, ns[c]);
+            }
+            T* eb = edge + ((kk & 1) * Z::SUB + sidx) * Z::EDGE;
+#pragma unroll
+            for (int c = 0; c < Z::CPT; ++c) zm.edge_put(eb, col0 + c * C::NT, pl[c][1]);
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < Z::CPT; ++c) {
+                const unsigned i = col0 + c * C::NT;
+                PairIn<T> in;
+                zm.pair(pl[c][0], pl[c][1], pl[c][2], sd[c], zm.edge_get(eb, i), in);
+                cpx<T> qv = {T(0), T(0)};
+                if (valid) {
+                    const PairOut<T> o = pair_eval<T, COEF, WEIGHT>(g, in, v.rhs_mean, v.rmax, v.rinv);
+                    qv = {o.a.w * o.a.r, o.b.w * o.b.r};
+                    acc[0] += (double)o.a.r * o.a.r + (double)o.b.r * o.b.r;
+                    acc[1] += (double)o.a.bt * o.a.bt + (double)o.b.bt * o.b.bt;
+                    acc[2] += (double)o.a.pc + (double)o.b.pc;
+                    acc[3] += (double)o.a.pc * o.a.pc + (double)o.b.pc * o.b.pc;
+                }
+                lds[(sidx * Z::KC + kk) * C::LS + i] = qv;
+            }
+#pragma unroll
+            for (int c = 0; c < Z::CPT; ++c) {
+                pl[c][0] = pl[c][1];
+                pl[c][1] = pl[c][2];
+                pl[c][2] = nn[c];
+                sd[c] = ns[c];
+            }
+        }
+        __syncthreads();
+        fft_block_lines<T, N>(lds, tw);
+#pragma unroll
+        for (int it = 0; it < C::IT; ++it) {
+            const int e = threadIdx.x + it * C::NT;
+            const int l = e / N, k = e % N;
+            const unsigned ljp = tj * Z::SUB + l / Z::KC;
+            const unsigned lk = tk * Z::KC + l % Z::KC;
+            if (ljp < nyh && lk < nz) {
+                const unsigned P = lk * nyh + ljp;  // row pair index, rows 2P and 2P + 1
+                const cpx<T> h = hartley(lds[l * C::LS + k], lds[l * C::LS + (k == 0 ? 0 : N - k)]);
+                v.W[(2 * P) * N + k] = h.x;
+                v.W[(2 * P + 1) * N + k] = h.y;
+            }
+        }
+        __syncthreads();  // the next tile overwrites the lines
+    }
+    block_sums<C::NT, 4>(acc, red);
+    if (threadIdx.x == 0) {
+        double* out = s.partial + (unsigned long long)blockIdx.x * kPartialStride;
+        out[0] = acc[0]; out[1] = acc[1]; out[2] = acc[2]; out[3] = acc[3];
+    }
+}
+
+// Rows that fill whole waves, and a register budget for CPT marching columns.
+template <typename T, int N>
+constexpr bool use_zmarch() {
+    using C = LineCfg<T, N>;
+    if constexpr (N % 64 != 0) return false;
+    else return (N >= C::NT ? N / C::NT : 1) * (int)sizeof(T) <= 16;
+}
+
 // ---- P2 / P4: Hartley along y (AX = 1) of the pair-packed columns -------------
 // Line = (o, m): complex column m (real columns 2m, 2m+1) at outer index o;
 // element e along the axis.  y: address (o*ny + e)*nxh + m; z: (e*ny + o)*nxh + m.
@@ -390,10 +517,20 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
                 using C = LineCfg<T, N>;
                 const unsigned ng = (rows + C::L - 1) / C::L;
                 return dispatch_op(MODE == 1 ? 0 : g.coef, MODE == 1 ? 0 : g.weight, [&]<int CO, int WE>() {
-                    const void* k = (const void*)&k_resid_dhtx<T, N, MODE, CO, WE>;
-                    const int nb = persistent_grid(k, C::NT, ng, nslots);
-                    if (nblocks) *nblocks = nb;
-                    k_resid_dhtx<T, N, MODE, CO, WE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
+                    if constexpr (MODE == 0 && use_zmarch<T, N>()) {
+                        using Z = ZTile<N, C::NT, C::L>;
+                        const unsigned nt = (((unsigned)g.ny / 2 + Z::SUB - 1) / Z::SUB) *
+                                            (((unsigned)g.nz + Z::KC - 1) / Z::KC);
+                        const void* k = (const void*)&k_resid_dhtx_z<T, N, CO, WE>;
+                        const int nb = persistent_grid(k, C::NT, nt, nslots);
+                        if (nblocks) *nblocks = nb;
+                        k_resid_dhtx_z<T, N, CO, WE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
+                    } else {
+                        const void* k = (const void*)&k_resid_dhtx<T, N, MODE, CO, WE>;
+                        const int nb = persistent_grid(k, C::NT, ng, nslots);
+                        if (nblocks) *nblocks = nb;
+                        k_resid_dhtx<T, N, MODE, CO, WE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
+                    }
                     return hipGetLastError();
                 });
             });
