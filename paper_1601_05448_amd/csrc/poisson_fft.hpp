@@ -166,28 +166,36 @@ constexpr int pick_radix(int rem) {
     return rem % 16 == 0 ? 16 : rem % 8 == 0 ? 8 : rem % 4 == 0 ? 4 : rem % 2 == 0 ? 2 : 3;
 }
 
+// LDS words of a line of n complex values: one pad after every 16 values (the
+// radix-16 stages of a Stockham FFT access a line at stride 16) and an odd
+// total, so that both in-line strides and the line-to-line stride spread over
+// the banks.
+constexpr int line_stride(int n) { return n >= 16 ? ((n + n / 16) | 1) : (n | 1); }
+
 constexpr int lines_per_block(int tt, int n, int elem_bytes) {
     int l = (256 % tt == 0) ? 256 / tt : 192 / tt;
-    while (l * (n + 1) * elem_bytes > 82000 && ((l / 2) * tt) % 64 == 0) l /= 2;
+    while (l * line_stride(n) * elem_bytes > 82000 && ((l / 2) * tt) % 64 == 0) l /= 2;
     return l;
 }
 
 // Threads per line TT (one radix-16 butterfly per thread in the first stage),
-// lines per block L (threads a multiple of 64), LDS line stride LS (one
-// complex of padding against bank conflicts on column-wise accesses).
+// lines per block L (threads a multiple of 64), LDS line stride LS and the LDS
+// position pos(e) of element e within a line (see line_stride).
 template <typename T, int N>
 struct LineCfg {
     static constexpr int TT = N >= 16 ? N / 16 : 1;
     static constexpr int L = lines_per_block(TT, N, (int)sizeof(cpx<T>));
     static constexpr int NT = L * TT;
     static constexpr int IT = N / TT;  // elements per thread when a block walks its L lines
-    static constexpr int LS = N + 1;
+    static constexpr int LS = line_stride(N);
     static_assert(NT % 64 == 0, "block must be whole wavefronts");
+    static __device__ __forceinline__ constexpr int pos(int e) { return N >= 16 ? e + e / 16 : e; }
 };
 
 // One Stockham stage on a line in LDS (all threads of the block call it).
 template <typename T, int N, int R, int NS, int TT>
 __device__ __forceinline__ void stockham_stage(cpx<T>* ln, int t, const cpx<T>* tw) {
+    auto pad = [](int e) { return LineCfg<T, N>::pos(e); };
     constexpr int NB = N / R;
     constexpr int BPT = (NB + TT - 1) / TT;
     cpx<T> v[BPT][R];
@@ -196,7 +204,7 @@ __device__ __forceinline__ void stockham_stage(cpx<T>* ln, int t, const cpx<T>* 
         const int j = t + u * TT;
         if (NB % TT == 0 || j < NB) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[u][r] = ln[j + r * NB];
+            for (int r = 0; r < R; ++r) v[u][r] = ln[pad(j + r * NB)];
         }
     }
     __syncthreads();
@@ -212,7 +220,7 @@ __device__ __forceinline__ void stockham_stage(cpx<T>* ln, int t, const cpx<T>* 
             dft<T, R>(v[u]);
             const int base = (j / NS) * NS * R + jm;
 #pragma unroll
-            for (int r = 0; r < R; ++r) ln[base + r * NS] = v[u][r];
+            for (int r = 0; r < R; ++r) ln[pad(base + r * NS)] = v[u][r];
         }
     }
     __syncthreads();

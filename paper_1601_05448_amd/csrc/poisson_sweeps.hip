@@ -75,7 +75,7 @@ k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
             acc[2] += (double)o.a.pc + (double)o.b.pc;
             acc[3] += (double)o.a.pc * o.a.pc + (double)o.b.pc * o.b.pc;
         }
-        lds[l * C::LS + i] = qv;
+        lds[l * C::LS + C::pos(i)] = qv;
     };
 
     unsigned grp = blockIdx.x;
@@ -99,7 +99,7 @@ k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                 const int l = e / N, i = e % N;
                 const unsigned P = grp * C::L + l;
                 const POIS_GLOBAL double* q = gptr(s.b);
-                lds[l * C::LS + i] = (P < nlines) ? cpx<T>{T(q[(2 * P) * N + i]), T(q[(2 * P + 1) * N + i])}
+                lds[l * C::LS + C::pos(i)] = (P < nlines) ? cpx<T>{T(q[(2 * P) * N + i]), T(q[(2 * P + 1) * N + i])}
                                                   : cpx<T>{T(0), T(0)};
             }
         }
@@ -111,7 +111,7 @@ k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
             const int l = e / N, k = e % N;
             const unsigned P = grp * C::L + l;
             if (P < nlines) {
-                const cpx<T> h = hartley(lds[l * C::LS + k], lds[l * C::LS + (k == 0 ? 0 : N - k)]);
+                const cpx<T> h = hartley(lds[l * C::LS + C::pos(k)], lds[l * C::LS + C::pos((k == 0 ? 0 : N - k))]);
                 W[(2 * P) * N + k] = h.x;
                 W[(2 * P + 1) * N + k] = h.y;
             }
@@ -214,7 +214,7 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                     acc[2] += (double)o.a.pc + (double)o.b.pc;
                     acc[3] += (double)o.a.pc * o.a.pc + (double)o.b.pc * o.b.pc;
                 }
-                lds[(sidx * Z::KC + kk) * C::LS + i] = qv;
+                lds[(sidx * Z::KC + kk) * C::LS + C::pos(i)] = qv;
             }
 #pragma unroll
             for (int c = 0; c < Z::CPT; ++c) {
@@ -234,7 +234,7 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
             const unsigned lk = tk * Z::KC + l % Z::KC;
             if (ljp < nyh && lk < nz) {
                 const unsigned P = lk * nyh + ljp;  // row pair index, rows 2P and 2P + 1
-                const cpx<T> h = hartley(lds[l * C::LS + k], lds[l * C::LS + (k == 0 ? 0 : N - k)]);
+                const cpx<T> h = hartley(lds[l * C::LS + C::pos(k)], lds[l * C::LS + C::pos((k == 0 ? 0 : N - k))]);
                 v.W[(2 * P) * N + k] = h.x;
                 v.W[(2 * P + 1) * N + k] = h.y;
             }
@@ -297,7 +297,7 @@ k_dht_cols(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     load(grp, valid, base);
     while (true) {
 #pragma unroll
-        for (int it = 0; it < C::IT; ++it) lds[l * C::LS + e0 + it * C::TT] = buf[it];
+        for (int it = 0; it < C::IT; ++it) lds[l * C::LS + C::pos(e0 + it * C::TT)] = buf[it];
         const bool cur_valid = valid;
         const unsigned cur_base = base;
         const unsigned ng = grp + gridDim.x;
@@ -309,7 +309,7 @@ k_dht_cols(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
             for (int it = 0; it < C::IT; ++it) {
                 const int idx = e0 + it * C::TT;
                 gstore_c(Wc, cur_base + (unsigned)idx * se,
-                         hartley(lds[l * C::LS + idx], lds[l * C::LS + (idx == 0 ? 0 : N - idx)]));
+                         hartley(lds[l * C::LS + C::pos(idx)], lds[l * C::LS + C::pos((idx == 0 ? 0 : N - idx))]));
             }
         }
         grp = ng;
@@ -353,7 +353,7 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     load(grp, valid, base);
     while (true) {
 #pragma unroll
-        for (int it = 0; it < C::IT; ++it) lds[l * C::LS + e0 + it * C::TT] = buf[it];
+        for (int it = 0; it < C::IT; ++it) lds[l * C::LS + C::pos(e0 + it * C::TT)] = buf[it];
         const bool cur_valid = valid;
         const unsigned cur_base = base;
         // symbol of this thread's line: x wavenumbers 2m, 2m+1 (the pair), y wavenumber j
@@ -367,15 +367,15 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
         // Hartley coefficients of the pairs (k, N-k) of this thread's line, scaled by 1/(n lambda)
         for (int k = e0; k <= N / 2; k += C::TT) {
             const int km = (k == 0) ? 0 : N - k;
-            const cpx<T> zk = lds[l * C::LS + k], zm = lds[l * C::LS + km];
+            const cpx<T> zk = lds[l * C::LS + C::pos(k)], zm = lds[l * C::LS + C::pos(km)];
             cpx<T> hk = hartley(zk, zm), hm = hartley(zm, zk);
             const T lzk = lamz[k], lzm = lamz[km];
             hk.x *= inv_symbol(lxe, lyj, lzk, nn);
             hk.y *= inv_symbol(lxo, lyj, lzk, nn);
             hm.x *= inv_symbol(lxe, lyj, lzm, nn);
             hm.y *= inv_symbol(lxo, lyj, lzm, nn);
-            lds[l * C::LS + k] = hk;
-            lds[l * C::LS + km] = hm;
+            lds[l * C::LS + C::pos(k)] = hk;
+            lds[l * C::LS + C::pos(km)] = hm;
         }
         __syncthreads();
         fft_block_lines<T, N>(lds, tw);
@@ -384,7 +384,7 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
             for (int it = 0; it < C::IT; ++it) {
                 const int idx = e0 + it * C::TT;
                 gstore_c(Wc, cur_base + (unsigned)idx * se,
-                         hartley(lds[l * C::LS + idx], lds[l * C::LS + (idx == 0 ? 0 : N - idx)]));
+                         hartley(lds[l * C::LS + C::pos(idx)], lds[l * C::LS + C::pos((idx == 0 ? 0 : N - idx))]));
             }
         }
         grp = ng;
@@ -429,7 +429,7 @@ k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
 #pragma unroll
         for (int it = 0; it < C::IT; ++it) {
             const int e = threadIdx.x + it * C::NT;
-            lds[(e / N) * C::LS + e % N] = wb[it];
+            lds[(e / N) * C::LS + C::pos(e % N)] = wb[it];
         }
         // FP32: the values to update are loaded now and are in flight during the
         // FFT; FP64 has no registers to spare for them and loads them after it
@@ -461,7 +461,7 @@ k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
             const int l = e / N, k = e % N;
             const unsigned P = grp * C::L + l;
             if (P < nlines) {
-                const cpx<T> h = hartley(lds[l * C::LS + k], lds[l * C::LS + (k == 0 ? 0 : N - k)]);
+                const cpx<T> h = hartley(lds[l * C::LS + C::pos(k)], lds[l * C::LS + C::pos((k == 0 ? 0 : N - k))]);
                 const unsigned a = (2 * P) * N + k, b = a + N;
                 if (MODE == 0) {
                     out[a] = pb[it].x + h.x - shift;
