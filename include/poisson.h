@@ -77,6 +77,8 @@ typedef struct {
     int weight;           /* POISSON_W_*                                            */
     int max_iter;         /* cap on (inner) iterations; <= 0 selects 1000           */
     void* stream;         /* hipStream_t to run on; NULL = the null stream          */
+    double inner_tol;     /* FP32_REFINE: relative residual at which the FP32 inner
+                             sweeps of a refinement step stop; <= 0 selects 1e-4   */
 } poisson_opts;
 
 typedef struct {
@@ -141,8 +143,10 @@ int poisson_lap_pinv(poisson_t h, const double* q, double* delta);
  * back to back between two HIP events on the handle's stream (after one
  * warm-up launch), written to *avg_ms.  sweep: 1 residual + weight + Hartley
  * along x; 2 Hartley along y; 3 Hartley along z, symbol division, Hartley
- * along z; 5 Hartley along x + update.  fp32 != 0 times the FP32 sweeps of a
- * POISSON_FP32_REFINE handle.  p is used as scratch: its contents are lost. */
+ * along z; 5 Hartley along x + update; 6 (POISSON_FP32_REFINE handles only)
+ * the FP64 outer residual of a refinement step with its FP32 outputs.
+ * fp32 != 0 times the FP32 sweeps of a POISSON_FP32_REFINE handle.  p is used
+ * as scratch: its contents are lost. */
 int poisson_time_sweep(poisson_t h, int sweep, int fp32, const double* rho, const double* b, double* p, int reps,
                        double* avg_ms);
 

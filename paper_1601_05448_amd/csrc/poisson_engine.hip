@@ -183,15 +183,13 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
     if ((e = launch_setup(g, geo, d_slots, nslots, fp32, s)) != hipSuccess) return hip_status(e);
     if ((e = launch_setup_finalize(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
     const size_t hb = offsetof(SolveState, hist);
-    auto poll = [&](bool want_inner) -> int {  // 1: all done (or inner done), 0: not yet, <0 error
+    auto poll = [&]() -> int {  // 1: all done, 0: not yet, <0 error
         for (int q = 0; q < nslots; ++q)
             if ((e = hipMemcpyAsync(&hdr[q], d_states[q], hb, hipMemcpyDeviceToHost, s)) != hipSuccess)
                 return hip_status(e);
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_status(e);
         for (int q = 0; q < nslots; ++q) {
-            if (hdr[q].done) continue;
-            if (want_inner && hdr[q].inner_done) continue;
-            return 0;
+            if (!hdr[q].done) return 0;
         }
         return 1;
     };
@@ -201,30 +199,43 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
         while (true) {
             for (int c = 0; c < chunk && launched < cap; ++c, ++launched)
                 if ((e = launch_iteration(g, geo, t, d_slots, nslots, false, s)) != hipSuccess) return hip_status(e);
-            const int r = poll(false);
+            const int r = poll();
             if (r < 0) return r;
             if (r == 1 || launched >= cap) break;
             chunk = std::min(chunk * 2, prm.max_chunk);
         }
     } else {
-        for (int outer = 0; outer <= prm.max_outer; ++outer) {
+        // Speculative refinement cycles: outer residual, `chunk` inner sweeps,
+        // update.  Every kernel runs only in its stage of the device state, so
+        // a cycle whose inner sweeps stop early idles through the rest, and one
+        // whose inner sweeps are not done leaves the update and the next outer
+        // residual to idle until they are.  Each cycle moves every unfinished
+        // solve on by at least one stage, so the count of cycles is bounded.
+        int chunk = prm.first_chunk;
+        const int max_cycles = prm.max_outer + prm.max_iter + 2;
+        for (int cycle = 0; cycle < max_cycles; ++cycle) {
             if ((e = launch_outer_residual(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
-            int r = poll(false);
+            for (int c = 0; c < chunk; ++c)
+                if ((e = launch_iteration(g, geo, t, d_slots, nslots, true, s)) != hipSuccess) return hip_status(e);
+            if ((e = launch_outer_update(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
+            const int r = poll();
             if (r < 0) return r;
             if (r == 1) break;
-            // the device stops the inner sweeps (tolerance, stagnation, or the
-            // max_iter budget, so at most max_iter + 1 launches are ever needed)
-            int launched = 0, chunk = prm.first_chunk;
-            while (true) {
-                for (int c = 0; c < chunk && launched < prm.max_iter + 1; ++c, ++launched)
-                    if ((e = launch_iteration(g, geo, t, d_slots, nslots, true, s)) != hipSuccess)
-                        return hip_status(e);
-                r = poll(true);
-                if (r < 0) return r;
-                if (r == 1 || launched >= prm.max_iter + 1) break;
-                chunk = std::min(chunk * 2, prm.max_chunk);
+            // the next cycle's inner sweeps: as many as any solve used in its
+            // last finished step (steps need about the same number), doubled
+            // while a solve is still inside its inner sweeps, none when every
+            // open solve is predicted to pass its tolerance at the next outer
+            // residual (last outer residual times the last inner reduction)
+            int most = 0;
+            bool inner_open = false, all_pass = true;
+            for (int q = 0; q < nslots; ++q) {
+                if (hdr[q].done) continue;
+                inner_open |= hdr[q].stage == 1;
+                most = std::max(most, hdr[q].inner_last);
+                all_pass &= hdr[q].stage == 0 && hdr[q].rel * hdr[q].rel_in <= 0.5 * hdr[q].tol;
             }
-            if ((e = launch_outer_update(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
+            if (inner_open) chunk = std::max(1, std::min(std::max(chunk, 1) * 2, prm.max_chunk));
+            else chunk = all_pass ? 0 : std::clamp(most, 1, prm.max_chunk);
         }
     }
     if ((e = launch_fixup(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
@@ -315,6 +326,7 @@ int poisson_create(const poisson_opts* o, poisson_t* out) {
     if (!h) return POISSON_ENOMEM;
     h->o = *o;
     if (h->o.max_iter <= 0) h->o.max_iter = 1000;
+    if (!(h->o.inner_tol > 0.0)) h->o.inner_tol = 1e-4;
     h->stream = static_cast<hipStream_t>(o->stream);
     if (hipGetDevice(&h->device) != hipSuccess) {
         delete h;
@@ -359,6 +371,7 @@ int poisson_solve(poisson_t h, const double* rho, const double* b, double* p, do
     prm.tol = tol;
     prm.precision = h->o.precision;
     prm.max_iter = h->o.max_iter;
+    prm.inner_tol = h->o.inner_tol;
     if ((rc = hip_status(hipEventRecord(h->ev0, h->stream))) != POISSON_OK) return rc;
     SolveState* dst = h->ws.st;
     rc = drive_solve(h->g, h->geo, h->tables.t, h->d_slot, 1, &dst, h->h_state, prm, h->stream);
@@ -429,8 +442,8 @@ int poisson_residual(poisson_t h, const double* rho, const double* b, const doub
 int poisson_time_sweep(poisson_t h, int sweep, int fp32, const double* rho, const double* b, double* p, int reps,
                        double* avg_ms) {
     if (!h || !rho || !b || !p || !avg_ms || reps < 1) return POISSON_EINVAL;
-    if (sweep != 1 && sweep != 2 && sweep != 3 && sweep != 5) return POISSON_EINVAL;
-    if (fp32 && h->o.precision != POISSON_FP32_REFINE) return POISSON_EINVAL;
+    if (sweep != 1 && sweep != 2 && sweep != 3 && sweep != 5 && sweep != 6) return POISSON_EINVAL;
+    if ((fp32 || sweep == 6) && h->o.precision != POISSON_FP32_REFINE) return POISSON_EINVAL;
     // a state that never converges (tol 0) so that every sweep does its work
     int rc = set_slot(h, h->ws.slot(rho, b, p, 0.0));
     if (rc != POISSON_OK) return rc;
@@ -439,14 +452,18 @@ int poisson_time_sweep(poisson_t h, int sweep, int fp32, const double* rho, cons
         return hip_status(e);
     if ((e = launch_setup(h->g, h->geo, h->d_slot, 1, fp32 != 0, h->stream)) != hipSuccess) return hip_status(e);
     if ((e = launch_setup_finalize(h->g, h->geo, h->d_slot, 1, h->stream)) != hipSuccess) return hip_status(e);
-    if (fp32 && (e = launch_outer_residual(h->g, h->geo, h->d_slot, 1, h->stream)) != hipSuccess)
+    // the inner sweeps run in stage 1, which the outer residual opens; the
+    // outer residual sweep itself in stage 0
+    if (fp32 && sweep != 6 && (e = launch_outer_residual(h->g, h->geo, h->d_slot, 1, h->stream)) != hipSuccess)
         return hip_status(e);
-    if ((e = launch_sweep(h->g, h->tables.t, h->d_slot, 1, fp32 != 0, sweep, h->stream)) != hipSuccess)
-        return hip_status(e);  // warm
+    auto one = [&]() {
+        return sweep == 6 ? launch_outer_resid_sweep(h->g, h->d_slot, 1, h->stream, nullptr)
+                          : launch_sweep(h->g, h->tables.t, h->d_slot, 1, fp32 != 0, sweep, h->stream);
+    };
+    if ((e = one()) != hipSuccess) return hip_status(e);  // warm
     if ((e = hipEventRecord(h->ev0, h->stream)) != hipSuccess) return hip_status(e);
     for (int r = 0; r < reps; ++r)
-        if ((e = launch_sweep(h->g, h->tables.t, h->d_slot, 1, fp32 != 0, sweep, h->stream)) != hipSuccess)
-            return hip_status(e);
+        if ((e = one()) != hipSuccess) return hip_status(e);
     if ((e = hipEventRecord(h->ev1, h->stream)) != hipSuccess) return hip_status(e);
     if ((e = hipEventSynchronize(h->ev1)) != hipSuccess) return hip_status(e);
     float ms = 0.f;

@@ -58,6 +58,7 @@ struct SolveState {
     int inner_iter;     // inner iteration within the current outer step
     int inner_done;
     int inner_total;
+    int inner_last;     // inner-sweep launches the last finished outer step used
     int since_best;
     double inv_s;       // r32 = r * inv_s (a power of two)
     double rhs_mean32;  // mean of r32, removed inside the inner sweeps
@@ -125,6 +126,8 @@ hipError_t launch_sweep_mode(const GridArgs& g, const Tables& t, const Slot* slo
                              int mode, hipStream_t s, int* nblocks);
 unsigned sweep_groups_x(const GridArgs& g);
 // FP32_REFINE outer step pieces.
+// the FP64 outer residual sweep alone (no finalize); *nblocks = partial sums written
+hipError_t launch_outer_resid_sweep(const GridArgs& g, const Slot* slots, int nslots, hipStream_t s, int* nblocks);
 hipError_t launch_outer_residual(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,
                                  hipStream_t s);
 hipError_t launch_outer_update(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,

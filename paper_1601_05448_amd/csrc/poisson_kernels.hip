@@ -276,6 +276,7 @@ __global__ void __launch_bounds__(256) k_finalize_inner(GridArgs g, const Slot* 
     if (t >= max_inner || st->inner_total >= st->max_iter) stop = true;
     if (stop) {
         st->inner_done = 1;
+        st->inner_last = t + 1;
         st->stage = 2;
     } else {
         st->inner_iter = t + 1;
@@ -332,13 +333,121 @@ k_stencil(GridArgs g, const Slot* __restrict__ slots, const double* __restrict__
     }
 }
 
-// FP32_REFINE outer residual in FP64 on row pairs (the layout of P1, so that the
-// neighbour rows of a block are read once from HBM): r = b~ - A p, r32 = r inv_s,
-// d32 = 0.  Partials: sum r^2, sum bt^2, sum p, sum p^2, sum r.
+// FP32_REFINE outer residual in FP64: r = b~ - A p, r32 = r inv_s, d32 = 0, by
+// z-marching columns (see ZMarch) over tiles of kOuterPlanes planes x SUB row
+// pairs (rows of the lengths OuterCfg accepts; others take k_outer_resid_rows).  Partials:
+// sum r^2, sum bt^2, sum p, sum p^2, sum r.
+constexpr int kOuterPlanes = 16;
+
+// 256 threads: SUB = 256 / N strips of one column per thread, or CPT = N / 256
+// columns per thread; rows whose length divides or is a multiple of 256.
+template <int N>
+struct OuterCfg {
+    static constexpr bool ok = N % 64 == 0 && (N >= 256 ? N % 256 == 0 : 256 % N == 0);
+    static constexpr int CPT = N >= 256 ? N / 256 : 1;
+    static constexpr int SUB = N >= 256 ? 1 : 256 / N;
+};
+
+template <int N, int COEF, int WEIGHT>
+__global__ void __launch_bounds__(256) k_outer_resid(GridArgs g, const Slot* __restrict__ slots) {
+    using O = OuterCfg<N>;
+    constexpr int EDGE = (N / 64) * 2 * 4;
+    __shared__ double red[(256 / 64) * 5];
+    __shared__ double edge[2 * O::SUB * EDGE];
+    const Slot& s = slots[blockIdx.y];
+    SolveState* st = s.st;
+    if (st->done || st->stage != 0) return;
+    const double bm = st->b_mean, inv_s = st->inv_s, rmax = st->rho_max, rinv = recip(st->rho_max);
+    const unsigned nyh = (unsigned)g.ny / 2, nz = (unsigned)g.nz;
+    const unsigned ngj = (nyh + O::SUB - 1) / O::SUB, ngk = (nz + kOuterPlanes - 1) / kOuterPlanes;
+    const unsigned ntiles = ngj * ngk;
+    const int sidx = (N >= 256) ? 0 : (int)threadIdx.x / N;
+    const unsigned col0 = (N >= 256) ? threadIdx.x : threadIdx.x % N;
+    POIS_GLOBAL float* r32 = gptr(s.r32);
+    POIS_GLOBAL float* d32 = gptr(s.d32);
+    ZMarch<double> zm;
+    zm.p = gptr(s.p);
+    zm.rho = gptr(s.rho);
+    zm.rhs = gptr(s.b);
+    zm.nx = (unsigned)g.nx;
+    zm.nz = nz;
+    zm.sz = (unsigned)g.nx * (unsigned)g.ny;
+    zm.lane = (int)(threadIdx.x & 63);
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (unsigned tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const unsigned tj = tile % ngj, tk = tile / ngj;
+        const unsigned jp = tj * O::SUB + sidx;
+        const bool jvalid = jp < nyh;
+        zm.rows_of(jvalid ? jp : 0u, (unsigned)g.ny);
+        const int k0 = (int)(tk * kOuterPlanes);
+        PlaneRows<double> pl[O::CPT][3];
+        PlaneSide<double> sd[O::CPT];
+#pragma unroll
+        for (int c = 0; c < O::CPT; ++c) {
+            const unsigned i = col0 + c * 256;
+            zm.load_rows(zm.plane(k0 - 1), i, pl[c][0]);
+            zm.load_rows(zm.plane(k0), i, pl[c][1]);
+            zm.load_rows(zm.plane(k0 + 1), i, pl[c][2]);
+            zm.load_side(zm.plane(k0), i, sd[c]);
+        }
+#pragma unroll
+        for (int kk = 0; kk < kOuterPlanes; ++kk) {
+            const int k = k0 + kk;
+            const bool valid = jvalid && k < (int)nz;
+            PlaneRows<double> nn[O::CPT];
+            PlaneSide<double> ns[O::CPT];
+#pragma unroll
+            for (int c = 0; c < O::CPT; ++c) {
+                const unsigned i = col0 + c * 256;
+                zm.load_rows(zm.plane(k + 2), i, nn[c]);
+                zm.load_side(zm.plane(k + 1), i, ns[c]);
+            }
+            double* eb = edge + ((kk & 1) * O::SUB + sidx) * EDGE;
+#pragma unroll
+            for (int c = 0; c < O::CPT; ++c) zm.edge_put(eb, col0 + c * 256, pl[c][1]);
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < O::CPT; ++c) {
+                const unsigned i = col0 + c * 256;
+                PairIn<double> in;
+                zm.pair(pl[c][0], pl[c][1], pl[c][2], sd[c], zm.edge_get(eb, i), in);
+                if (valid) {
+                    const PairOut<double> pr = pair_eval<double, COEF, WEIGHT>(g, in, bm, rmax, rinv);
+                    const unsigned a = (unsigned)k * zm.sz + zm.ra + i, b = a + (unsigned)g.nx;
+                    acc[0] += pr.a.r * pr.a.r + pr.b.r * pr.b.r;
+                    acc[1] += pr.a.bt * pr.a.bt + pr.b.bt * pr.b.bt;
+                    acc[2] += pr.a.pc + pr.b.pc;
+                    acc[3] += pr.a.pc * pr.a.pc + pr.b.pc * pr.b.pc;
+                    acc[4] += pr.a.r + pr.b.r;
+                    r32[a] = (float)(pr.a.r * inv_s);
+                    r32[b] = (float)(pr.b.r * inv_s);
+                    d32[a] = 0.0f;
+                    d32[b] = 0.0f;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < O::CPT; ++c) {
+                pl[c][0] = pl[c][1];
+                pl[c][1] = pl[c][2];
+                pl[c][2] = nn[c];
+                sd[c] = ns[c];
+            }
+        }
+    }
+    block_sums<256, 5>(acc, red);
+    if (threadIdx.x == 0) {
+        double* o = s.partial + (unsigned long long)blockIdx.x * kPartialStride;
+        o[0] = acc[0]; o[1] = acc[1]; o[2] = acc[2]; o[3] = acc[3]; o[4] = acc[4];
+    }
+}
+
+// The same for rows of any length: row pairs gathered with all their neighbours
+// (the layout of P1's line groups), one pair evaluated while the next one's
+// loads are in flight.
 constexpr int kOuterElems = 2048;  // (pair, column) elements per block
 
 template <int N, int COEF, int WEIGHT>
-__global__ void __launch_bounds__(kPtThreads) k_outer_resid(GridArgs g, const Slot* __restrict__ slots) {
+__global__ void __launch_bounds__(kPtThreads) k_outer_resid_rows(GridArgs g, const Slot* __restrict__ slots) {
     constexpr int RPB = N >= kOuterElems ? 1 : kOuterElems / N;  // row pairs per block
     __shared__ double red[(kPtThreads / 64) * 5];
     __shared__ int s_j0[RPB], s_k0[RPB];
@@ -410,9 +519,16 @@ __global__ void __launch_bounds__(kPtThreads) k_outer_resid(GridArgs g, const Sl
 
 template <int N>
 static int blocks_outer(const GridArgs& g) {
-    constexpr int RPB = N >= kOuterElems ? 1 : kOuterElems / N;
-    const long long np = (long long)g.ny * g.nz / 2;
-    return (int)((np + RPB - 1) / RPB);
+    if constexpr (OuterCfg<N>::ok) {
+        using O = OuterCfg<N>;
+        const long long ngj = ((long long)g.ny / 2 + O::SUB - 1) / O::SUB;
+        const long long ngk = ((long long)g.nz + kOuterPlanes - 1) / kOuterPlanes;
+        return (int)std::min<long long>(ngj * ngk, 2048);
+    } else {
+        constexpr int RPB = N >= kOuterElems ? 1 : kOuterElems / N;
+        const long long np = (long long)g.ny * g.nz / 2;
+        return (int)((np + RPB - 1) / RPB);
+    }
 }
 
 // FP32_REFINE outer update: p += d32 / inv_s - p_shift (FP64), then the next scale.
@@ -536,17 +652,23 @@ hipError_t launch_iteration(const GridArgs& g, const Geometry& geo, const Tables
     return five_sweeps(g, t, slots, nslots, fp32, 0, s);
 }
 
+hipError_t launch_outer_resid_sweep(const GridArgs& g, const Slot* slots, int nslots, hipStream_t s, int* nblocks) {
+    return dispatch_len(g.nx, [&]<int N>() {
+        const int nb = blocks_outer<N>(g);
+        if (nblocks) *nblocks = nb;
+        return dispatch_op(g.coef, g.weight, [&]<int C, int W>() {
+            if constexpr (OuterCfg<N>::ok) k_outer_resid<N, C, W><<<dim3(nb, nslots), 256, 0, s>>>(g, slots);
+            else k_outer_resid_rows<N, C, W><<<dim3(nb, nslots), kPtThreads, 0, s>>>(g, slots);
+            return hipGetLastError();
+        });
+    });
+}
+
 hipError_t launch_outer_residual(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,
                                  hipStream_t s) {
     (void)geo;
     int nb = 0;
-    hipError_t e = dispatch_len(g.nx, [&]<int N>() {
-        nb = blocks_outer<N>(g);
-        return dispatch_op(g.coef, g.weight, [&]<int C, int W>() {
-            k_outer_resid<N, C, W><<<dim3(nb, nslots), kPtThreads, 0, s>>>(g, slots);
-            return hipGetLastError();
-        });
-    });
+    hipError_t e = launch_outer_resid_sweep(g, slots, nslots, s, &nb);
     if (e != hipSuccess) return e;
     k_finalize_outer<<<nslots, 256, 0, s>>>(g, slots, nb);
     return hipGetLastError();

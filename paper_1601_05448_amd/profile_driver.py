@@ -19,6 +19,7 @@ def main():
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--paths", default="fp64,fp32")
+    ap.add_argument("--inner-tols", default="", help="comma list: extra FP32+refine solves at these inner tolerances")
     args = ap.parse_args()
 
     import torch
@@ -34,12 +35,20 @@ def main():
     for name in args.paths.split(","):
         prec = P.POISSON_FP64 if name == "fp64" else P.POISSON_FP32_REFINE
         with P.Solver(prob.shape, prob.lengths, precision=prec) as s:
-            for sw in (1, 2, 3, 5):
-                ms = P.poisson_time_sweep(s.h, sw, prec == P.POISSON_FP32_REFINE, rho, b, p, args.reps)
+            fp32 = prec == P.POISSON_FP32_REFINE
+            for sw in (1, 2, 3, 5, 6) if fp32 else (1, 2, 3, 5):
+                ms = P.poisson_time_sweep(s.h, sw, fp32 and sw != 6, rho, b, p, args.reps)
                 print(f"{name} sweep {sw}: {ms * 1e3:.1f} us", flush=True)
             p.zero_()
             st = s.solve(rho, b, p, 1e-10)
             print(f"{name} solve: {st['ms']:.3f} ms iters {st['iters']} outer {st['outer_iters']}", flush=True)
+    for it in (float(v) for v in args.inner_tols.split(",") if v):
+        with P.Solver(prob.shape, prob.lengths, precision=P.POISSON_FP32_REFINE, inner_tol=it) as s:
+            for _ in range(3):
+                p.zero_()
+                st = s.solve(rho, b, p, 1e-10)
+            print(f"fp32 inner_tol {it:g} solve: {st['ms']:.3f} ms iters {st['iters']} outer {st['outer_iters']} "
+                  f"rel {st['rel_resid']:.2e}", flush=True)
     n = args.copy_mib * (1 << 20) // 8
     src = torch.ones(n, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
