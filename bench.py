@@ -23,7 +23,27 @@ HBM_PEAK_GBS = 8000.0
 # algorithmic HBM bytes per cell of each sweep (FP64, FP32): read inputs once,
 # write outputs once
 SWEEP_BYTES = {1: (32, 16), 2: (16, 8), 3: (16, 8), 5: (24, 12)}
-SWEEP_NAMES = {1: "k_resid_dhtx", 2: "k_dht_cols (y)", 3: "k_dht_z_solve", 5: "k_dhtx_update"}
+SWEEP_NAMES = {1: "k_resid_dhtx_z", 2: "k_dht_cols", 3: "k_dht_z_solve", 5: "k_dhtx_update"}
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def measured_traffic(kernel, size):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size), or None when
+    there is none for this kernel and size or the kernel sources have changed
+    since the counters were taken."""
+    from paper_1601_05448_amd import profile_summary
+
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f).get(f"{kernel}@{size}")
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_sha256") != profile_summary.kernel_source_hash():
+        return None
+    return rec["bytes_per_launch"]
 
 
 def percentile(xs, q):
@@ -36,6 +56,10 @@ def percentile(xs, q):
 
 
 def time_path(P, torch, prob, precision, steps, warmup, tol):
+    """Warm up, then time `steps` solves from p = 0.  Inside the timed region
+    every launch of the path's residual sweep P1 (the dominant kernel) is
+    bracketed by HIP events on the solver's stream (poisson_kernel_timer)."""
+    fp32 = precision == P.POISSON_FP32_REFINE
     rho = torch.from_numpy(prob.rho).cuda()
     b = torch.from_numpy(prob.b).cuda()
     p = torch.zeros(prob.shape, dtype=torch.float64, device="cuda")
@@ -45,28 +69,39 @@ def time_path(P, torch, prob, precision, steps, warmup, tol):
         p.zero_()
         stats = s.solve(rho, b, p, tol)
     torch.cuda.synchronize()
+    P.poisson_kernel_timer(s.h, 1, fp32)
     lat = []
+    p1_work = 0
     t0 = time.perf_counter()
     for _ in range(steps):
         a = time.perf_counter()
         p.zero_()
         stats = s.solve(rho, b, p, tol)
         lat.append((time.perf_counter() - a) * 1e3)
+        p1_work += stats["p1_sweeps"]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    k_ms, k_launches = P.poisson_kernel_timer_read(s.h)
+    P.poisson_kernel_timer(s.h, 0)
     if stats["status"] != 0:
         raise RuntimeError(f"solve failed: {stats}")
+    bytes_p1 = SWEEP_BYTES[1][1 if fp32 else 0] * prob.n
     out = dict(solves_per_s=steps / (t1 - t0), ms_per_solve=(t1 - t0) * 1e3 / steps,
                p50_ms=percentile(lat, 0.5), p99_ms=percentile(lat, 0.99), iters=stats["iters"],
                outer_iters=stats["outer_iters"], rel_resid=stats["rel_resid"],
-               err_bound_rel=stats["err_bound_rel"], device_ms=stats["ms"])
-    # per-sweep device time with HIP events on the solver's stream
+               err_bound_rel=stats["err_bound_rel"], device_ms=stats["ms"],
+               p1=dict(kernel=("f32:" if fp32 else "f64:") + SWEEP_NAMES[1], launches=k_launches,
+                       working_launches=p1_work, total_ms=k_ms, avg_launch_us=1e3 * k_ms / max(k_launches, 1),
+                       bytes_per_launch=bytes_p1,
+                       # algorithmic bytes of the launches that did work over the time of all launches
+                       gbs=bytes_p1 * p1_work / (k_ms * 1e6) if k_ms > 0 else 0.0))
+    # each sweep alone, back to back between two HIP events on the solver's stream
     sweeps = {}
     for sw in (1, 2, 3, 5):
-        for fp32 in ((False, True) if precision == P.POISSON_FP32_REFINE else (False,)):
-            ms = P.poisson_time_sweep(s.h, sw, fp32, rho, b, p, 20)
-            nbytes = SWEEP_BYTES[sw][1 if fp32 else 0] * prob.n
-            sweeps[f"{'f32' if fp32 else 'f64'}:{SWEEP_NAMES[sw]}"] = dict(
+        for f32 in ((False, True) if fp32 else (False,)):
+            ms = P.poisson_time_sweep(s.h, sw, f32, rho, b, p, 20)
+            nbytes = SWEEP_BYTES[sw][1 if f32 else 0] * prob.n
+            sweeps[f"{'f32' if f32 else 'f64'}:{SWEEP_NAMES[sw]}"] = dict(
                 ms=ms, bytes=nbytes, gbs=nbytes / ms / 1e6)
     s.close()
     out["sweeps"] = sweeps
@@ -119,12 +154,13 @@ def main():
     fp32 = time_path(P, torch, prob, P.POISSON_FP32_REFINE, args.steps, args.warmup, args.tol)
     best_name, best = ("fp32_refine", fp32) if fp32["solves_per_s"] > fp64["solves_per_s"] else ("fp64", fp64)
 
-    # dominant kernel of the headline path: the sweep with the largest share of an iteration
-    sw = best["sweeps"]
-    key = max(sw, key=lambda k: sw[k]["ms"] * (2 if "k_dht_cols" in k else 1))
-    dom = sw[key]
-    roofline = {"bound": "hbm", "kernel": key, "achieved": dom["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": dom["gbs"] / HBM_PEAK_GBS, "traffic": None}
+    # dominant kernel of the headline path: its residual sweep P1, timed live
+    dom = best["p1"]
+    roofline = {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": dom["gbs"] / HBM_PEAK_GBS,
+                "traffic": measured_traffic(dom["kernel"], args.size),
+                "bytes_per_launch": dom["bytes_per_launch"], "avg_launch_us": dom["avg_launch_us"],
+                "launches": dom["launches"], "working_launches": dom["working_launches"]}
 
     line = {
         "metric": METRIC,

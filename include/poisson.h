@@ -92,6 +92,8 @@ typedef struct {
     double err_bound_rel;   /* bound on ||p - p*||_2 / ||p||_2 from the final residual:   */
                             /* rho_max ||r||_2 / min_d(4 sin^2(pi/N_d)/h_d^2) / ||p||_2   */
     double ms;              /* device time of the solve (HIP events on the stream)        */
+    int p1_sweeps;          /* launches of the residual sweep that did work: FP64 residual
+                               evaluations, or FP32 inner residual evaluations           */
 } poisson_stats;
 
 /* Create a solver for one grid: validates the options, builds the transform
@@ -131,6 +133,19 @@ int poisson_apply(poisson_t h, const double* rho, const double* p, double* out);
  * r_norm and b_norm (host pointers, may be NULL).  r may be NULL. */
 int poisson_residual(poisson_t h, const double* rho, const double* b, const double* p, double* r,
                      double* r_norm, double* b_norm);
+
+/* Device time of one sweep kind inside the solves of this handle.  After
+ * poisson_kernel_timer(h, sweep, fp32) with sweep 1, 2, 3 or 5 (as in
+ * poisson_time_sweep; fp32 != 0 selects the FP32 sweeps of a
+ * POISSON_FP32_REFINE handle), every launch of that sweep by poisson_solve is
+ * bracketed by two HIP events on the handle's stream (up to 256 launches per
+ * solve) and the elapsed times are summed when the solve returns; launches
+ * that find their solve finished or out of stage are counted too (compare
+ * poisson_stats.p1_sweeps).  sweep 0 stops the timer.  Every call resets the
+ * sums. */
+int poisson_kernel_timer(poisson_t h, int sweep, int fp32);
+/* Summed bracketed time (ms) and bracketed launches since the timer was set. */
+int poisson_kernel_timer_read(poisson_t h, double* total_ms, long long* launches);
 
 /* delta = L^+ q: zero-mean solution of L delta = q - mean(q) with L the
  * constant-coefficient 7-point Laplacian, by separable real (Hartley)

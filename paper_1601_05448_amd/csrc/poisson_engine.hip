@@ -174,7 +174,8 @@ Slot Workspace::slot(const double* rho, const double* b, double* p, double tol) 
 // header of slot 0..nslots-1 between chunks.  `hdr` is pinned host memory for
 // nslots state headers.
 int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* d_slots, int nslots,
-                SolveState* const* d_states, SolveState* hdr, const SolveParams& prm, hipStream_t s) {
+                SolveState* const* d_states, SolveState* hdr, const SolveParams& prm, hipStream_t s,
+                SweepTimer* tm) {
     hipError_t e;
     const bool fp32 = prm.precision == POISSON_FP32_REFINE;
     if ((e = launch_init(g, d_slots, nslots, prm.inner_tol, prm.max_iter, prm.max_outer, prm.precision, s)) !=
@@ -194,15 +195,39 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
         return 1;
     };
     if (!fp32) {
+        // Chunks of iterations between polls.  After the first chunk the next
+        // one is sized from the contraction observed so far: the iterations
+        // that bring the last residual below the tolerance at that rate, plus a
+        // quarter of one (an idle launch costs less than another poll).
         int launched = 0, chunk = prm.first_chunk;
         const int cap = prm.max_iter + 1;
+        std::vector<int> k_prev(nslots, -1);
+        std::vector<double> r_prev(nslots, 0.0);
         while (true) {
             for (int c = 0; c < chunk && launched < cap; ++c, ++launched)
-                if ((e = launch_iteration(g, geo, t, d_slots, nslots, false, s)) != hipSuccess) return hip_status(e);
+                if ((e = launch_iteration(g, geo, t, d_slots, nslots, false, s, tm)) != hipSuccess)
+                    return hip_status(e);
             const int r = poll();
             if (r < 0) return r;
             if (r == 1 || launched >= cap) break;
-            chunk = std::min(chunk * 2, prm.max_chunk);
+            int need = 0;
+            for (int q = 0; q < nslots; ++q) {
+                const SolveState& h = hdr[q];
+                if (h.done) continue;
+                const int k = h.iter - 1;  // index of the last residual evaluated
+                double rate = 1.0;
+                if (k_prev[q] >= 0 && k > k_prev[q] && r_prev[q] > 0.0)
+                    rate = std::pow(h.rel / r_prev[q], 1.0 / (k - k_prev[q]));
+                else if (k >= 1 && h.rel0 > 0.0)
+                    rate = std::pow(h.rel / h.rel0, 1.0 / k);
+                k_prev[q] = k;
+                r_prev[q] = h.rel;
+                int m = 2 * chunk;
+                if (rate > 0.0 && rate < 0.95 && h.rel > 0.0)
+                    m = (int)std::ceil(std::log(h.tol / h.rel) / std::log(rate) + 0.25);
+                need = std::max(need, m);
+            }
+            chunk = std::clamp(need, 1, prm.max_chunk);
         }
     } else {
         // Speculative refinement cycles: outer residual, `chunk` inner sweeps,
@@ -216,7 +241,8 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
         for (int cycle = 0; cycle < max_cycles; ++cycle) {
             if ((e = launch_outer_residual(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
             for (int c = 0; c < chunk; ++c)
-                if ((e = launch_iteration(g, geo, t, d_slots, nslots, true, s)) != hipSuccess) return hip_status(e);
+                if ((e = launch_iteration(g, geo, t, d_slots, nslots, true, s, tm)) != hipSuccess)
+                    return hip_status(e);
             if ((e = launch_outer_update(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
             const int r = poll();
             if (r < 0) return r;
@@ -260,6 +286,7 @@ void fill_stats(const GridArgs& g, const SolveState& st, poisson_stats* out) {
     const double bound = st.rho_max * st.r_norm / min_symbol(g);
     s.err_bound_rel = (pn > 0.0 && st.status != POISSON_EDOMAIN) ? bound / pn : 0.0;
     s.ms = 0.0;
+    s.p1_sweeps = st.p1_work;
     *out = s;
 }
 
@@ -281,6 +308,9 @@ struct poisson_s {
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     poisson_stats stats{};
     int hist_count = 0;
+    SweepTimer timer;            // events around one sweep kind inside solves
+    double timer_ms = 0.0;       // summed bracketed time since the timer was set
+    long long timer_launches = 0;
 };
 
 extern "C" {
@@ -308,6 +338,8 @@ void poisson_destroy(poisson_t h) {
     if (h->h_state) (void)hipHostFree(h->h_state);
     if (h->ev0) (void)hipEventDestroy(h->ev0);
     if (h->ev1) (void)hipEventDestroy(h->ev1);
+    for (hipEvent_t& ev : h->timer.ev)
+        if (ev) (void)hipEventDestroy(ev);
     h->ws.release();
     h->tables.release();
     delete h;
@@ -374,7 +406,9 @@ int poisson_solve(poisson_t h, const double* rho, const double* b, double* p, do
     prm.inner_tol = h->o.inner_tol;
     if ((rc = hip_status(hipEventRecord(h->ev0, h->stream))) != POISSON_OK) return rc;
     SolveState* dst = h->ws.st;
-    rc = drive_solve(h->g, h->geo, h->tables.t, h->d_slot, 1, &dst, h->h_state, prm, h->stream);
+    h->timer.used = 0;
+    rc = drive_solve(h->g, h->geo, h->tables.t, h->d_slot, 1, &dst, h->h_state, prm, h->stream,
+                     h->timer.sweep ? &h->timer : nullptr);
     if (rc != POISSON_OK) return rc;
     if ((rc = hip_status(hipEventRecord(h->ev1, h->stream))) != POISSON_OK) return rc;
     if ((rc = hip_status(hipMemcpyAsync(h->h_state, h->ws.st, sizeof(SolveState), hipMemcpyDeviceToHost,
@@ -385,6 +419,14 @@ int poisson_solve(poisson_t h, const double* rho, const double* b, double* p, do
     fill_stats(h->g, st, &h->stats);
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, h->ev0, h->ev1) == hipSuccess) h->stats.ms = ms;
+    for (int q = 0; q < h->timer.used; ++q) {
+        float kms = 0.f;
+        if ((rc = hip_status(hipEventElapsedTime(&kms, h->timer.ev[2 * q], h->timer.ev[2 * q + 1]))) != POISSON_OK)
+            return rc;
+        h->timer_ms += kms;
+        h->timer_launches += 1;
+    }
+    h->timer.used = 0;
     h->hist_count = std::min(st.iter + 1, kHistCap);
     if (st.status == POISSON_EDOMAIN) h->hist_count = 0;
     return h->stats.status;
@@ -469,6 +511,28 @@ int poisson_time_sweep(poisson_t h, int sweep, int fp32, const double* rho, cons
     float ms = 0.f;
     if ((e = hipEventElapsedTime(&ms, h->ev0, h->ev1)) != hipSuccess) return hip_status(e);
     *avg_ms = (double)ms / reps;
+    return POISSON_OK;
+}
+
+int poisson_kernel_timer(poisson_t h, int sweep, int fp32) {
+    if (!h || (sweep != 0 && sweep != 1 && sweep != 2 && sweep != 3 && sweep != 5)) return POISSON_EINVAL;
+    if (fp32 && h->o.precision != POISSON_FP32_REFINE) return POISSON_EINVAL;
+    if (sweep != 0 && !h->timer.ev[0]) {
+        for (hipEvent_t& ev : h->timer.ev)
+            if (hipEventCreate(&ev) != hipSuccess) return POISSON_EHIP;
+    }
+    h->timer.sweep = sweep;
+    h->timer.fp32 = fp32 != 0;
+    h->timer.used = 0;
+    h->timer_ms = 0.0;
+    h->timer_launches = 0;
+    return POISSON_OK;
+}
+
+int poisson_kernel_timer_read(poisson_t h, double* total_ms, long long* launches) {
+    if (!h || !total_ms || !launches) return POISSON_EINVAL;
+    *total_ms = h->timer_ms;
+    *launches = h->timer_launches;
     return POISSON_OK;
 }
 

@@ -48,7 +48,8 @@ GridArgs make_grid(int nx, int ny, int nz, double lx, double ly, double lz, int 
 double min_symbol(const GridArgs& g);
 size_t workspace_bytes(const GridArgs& g, const Geometry& geo, int precision);
 int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* d_slots, int nslots,
-                SolveState* const* d_states, SolveState* hdr, const SolveParams& prm, hipStream_t s);
+                SolveState* const* d_states, SolveState* hdr, const SolveParams& prm, hipStream_t s,
+                SweepTimer* tm = nullptr);
 void fill_stats(const GridArgs& g, const SolveState& st, poisson_stats* out);
 
 }  // namespace pois

@@ -47,6 +47,7 @@ struct SolveState {
     double b_norm;      // ||b - mean b||
     double r_norm;      // last FP64 residual norm
     double rel;         // last relative residual
+    double rel0;        // relative residual of the first FP64 evaluation
     double p_shift;     // mean of the incoming p, removed by the first update
     double p_sum;       // sum p and sum p^2 of the last iterate whose residual was taken
     double p_sumsq;
@@ -59,6 +60,7 @@ struct SolveState {
     int inner_done;
     int inner_total;
     int inner_last;     // inner-sweep launches the last finished outer step used
+    int p1_work;        // launches of the residual sweep P1 that did their work
     int since_best;
     double inv_s;       // r32 = r * inv_s (a power of two)
     double rhs_mean32;  // mean of r32, removed inside the inner sweeps
@@ -114,8 +116,17 @@ hipError_t launch_setup_finalize(const GridArgs& g, const Geometry& geo, const S
                                  hipStream_t s);
 // One iteration of the paper's method on all slots (FP64 fields) or one inner
 // iteration (FP32 fields).
+// HIP events around the launches of one sweep kind inside solves (sweep 0: off);
+// the host reads the `used` pairs after the solve and resets `used`.
+struct SweepTimer {
+    static constexpr int kCap = 256;
+    int sweep = 0;
+    bool fp32 = false;
+    int used = 0;
+    hipEvent_t ev[2 * kCap] = {};
+};
 hipError_t launch_iteration(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slots,
-                            int nslots, bool fp32, hipStream_t s);
+                            int nslots, bool fp32, hipStream_t s, SweepTimer* tm = nullptr);
 // One sweep alone (1: P1, 2: P2 and P4, 3: P3, 5: P5), for timing.
 hipError_t launch_sweep(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32, int which,
                         hipStream_t s);

@@ -159,6 +159,7 @@ __global__ void __launch_bounds__(256) k_finalize(GridArgs g, const Slot* __rest
     double sums[4];  // sum r^2, sum bt^2, sum p, sum p^2
     sum_partials<4>(s.partial, nblk, sums, red);
     if (threadIdx.x != 0) return;
+    st->p1_work += 1;  // this kernel runs exactly when P1 did
     const int k = st->iter;
     st->p_sum = sums[2];
     st->p_sumsq = sums[3];
@@ -180,6 +181,7 @@ __global__ void __launch_bounds__(256) k_finalize(GridArgs g, const Slot* __rest
     const double rel = rn / st->b_norm;
     st->r_norm = rn;
     st->rel = rel;
+    if (k == 0) st->rel0 = rel;
     if (k < kHistCap) st->hist[k] = rel;
     if (rel <= st->tol) {
         st->done = 1;
@@ -255,6 +257,7 @@ __global__ void __launch_bounds__(256) k_finalize_inner(GridArgs g, const Slot* 
     double sums[2];
     sum_partials<2>(s.partial, nblk, sums, red);
     if (threadIdx.x != 0) return;
+    st->p1_work += 1;  // this kernel runs exactly when P1 did
     const int t = st->inner_iter;
     if (t == 0) st->rhs_norm32 = sqrt(sums[1]);
     const double rel = (st->rhs_norm32 > 0.0) ? sqrt(sums[0]) / st->rhs_norm32 : 0.0;
@@ -626,19 +629,30 @@ hipError_t launch_setup_finalize(const GridArgs& g, const Geometry& geo, const S
 // P1, convergence check, P2, P3, P4 (= P2), P5.  MODE 1 is the stand-alone
 // L^+ q sweep (q in slot.b, result in slot.p), which has no check.
 static hipError_t five_sweeps(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32,
-                              int mode, hipStream_t s) {
+                              int mode, hipStream_t s, SweepTimer* tm) {
     hipError_t e;
     int nbx = 0;
-    if ((e = launch_sweep_mode(g, t, slots, nslots, fp32, 1, mode, s, &nbx)) != hipSuccess) return e;
+    // one sweep, bracketed by the timer's events when it times this sweep
+    auto sweep = [&](int which, int* nb) -> hipError_t {
+        const bool timed = tm && tm->sweep == which && tm->fp32 == fp32 && tm->used < SweepTimer::kCap;
+        if (timed && (e = hipEventRecord(tm->ev[2 * tm->used], s)) != hipSuccess) return e;
+        if ((e = launch_sweep_mode(g, t, slots, nslots, fp32, which, mode, s, nb)) != hipSuccess) return e;
+        if (timed) {
+            if ((e = hipEventRecord(tm->ev[2 * tm->used + 1], s)) != hipSuccess) return e;
+            ++tm->used;
+        }
+        return hipSuccess;
+    };
+    if ((e = sweep(1, &nbx)) != hipSuccess) return e;
     if (mode == 0) {
         if (!fp32) k_finalize<<<nslots, 256, 0, s>>>(g, slots, nbx);
         else k_finalize_inner<<<nslots, 256, 0, s>>>(g, slots, nbx, kMaxInnerPerStep);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if ((e = launch_sweep_mode(g, t, slots, nslots, fp32, 2, mode, s, nullptr)) != hipSuccess) return e;
-    if ((e = launch_sweep_mode(g, t, slots, nslots, fp32, 3, mode, s, nullptr)) != hipSuccess) return e;
-    if ((e = launch_sweep_mode(g, t, slots, nslots, fp32, 2, mode, s, nullptr)) != hipSuccess) return e;
-    return launch_sweep_mode(g, t, slots, nslots, fp32, 5, mode, s, nullptr);
+    if ((e = sweep(2, nullptr)) != hipSuccess) return e;
+    if ((e = sweep(3, nullptr)) != hipSuccess) return e;
+    if ((e = sweep(2, nullptr)) != hipSuccess) return e;
+    return sweep(5, nullptr);
 }
 
 hipError_t launch_sweep(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32, int which,
@@ -647,9 +661,9 @@ hipError_t launch_sweep(const GridArgs& g, const Tables& t, const Slot* slots, i
 }
 
 hipError_t launch_iteration(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slots,
-                            int nslots, bool fp32, hipStream_t s) {
+                            int nslots, bool fp32, hipStream_t s, SweepTimer* tm) {
     (void)geo;
-    return five_sweeps(g, t, slots, nslots, fp32, 0, s);
+    return five_sweeps(g, t, slots, nslots, fp32, 0, s, tm);
 }
 
 hipError_t launch_outer_resid_sweep(const GridArgs& g, const Slot* slots, int nslots, hipStream_t s, int* nblocks) {
@@ -702,7 +716,7 @@ hipError_t launch_residual(const GridArgs& g, const Geometry& geo, const Slot* s
 hipError_t launch_lap_pinv(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slot,
                            hipStream_t s) {
     (void)geo;
-    return five_sweeps(g, t, slot, 1, false, 1, s);
+    return five_sweeps(g, t, slot, 1, false, 1, s, nullptr);
 }
 
 }  // namespace pois

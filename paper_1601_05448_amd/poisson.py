@@ -48,7 +48,7 @@ class poisson_stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("outer_iters", ctypes.c_int),
                 ("rel_resid", ctypes.c_double), ("b_mean_removed", ctypes.c_double),
                 ("b_norm", ctypes.c_double), ("rho_min", ctypes.c_double), ("rho_max", ctypes.c_double),
-                ("err_bound_rel", ctypes.c_double), ("ms", ctypes.c_double)]
+                ("err_bound_rel", ctypes.c_double), ("ms", ctypes.c_double), ("p1_sweeps", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -91,6 +91,8 @@ def load() -> ctypes.CDLL:
     lib.poisson_residual.argtypes = [vp, vp, vp, vp, vp, pd, pd]
     lib.poisson_lap_pinv.argtypes = [vp, vp, vp]
     lib.poisson_time_sweep.argtypes = [vp, i, i, vp, vp, vp, i, pd]
+    lib.poisson_kernel_timer.argtypes = [vp, i, i]
+    lib.poisson_kernel_timer_read.argtypes = [vp, pd, ctypes.POINTER(ll)]
     if hasattr(lib, "poisson_server_create"):
         lib.poisson_server_create.argtypes = [ctypes.c_size_t, i, i, i, i, i, vp, ctypes.POINTER(vp)]
         lib.poisson_server_submit.argtypes = [vp, i, i, i, d, d, d, vp, vp, vp, d, ctypes.POINTER(ll)]
@@ -191,12 +193,30 @@ def poisson_lap_pinv(h: int, q, delta) -> None:
 
 
 def poisson_time_sweep(h: int, sweep: int, fp32: bool, rho, b, p, reps: int) -> float:
-    """Average milliseconds of one sweep (1, 2, 3 or 5); p is overwritten."""
+    """Average milliseconds of one sweep (1, 2, 3, 5, or 6 = FP64 outer residual
+    of a FP32_REFINE handle); p is overwritten."""
     ms = ctypes.c_double()
     rc = load().poisson_time_sweep(h, sweep, 1 if fp32 else 0, _ptr(rho), _ptr(b), _ptr(p), reps, ctypes.byref(ms))
     if rc != POISSON_OK:
         raise PoissonError(rc, "poisson_time_sweep")
     return ms.value
+
+
+def poisson_kernel_timer(h: int, sweep: int, fp32: bool = False) -> None:
+    """Bracket every later launch of `sweep` (1, 2, 3, 5; 0 = off) inside solves
+    with HIP events; resets the sums."""
+    rc = load().poisson_kernel_timer(h, sweep, 1 if fp32 else 0)
+    if rc != POISSON_OK:
+        raise PoissonError(rc, "poisson_kernel_timer")
+
+
+def poisson_kernel_timer_read(h: int) -> tuple:
+    """(summed milliseconds, bracketed launches) since the timer was set."""
+    ms, n = ctypes.c_double(), ctypes.c_longlong()
+    rc = load().poisson_kernel_timer_read(h, ctypes.byref(ms), ctypes.byref(n))
+    if rc != POISSON_OK:
+        raise PoissonError(rc, "poisson_kernel_timer_read")
+    return ms.value, n.value
 
 
 # ---- serving -------------------------------------------------------------------

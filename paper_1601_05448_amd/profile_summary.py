@@ -1,0 +1,169 @@
+"""Short text summaries of rocprofv3 output (its SQLite ``*_results.db``).
+
+    # per-kernel durations of a --kernel-trace run
+    python -m paper_1601_05448_amd.profile_summary stats DIR [--top 20]
+
+    # HBM bytes per launch of one kernel from a FETCH_SIZE run and a WRITE_SIZE
+    # run, each scaled by what the counter reads for a device copy of known size
+    python -m paper_1601_05448_amd.profile_summary traffic --fetch DIR --write DIR \\
+        --kernel 'k_resid_dhtx_z<float, 256' --key f32:k_resid_dhtx_z@256 --copy-mib 1024 \\
+        --json profiles/traffic.json
+
+    # HBM bytes per cell of every kernel from the same two runs
+    python -m paper_1601_05448_amd.profile_summary bytes --fetch DIR --write DIR --cells 16777216
+
+The traffic record carries a hash of the kernel sources, so that a reader can
+tell counters taken on older code from current ones.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sqlite3
+import statistics
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("poisson_sweeps.hip", "poisson_device.hpp", "poisson_fft.hpp", "poisson_internal.hpp",
+                  "poisson_kernels.hip")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def _db(d: str) -> sqlite3.Connection:
+    files = sorted(glob.glob(os.path.join(d, "**", "*.db"), recursive=True))
+    if not files:
+        raise SystemExit(f"no rocprofv3 database under {d}")
+    return sqlite3.connect(files[0])
+
+
+def kernel_durations(d: str) -> dict:
+    """kernel name -> list of dispatch durations (ns)."""
+    out: dict = {}
+    for name, dur in _db(d).execute("select name, duration from kernels"):
+        out.setdefault(name, []).append(float(dur))
+    return out
+
+
+def counter_values(d: str, counter: str) -> dict:
+    """kernel name -> list of per-dispatch values of `counter` (summed over the
+    dispatch's instances)."""
+    per: dict = {}
+    q = "select dispatch_id, kernel_name, value from counters_collection where counter_name = ?"
+    for disp, name, val in _db(d).execute(q, (counter,)):
+        key = (disp, name)
+        per[key] = per.get(key, 0.0) + float(val)
+    out: dict = {}
+    for (_, name), v in per.items():
+        out.setdefault(name, []).append(v)
+    return out
+
+
+def cmd_stats(a) -> None:
+    durs = kernel_durations(a.dir)
+    total = sum(sum(v) for v in durs.values())
+    rows = sorted(durs.items(), key=lambda kv: -sum(kv[1]))[: a.top]
+    print(f"{'calls':>6} {'total_ms':>9} {'avg_us':>8} {'min_us':>8} {'max_us':>8} {'pct':>6}  kernel")
+    for name, v in rows:
+        print(f"{len(v):6d} {sum(v) / 1e6:9.3f} {statistics.fmean(v) / 1e3:8.1f} {min(v) / 1e3:8.1f} "
+              f"{max(v) / 1e3:8.1f} {100 * sum(v) / total:6.2f}  {name[:150]}")
+
+
+def _pick(values: dict, match: str) -> tuple:
+    names = [n for n in values if match in n]
+    if not names:
+        raise SystemExit(f"no kernel matching {match!r}; have: {sorted(values)[:20]}")
+    vals = [x for n in names for x in values[n]]
+    return names, vals
+
+
+def cmd_traffic(a) -> None:
+    copy_bytes = a.copy_mib * (1 << 20)
+    res = {}
+    for counter, d in (("FETCH_SIZE", a.fetch), ("WRITE_SIZE", a.write)):
+        vals = counter_values(d, counter)
+        _, copies = _pick(vals, a.copy_kernel)
+        copy_kib = max(copies)  # the 1 GiB copy is the largest dispatch of its kernel
+        scale = (copy_bytes / 1024.0) / copy_kib
+        names, kv = _pick(vals, a.kernel)
+        # launches that did their work (an idle launch reads a few KiB)
+        big = [x for x in kv if x > 0.1 * max(kv)]
+        kib = statistics.median(big)
+        res[counter] = dict(kib_per_launch=kib, launches=len(big), copy_kib=copy_kib, scale=scale,
+                            bytes_per_launch=kib * 1024.0 * scale, kernels=names)
+    total = res["FETCH_SIZE"]["bytes_per_launch"] + res["WRITE_SIZE"]["bytes_per_launch"]
+    for counter, r in res.items():
+        print(f"{counter}: {r['kib_per_launch']:.0f} KiB per launch (median of {r['launches']}), copy of "
+              f"{a.copy_mib} MiB reads {r['copy_kib']:.0f} KiB -> scale {r['scale']:.4f} -> "
+              f"{r['bytes_per_launch'] / 1e6:.1f} MB per launch")
+    print(f"HBM traffic per launch: {total / 1e6:.1f} MB ({a.key})")
+    if a.json:
+        try:
+            with open(a.json) as f:
+                db = json.load(f)
+        except (OSError, ValueError):
+            db = {}
+        db[a.key] = dict(bytes_per_launch=total, fetch_bytes=res["FETCH_SIZE"]["bytes_per_launch"],
+                         write_bytes=res["WRITE_SIZE"]["bytes_per_launch"],
+                         fetch_scale=res["FETCH_SIZE"]["scale"], write_scale=res["WRITE_SIZE"]["scale"],
+                         kernels=res["FETCH_SIZE"]["kernels"], source_sha256=kernel_source_hash())
+        with open(a.json, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+            f.write("\n")
+
+
+def cmd_bytes(a) -> None:
+    """HBM bytes per grid cell read and written by every kernel, each counter
+    scaled by the copy kernel's reading (working launches only)."""
+    copy_kib = a.copy_mib * 1024.0
+    f = counter_values(a.fetch, "FETCH_SIZE")
+    w = counter_values(a.write, "WRITE_SIZE")
+    fs = copy_kib / max(_pick(f, a.copy_kernel)[1])
+    ws = copy_kib / max(_pick(w, a.copy_kernel)[1])
+    print(f"scales: FETCH_SIZE x{fs:.4f}, WRITE_SIZE x{ws:.4f} (copy of {a.copy_mib} MiB); cells {a.cells}")
+    print(f"{'read B/cell':>11} {'write B/cell':>12}  kernel")
+    for name in sorted(f, key=lambda n: -max(f[n])):
+        fv = [x for x in f[name] if x > 0.1 * max(f[name])]
+        wl = w.get(name, [0.0])
+        wv = [x for x in wl if x >= 0.1 * max(wl)] or [0.0]
+        if max(fv) * fs * 1024 < 0.5 * a.cells:
+            continue
+        print(f"{statistics.median(fv) * fs * 1024 / a.cells:11.2f} {statistics.median(wv) * ws * 1024 / a.cells:12.2f}"
+              f"  {name[:110]}")
+
+
+def main(argv=None) -> None:
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("--top", type=int, default=20)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--kernel", required=True, help="substring of the kernel name")
+    t.add_argument("--key", required=True)
+    t.add_argument("--copy-kernel", default="copy", help="substring of the copy kernel's name")
+    t.add_argument("--copy-mib", type=int, default=1024)
+    t.add_argument("--json", default="")
+    b = sub.add_parser("bytes")
+    b.add_argument("--fetch", required=True)
+    b.add_argument("--write", required=True)
+    b.add_argument("--cells", type=int, required=True)
+    b.add_argument("--copy-kernel", default="copy")
+    b.add_argument("--copy-mib", type=int, default=1024)
+    a = ap.parse_args(argv)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "bytes": cmd_bytes}[a.cmd](a)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -110,13 +110,15 @@ def _solve_gpu(prob, precision=P.POISSON_FP64, coef=0, weight=0, tol=1e-10, p0=N
     return host(p), st, hist
 
 
-def _check_solution(prob, p, st, ref, coef=0, tol=1e-10):
+def _check_solution(prob, p, st, ref, coef=0, tol=1e-10, ref_bound=0.0):
+    """ref_bound: bound on the reference's own relative error (added to the
+    GPU answer's bound when the reference is not much more accurate)."""
     res = oracle.residual(prob.rho, prob.b, p, prob.lengths, coef)
     assert st["code"] == P.POISSON_OK, st
     assert res["rel"] <= tol, res
     assert abs(st["rel_resid"] - res["rel"]) <= 1e-3 * res["rel"] + 1e-15
     err = rel_l2(p, ref)
-    assert err <= st["err_bound_rel"] * (1 + 1e-6) + 1e-14, (err, st["err_bound_rel"])
+    assert err <= st["err_bound_rel"] * (1 + 1e-6) + ref_bound + 1e-14, (err, st["err_bound_rel"], ref_bound)
     assert err <= 1e-8
     assert abs(p.mean()) <= 1e-12 * np.max(np.abs(p))
     return err
@@ -156,6 +158,46 @@ def test_solve_ragged_tiles(shape):
     ref = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, tol=1e-13)
     p, st, _ = _solve_gpu(prob)
     _check_solution(prob, p, st, ref["p"])
+
+
+@pytest.mark.parametrize("shape", [(6, 12, 128), (24, 6, 512), (24, 12, 64), (12, 8, 1024)])
+def test_solve_fp32_refine_ragged_outer_tiles(shape):
+    """FP32 refinement where the FP64 outer residual's column tiles are ragged:
+    fewer planes than a tile, row-pair strips past the grid, two and four
+    columns per thread."""
+    announce("solve fp32 refine ragged", shape)
+    prob = inputs.small_problem(shape=shape, lengths=(TWO_PI, TWO_PI, TWO_PI), ratio=4.0)
+    # with 512 or 1024 cells along x and a few along y the FP64 rounding floor of
+    # the relative residual is near 1e-12: the reference takes what 40
+    # iterations reach, and its own a-posteriori bound joins the GPU's
+    ref = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, tol=1e-14, max_iter=40, allow_noconv=True)
+    rr = oracle.residual(prob.rho, prob.b, ref["p"], prob.lengths)
+    ref_bound = oracle.error_bound(prob.shape, prob.lengths, float(prob.rho.max()), rr["r_norm"]) / \
+        np.linalg.norm(ref["p"])
+    p, st, _ = _solve_gpu(prob, precision=P.POISSON_FP32_REFINE)
+    _check_solution(prob, p, st, ref["p"], ref_bound=ref_bound)
+
+
+@pytest.mark.parametrize("precision", [P.POISSON_FP64, P.POISSON_FP32_REFINE])
+def test_kernel_timer_counts_residual_sweeps(precision):
+    """The event timer brackets every launch of P1 inside a solve; the launches
+    that did work are one per residual evaluation."""
+    announce("kernel timer", precision)
+    prob = inputs.workload2(64)
+    fp32 = precision == P.POISSON_FP32_REFINE
+    with P.Solver(prob.shape, prob.lengths, precision=precision) as s:
+        P.poisson_kernel_timer(s.h, 1, fp32)
+        p = dev(np.zeros(prob.shape))
+        st = s.solve(dev(prob.rho), dev(prob.b), p, 1e-10)
+        ms, n = P.poisson_kernel_timer_read(s.h)
+        P.poisson_kernel_timer(s.h, 0)
+        st2 = s.solve(dev(prob.rho), dev(prob.b), p, 1e-10)
+        assert P.poisson_kernel_timer_read(s.h) == (0.0, 0)
+    assert st["code"] == P.POISSON_OK
+    want = st["iters"] + (st["outer_iters"] if fp32 else 1)
+    assert st["p1_sweeps"] == want, st
+    assert n >= want and ms > 0.0
+    assert st2["code"] == P.POISSON_OK
 
 
 @pytest.mark.parametrize("maker", ["sinusoidal32", "lognormal64", "deposit64"])
