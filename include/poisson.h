@@ -78,7 +78,7 @@ typedef struct {
     int max_iter;         /* cap on (inner) iterations; <= 0 selects 1000           */
     void* stream;         /* hipStream_t to run on; NULL = the null stream          */
     double inner_tol;     /* FP32_REFINE: relative residual at which the FP32 inner
-                             sweeps of a refinement step stop; <= 0 selects 1e-4   */
+                             sweeps of a refinement step stop; <= 0 selects 5e-4   */
 } poisson_opts;
 
 typedef struct {

@@ -328,6 +328,17 @@ struct ZMarch {
     }
 };
 
+// The blocks of a launch go to the chip's 8 XCDs round-robin (block b to XCD
+// b % 8), and every XCD has its own L2.  xcd_block renumbers the blocks so that
+// the ones on one XCD hold consecutive numbers: neighbouring z-marching tiles,
+// which read each other's y halo rows, then meet in the same L2 instead of
+// fetching those rows from HBM again.  A bijection of [0, nb); the identity
+// when nb is not a multiple of 8.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+    constexpr unsigned kXcds = 8;
+    return (nb % kXcds != 0) ? b : (b % kXcds) * (nb / kXcds) + b / kXcds;
+}
+
 // Thread layout of a z-marching tile for rows of length N handled by NT
 // threads: SUB strips (row pairs) of N threads each when N < NT, or CPT columns
 // per thread when N >= NT; KC planes per tile so that a tile has L row pairs.

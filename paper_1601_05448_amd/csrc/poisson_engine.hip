@@ -236,7 +236,10 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
         // whose inner sweeps are not done leaves the update and the next outer
         // residual to idle until they are.  Each cycle moves every unfinished
         // solve on by at least one stage, so the count of cycles is bounded.
-        int chunk = prm.first_chunk;
+        // inner launches of the first step: a contraction of 0.2 per sweep
+        // (typical of the method on smooth densities), plus the launch whose
+        // residual evaluation stops the sweeps
+        int chunk = std::clamp((int)std::ceil(std::log(prm.inner_tol) / std::log(0.2)) + 1, 1, prm.max_chunk);
         const int max_cycles = prm.max_outer + prm.max_iter + 2;
         for (int cycle = 0; cycle < max_cycles; ++cycle) {
             if ((e = launch_outer_residual(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
@@ -247,21 +250,34 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
             const int r = poll();
             if (r < 0) return r;
             if (r == 1) break;
-            // the next cycle's inner sweeps: as many as any solve used in its
-            // last finished step (steps need about the same number), doubled
-            // while a solve is still inside its inner sweeps, none when every
-            // open solve is predicted to pass its tolerance at the next outer
-            // residual (last outer residual times the last inner reduction)
-            int most = 0;
-            bool inner_open = false, all_pass = true;
+            // The next cycle's inner launches.  A solve still inside its inner
+            // sweeps: the launches that bring its inner residual to the inner
+            // tolerance at the contraction it has shown (twice the last chunk
+            // when it has shown none).  A solve between steps: as many as its
+            // last step used (steps need about the same number), or none when
+            // the next outer residual is predicted to pass the tolerance (last
+            // outer residual times the last inner reduction).
+            int need = 0;
+            bool all_pass = true;
             for (int q = 0; q < nslots; ++q) {
-                if (hdr[q].done) continue;
-                inner_open |= hdr[q].stage == 1;
-                most = std::max(most, hdr[q].inner_last);
-                all_pass &= hdr[q].stage == 0 && hdr[q].rel * hdr[q].rel_in <= 0.5 * hdr[q].tol;
+                const SolveState& h = hdr[q];
+                if (h.done) continue;
+                int m;
+                if (h.stage == 1) {
+                    all_pass = false;
+                    m = 2 * std::max(chunk, 1);
+                    const int k = h.inner_iter - 1;  // index of the last inner residual evaluated
+                    if (k >= 1 && h.rel_in > 0.0 && h.rel_in < 1.0) {
+                        const double rate = std::pow(h.rel_in, 1.0 / k);
+                        if (rate < 0.95) m = (int)std::ceil(std::log(h.inner_tol / h.rel_in) / std::log(rate) + 0.25);
+                    }
+                } else {
+                    all_pass &= h.rel * h.rel_in <= 0.5 * h.tol;
+                    m = h.inner_last;
+                }
+                need = std::max(need, m);
             }
-            if (inner_open) chunk = std::max(1, std::min(std::max(chunk, 1) * 2, prm.max_chunk));
-            else chunk = all_pass ? 0 : std::clamp(most, 1, prm.max_chunk);
+            chunk = all_pass ? 0 : std::clamp(need, 1, prm.max_chunk);
         }
     }
     if ((e = launch_fixup(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
@@ -358,7 +374,7 @@ int poisson_create(const poisson_opts* o, poisson_t* out) {
     if (!h) return POISSON_ENOMEM;
     h->o = *o;
     if (h->o.max_iter <= 0) h->o.max_iter = 1000;
-    if (!(h->o.inner_tol > 0.0)) h->o.inner_tol = 1e-4;
+    if (!(h->o.inner_tol > 0.0)) h->o.inner_tol = 5e-4;
     h->stream = static_cast<hipStream_t>(o->stream);
     if (hipGetDevice(&h->device) != hipSuccess) {
         delete h;

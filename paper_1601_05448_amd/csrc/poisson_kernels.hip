@@ -377,7 +377,7 @@ __global__ void __launch_bounds__(256) k_outer_resid(GridArgs g, const Slot* __r
     zm.sz = (unsigned)g.nx * (unsigned)g.ny;
     zm.lane = (int)(threadIdx.x & 63);
     double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (unsigned tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (unsigned tile = xcd_block(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x) {
         const unsigned tj = tile % ngj, tk = tile / ngj;
         const unsigned jp = tj * O::SUB + sidx;
         const bool jvalid = jp < nyh;

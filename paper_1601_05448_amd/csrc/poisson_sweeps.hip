@@ -163,7 +163,7 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     zm.lane = (int)(threadIdx.x & 63);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};  // sum r^2, sum bt^2, sum p, sum p^2
 
-    for (unsigned tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (unsigned tile = xcd_block(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x) {
         const unsigned tj = tile % ngj, tk = tile / ngj;
         const unsigned jp = tj * Z::SUB + sidx;
         const bool jvalid = jp < nyh;
