@@ -108,6 +108,39 @@ def time_path(P, torch, prob, precision, steps, warmup, tol):
     return out
 
 
+def serve_leg(P, torch, count, budget_gb, slots, precision):
+    """The served stream (Poisson arrivals, grids drawn from 64^3..192^3, each
+    with its own lognormal rho): first all requests at once to measure the
+    capacity, then in real time at 0.7x that rate; latency = arrival to done."""
+    from paper_1601_05448_amd import inputs, serve
+
+    reqs = inputs.request_stream(count)
+    fields = [inputs.request_fields_device(r) for r in reqs]
+    budget = int(budget_gb * (1 << 30))
+
+    def jobs_for(stream):
+        return [serve.Job(r.arrival_s, (r.n,) * 3, (2 * math.pi,) * 3, f[0], f[1],
+                          torch.zeros((r.n,) * 3, dtype=torch.float64, device="cuda"))
+                for r, f in zip(stream, fields)]
+
+    with serve.Server(budget, slots, precision=precision) as srv:
+        serve.replay(srv, jobs_for(reqs[: min(16, count)]), realtime=False)  # warm-up
+        torch.cuda.synchronize()
+        cap = serve.replay(srv, jobs_for(reqs), realtime=False)
+        capacity = len(cap.outcomes) / cap.wall_s
+        rate = 0.7 * capacity
+        stream = inputs.request_stream(count, rate_hz=rate)
+        live = serve.replay(srv, jobs_for(stream), realtime=True)
+    bad = [o for o in live.outcomes if o.stats["status"] != 0 or o.stats["rel_resid"] > 1e-10]
+    if bad or len(live.outcomes) != count:
+        raise RuntimeError(f"served solves failed: {len(bad)} bad of {len(live.outcomes)}")
+    lat = live.latencies()
+    return {"requests": count, "sizes": list(inputs.SERVE_SIZES), "budget_gb": budget_gb, "slots": slots,
+            "precision": "fp64" if precision == P.POISSON_FP64 else "fp32_refine", "tol": 1e-10,
+            "capacity_solves_per_s": capacity, "rate_hz": rate, "solves_per_s": len(lat) / live.wall_s,
+            "p50_ms": percentile(lat, 0.5), "p99_ms": percentile(lat, 0.99)}
+
+
 def cpu_baseline(prob, fp64_iters):
     """The oracle (single-threaded C, FP64) on a bounded sample of the same
     workload: one residual evaluation plus one iteration, scaled to the
@@ -137,6 +170,8 @@ def main():
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=512, help="0 skips the served stream")
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see the design notes on "
@@ -180,6 +215,8 @@ def main():
         "paths": {"fp64": fp64, "fp32_refine": fp32},
         "roofline": roofline,
     }
+    if args.serve_requests > 0:
+        line["serving"] = serve_leg(P, torch, args.serve_requests, args.serve_budget_gb, 64, P.POISSON_FP64)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prob, fp64["iters"])
     print(json.dumps(line))
