@@ -76,9 +76,14 @@ typedef struct {
     int coef;             /* POISSON_COEF_*                                         */
     int weight;           /* POISSON_W_*                                            */
     int max_iter;         /* cap on (inner) iterations; <= 0 selects 1000           */
-    void* stream;         /* hipStream_t to run on; NULL = the null stream          */
+    void* stream;         /* the caller's hipStream_t (NULL = the null stream): a
+                             solve is ordered after the work enqueued on it before
+                             the call and runs on a stream of the handle's own      */
     double inner_tol;     /* FP32_REFINE: relative residual at which the FP32 inner
                              sweeps of a refinement step stop; <= 0 selects 5e-4   */
+    int use_graphs;       /* nonzero: chunks of iterations are captured once into
+                             HIP graphs and replayed; 0: every kernel is launched
+                             directly (same kernels, same results)                 */
 } poisson_opts;
 
 typedef struct {

@@ -175,8 +175,32 @@ Slot Workspace::slot(const double* rho, const double* b, double* p, double tol) 
 // nslots state headers.
 int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* d_slots, int nslots,
                 SolveState* const* d_states, SolveState* hdr, const SolveParams& prm, hipStream_t s,
-                SweepTimer* tm) {
+                SweepTimer* tm, GraphCache* gc) {
     hipError_t e;
+    // n iterations: replayed graphs of 16, 8, 4, 2, 1 iterations when a graph
+    // cache is given (and no timer brackets single launches), else direct launches
+    auto iterations = [&](int n, bool f32) -> hipError_t {
+        if (!gc || tm) {
+            for (int c = 0; c < n; ++c) {
+                const hipError_t le = launch_iteration(g, geo, t, d_slots, nslots, f32, s, tm);
+                if (le != hipSuccess) return le;
+            }
+            return hipSuccess;
+        }
+        for (int b = 4; b >= 0; --b) {
+            for (; n >= (1 << b); n -= (1 << b)) {
+                const hipError_t le = gc->run((f32 ? 16 : 0) + b, s, [&]() -> hipError_t {
+                    for (int c = 0; c < (1 << b); ++c) {
+                        const hipError_t ie = launch_iteration(g, geo, t, d_slots, nslots, f32, s, nullptr);
+                        if (ie != hipSuccess) return ie;
+                    }
+                    return hipSuccess;
+                });
+                if (le != hipSuccess) return le;
+            }
+        }
+        return hipSuccess;
+    };
     const bool fp32 = prm.precision == POISSON_FP32_REFINE;
     if ((e = launch_init(g, d_slots, nslots, prm.inner_tol, prm.max_iter, prm.max_outer, prm.precision, s)) !=
         hipSuccess)
@@ -204,9 +228,9 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
         std::vector<int> k_prev(nslots, -1);
         std::vector<double> r_prev(nslots, 0.0);
         while (true) {
-            for (int c = 0; c < chunk && launched < cap; ++c, ++launched)
-                if ((e = launch_iteration(g, geo, t, d_slots, nslots, false, s, tm)) != hipSuccess)
-                    return hip_status(e);
+            const int now = std::min(chunk, cap - launched);
+            if ((e = iterations(now, false)) != hipSuccess) return hip_status(e);
+            launched += now;
             const int r = poll();
             if (r < 0) return r;
             if (r == 1 || launched >= cap) break;
@@ -243,9 +267,7 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
         const int max_cycles = prm.max_outer + prm.max_iter + 2;
         for (int cycle = 0; cycle < max_cycles; ++cycle) {
             if ((e = launch_outer_residual(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
-            for (int c = 0; c < chunk; ++c)
-                if ((e = launch_iteration(g, geo, t, d_slots, nslots, true, s, tm)) != hipSuccess)
-                    return hip_status(e);
+            if ((e = iterations(chunk, true)) != hipSuccess) return hip_status(e);
             if ((e = launch_outer_update(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
             const int r = poll();
             if (r < 0) return r;
@@ -314,7 +336,10 @@ struct poisson_s {
     poisson_opts o{};
     GridArgs g{};
     Geometry geo{};
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // the caller's stream
+    hipStream_t run = nullptr;     // the library's stream for solves (graph capture needs one of its own)
+    hipEvent_t ev_in = nullptr;    // orders a solve after the caller's earlier work
+    GraphCache graphs;
     int device = 0;
     GridTables tables;
     Workspace ws;
@@ -356,6 +381,9 @@ void poisson_destroy(poisson_t h) {
     if (h->ev1) (void)hipEventDestroy(h->ev1);
     for (hipEvent_t& ev : h->timer.ev)
         if (ev) (void)hipEventDestroy(ev);
+    h->graphs.release();
+    if (h->ev_in) (void)hipEventDestroy(h->ev_in);
+    if (h->run) (void)hipStreamDestroy(h->run);
     h->ws.release();
     h->tables.release();
     delete h;
@@ -389,8 +417,11 @@ int poisson_create(const poisson_opts* o, poisson_t* out) {
         rc = POISSON_ENOMEM;
     if (rc == POISSON_OK && hipHostMalloc(&h->h_state, sizeof(SolveState), hipHostMallocDefault) != hipSuccess)
         rc = POISSON_ENOMEM;
-    if (rc == POISSON_OK && (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess))
+    if (rc == POISSON_OK && (hipEventCreate(&h->ev0) != hipSuccess || hipEventCreate(&h->ev1) != hipSuccess ||
+                             hipEventCreateWithFlags(&h->ev_in, hipEventDisableTiming) != hipSuccess))
         rc = POISSON_EHIP;
+    // default priority (no priority argument anywhere)
+    if (rc == POISSON_OK && hipStreamCreateWithFlags(&h->run, hipStreamNonBlocking) != hipSuccess) rc = POISSON_EHIP;
     if (rc != POISSON_OK) {
         poisson_destroy(h);
         return rc;
@@ -404,33 +435,38 @@ static bool overlaps(const void* a, const void* b, size_t bytes) {
     return x < y + bytes && y < x + bytes;
 }
 
-static int set_slot(poisson_t h, const Slot& s) {
+static int set_slot(poisson_t h, const Slot& s, hipStream_t st) {
     *h->h_slot = s;
-    return hip_status(hipMemcpyAsync(h->d_slot, h->h_slot, sizeof(Slot), hipMemcpyHostToDevice, h->stream));
+    return hip_status(hipMemcpyAsync(h->d_slot, h->h_slot, sizeof(Slot), hipMemcpyHostToDevice, st));
 }
+
+static int set_slot(poisson_t h, const Slot& s) { return set_slot(h, s, h->stream); }
 
 int poisson_solve(poisson_t h, const double* rho, const double* b, double* p, double tol) {
     if (!h || !rho || !b || !p || !(tol > 0.0) || !std::isfinite(tol)) return POISSON_EINVAL;
     const size_t bytes = (size_t)h->g.n * sizeof(double);
     if (overlaps(rho, b, bytes) || overlaps(rho, p, bytes) || overlaps(b, p, bytes)) return POISSON_EINVAL;
-    int rc = set_slot(h, h->ws.slot(rho, b, p, tol));
+    // the solve runs on the library's stream, after the caller's earlier work
+    int rc = hip_status(hipEventRecord(h->ev_in, h->stream));
+    if (rc == POISSON_OK) rc = hip_status(hipStreamWaitEvent(h->run, h->ev_in, 0));
+    if (rc == POISSON_OK) rc = set_slot(h, h->ws.slot(rho, b, p, tol), h->run);
     if (rc != POISSON_OK) return rc;
     SolveParams prm;
     prm.tol = tol;
     prm.precision = h->o.precision;
     prm.max_iter = h->o.max_iter;
     prm.inner_tol = h->o.inner_tol;
-    if ((rc = hip_status(hipEventRecord(h->ev0, h->stream))) != POISSON_OK) return rc;
+    if ((rc = hip_status(hipEventRecord(h->ev0, h->run))) != POISSON_OK) return rc;
     SolveState* dst = h->ws.st;
     h->timer.used = 0;
-    rc = drive_solve(h->g, h->geo, h->tables.t, h->d_slot, 1, &dst, h->h_state, prm, h->stream,
-                     h->timer.sweep ? &h->timer : nullptr);
+    rc = drive_solve(h->g, h->geo, h->tables.t, h->d_slot, 1, &dst, h->h_state, prm, h->run,
+                     h->timer.sweep ? &h->timer : nullptr, h->o.use_graphs ? &h->graphs : nullptr);
     if (rc != POISSON_OK) return rc;
-    if ((rc = hip_status(hipEventRecord(h->ev1, h->stream))) != POISSON_OK) return rc;
+    if ((rc = hip_status(hipEventRecord(h->ev1, h->run))) != POISSON_OK) return rc;
     if ((rc = hip_status(hipMemcpyAsync(h->h_state, h->ws.st, sizeof(SolveState), hipMemcpyDeviceToHost,
-                                        h->stream))) != POISSON_OK)
+                                        h->run))) != POISSON_OK)
         return rc;
-    if ((rc = hip_status(hipStreamSynchronize(h->stream))) != POISSON_OK) return rc;
+    if ((rc = hip_status(hipStreamSynchronize(h->run))) != POISSON_OK) return rc;
     const SolveState& st = *h->h_state;
     fill_stats(h->g, st, &h->stats);
     float ms = 0.f;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <map>
 
 #include "../../include/poisson.h"
 #include "poisson_internal.hpp"
@@ -42,6 +43,42 @@ struct Workspace {
     Slot slot(const double* rho, const double* b, double* p, double tol) const;
 };
 
+// Captured HIP graphs of fixed launch sequences, keyed by an integer: the first
+// run of a key captures what `enqueue` launches on the stream and instantiates
+// it; every run replays the instantiated graph on the stream.  The sequences
+// hold kernel launches only (no memsets, no host work), and their arguments
+// point at device records (slots, states) whose contents may change between
+// replays.
+struct GraphCache {
+    std::map<long long, hipGraphExec_t> exec;
+
+    template <class F>
+    hipError_t run(long long key, hipStream_t s, F&& enqueue) {
+        auto it = exec.find(key);
+        if (it == exec.end()) {
+            hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return e;
+            const hipError_t le = enqueue();
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(s, &g);
+            if (le != hipSuccess || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return le != hipSuccess ? le : e;
+            }
+            hipGraphExec_t x = nullptr;
+            e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) return e;
+            it = exec.emplace(key, x).first;
+        }
+        return hipGraphLaunch(it->second, s);
+    }
+    void release() {
+        for (auto& kv : exec) (void)hipGraphExecDestroy(kv.second);
+        exec.clear();
+    }
+};
+
 int hip_status(hipError_t e);
 bool valid_lengths(double lx, double ly, double lz);
 GridArgs make_grid(int nx, int ny, int nz, double lx, double ly, double lz, int coef, int weight);
@@ -49,7 +86,7 @@ double min_symbol(const GridArgs& g);
 size_t workspace_bytes(const GridArgs& g, const Geometry& geo, int precision);
 int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* d_slots, int nslots,
                 SolveState* const* d_states, SolveState* hdr, const SolveParams& prm, hipStream_t s,
-                SweepTimer* tm = nullptr);
+                SweepTimer* tm = nullptr, GraphCache* gc = nullptr);
 void fill_stats(const GridArgs& g, const SolveState& st, poisson_stats* out);
 
 }  // namespace pois

@@ -41,7 +41,8 @@ class poisson_opts(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
                 ("precision", ctypes.c_int), ("coef", ctypes.c_int), ("weight", ctypes.c_int),
-                ("max_iter", ctypes.c_int), ("stream", ctypes.c_void_p), ("inner_tol", ctypes.c_double)]
+                ("max_iter", ctypes.c_int), ("stream", ctypes.c_void_p), ("inner_tol", ctypes.c_double),
+                ("use_graphs", ctypes.c_int)]
 
 
 class poisson_stats(ctypes.Structure):
@@ -131,11 +132,12 @@ def _stream_ptr(stream) -> Optional[int]:
 
 def poisson_create(shape: Sequence[int], lengths: Sequence[float], precision: int = POISSON_FP64,
                    coef: int = POISSON_COEF_RHO_FACE_MEAN, weight: int = POISSON_W_RHO,
-                   max_iter: int = 0, stream=None, inner_tol: float = 0.0) -> int:
+                   max_iter: int = 0, stream=None, inner_tol: float = 0.0, use_graphs: bool = False) -> int:
     """Handle for grid `shape` = (nz, ny, nx) on box `lengths` = (lx, ly, lz)."""
     nz, ny, nx = (int(v) for v in shape)
     o = poisson_opts(nx, ny, nz, float(lengths[0]), float(lengths[1]), float(lengths[2]),
-                     precision, coef, weight, max_iter, _stream_ptr(stream), float(inner_tol))
+                     precision, coef, weight, max_iter, _stream_ptr(stream), float(inner_tol),
+                     1 if use_graphs else 0)
     h = ctypes.c_void_p()
     rc = load().poisson_create(ctypes.byref(o), ctypes.byref(h))
     if rc != POISSON_OK:
@@ -275,10 +277,11 @@ class Solver:
     max_iter: int = 0
     stream: object = None
     inner_tol: float = 0.0
+    use_graphs: bool = False
 
     def __post_init__(self):
         self.h = poisson_create(self.shape, self.lengths, self.precision, self.coef, self.weight,
-                                self.max_iter, self.stream, self.inner_tol)
+                                self.max_iter, self.stream, self.inner_tol, self.use_graphs)
 
     def solve(self, rho, b, p, tol: float = 1e-10) -> dict:
         rc = poisson_solve(self.h, rho, b, p, tol)

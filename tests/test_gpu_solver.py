@@ -200,6 +200,35 @@ def test_kernel_timer_counts_residual_sweeps(precision):
     assert st2["code"] == P.POISSON_OK
 
 
+@pytest.mark.parametrize("precision", [P.POISSON_FP64, P.POISSON_FP32_REFINE])
+@pytest.mark.parametrize("n", [32, 64])
+def test_graph_replays_match_plain_launches(precision, n):
+    """Captured HIP graphs of iteration chunks against the same kernels launched
+    one by one: three solves each, with eager work on the caller's stream
+    between them, bitwise equal results and equal iteration counts on every
+    replay."""
+    announce("graph replays", precision, n)
+    import torch
+
+    prob = inputs.workload2(n)
+    rho, b = dev(prob.rho), dev(prob.b)
+    outs = {}
+    for plain in (True, False):
+        with P.Solver(prob.shape, prob.lengths, precision=precision, use_graphs=not plain) as s:
+            p = dev(np.zeros(prob.shape))
+            runs = []
+            for rep in range(3):
+                p.zero_()
+                junk = torch.sin(rho) * (rep + 1)  # eager work between replays
+                st = s.solve(rho, b, p, 1e-10)
+                assert float(junk.sum()) != 0.0
+                runs.append((host(p).copy(), st["iters"], st["outer_iters"], st["rel_resid"]))
+            outs[plain] = runs
+    for (pa, ia, oa, ra), (pb, ib, ob, rb) in zip(outs[True], outs[False]):
+        assert np.array_equal(pa, pb) and (ia, oa, ra) == (ib, ob, rb)
+    assert all(np.array_equal(outs[False][0][0], r[0]) for r in outs[False])
+
+
 @pytest.mark.parametrize("maker", ["sinusoidal32", "lognormal64", "deposit64"])
 def test_solve_fp32_refine_matches_oracle(maker):
     """FP32 sweeps + FP64 refinement reach the same 1e-10 answer."""
