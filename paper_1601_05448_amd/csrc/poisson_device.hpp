@@ -251,11 +251,30 @@ struct PlaneSide {
     T ba, bb;
 };
 
+// Raw buffer loads (vector memory, no 64-bit address arithmetic per load): the
+// resource holds the base of one plane, so the per-thread offset within the
+// plane stays a 32-bit constant of the tile while the plane base is uniform
+// and lives in scalar registers.  Offsets past the plane read 0 instead of
+// faulting.
+constexpr int kBufferWord3 = 0x00020000;  // raw (untyped) buffer access on gfx9
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* base, unsigned long long off,
+                                                             unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char*>(static_cast<const char*>(base)) + off, (short)0,
+                                             (int)bytes, kBufferWord3);
+}
+
+template <typename T>
+__device__ __forceinline__ T buffer_load(__amdgpu_buffer_rsrc_t r, unsigned voff) {
+    if constexpr (sizeof(T) == 4) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, voff, 0, 0));
+    else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, voff, 0, 0));
+}
+
 template <typename T>
 struct ZMarch {
-    const POIS_GLOBAL T* p;
-    const POIS_GLOBAL T* rho;
-    const POIS_GLOBAL T* rhs;
+    const T* p;
+    const T* rho;
+    const T* rhs;
     unsigned nx, nz, sz;
     unsigned ra, rb, rm, rp;  // row offsets (row * nx) of a, b and the two halo rows
     int lane;
@@ -267,24 +286,31 @@ struct ZMarch {
         rm = (ja == 0 ? ny - 1 : ja - 1) * nx;
         rp = (jb + 1 == ny ? 0 : jb + 1) * nx;
     }
-    __device__ unsigned plane(int k) const {  // periodic plane index -> offset (k >= -1)
-        return ((unsigned)(k + (int)nz) % nz) * sz;
+    __device__ unsigned plane(int k) const {  // periodic plane index (k >= -1)
+        return (unsigned)(k + (int)nz) % nz;
+    }
+    __device__ __amdgpu_buffer_rsrc_t rsrc(const T* f, unsigned kp) const {
+        return plane_rsrc(f, (unsigned long long)kp * sz * sizeof(T), sz * (unsigned)sizeof(T));
     }
     // No load sits under divergent control flow: the compiler's wait counts stay
     // exact, so the loads of the next plane really overlap this plane's work.
-    __device__ void load_rows(unsigned po, unsigned i, PlaneRows<T>& r) const {
-        r.pa = p[po + ra + i];
-        r.pb = p[po + rb + i];
-        r.ra = rho[po + ra + i];
-        r.rb = rho[po + rb + i];
+    __device__ void load_rows(unsigned kp, unsigned i, PlaneRows<T>& r) const {
+        const auto bp = rsrc(p, kp), br = rsrc(rho, kp);
+        constexpr unsigned S = sizeof(T);
+        r.pa = buffer_load<T>(bp, (ra + i) * S);
+        r.pb = buffer_load<T>(bp, (rb + i) * S);
+        r.ra = buffer_load<T>(br, (ra + i) * S);
+        r.rb = buffer_load<T>(br, (rb + i) * S);
     }
-    __device__ void load_side(unsigned po, unsigned i, PlaneSide<T>& s) const {
-        s.pym = p[po + rm + i];
-        s.rym = rho[po + rm + i];
-        s.pyp = p[po + rp + i];
-        s.ryp = rho[po + rp + i];
-        s.ba = rhs[po + ra + i];
-        s.bb = rhs[po + rb + i];
+    __device__ void load_side(unsigned kp, unsigned i, PlaneSide<T>& s) const {
+        const auto bp = rsrc(p, kp), br = rsrc(rho, kp), bb = rsrc(rhs, kp);
+        constexpr unsigned S = sizeof(T);
+        s.pym = buffer_load<T>(bp, (rm + i) * S);
+        s.rym = buffer_load<T>(br, (rm + i) * S);
+        s.pyp = buffer_load<T>(bp, (rp + i) * S);
+        s.ryp = buffer_load<T>(br, (rp + i) * S);
+        s.ba = buffer_load<T>(bb, (ra + i) * S);
+        s.bb = buffer_load<T>(bb, (rb + i) * S);
     }
     // The columns beyond a wave's edges come from the neighbouring waves through
     // LDS: `edge` holds, per strip, two slots (lane 0, lane 63) of 4 values for

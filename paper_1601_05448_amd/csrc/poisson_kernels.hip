@@ -369,9 +369,9 @@ __global__ void __launch_bounds__(256) k_outer_resid(GridArgs g, const Slot* __r
     POIS_GLOBAL float* r32 = gptr(s.r32);
     POIS_GLOBAL float* d32 = gptr(s.d32);
     ZMarch<double> zm;
-    zm.p = gptr(s.p);
-    zm.rho = gptr(s.rho);
-    zm.rhs = gptr(s.b);
+    zm.p = s.p;
+    zm.rho = s.rho;
+    zm.rhs = s.b;
     zm.nx = (unsigned)g.nx;
     zm.nz = nz;
     zm.sz = (unsigned)g.nx * (unsigned)g.ny;

@@ -154,9 +154,9 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     const int sidx = (N >= C::NT) ? 0 : (int)threadIdx.x / N;
     const unsigned col0 = (N >= C::NT) ? threadIdx.x : threadIdx.x % N;
     ZMarch<T> zm;
-    zm.p = v.p;
-    zm.rho = v.rho;
-    zm.rhs = v.rhs;
+    zm.p = (const T*)v.p;
+    zm.rho = (const T*)v.rho;
+    zm.rhs = (const T*)v.rhs;
     zm.nx = (unsigned)g.nx;
     zm.nz = nz;
     zm.sz = (unsigned)g.nx * (unsigned)g.ny;
@@ -171,6 +171,7 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
         const int k0 = (int)(tk * Z::KC);
         PlaneRows<T> pl[Z::CPT][3];
         PlaneSide<T> sd[Z::CPT];
+        T tacc[2] = {T(0), T(0)};
 #pragma unroll
         for (int c = 0; c < Z::CPT; ++c) {
             const unsigned i = col0 + c * C::NT;
@@ -209,10 +210,17 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                 if (valid) {
                     const PairOut<T> o = pair_eval<T, COEF, WEIGHT>(g, in, v.rhs_mean, v.rmax, v.rinv);
                     qv = {o.a.w * o.a.r, o.b.w * o.b.r};
-                    acc[0] += (double)o.a.r * o.a.r + (double)o.b.r * o.b.r;
-                    acc[1] += (double)o.a.bt * o.a.bt + (double)o.b.bt * o.b.bt;
-                    acc[2] += (double)o.a.pc + (double)o.b.pc;
-                    acc[3] += (double)o.a.pc * o.a.pc + (double)o.b.pc * o.b.pc;
+                    if constexpr (sizeof(T) == 8) {
+                        acc[0] += o.a.r * o.a.r + o.b.r * o.b.r;
+                        acc[1] += o.a.bt * o.a.bt + o.b.bt * o.b.bt;
+                        acc[2] += o.a.pc + o.b.pc;
+                        acc[3] += o.a.pc * o.a.pc + o.b.pc * o.b.pc;
+                    } else {
+                        // FP32 inner sweeps: only the two norms are used (the
+                        // stopping test), summed in FP32 over the tile
+                        tacc[0] += o.a.r * o.a.r + o.b.r * o.b.r;
+                        tacc[1] += o.a.bt * o.a.bt + o.b.bt * o.b.bt;
+                    }
                 }
                 lds[(sidx * Z::KC + kk) * C::LS + C::pos(i)] = qv;
             }
@@ -223,6 +231,10 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                 pl[c][2] = nn[c];
                 sd[c] = ns[c];
             }
+        }
+        if constexpr (sizeof(T) == 4) {
+            acc[0] += (double)tacc[0];
+            acc[1] += (double)tacc[1];
         }
         __syncthreads();
         fft_block_lines<T, N>(lds, tw);
