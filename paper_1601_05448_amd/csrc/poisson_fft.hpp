@@ -245,6 +245,31 @@ __device__ __forceinline__ void fft_block_lines(cpx<T>* lds, const cpx<T>* tw) {
     fft_stages<T, N, 1, C::TT>(lds + line * C::LS, t, tw);
 }
 
+// Forward DFT of the block's lines for N = 256 = 16 x 16 with the line held in
+// registers: the thread with column index c (0..15) of a line enters with
+// v[a] = x[c + 16 a] and leaves with v[b] = X[c + 16 b].  Writing n = c + 16 a
+// and k = k1 + 16 b, X[k] = sum_c W16^(c b) W256^(c k1) sum_a x[c + 16 a] W16^(a k1):
+// a length-16 DFT over a in registers, the twiddles W256^(c k1), one transpose
+// through the line's LDS row (thread c writes (c, k1) to position 16 k1 + c and
+// then reads row 16 c + .., taking over the role k1 = c), and a length-16 DFT
+// in registers.  `ln` is the thread's line in LDS (LineCfg<T, 256> layout),
+// `tw` the 256 twiddles exp(-2 pi i t/256).  All threads of the block call it:
+// it holds two barriers, the second one guarding `ln` for its next writer.
+template <typename T>
+__device__ __forceinline__ void fft256_regs(cpx<T> (&v)[16], cpx<T>* ln, int c, const cpx<T>* tw) {
+    using C = LineCfg<T, 256>;
+    dft16(v);
+#pragma unroll
+    for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmul(v[k1], tw[c * k1]);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) ln[C::pos(16 * k1 + c)] = v[k1];
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 16; ++a) v[a] = ln[C::pos(16 * c + a)];
+    __syncthreads();
+    dft16(v);
+}
+
 // Hartley value of the pair-packed line at k from its DFT Z:
 // ((1+i) Z_k + (1-i) Z_{N-k}) / 2.
 template <typename T>

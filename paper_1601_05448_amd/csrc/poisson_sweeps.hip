@@ -30,7 +30,7 @@ namespace pois {
 // MODE 0: stencil residual of the iteration view; MODE 1: q = b (copy, for the
 // stand-alone L^+ sweep).
 template <typename T, int N, int MODE, int COEF, int WEIGHT>
-__global__ void __launch_bounds__((LineCfg<T, N>::NT))
+__global__ void __launch_bounds__((LineCfg<T, N>::NT), 2)
 k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     using C = LineCfg<T, N>;
     __shared__ cpx<T> lds[C::L * C::LS];
@@ -134,7 +134,7 @@ k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
 // then the tile's L lines are transformed along x.  The tile's line l = s KC + kk
 // is row pair jp = tj SUB + s of plane k = tk KC + kk.
 template <typename T, int N, int COEF, int WEIGHT>
-__global__ void __launch_bounds__((LineCfg<T, N>::NT))
+__global__ void __launch_bounds__((LineCfg<T, N>::NT), 2)
 k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     using C = LineCfg<T, N>;
     using Z = ZTile<N, C::NT, C::L>;
@@ -280,7 +280,7 @@ __device__ __forceinline__ unsigned col_base(const GridArgs& g, unsigned line) {
 }
 
 template <typename T, int N, int AX, int MODE>
-__global__ void __launch_bounds__((LineCfg<T, N>::NT))
+__global__ void __launch_bounds__((LineCfg<T, N>::NT), 2)
 k_dht_cols(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     using C = LineCfg<T, N>;
     __shared__ cpx<T> lds[C::L * C::LS];
@@ -307,6 +307,36 @@ k_dht_cols(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     unsigned grp = blockIdx.x, base;
     bool valid;
     load(grp, valid, base);
+    if constexpr (N == 256) {
+        // the line stays in registers; LDS only for one transpose and the
+        // exchange of the (k, N-k) partners
+        __syncthreads();  // twiddles
+        cpx<T>* ln = lds + l * C::LS;
+        while (true) {
+            cpx<T> v[16];
+#pragma unroll
+            for (int a = 0; a < 16; ++a) v[a] = buf[a];
+            const bool cur_valid = valid;
+            const unsigned cur_base = base;
+            const unsigned ng = grp + gridDim.x;
+            if (ng < ngroups) load(ng, valid, base);  // in flight during the FFT
+            fft256_regs<T>(v, ln, e0, tw);
+#pragma unroll
+            for (int b = 0; b < 16; ++b) ln[C::pos(e0 + 16 * b)] = v[b];
+            __syncthreads();
+            if (cur_valid) {
+#pragma unroll
+                for (int b = 0; b < 16; ++b) {
+                    const int k = e0 + 16 * b;
+                    gstore_c(Wc, cur_base + (unsigned)k * se, hartley(v[b], ln[C::pos((N - k) & (N - 1))]));
+                }
+            }
+            grp = ng;
+            if (grp >= ngroups) break;
+            __syncthreads();
+        }
+        return;
+    }
     while (true) {
 #pragma unroll
         for (int it = 0; it < C::IT; ++it) lds[l * C::LS + C::pos(e0 + it * C::TT)] = buf[it];
@@ -332,7 +362,7 @@ k_dht_cols(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
 
 // ---- P3: Hartley along z, divide by n * symbol, Hartley along z ----------------
 template <typename T, int N, int MODE>
-__global__ void __launch_bounds__((LineCfg<T, N>::NT))
+__global__ void __launch_bounds__((LineCfg<T, N>::NT), 2)
 k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     using C = LineCfg<T, N>;
     __shared__ cpx<T> lds[C::L * C::LS];
@@ -363,6 +393,53 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     unsigned grp = blockIdx.x, base;
     bool valid;
     load(grp, valid, base);
+    if constexpr (N == 256) {
+        // the line stays in registers (see fft256_regs); LDS only for the
+        // transposes and the exchange of the (k, N-k) partners
+        __syncthreads();  // twiddles
+        cpx<T>* ln = lds + l * C::LS;
+        while (true) {
+            cpx<T> v[16];
+#pragma unroll
+            for (int a = 0; a < 16; ++a) v[a] = buf[a];
+            const bool cur_valid = valid;
+            const unsigned cur_base = base;
+            const unsigned line = grp * C::L + l;
+            const unsigned j = cur_valid ? line / (unsigned)g.nxh : 0u, m = cur_valid ? line - j * (unsigned)g.nxh : 0u;
+            const T lxe = lamx[2 * m], lxo = lamx[2 * m + 1], lyj = lamy[j];
+            const unsigned ng = grp + gridDim.x;
+            if (ng < ngroups) load(ng, valid, base);  // in flight during the two FFTs
+            fft256_regs<T>(v, ln, e0, tw);  // v[b] = X[e0 + 16 b]
+#pragma unroll
+            for (int b = 0; b < 16; ++b) ln[C::pos(e0 + 16 * b)] = v[b];
+            __syncthreads();
+#pragma unroll
+            for (int b = 0; b < 16; ++b) {
+                const int k = e0 + 16 * b;
+                cpx<T> h = hartley(v[b], ln[C::pos((N - k) & (N - 1))]);
+                const T lzk = lamz[k];
+                h.x *= inv_symbol(lxe, lyj, lzk, nn);
+                h.y *= inv_symbol(lxo, lyj, lzk, nn);
+                v[b] = h;  // the second transform's input x[e0 + 16 b]
+            }
+            __syncthreads();
+            fft256_regs<T>(v, ln, e0, tw);
+#pragma unroll
+            for (int b = 0; b < 16; ++b) ln[C::pos(e0 + 16 * b)] = v[b];
+            __syncthreads();
+            if (cur_valid) {
+#pragma unroll
+                for (int b = 0; b < 16; ++b) {
+                    const int k = e0 + 16 * b;
+                    gstore_c(Wc, cur_base + (unsigned)k * se, hartley(v[b], ln[C::pos((N - k) & (N - 1))]));
+                }
+            }
+            grp = ng;
+            if (grp >= ngroups) break;
+            __syncthreads();
+        }
+        return;
+    }
     while (true) {
 #pragma unroll
         for (int it = 0; it < C::IT; ++it) lds[l * C::LS + C::pos(e0 + it * C::TT)] = buf[it];
@@ -408,7 +485,7 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
 // ---- P5: Hartley along x, update -----------------------------------------------
 // MODE 0: FP64 p += dp - mean(p) (or FP32 d32 += dp); MODE 1: assign to p (L^+ sweep).
 template <typename T, int N, int MODE>
-__global__ void __launch_bounds__((LineCfg<T, N>::NT))
+__global__ void __launch_bounds__((LineCfg<T, N>::NT), 2)
 k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     using C = LineCfg<T, N>;
     __shared__ cpx<T> lds[C::L * C::LS];
