@@ -172,6 +172,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=512, help="0 skips the served stream")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--large", action="store_true",
+                    help="also time the 512^3 particle-deposit workload (fields beyond the 256 MB MALL)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see the design notes on "
@@ -215,6 +217,12 @@ def main():
         "paths": {"fp64": fp64, "fp32_refine": fp32},
         "roofline": roofline,
     }
+    if args.large:
+        big = inputs.workload3(512)
+        line["large"] = {"workload": "512^3 particle-deposit rho (ratio 10), band-limited b, tol 1e-10",
+                         "fp64": time_path(P, torch, big, P.POISSON_FP64, 3, 1, args.tol),
+                         "fp32_refine": time_path(P, torch, big, P.POISSON_FP32_REFINE, 3, 1, args.tol)}
+        del big
     if args.serve_requests > 0:
         line["serving"] = serve_leg(P, torch, args.serve_requests, args.serve_budget_gb, 64, P.POISSON_FP64)
     if not args.no_cpu_baseline:

@@ -367,15 +367,20 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
 
 // Thread layout of a z-marching tile for rows of length N handled by NT
 // threads: SUB strips (row pairs) of N threads each when N < NT, or CPT columns
-// per thread when N >= NT; KC planes per tile so that a tile has L row pairs.
+// per thread when N >= NT.  A tile marches KM planes; every KF planes its L = SUB
+// KF lines are full and are transformed and written out ("flushed"), so that the
+// two z halo planes a tile reads are shared by KM >= 16 planes however few
+// lines the transform's LDS holds.
 template <int N, int NT, int L>
 struct ZTile {
     static constexpr int CPT = N >= NT ? N / NT : 1;
     static constexpr int SUB = N >= NT ? 1 : NT / N;
-    static constexpr int KC = L / SUB;
+    static constexpr int KF = L / SUB;
+    static constexpr int KM = KF >= 16 ? KF : 16;
     static constexpr int EDGE = (N / 64) * 2 * 4;  // edge values per strip and buffer
     static_assert(N % 64 == 0, "columns must fill whole waves");
-    static_assert(SUB * KC == L && (N >= NT ? N % NT == 0 : NT % N == 0), "tile shape");
+    static_assert(SUB * KF == L && (N >= NT ? N % NT == 0 : NT % N == 0), "tile shape");
+    static_assert(KM % KF == 0 && KF % 2 == 0, "flushes");
 };
 
 // One cell, plain IEEE divisions: the stand-alone operator and residual sweeps

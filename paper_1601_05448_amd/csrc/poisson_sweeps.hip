@@ -30,7 +30,7 @@ namespace pois {
 // MODE 0: stencil residual of the iteration view; MODE 1: q = b (copy, for the
 // stand-alone L^+ sweep).
 template <typename T, int N, int MODE, int COEF, int WEIGHT>
-__global__ void __launch_bounds__((LineCfg<T, N>::NT), 2)
+__global__ void __launch_bounds__((LineCfg<T, N>::NT))
 k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     using C = LineCfg<T, N>;
     __shared__ cpx<T> lds[C::L * C::LS];
@@ -130,9 +130,10 @@ k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
 }
 
 // P1 for rows whose length is a multiple of the wave size: the residual of a tile
-// of KC planes x SUB row pairs is computed by z-marching columns (see ZMarch),
-// then the tile's L lines are transformed along x.  The tile's line l = s KC + kk
-// is row pair jp = tj SUB + s of plane k = tk KC + kk.
+// of KM planes x SUB row pairs is computed by z-marching columns (see ZMarch);
+// every KF planes the tile's L lines are transformed along x and written out.
+// Within a flush, line l = s KF + q is row pair jp = tj SUB + s of plane
+// k = tk KM + f KF + q.
 template <typename T, int N, int COEF, int WEIGHT>
 __global__ void __launch_bounds__((LineCfg<T, N>::NT), 2)
 k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
@@ -149,7 +150,7 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     const IterView<T> v(s);
 
     const unsigned nyh = (unsigned)g.ny / 2, nz = (unsigned)g.nz;
-    const unsigned ngj = (nyh + Z::SUB - 1) / Z::SUB, ngk = (nz + Z::KC - 1) / Z::KC;
+    const unsigned ngj = (nyh + Z::SUB - 1) / Z::SUB, ngk = (nz + Z::KM - 1) / Z::KM;
     const unsigned ntiles = ngj * ngk;
     const int sidx = (N >= C::NT) ? 0 : (int)threadIdx.x / N;
     const unsigned col0 = (N >= C::NT) ? threadIdx.x : threadIdx.x % N;
@@ -168,10 +169,9 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
         const unsigned jp = tj * Z::SUB + sidx;
         const bool jvalid = jp < nyh;
         zm.rows_of(jvalid ? jp : 0u, (unsigned)g.ny);
-        const int k0 = (int)(tk * Z::KC);
+        const int k0 = (int)(tk * Z::KM);
         PlaneRows<T> pl[Z::CPT][3];
         PlaneSide<T> sd[Z::CPT];
-        T tacc[2] = {T(0), T(0)};
 #pragma unroll
         for (int c = 0; c < Z::CPT; ++c) {
             const unsigned i = col0 + c * C::NT;
@@ -180,78 +180,82 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
             zm.load_rows(zm.plane(k0 + 1), i, pl[c][2]);
             zm.load_side(zm.plane(k0), i, sd[c]);
         }
-        // fully unrolled, so that the rotation of the plane registers below is a
-        // renaming and not a copy that would wait for the prefetched loads
+        for (int f = 0; f < Z::KM / Z::KF; ++f) {
+            T tacc[2] = {T(0), T(0)};
+            // fully unrolled, so that the rotation of the plane registers below
+            // is a renaming and not a copy that would wait for the prefetched loads
 #pragma unroll
-        for (int kk = 0; kk < Z::KC; ++kk) {
-            const int k = k0 + kk;
-            const bool valid = jvalid && k < (int)nz;
-            // the next step's plane and side fly while this step computes (also on
-            // the last step, wrapped in z and unused, so that the wait counts are
-            // the same every step)
-            PlaneRows<T> nn[Z::CPT];
-            PlaneSide<T> ns[Z::CPT];
+            for (int q = 0; q < Z::KF; ++q) {
+                const int k = k0 + f * Z::KF + q;
+                const bool valid = jvalid && k < (int)nz;
+                // the next step's plane and side fly while this step computes (also
+                // on the tile's last step, wrapped in z and unused, so that the wait
+                // counts are the same every step)
+                PlaneRows<T> nn[Z::CPT];
+                PlaneSide<T> ns[Z::CPT];
 #pragma unroll
-            for (int c = 0; c < Z::CPT; ++c) {
-                const unsigned i = col0 + c * C::NT;
-                zm.load_rows(zm.plane(k + 2), i, nn[c]);
-                zm.load_side(zm.plane(k + 1), i, ns[c]);
-            }
-            T* eb = edge + ((kk & 1) * Z::SUB + sidx) * Z::EDGE;
-#pragma unroll
-            for (int c = 0; c < Z::CPT; ++c) zm.edge_put(eb, col0 + c * C::NT, pl[c][1]);
-            __syncthreads();
-#pragma unroll
-            for (int c = 0; c < Z::CPT; ++c) {
-                const unsigned i = col0 + c * C::NT;
-                PairIn<T> in;
-                zm.pair(pl[c][0], pl[c][1], pl[c][2], sd[c], zm.edge_get(eb, i), in);
-                cpx<T> qv = {T(0), T(0)};
-                if (valid) {
-                    const PairOut<T> o = pair_eval<T, COEF, WEIGHT>(g, in, v.rhs_mean, v.rmax, v.rinv);
-                    qv = {o.a.w * o.a.r, o.b.w * o.b.r};
-                    if constexpr (sizeof(T) == 8) {
-                        acc[0] += o.a.r * o.a.r + o.b.r * o.b.r;
-                        acc[1] += o.a.bt * o.a.bt + o.b.bt * o.b.bt;
-                        acc[2] += o.a.pc + o.b.pc;
-                        acc[3] += o.a.pc * o.a.pc + o.b.pc * o.b.pc;
-                    } else {
-                        // FP32 inner sweeps: only the two norms are used (the
-                        // stopping test), summed in FP32 over the tile
-                        tacc[0] += o.a.r * o.a.r + o.b.r * o.b.r;
-                        tacc[1] += o.a.bt * o.a.bt + o.b.bt * o.b.bt;
-                    }
+                for (int c = 0; c < Z::CPT; ++c) {
+                    const unsigned i = col0 + c * C::NT;
+                    zm.load_rows(zm.plane(k + 2), i, nn[c]);
+                    zm.load_side(zm.plane(k + 1), i, ns[c]);
                 }
-                lds[(sidx * Z::KC + kk) * C::LS + C::pos(i)] = qv;
-            }
+                T* eb = edge + ((q & 1) * Z::SUB + sidx) * Z::EDGE;
 #pragma unroll
-            for (int c = 0; c < Z::CPT; ++c) {
-                pl[c][0] = pl[c][1];
-                pl[c][1] = pl[c][2];
-                pl[c][2] = nn[c];
-                sd[c] = ns[c];
-            }
-        }
-        if constexpr (sizeof(T) == 4) {
-            acc[0] += (double)tacc[0];
-            acc[1] += (double)tacc[1];
-        }
-        __syncthreads();
-        fft_block_lines<T, N>(lds, tw);
+                for (int c = 0; c < Z::CPT; ++c) zm.edge_put(eb, col0 + c * C::NT, pl[c][1]);
+                __syncthreads();
 #pragma unroll
-        for (int it = 0; it < C::IT; ++it) {
-            const int e = threadIdx.x + it * C::NT;
-            const int l = e / N, k = e % N;
-            const unsigned ljp = tj * Z::SUB + l / Z::KC;
-            const unsigned lk = tk * Z::KC + l % Z::KC;
-            if (ljp < nyh && lk < nz) {
-                const unsigned P = lk * nyh + ljp;  // row pair index, rows 2P and 2P + 1
-                const cpx<T> h = hartley(lds[l * C::LS + C::pos(k)], lds[l * C::LS + C::pos((k == 0 ? 0 : N - k))]);
-                v.W[(2 * P) * N + k] = h.x;
-                v.W[(2 * P + 1) * N + k] = h.y;
+                for (int c = 0; c < Z::CPT; ++c) {
+                    const unsigned i = col0 + c * C::NT;
+                    PairIn<T> in;
+                    zm.pair(pl[c][0], pl[c][1], pl[c][2], sd[c], zm.edge_get(eb, i), in);
+                    cpx<T> qv = {T(0), T(0)};
+                    if (valid) {
+                        const PairOut<T> o = pair_eval<T, COEF, WEIGHT>(g, in, v.rhs_mean, v.rmax, v.rinv);
+                        qv = {o.a.w * o.a.r, o.b.w * o.b.r};
+                        if constexpr (sizeof(T) == 8) {
+                            acc[0] += o.a.r * o.a.r + o.b.r * o.b.r;
+                            acc[1] += o.a.bt * o.a.bt + o.b.bt * o.b.bt;
+                            acc[2] += o.a.pc + o.b.pc;
+                            acc[3] += o.a.pc * o.a.pc + o.b.pc * o.b.pc;
+                        } else {
+                            // FP32 inner sweeps: only the two norms are used (the
+                            // stopping test), summed in FP32 over the flush
+                            tacc[0] += o.a.r * o.a.r + o.b.r * o.b.r;
+                            tacc[1] += o.a.bt * o.a.bt + o.b.bt * o.b.bt;
+                        }
+                    }
+                    lds[(sidx * Z::KF + q) * C::LS + C::pos(i)] = qv;
+                }
+#pragma unroll
+                for (int c = 0; c < Z::CPT; ++c) {
+                    pl[c][0] = pl[c][1];
+                    pl[c][1] = pl[c][2];
+                    pl[c][2] = nn[c];
+                    sd[c] = ns[c];
+                }
             }
+            if constexpr (sizeof(T) == 4) {
+                acc[0] += (double)tacc[0];
+                acc[1] += (double)tacc[1];
+            }
+            __syncthreads();
+            fft_block_lines<T, N>(lds, tw);
+#pragma unroll
+            for (int it = 0; it < C::IT; ++it) {
+                const int e = threadIdx.x + it * C::NT;
+                const int l = e / N, k = e % N;
+                const unsigned ljp = tj * Z::SUB + l / Z::KF;
+                const unsigned lk = (unsigned)(k0 + f * Z::KF) + l % Z::KF;
+                if (ljp < nyh && lk < nz) {
+                    const unsigned P = lk * nyh + ljp;  // row pair index, rows 2P and 2P + 1
+                    const cpx<T> h = hartley(lds[l * C::LS + C::pos(k)],
+                                             lds[l * C::LS + C::pos((k == 0 ? 0 : N - k))]);
+                    v.W[(2 * P) * N + k] = h.x;
+                    v.W[(2 * P + 1) * N + k] = h.y;
+                }
+            }
+            __syncthreads();  // the next flush overwrites the lines
         }
-        __syncthreads();  // the next tile overwrites the lines
     }
     block_sums<C::NT, 4>(acc, red);
     if (threadIdx.x == 0) {
@@ -485,7 +489,7 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
 // ---- P5: Hartley along x, update -----------------------------------------------
 // MODE 0: FP64 p += dp - mean(p) (or FP32 d32 += dp); MODE 1: assign to p (L^+ sweep).
 template <typename T, int N, int MODE>
-__global__ void __launch_bounds__((LineCfg<T, N>::NT), 2)
+__global__ void __launch_bounds__((LineCfg<T, N>::NT))
 k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     using C = LineCfg<T, N>;
     __shared__ cpx<T> lds[C::L * C::LS];
@@ -609,7 +613,7 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
                     if constexpr (MODE == 0 && use_zmarch<T, N>()) {
                         using Z = ZTile<N, C::NT, C::L>;
                         const unsigned nt = (((unsigned)g.ny / 2 + Z::SUB - 1) / Z::SUB) *
-                                            (((unsigned)g.nz + Z::KC - 1) / Z::KC);
+                                            (((unsigned)g.nz + Z::KM - 1) / Z::KM);
                         const void* k = (const void*)&k_resid_dhtx_z<T, N, CO, WE>;
                         const int nb = persistent_grid(k, C::NT, nt, nslots);
                         if (nblocks) *nblocks = nb;

@@ -168,32 +168,35 @@ def cic_deposit(shape: Sequence[int], lengths: Sequence[float], pos: np.ndarray)
 
 
 def gaussian_blobs(shape: Sequence[int], lengths: Sequence[float], centres_xyz: np.ndarray,
-                   sigma_cells: float, cut_sigmas: float = 4.0) -> np.ndarray:
+                   sigma_cells: float, cut_sigmas: float = 4.0, batch: int = 4096) -> np.ndarray:
     """Sum of unit-amplitude periodic Gaussian blobs of width sigma_cells (in
     cells), truncated at cut_sigmas widths, evaluated at cell centres.  Each blob
     is separable, exp(-|x-c|^2 / (2 s^2)) = gx * gy * gz, so it is laid down as
-    an outer product over its (2R+1)^3 support."""
+    an outer product over its (2R+1)^3 support; batches of blobs are summed
+    into the grid with bincount (a fixed summation order)."""
     nz, ny, nx = shape
     ns = (nx, ny, nz)
     hs = [lengths[d] / ns[d] for d in range(3)]
     R = int(math.ceil(cut_sigmas * sigma_cells))
     offs = np.arange(-R, R + 1)
-    out = np.zeros(shape)
-    for c in centres_xyz:
-        gs = []
-        ids = []
+    n = nx * ny * nz
+    out = np.zeros(n)
+    cen = np.asarray(centres_xyz, dtype=np.float64)
+    for b0 in range(0, len(cen), batch):
+        c = cen[b0:b0 + batch]
+        gs, ids = [], []
         for d in range(3):
-            s = c[d] / hs[d] - 0.5  # position in cell-centre index units
-            i0 = int(math.floor(s))
-            cells = i0 + offs
-            dist = cells - s
+            s = c[:, d] / hs[d] - 0.5                     # position in cell-centre index units
+            cells = np.floor(s).astype(np.int64)[:, None] + offs[None, :]
+            dist = cells - s[:, None]
             g = np.exp(-0.5 * (dist / sigma_cells) ** 2)
             g[np.abs(dist) > cut_sigmas * sigma_cells] = 0.0
             gs.append(g)
             ids.append(cells % ns[d])
-        block = gs[2][:, None, None] * gs[1][None, :, None] * gs[0][None, None, :]
-        out[np.ix_(ids[2], ids[1], ids[0])] += block
-    return out
+        w = gs[2][:, :, None, None] * gs[1][:, None, :, None] * gs[0][:, None, None, :]
+        flat = (ids[2][:, :, None, None] * ny + ids[1][:, None, :, None]) * nx + ids[0][:, None, None, :]
+        out += np.bincount(flat.ravel(), weights=w.ravel(), minlength=n)
+    return out.reshape(shape)
 
 
 @dataclass
