@@ -141,6 +141,48 @@ def serve_leg(P, torch, count, budget_gb, slots, precision):
             "p50_ms": percentile(lat, 0.5), "p99_ms": percentile(lat, 0.99)}
 
 
+def serve_mixed(P, torch, count, budget_gb):
+    """A stream of 128^3 requests (FP32+refine) served alone, then with the
+    1024x512x512 hot-blob solve admitted at the start of the same stream:
+    p50/p99 of the small requests both ways and the big solve's latency."""
+    from paper_1601_05448_amd import inputs, serve
+
+    reqs = inputs.request_stream(count, sizes=(128,))
+    fields = [inputs.request_fields_device(r) for r in reqs]
+    big = inputs.workload5()
+    big_rho, big_b = torch.from_numpy(big.rho).cuda(), torch.from_numpy(big.b).cuda()
+    budget = int(budget_gb * (1 << 30))
+
+    def jobs_for(stream):
+        return [serve.Job(r.arrival_s, (128,) * 3, (2 * math.pi,) * 3, f[0], f[1],
+                          torch.zeros((128,) * 3, dtype=torch.float64, device="cuda"), tag="small")
+                for r, f in zip(stream, fields)]
+
+    out = {"small": "128^3 lognormal rho (ratio 2-8), FP32+refine, tol 1e-10",
+           "big": big.name + ", FP32+refine, tol 1e-10", "requests": count, "budget_gb": budget_gb}
+    with serve.Server(budget, 64, precision=P.POISSON_FP32_REFINE) as srv:
+        serve.replay(srv, jobs_for(reqs[:8]), realtime=False)  # warm-up
+        cap = serve.replay(srv, jobs_for(reqs), realtime=False)
+        rate = 0.5 * len(cap.outcomes) / cap.wall_s
+        stream = inputs.request_stream(count, rate_hz=rate, sizes=(128,))
+        alone = serve.replay(srv, jobs_for(stream), realtime=True)
+        jobs = jobs_for(stream)
+        jobs.insert(0, serve.Job(0.0, big.shape, big.lengths, big_rho, big_b,
+                                 torch.zeros(big.shape, dtype=torch.float64, device="cuda"), tag="big"))
+        mixed = serve.replay(srv, jobs, realtime=True)
+    for res in (alone, mixed):
+        bad = [o for o in res.outcomes if o.stats["status"] != 0 or o.stats["rel_resid"] > 1e-10]
+        if bad:
+            raise RuntimeError(f"served solves failed: {len(bad)}")
+    small_mixed = [o.latency_ms for o in mixed.outcomes if o.job.tag == "small"]
+    big_ms = [o.latency_ms for o in mixed.outcomes if o.job.tag == "big"][0]
+    out.update(rate_hz=rate, alone_p50_ms=percentile(alone.latencies(), 0.5),
+               alone_p99_ms=percentile(alone.latencies(), 0.99),
+               with_big_p50_ms=percentile(small_mixed, 0.5), with_big_p99_ms=percentile(small_mixed, 0.99),
+               big_latency_ms=big_ms)
+    return out
+
+
 def cpu_baseline(prob, fp64_iters):
     """The oracle (single-threaded C, FP64) on a bounded sample of the same
     workload: one residual evaluation plus one iteration, scaled to the
@@ -223,6 +265,7 @@ def main():
                          "fp64": time_path(P, torch, big, P.POISSON_FP64, 3, 1, args.tol),
                          "fp32_refine": time_path(P, torch, big, P.POISSON_FP32_REFINE, 3, 1, args.tol)}
         del big
+        line["large"]["served_alongside"] = serve_mixed(P, torch, 128, 32.0)
     if args.serve_requests > 0:
         line["serving"] = serve_leg(P, torch, args.serve_requests, args.serve_budget_gb, 64, P.POISSON_FP64)
     if not args.no_cpu_baseline:

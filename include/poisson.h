@@ -195,9 +195,12 @@ int poisson_server_create(size_t budget_bytes, int max_slots, int precision, int
 int poisson_server_submit(poisson_server_t s, int nx, int ny, int nz, double lx, double ly, double lz,
                           const double* rho, const double* b, double* p, double tol, long long* id);
 
-/* Run one scheduling tick: admit queued requests that fit, advance every
- * resident batch by a few iterations, retire finished requests.  Blocks for
- * the tick.  Returns the number of requests still queued or resident. */
+/* Run one scheduling tick: retire the finished requests of every batch whose
+ * last chunk of iterations has completed, admit queued requests that fit, and
+ * enqueue the next chunk of every idle batch.  Batches of different grid sizes
+ * progress independently on their own streams; the tick does not wait for
+ * running chunks, so a caller drives the server by calling it in a loop.
+ * Returns the number of requests still queued or resident. */
 int poisson_server_tick(poisson_server_t s);
 
 /* 0 and *stats filled if the request is done, 1 if still queued or running,

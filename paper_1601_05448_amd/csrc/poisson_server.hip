@@ -72,6 +72,8 @@ struct SizeClass {
     SolveState* h_hdr = nullptr;   // pinned state headers
     size_t ws_bytes = 0;
     long long cells = 0;
+    bool in_flight = false;  // a chunk of this class is enqueued and not yet retired
+    int n_launched = 0;      // active[0, n_launched) are the solves of that chunk
 
     ~SizeClass() {
         for (Workspace* w : pool) {
@@ -236,16 +238,21 @@ static int launch_class(poisson_server_s* s, SizeClass* c) {
             hipSuccess)
             return hip_status(e);
     if ((e = hipEventRecord(c->done_ev, c->stream)) != hipSuccess) return hip_status(e);
+    c->n_launched = n;
+    c->in_flight = true;
     return POISSON_OK;
 }
 
-// After the tick's work of a class: finish and retire the solves that are done.
+// After a class's chunk has completed: finish and retire the solves that are
+// done.  Requests admitted while the chunk ran sit after active[n_launched).
 static int retire_class(poisson_server_s* s, SizeClass* c) {
     hipError_t e;
     if ((e = hipEventSynchronize(c->done_ev)) != hipSuccess) return hip_status(e);
+    c->in_flight = false;
     std::vector<int> done;
-    for (int q = 0; q < (int)c->active.size(); ++q)
+    for (int q = 0; q < c->n_launched; ++q)
         if (c->h_hdr[q].done) done.push_back(q);
+    c->n_launched = 0;
     if (done.empty()) return POISSON_OK;
     // end-of-solve fix-up (mean of p, b~ = 0) for the finished ones
     for (int u = 0; u < (int)done.size(); ++u) {
@@ -336,20 +343,28 @@ int poisson_server_submit(poisson_server_t s, int nx, int ny, int nz, double lx,
 
 int poisson_server_tick(poisson_server_t s) {
     if (!s) return POISSON_EINVAL;
-    int rc = admit(s);
-    if (rc != POISSON_OK) return rc;
-    // the classes start after the caller's earlier work on its stream
-    if (hipEventRecord(s->fork_ev, s->stream) != hipSuccess) return POISSON_EHIP;
+    int rc;
+    // retire the classes whose chunk has completed; the others keep running
     for (auto& kv : s->classes) {
         SizeClass* c = kv.second.get();
-        if (c->active.empty()) continue;
+        if (!c->in_flight) continue;
+        const hipError_t q = hipEventQuery(c->done_ev);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return POISSON_EHIP;
+        if ((rc = retire_class(s, c)) != POISSON_OK) return rc;
+    }
+    if ((rc = admit(s)) != POISSON_OK) return rc;
+    // idle classes start their next chunk, after the caller's earlier work on its stream
+    bool forked = false;
+    for (auto& kv : s->classes) {
+        SizeClass* c = kv.second.get();
+        if (c->in_flight || c->active.empty()) continue;
+        if (!forked) {
+            if (hipEventRecord(s->fork_ev, s->stream) != hipSuccess) return POISSON_EHIP;
+            forked = true;
+        }
         if (hipStreamWaitEvent(c->stream, s->fork_ev, 0) != hipSuccess) return POISSON_EHIP;
         if ((rc = launch_class(s, c)) != POISSON_OK) return rc;
-    }
-    for (auto& kv : s->classes) {
-        SizeClass* c = kv.second.get();
-        if (c->active.empty()) continue;
-        if ((rc = retire_class(s, c)) != POISSON_OK) return rc;
     }
     return (int)s->queue.size() + s->resident;
 }
