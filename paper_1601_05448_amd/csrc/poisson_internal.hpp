@@ -99,6 +99,7 @@ struct Geometry {
     int blocks_pt;     // pointwise kernels
     int blocks_outer;  // FP64 outer residual
     int max_blocks;    // partial-sum capacity needed
+    float share;       // fraction of the chip's resident blocks the persistent sweeps take
 };
 
 // ---- launchers (poisson_kernels.hip) ----------------------------------------
@@ -134,7 +135,8 @@ hipError_t launch_sweep(const GridArgs& g, const Tables& t, const Slot* slots, i
 // sweep (FP64).  *nblocks (may be NULL) receives the grid width, i.e. the
 // number of partial sums P1 wrote.
 hipError_t launch_sweep_mode(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32, int which,
-                             int mode, hipStream_t s, int* nblocks);
+                             int mode, hipStream_t s, int* nblocks,
+                             float share = 1.0f);
 unsigned sweep_groups_x(const GridArgs& g);
 // FP32_REFINE outer step pieces.
 // the FP64 outer residual sweep alone (no finalize); *nblocks = partial sums written

@@ -600,6 +600,7 @@ Geometry make_geometry(const GridArgs& g) {
     });
     geo.blocks_outer = nbo;
     geo.max_blocks = std::max(std::max(std::max(geo.blocks_x, geo.blocks_pt), nbo), kMaxSetupBlocks);
+    geo.share = 1.0f;
     return geo;
 }
 
@@ -629,14 +630,14 @@ hipError_t launch_setup_finalize(const GridArgs& g, const Geometry& geo, const S
 // P1, convergence check, P2, P3, P4 (= P2), P5.  MODE 1 is the stand-alone
 // L^+ q sweep (q in slot.b, result in slot.p), which has no check.
 static hipError_t five_sweeps(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32,
-                              int mode, hipStream_t s, SweepTimer* tm) {
+                              int mode, hipStream_t s, SweepTimer* tm, float share = 1.0f) {
     hipError_t e;
     int nbx = 0;
     // one sweep, bracketed by the timer's events when it times this sweep
     auto sweep = [&](int which, int* nb) -> hipError_t {
         const bool timed = tm && tm->sweep == which && tm->fp32 == fp32 && tm->used < SweepTimer::kCap;
         if (timed && (e = hipEventRecord(tm->ev[2 * tm->used], s)) != hipSuccess) return e;
-        if ((e = launch_sweep_mode(g, t, slots, nslots, fp32, which, mode, s, nb)) != hipSuccess) return e;
+        if ((e = launch_sweep_mode(g, t, slots, nslots, fp32, which, mode, s, nb, share)) != hipSuccess) return e;
         if (timed) {
             if ((e = hipEventRecord(tm->ev[2 * tm->used + 1], s)) != hipSuccess) return e;
             ++tm->used;
@@ -662,8 +663,7 @@ hipError_t launch_sweep(const GridArgs& g, const Tables& t, const Slot* slots, i
 
 hipError_t launch_iteration(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slots,
                             int nslots, bool fp32, hipStream_t s, SweepTimer* tm) {
-    (void)geo;
-    return five_sweeps(g, t, slots, nslots, fp32, 0, s, tm);
+    return five_sweeps(g, t, slots, nslots, fp32, 0, s, tm, geo.share);
 }
 
 hipError_t launch_outer_resid_sweep(const GridArgs& g, const Slot* slots, int nslots, hipStream_t s, int* nblocks) {

@@ -354,11 +354,19 @@ int poisson_server_tick(poisson_server_t s) {
         if ((rc = retire_class(s, c)) != POISSON_OK) return rc;
     }
     if ((rc = admit(s)) != POISSON_OK) return rc;
+    // A class at least four times larger than the smallest active one takes
+    // three quarters of the chip's resident blocks in its persistent sweeps,
+    // so that the small classes' blocks find room beside it instead of waiting
+    // for each of its sweeps to end.
+    long long smallest = 0;
+    for (auto& kv : s->classes)
+        if (!kv.second->active.empty() && (smallest == 0 || kv.second->cells < smallest)) smallest = kv.second->cells;
     // idle classes start their next chunk, after the caller's earlier work on its stream
     bool forked = false;
     for (auto& kv : s->classes) {
         SizeClass* c = kv.second.get();
         if (c->in_flight || c->active.empty()) continue;
+        c->geo.share = (c->cells >= 4 * smallest) ? 0.75f : 1.0f;
         if (!forked) {
             if (hipEventRecord(s->fork_ev, s->stream) != hipSuccess) return POISSON_EHIP;
             forked = true;

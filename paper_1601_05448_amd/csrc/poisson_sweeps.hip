@@ -595,14 +595,14 @@ static int resident_blocks(const void* kernel, int threads) {
     return it->second * cus;
 }
 
-static int persistent_grid(const void* kernel, int threads, unsigned ngroups, int nslots) {
-    const int cap = std::max(1, resident_blocks(kernel, threads) / std::max(1, nslots));
+static int persistent_grid(const void* kernel, int threads, unsigned ngroups, int nslots, float share) {
+    const int cap = std::max(1, (int)(resident_blocks(kernel, threads) * share) / std::max(1, nslots));
     return (int)std::min<unsigned>(ngroups, (unsigned)cap);
 }
 
 template <typename T, int MODE>
 static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, int which,
-                          hipStream_t s, int* nblocks) {
+                          hipStream_t s, int* nblocks, float share) {
     const unsigned rows = (unsigned)(g.ny * g.nz / 2);
     switch (which) {
         case 1:
@@ -615,12 +615,12 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
                         const unsigned nt = (((unsigned)g.ny / 2 + Z::SUB - 1) / Z::SUB) *
                                             (((unsigned)g.nz + Z::KM - 1) / Z::KM);
                         const void* k = (const void*)&k_resid_dhtx_z<T, N, CO, WE>;
-                        const int nb = persistent_grid(k, C::NT, nt, nslots);
+                        const int nb = persistent_grid(k, C::NT, nt, nslots, share);
                         if (nblocks) *nblocks = nb;
                         k_resid_dhtx_z<T, N, CO, WE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
                     } else {
                         const void* k = (const void*)&k_resid_dhtx<T, N, MODE, CO, WE>;
-                        const int nb = persistent_grid(k, C::NT, ng, nslots);
+                        const int nb = persistent_grid(k, C::NT, ng, nslots, share);
                         if (nblocks) *nblocks = nb;
                         k_resid_dhtx<T, N, MODE, CO, WE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
                     }
@@ -631,7 +631,7 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
             return dispatch_len(g.ny, [&]<int N>() {
                 using C = LineCfg<T, N>;
                 const unsigned ng = ((unsigned)(g.nxh * g.nz) + C::L - 1) / C::L;
-                const int nb = persistent_grid((const void*)&k_dht_cols<T, N, 1, MODE>, C::NT, ng, nslots);
+                const int nb = persistent_grid((const void*)&k_dht_cols<T, N, 1, MODE>, C::NT, ng, nslots, share);
                 k_dht_cols<T, N, 1, MODE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
                 return hipGetLastError();
             });
@@ -639,7 +639,7 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
             return dispatch_len(g.nz, [&]<int N>() {
                 using C = LineCfg<T, N>;
                 const unsigned ng = ((unsigned)(g.nxh * g.ny) + C::L - 1) / C::L;
-                const int nb = persistent_grid((const void*)&k_dht_z_solve<T, N, MODE>, C::NT, ng, nslots);
+                const int nb = persistent_grid((const void*)&k_dht_z_solve<T, N, MODE>, C::NT, ng, nslots, share);
                 k_dht_z_solve<T, N, MODE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
                 return hipGetLastError();
             });
@@ -647,7 +647,7 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
             return dispatch_len(g.nx, [&]<int N>() {
                 using C = LineCfg<T, N>;
                 const unsigned ng = (rows + C::L - 1) / C::L;
-                const int nb = persistent_grid((const void*)&k_dhtx_update<T, N, MODE>, C::NT, ng, nslots);
+                const int nb = persistent_grid((const void*)&k_dhtx_update<T, N, MODE>, C::NT, ng, nslots, share);
                 k_dhtx_update<T, N, MODE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
                 return hipGetLastError();
             });
@@ -657,10 +657,10 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
 }
 
 hipError_t launch_sweep_mode(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32, int which,
-                             int mode, hipStream_t s, int* nblocks) {
-    if (mode == 1) return sweep_t<double, 1>(g, t, slots, nslots, which, s, nblocks);
-    return fp32 ? sweep_t<float, 0>(g, t, slots, nslots, which, s, nblocks)
-                : sweep_t<double, 0>(g, t, slots, nslots, which, s, nblocks);
+                             int mode, hipStream_t s, int* nblocks, float share) {
+    if (mode == 1) return sweep_t<double, 1>(g, t, slots, nslots, which, s, nblocks, share);
+    return fp32 ? sweep_t<float, 0>(g, t, slots, nslots, which, s, nblocks, share)
+                : sweep_t<double, 0>(g, t, slots, nslots, which, s, nblocks, share);
 }
 
 unsigned sweep_groups_x(const GridArgs& g) {
