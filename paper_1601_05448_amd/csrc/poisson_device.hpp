@@ -439,6 +439,30 @@ __device__ __forceinline__ void block_sums(double (&v)[K], double* red) {
     }
 }
 
+// Units' K sums, added by the NT threads of a block in a fixed order; the total
+// is in out[] of thread 0.
+template <int NT, int K>
+__device__ __forceinline__ void sum_units(const double* part, unsigned n, double (&out)[K], double* red) {
+#pragma unroll
+    for (int q = 0; q < K; ++q) out[q] = 0.0;
+    for (unsigned u = threadIdx.x; u < n; u += NT)
+#pragma unroll
+        for (int q = 0; q < K; ++q) out[q] += part[(unsigned long long)u * kPartialStride + q];
+    block_sums<NT, K>(out, red);
+}
+
+// Store this block's sums of one unit (thread 0 writes), then clear them.
+template <int NT, int K>
+__device__ __forceinline__ void put_unit_sums(double (&v)[K], double* red, double* dst) {
+    block_sums<NT, K>(v, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < K; ++q) dst[q] = v[q];
+#pragma unroll
+    for (int q = 0; q < K; ++q) v[q] = 0.0;
+    __syncthreads();  // red is reused by the next unit
+}
+
 template <typename T>
 struct IterView;
 

@@ -132,15 +132,15 @@ hipError_t launch_iteration(const GridArgs& g, const Geometry& geo, const Tables
 hipError_t launch_sweep(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32, int which,
                         hipStream_t s);
 // poisson_sweeps.hip: one sweep; mode 0 iteration, mode 1 the stand-alone L^+ q
-// sweep (FP64).  *nblocks (may be NULL) receives the grid width, i.e. the
-// number of partial sums P1 wrote.
+// sweep (FP64).  *nunits (may be NULL) receives the number of partial sums P1
+// wrote.  `share`: fraction of the resident blocks the persistent sweeps take.
 hipError_t launch_sweep_mode(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32, int which,
-                             int mode, hipStream_t s, int* nblocks,
-                             float share = 1.0f);
+                             int mode, hipStream_t s, int* nunits, float share = 1.0f);
 unsigned sweep_groups_x(const GridArgs& g);
 // FP32_REFINE outer step pieces.
-// the FP64 outer residual sweep alone (no finalize); *nblocks = partial sums written
-hipError_t launch_outer_resid_sweep(const GridArgs& g, const Slot* slots, int nslots, hipStream_t s, int* nblocks);
+// the FP64 outer residual sweep alone (no decision); *nunits (may be NULL)
+// receives the number of partial sums it wrote
+hipError_t launch_outer_resid_sweep(const GridArgs& g, const Slot* slots, int nslots, hipStream_t s, int* nunits);
 hipError_t launch_outer_residual(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,
                                  hipStream_t s);
 hipError_t launch_outer_update(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,

@@ -6,9 +6,10 @@
 // equation by transforms in the periodic directions, p_g <- p_g + dp) is, in
 // residual form,
 //     r = b~ - A p,  q = w r,  dp = L^+ q,  p += dp,
-// and runs as five sweeps over the field plus one tiny reduction:
-//   P1 k_resid_dhtx   stencil residual, weight, partial norms, Hartley along x -> W
-//   F  k_finalize     ||r|| / ||b~||: convergence, divergence, iteration cap
+// and runs as five sweeps over the field:
+//   P1 k_resid_dhtx   stencil residual, weight, partial norms, Hartley along x -> W;
+//                     its last block takes ||r|| / ||b~|| and the decision
+//                     (convergence, divergence, iteration cap; poisson_control.hpp)
 //   P2 k_dht_cols<Y>  Hartley along y of W
 //   P3 k_dht_z_solve  Hartley along z, divide by n * symbol, Hartley along z
 //   P4 k_dht_cols<Y>  Hartley along y
@@ -22,6 +23,7 @@
 
 #include <algorithm>
 
+#include "poisson_control.hpp"
 #include "poisson_device.hpp"
 
 namespace pois {
@@ -127,164 +129,31 @@ __global__ void __launch_bounds__(256) k_setup_finalize(GridArgs g, const Slot* 
     }
 }
 
-// ---- convergence control -----------------------------------------------------------
+// ---- decisions (one block per solve, after the sweep that wrote the sums) -------------
 
-template <int K>
-__device__ void sum_partials(const double* part, int nblk, double* out, double* red) {
-    // fixed-order two-level sum of K values over nblk blocks (256 threads)
-    double v[K];
-#pragma unroll
-    for (int q = 0; q < K; ++q) v[q] = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 256)
-#pragma unroll
-        for (int q = 0; q < K; ++q) v[q] += part[(long long)b * kPartialStride + q];
-    const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
-#pragma unroll
-    for (int q = 0; q < K; ++q) {
-        const double t = wave_sum(v[q]);
-        if (lane == 0) red[w * K + q] = t;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int q = 0; q < K; ++q) out[q] = red[q] + red[K + q] + red[2 * K + q] + red[3 * K + q];
-}
-
-// FP64 path, after P1 of iteration st->iter.
-__global__ void __launch_bounds__(256) k_finalize(GridArgs g, const Slot* __restrict__ slots, int nblk) {
-    __shared__ double red[16];
+// After P1 of an iteration: FP64 path (fp32 = 0) or an FP32 inner sweep.
+__global__ void __launch_bounds__(256) k_decide_iter(GridArgs g, const Slot* __restrict__ slots, int nunits,
+                                                     int fp32) {
+    __shared__ double red[(256 / 64) * 4];
     const Slot& s = slots[blockIdx.x];
     SolveState* st = s.st;
-    if (st->done) return;
-    double sums[4];  // sum r^2, sum bt^2, sum p, sum p^2
-    sum_partials<4>(s.partial, nblk, sums, red);
+    if (fp32 ? (st->done || st->stage != 1 || st->inner_done) : st->done) return;
+    double sums[4];
+    sum_units<256, 4>(s.partial, (unsigned)nunits, sums, red);
     if (threadIdx.x != 0) return;
-    st->p1_work += 1;  // this kernel runs exactly when P1 did
-    const int k = st->iter;
-    st->p_sum = sums[2];
-    st->p_sumsq = sums[3];
-    // the update of this iteration also removes the mean of p (the zero-mean
-    // gauge), so rounding in dp never accumulates a constant
-    st->p_shift = sums[2] / (double)g.n;
-    if (k == 0) {
-        st->b_norm = sqrt(sums[1]);
-        if (st->b_norm == 0.0) {
-            st->rel = 0.0;
-            st->r_norm = 0.0;
-            st->hist[0] = 0.0;
-            st->done = 1;
-            st->status = POISSON_OK;
-            return;
-        }
-    }
-    const double rn = sqrt(sums[0]);
-    const double rel = rn / st->b_norm;
-    st->r_norm = rn;
-    st->rel = rel;
-    if (k == 0) st->rel0 = rel;
-    if (k < kHistCap) st->hist[k] = rel;
-    if (rel <= st->tol) {
-        st->done = 1;
-        st->status = POISSON_OK;
-    } else if (!(rel < 1e8)) {
-        st->done = 1;
-        st->status = POISSON_EDIVERGED;
-    } else if (k >= st->max_iter) {
-        st->done = 1;
-        st->status = POISSON_ENOCONV;
-    } else {
-        st->iter = k + 1;
-    }
+    if (fp32) decide_inner(st, sums, kMaxInnerPerStep);
+    else decide_fp64(g, st, sums);
 }
 
-// FP32_REFINE: after the FP64 outer residual of outer step st->iter.
-__global__ void __launch_bounds__(256) k_finalize_outer(GridArgs g, const Slot* __restrict__ slots, int nblk) {
-    __shared__ double red[20];
+// After the FP64 outer residual of a refinement step.
+__global__ void __launch_bounds__(256) k_decide_outer(GridArgs g, const Slot* __restrict__ slots, int nunits) {
+    __shared__ double red[(256 / 64) * 5];
     const Slot& s = slots[blockIdx.x];
     SolveState* st = s.st;
     if (st->done || st->stage != 0) return;
-    double sums[5];  // sum r^2, sum bt^2, sum p, sum p^2, sum r
-    sum_partials<5>(s.partial, nblk, sums, red);
-    if (threadIdx.x != 0) return;
-    const int m = st->iter;
-    st->p_sum = sums[2];
-    st->p_sumsq = sums[3];
-    if (m == 0) {
-        // the mean of the incoming p, removed by the update of step 0
-        st->p_shift = sums[2] / (double)g.n;
-        st->b_norm = sqrt(sums[1]);
-        if (st->b_norm == 0.0) {
-            st->rel = 0.0;
-            st->r_norm = 0.0;
-            st->hist[0] = 0.0;
-            st->done = 1;
-            st->status = POISSON_OK;
-            return;
-        }
-    }
-    const double rn = sqrt(sums[0]);
-    const double rel = rn / st->b_norm;
-    st->r_norm = rn;
-    st->rel = rel;
-    if (m < kHistCap) st->hist[m] = rel;
-    if (rel <= st->tol) {
-        st->done = 1;
-        st->status = POISSON_OK;
-    } else if (!(rel < 1e8)) {
-        st->done = 1;
-        st->status = POISSON_EDIVERGED;
-    } else if (m >= st->max_outer || st->inner_total >= st->max_iter) {
-        st->done = 1;
-        st->status = POISSON_ENOCONV;
-    } else {
-        st->rhs_mean32 = sums[4] * st->inv_s / (double)g.n;
-        st->stage = 1;
-        st->inner_iter = 0;
-        st->inner_done = 0;
-        st->since_best = 0;
-        st->best_in = INFINITY;
-        st->rel_in = 1.0;
-    }
-}
-
-// FP32_REFINE: after the FP32 P1 of an inner iteration.
-__global__ void __launch_bounds__(256) k_finalize_inner(GridArgs g, const Slot* __restrict__ slots, int nblk,
-                                                        int max_inner) {
-    __shared__ double red[16];
-    const Slot& s = slots[blockIdx.x];
-    SolveState* st = s.st;
-    if (st->done || st->stage != 1 || st->inner_done) return;
-    double sums[2];
-    sum_partials<2>(s.partial, nblk, sums, red);
-    if (threadIdx.x != 0) return;
-    st->p1_work += 1;  // this kernel runs exactly when P1 did
-    const int t = st->inner_iter;
-    if (t == 0) st->rhs_norm32 = sqrt(sums[1]);
-    const double rel = (st->rhs_norm32 > 0.0) ? sqrt(sums[0]) / st->rhs_norm32 : 0.0;
-    st->rel_in = rel;
-    bool stop = false;
-    if (!(rel < 1e8)) stop = true;  // non-finite or blown up: let the FP64 step judge
-    if (rel <= st->inner_tol) stop = true;
-    if (rel < 0.9 * st->best_in) {
-        st->best_in = rel;
-        st->since_best = 0;
-    } else {
-        ++st->since_best;
-    }
-    // Stagnation at the FP32 rounding floor: no 10% gain in 8 sweeps after the
-    // residual has come down.  The iteration can first grow by orders of
-    // magnitude on rough density before it contracts, so no stop counts before
-    // the best residual is below half its start.
-    if (st->best_in < 0.5 && st->since_best >= 8) stop = true;
-    if (t >= max_inner || st->inner_total >= st->max_iter) stop = true;
-    if (stop) {
-        st->inner_done = 1;
-        st->inner_last = t + 1;
-        st->stage = 2;
-    } else {
-        st->inner_iter = t + 1;
-        st->inner_total += 1;
-    }
+    double sums[5];
+    sum_units<256, 5>(s.partial, (unsigned)nunits, sums, red);
+    if (threadIdx.x == 0) decide_outer(g, st, sums);
 }
 
 // ---- pointwise FP64 stencil sweeps -------------------------------------------------
@@ -436,11 +305,7 @@ __global__ void __launch_bounds__(256) k_outer_resid(GridArgs g, const Slot* __r
                 sd[c] = ns[c];
             }
         }
-    }
-    block_sums<256, 5>(acc, red);
-    if (threadIdx.x == 0) {
-        double* o = s.partial + (unsigned long long)blockIdx.x * kPartialStride;
-        o[0] = acc[0]; o[1] = acc[1]; o[2] = acc[2]; o[3] = acc[3]; o[4] = acc[4];
+        put_unit_sums<256, 5>(acc, red, s.partial + (unsigned long long)tile * kPartialStride);
     }
 }
 
@@ -513,11 +378,7 @@ __global__ void __launch_bounds__(kPtThreads) k_outer_resid_rows(GridArgs g, con
         if (it + 2 < IT) fetch(it + 2, A);
         if (it + 1 < IT) evaluate(it + 1, B);
     }
-    block_sums<kPtThreads, 5>(acc, red);
-    if (threadIdx.x == 0) {
-        double* o = s.partial + (unsigned long long)blockIdx.x * kPartialStride;
-        o[0] = acc[0]; o[1] = acc[1]; o[2] = acc[2]; o[3] = acc[3]; o[4] = acc[4];
-    }
+    put_unit_sums<kPtThreads, 5>(acc, red, s.partial + (unsigned long long)blockIdx.x * kPartialStride);
 }
 
 template <int N>
@@ -533,6 +394,20 @@ static int blocks_outer(const GridArgs& g) {
         return (int)((np + RPB - 1) / RPB);
     }
 }
+
+// partial sums the outer residual writes: one per tile (z kernel) or per block
+template <int N>
+static int outer_units(const GridArgs& g) {
+    if constexpr (OuterCfg<N>::ok) {
+        using O = OuterCfg<N>;
+        const long long ngj = ((long long)g.ny / 2 + O::SUB - 1) / O::SUB;
+        const long long ngk = ((long long)g.nz + kOuterPlanes - 1) / kOuterPlanes;
+        return (int)(ngj * ngk);
+    } else {
+        return blocks_outer<N>(g);
+    }
+}
+
 
 // FP32_REFINE outer update: p += d32 / inv_s - p_shift (FP64), then the next scale.
 __global__ void __launch_bounds__(kPtThreads) k_outer_update(GridArgs g, const Slot* __restrict__ slots) {
@@ -599,7 +474,11 @@ Geometry make_geometry(const GridArgs& g) {
         return hipSuccess;
     });
     geo.blocks_outer = nbo;
-    geo.max_blocks = std::max(std::max(std::max(geo.blocks_x, geo.blocks_pt), nbo), kMaxSetupBlocks);
+    // partial sums: one set per block of the set-up and pointwise sweeps, per
+    // tile or line group of the residual sweeps (at most one per row pair)
+    const int row_pairs = (int)((long long)g.ny * g.nz / 2);
+    geo.max_blocks = std::max(std::max(std::max(std::max(geo.blocks_x, geo.blocks_pt), nbo), kMaxSetupBlocks),
+                              row_pairs);
     geo.share = 1.0f;
     return geo;
 }
@@ -632,28 +511,29 @@ hipError_t launch_setup_finalize(const GridArgs& g, const Geometry& geo, const S
 static hipError_t five_sweeps(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32,
                               int mode, hipStream_t s, SweepTimer* tm, float share = 1.0f) {
     hipError_t e;
-    int nbx = 0;
+    int nunits = 0;
     // one sweep, bracketed by the timer's events when it times this sweep
-    auto sweep = [&](int which, int* nb) -> hipError_t {
+    auto sweep = [&](int which) -> hipError_t {
         const bool timed = tm && tm->sweep == which && tm->fp32 == fp32 && tm->used < SweepTimer::kCap;
         if (timed && (e = hipEventRecord(tm->ev[2 * tm->used], s)) != hipSuccess) return e;
-        if ((e = launch_sweep_mode(g, t, slots, nslots, fp32, which, mode, s, nb, share)) != hipSuccess) return e;
+        if ((e = launch_sweep_mode(g, t, slots, nslots, fp32, which, mode, s, which == 1 ? &nunits : nullptr,
+                                   share)) != hipSuccess)
+            return e;
         if (timed) {
             if ((e = hipEventRecord(tm->ev[2 * tm->used + 1], s)) != hipSuccess) return e;
             ++tm->used;
         }
         return hipSuccess;
     };
-    if ((e = sweep(1, &nbx)) != hipSuccess) return e;
+    if ((e = sweep(1)) != hipSuccess) return e;
     if (mode == 0) {
-        if (!fp32) k_finalize<<<nslots, 256, 0, s>>>(g, slots, nbx);
-        else k_finalize_inner<<<nslots, 256, 0, s>>>(g, slots, nbx, kMaxInnerPerStep);
+        k_decide_iter<<<nslots, 256, 0, s>>>(g, slots, nunits, fp32 ? 1 : 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    if ((e = sweep(2, nullptr)) != hipSuccess) return e;
-    if ((e = sweep(3, nullptr)) != hipSuccess) return e;
-    if ((e = sweep(2, nullptr)) != hipSuccess) return e;
-    return sweep(5, nullptr);
+    if ((e = sweep(2)) != hipSuccess) return e;
+    if ((e = sweep(3)) != hipSuccess) return e;
+    if ((e = sweep(2)) != hipSuccess) return e;
+    return sweep(5);
 }
 
 hipError_t launch_sweep(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32, int which,
@@ -666,10 +546,10 @@ hipError_t launch_iteration(const GridArgs& g, const Geometry& geo, const Tables
     return five_sweeps(g, t, slots, nslots, fp32, 0, s, tm, geo.share);
 }
 
-hipError_t launch_outer_resid_sweep(const GridArgs& g, const Slot* slots, int nslots, hipStream_t s, int* nblocks) {
+hipError_t launch_outer_resid_sweep(const GridArgs& g, const Slot* slots, int nslots, hipStream_t s, int* nunits) {
     return dispatch_len(g.nx, [&]<int N>() {
         const int nb = blocks_outer<N>(g);
-        if (nblocks) *nblocks = nb;
+        if (nunits) *nunits = outer_units<N>(g);
         return dispatch_op(g.coef, g.weight, [&]<int C, int W>() {
             if constexpr (OuterCfg<N>::ok) k_outer_resid<N, C, W><<<dim3(nb, nslots), 256, 0, s>>>(g, slots);
             else k_outer_resid_rows<N, C, W><<<dim3(nb, nslots), kPtThreads, 0, s>>>(g, slots);
@@ -681,10 +561,10 @@ hipError_t launch_outer_resid_sweep(const GridArgs& g, const Slot* slots, int ns
 hipError_t launch_outer_residual(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,
                                  hipStream_t s) {
     (void)geo;
-    int nb = 0;
-    hipError_t e = launch_outer_resid_sweep(g, slots, nslots, s, &nb);
+    int nu = 0;
+    hipError_t e = launch_outer_resid_sweep(g, slots, nslots, s, &nu);
     if (e != hipSuccess) return e;
-    k_finalize_outer<<<nslots, 256, 0, s>>>(g, slots, nb);
+    k_decide_outer<<<nslots, 256, 0, s>>>(g, slots, nu);
     return hipGetLastError();
 }
 

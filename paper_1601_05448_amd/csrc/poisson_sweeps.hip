@@ -116,16 +116,10 @@ k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                 W[(2 * P + 1) * N + k] = h.y;
             }
         }
+        if (MODE == 0) put_unit_sums<C::NT, 4>(acc, red, s.partial + (unsigned long long)grp * kPartialStride);
         grp += gridDim.x;
         if (grp >= ngroups) break;
         __syncthreads();  // the next group overwrites the lines
-    }
-    if (MODE == 0) {
-        block_sums<C::NT, 4>(acc, red);
-        if (threadIdx.x == 0) {
-            double* out = s.partial + (unsigned long long)blockIdx.x * kPartialStride;
-            out[0] = acc[0]; out[1] = acc[1]; out[2] = acc[2]; out[3] = acc[3];
-        }
     }
 }
 
@@ -256,11 +250,7 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
             }
             __syncthreads();  // the next flush overwrites the lines
         }
-    }
-    block_sums<C::NT, 4>(acc, red);
-    if (threadIdx.x == 0) {
-        double* out = s.partial + (unsigned long long)blockIdx.x * kPartialStride;
-        out[0] = acc[0]; out[1] = acc[1]; out[2] = acc[2]; out[3] = acc[3];
+        put_unit_sums<C::NT, 4>(acc, red, s.partial + (unsigned long long)tile * kPartialStride);
     }
 }
 
@@ -602,7 +592,7 @@ static int persistent_grid(const void* kernel, int threads, unsigned ngroups, in
 
 template <typename T, int MODE>
 static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, int which,
-                          hipStream_t s, int* nblocks, float share) {
+                          hipStream_t s, int* nunits, float share) {
     const unsigned rows = (unsigned)(g.ny * g.nz / 2);
     switch (which) {
         case 1:
@@ -616,12 +606,12 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
                                             (((unsigned)g.nz + Z::KM - 1) / Z::KM);
                         const void* k = (const void*)&k_resid_dhtx_z<T, N, CO, WE>;
                         const int nb = persistent_grid(k, C::NT, nt, nslots, share);
-                        if (nblocks) *nblocks = nb;
+                        if (nunits) *nunits = (int)nt;
                         k_resid_dhtx_z<T, N, CO, WE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
                     } else {
                         const void* k = (const void*)&k_resid_dhtx<T, N, MODE, CO, WE>;
                         const int nb = persistent_grid(k, C::NT, ng, nslots, share);
-                        if (nblocks) *nblocks = nb;
+                        if (nunits) *nunits = (int)ng;
                         k_resid_dhtx<T, N, MODE, CO, WE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
                     }
                     return hipGetLastError();
@@ -657,10 +647,10 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
 }
 
 hipError_t launch_sweep_mode(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32, int which,
-                             int mode, hipStream_t s, int* nblocks, float share) {
-    if (mode == 1) return sweep_t<double, 1>(g, t, slots, nslots, which, s, nblocks, share);
-    return fp32 ? sweep_t<float, 0>(g, t, slots, nslots, which, s, nblocks, share)
-                : sweep_t<double, 0>(g, t, slots, nslots, which, s, nblocks, share);
+                             int mode, hipStream_t s, int* nunits, float share) {
+    if (mode == 1) return sweep_t<double, 1>(g, t, slots, nslots, which, s, nunits, share);
+    return fp32 ? sweep_t<float, 0>(g, t, slots, nslots, which, s, nunits, share)
+                : sweep_t<double, 0>(g, t, slots, nslots, which, s, nunits, share);
 }
 
 unsigned sweep_groups_x(const GridArgs& g) {

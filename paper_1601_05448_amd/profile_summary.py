@@ -28,7 +28,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ("poisson_sweeps.hip", "poisson_device.hpp", "poisson_fft.hpp", "poisson_internal.hpp",
-                  "poisson_kernels.hip")
+                  "poisson_kernels.hip", "poisson_control.hpp")
 
 
 def kernel_source_hash() -> str:

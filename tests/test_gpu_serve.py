@@ -66,6 +66,24 @@ def _served(probs, precision, budget=1 << 33, slots=64, tols=None):
 
 
 @pytest.mark.parametrize("precision", [P.POISSON_FP64, P.POISSON_FP32_REFINE])
+def test_same_bits_when_the_batch_shrinks_the_grids(precision):
+    """128^3 requests: alone a sweep gets every resident block, in a batch of four
+    each request gets a quarter, so the blocks cover different tiles; the
+    residual sums are kept per tile, so the answers are the same bits."""
+    announce("serve 128^3 batch invariance", precision)
+    probs = [inputs.small_problem(shape=(128, 128, 128), lengths=(TWO_PI,) * 3, ratio=2.0 + k, seed=300 + k)
+             for k in range(4)]
+    mixed, res = _served(probs, precision)
+    assert len(res.outcomes) == len(probs)
+    for k, pr in enumerate(probs):
+        p_alone, st_alone = _alone(pr, precision)
+        p_mix, st_mix = mixed[k]
+        assert st_mix["status"] == 0 and st_alone["status"] == 0
+        assert st_mix["iters"] == st_alone["iters"] and st_mix["outer_iters"] == st_alone["outer_iters"]
+        assert np.array_equal(p_mix, p_alone), k
+
+
+@pytest.mark.parametrize("precision", [P.POISSON_FP64, P.POISSON_FP32_REFINE])
 def test_each_result_same_alone_and_in_the_mix(precision):
     announce("serve mix invariance", precision)
     probs = _mix()
