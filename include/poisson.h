@@ -97,8 +97,10 @@ typedef struct {
     double err_bound_rel;   /* bound on ||p - p*||_2 / ||p||_2 from the final residual:   */
                             /* rho_max ||r||_2 / min_d(4 sin^2(pi/N_d)/h_d^2) / ||p||_2   */
     double ms;              /* device time of the solve (HIP events on the stream)        */
-    int p1_sweeps;          /* launches of the residual sweep that did work: FP64 residual
-                               evaluations, or FP32 inner residual evaluations           */
+    int p1_sweeps;          /* launches of the residual sweep P1 that did work: FP64, one
+                               per residual evaluation; FP32_REFINE, one per inner
+                               evaluation except the first of a refinement step where
+                               the outer residual sweep produced it                  */
 } poisson_stats;
 
 /* Create a solver for one grid: validates the options, builds the transform
@@ -164,7 +166,9 @@ int poisson_lap_pinv(poisson_t h, const double* q, double* delta);
  * warm-up launch), written to *avg_ms.  sweep: 1 residual + weight + Hartley
  * along x; 2 Hartley along y; 3 Hartley along z, symbol division, Hartley
  * along z; 5 Hartley along x + update; 6 (POISSON_FP32_REFINE handles only)
- * the FP64 outer residual of a refinement step with its FP32 outputs.
+ * the FP64 outer residual of a refinement step with its FP32 outputs (where
+ * the rows allow it, fused with the first inner sweep's residual and its
+ * transform along x).
  * fp32 != 0 times the FP32 sweeps of a POISSON_FP32_REFINE handle.  p is used
  * as scratch: its contents are lost. */
 int poisson_time_sweep(poisson_t h, int sweep, int fp32, const double* rho, const double* b, double* p, int reps,

@@ -56,8 +56,10 @@ __device__ inline void decide_fp64(const GridArgs& g, SolveState* st, const doub
 }
 
 // FP32_REFINE, after the FP64 outer residual of outer step st->iter.  sums: r^2,
-// bt^2, p, p^2, r.
-__device__ inline void decide_outer(const GridArgs& g, SolveState* st, const double* sums) {
+// bt^2, p, p^2, r.  fused: the sweep also produced the first inner sweep's
+// transformed residual, whose evaluation (rel 1 against the step's own right-
+// hand side) is taken here; the rest of that sweep is due next (kStageTail).
+__device__ inline void decide_outer(const GridArgs& g, SolveState* st, const double* sums, bool fused) {
     const int m = st->iter;
     st->p_sum = sums[2];
     st->p_sumsq = sums[3];
@@ -96,6 +98,16 @@ __device__ inline void decide_outer(const GridArgs& g, SolveState* st, const dou
         st->since_best = 0;
         st->best_in = INFINITY;
         st->rel_in = 1.0;
+        if (fused) {
+            // inner evaluation 0: ||r32 - mean|| from the FP64 sums, rel 1; not
+            // a stop (inner_total < max_iter here), so its update follows
+            const double n = (double)g.n;
+            st->rhs_norm32 = st->inv_s * sqrt(fmax(sums[0] - sums[4] * sums[4] / n, 0.0));
+            st->best_in = 1.0;
+            st->inner_iter = 1;
+            st->inner_total += 1;
+            st->stage = kStageTail;
+        }
     }
 }
 

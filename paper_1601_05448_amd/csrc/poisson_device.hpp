@@ -473,7 +473,10 @@ struct IterView<double> {
     __device__ IterView(const Slot& s)
         : p(gptr(s.p)), rhs(gptr(s.b)), rho(gptr(s.rho)), W(gptr(s.W)), rhs_mean(s.st->b_mean),
           rmax(s.st->rho_max), rinv(recip(s.st->rho_max)) {}
-    static __device__ bool skip(const SolveState* st) { return st->done != 0; }
+    static __device__ bool skip(const SolveState* st, int stage = 1) {
+        (void)stage;
+        return st->done != 0;
+    }
 };
 
 template <>
@@ -483,8 +486,10 @@ struct IterView<float> {
     __device__ IterView(const Slot& s)
         : p(gptr(s.d32)), rhs(gptr(s.r32)), rho(gptr(s.rho32)), W(gptr(s.W32)),
           rhs_mean((float)s.st->rhs_mean32), rmax((float)s.st->rho_max), rinv(recip((float)s.st->rho_max)) {}
-    static __device__ bool skip(const SolveState* st) {
-        return st->done != 0 || st->stage != 1 || st->inner_done != 0;
+    // `stage`: 1 for the inner sweeps, kStageTail for the rest of a first inner
+    // sweep whose residual the outer residual sweep produced
+    static __device__ bool skip(const SolveState* st, int stage = 1) {
+        return st->done != 0 || st->stage != stage || st->inner_done != 0;
     }
 };
 

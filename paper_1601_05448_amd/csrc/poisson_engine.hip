@@ -254,27 +254,32 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
             chunk = std::clamp(need, 1, prm.max_chunk);
         }
     } else {
-        // Speculative refinement cycles: outer residual, `chunk` inner sweeps,
+        // Speculative refinement cycles: outer residual, `full` inner sweeps,
         // update.  Every kernel runs only in its stage of the device state, so
         // a cycle whose inner sweeps stop early idles through the rest, and one
         // whose inner sweeps are not done leaves the update and the next outer
         // residual to idle until they are.  Each cycle moves every unfinished
         // solve on by at least one stage, so the count of cycles is bounded.
-        // inner launches of the first step: a contraction of 0.2 per sweep
-        // (typical of the method on smooth densities), plus the launch whose
-        // residual evaluation stops the sweeps
-        int chunk = std::clamp((int)std::ceil(std::log(prm.inner_tol) / std::log(0.2)) + 1, 1, prm.max_chunk);
+        // Where the outer residual is fused with the first inner sweep (and
+        // followed by the rest of it), a step needs one full sweep less.
+        const int first = outer_fusable(g) ? 1 : 0;
+        // sweeps of the first step: a contraction of 0.2 per sweep (typical of
+        // the method on smooth densities), plus the one whose residual
+        // evaluation stops the sweeps
+        const int guess = (int)std::ceil(std::log(prm.inner_tol) / std::log(0.2)) + 1;
+        int full = std::clamp(guess - first, 0, prm.max_chunk);
         const int max_cycles = prm.max_outer + prm.max_iter + 2;
         for (int cycle = 0; cycle < max_cycles; ++cycle) {
-            if ((e = launch_outer_residual(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
-            if ((e = iterations(chunk, true)) != hipSuccess) return hip_status(e);
+            if ((e = launch_outer_residual(g, geo, t, d_slots, nslots, s, nullptr)) != hipSuccess)
+                return hip_status(e);
+            if ((e = iterations(full, true)) != hipSuccess) return hip_status(e);
             if ((e = launch_outer_update(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
             const int r = poll();
             if (r < 0) return r;
             if (r == 1) break;
-            // The next cycle's inner launches.  A solve still inside its inner
-            // sweeps: the launches that bring its inner residual to the inner
-            // tolerance at the contraction it has shown (twice the last chunk
+            // The next cycle's full inner sweeps.  A solve still inside its
+            // inner sweeps: those that bring its inner residual to the inner
+            // tolerance at the contraction it has shown (twice the last count
             // when it has shown none).  A solve between steps: as many as its
             // last step used (steps need about the same number), or none when
             // the next outer residual is predicted to pass the tolerance (last
@@ -285,9 +290,9 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
                 const SolveState& h = hdr[q];
                 if (h.done) continue;
                 int m;
-                if (h.stage == 1) {
+                if (h.stage != 0) {
                     all_pass = false;
-                    m = 2 * std::max(chunk, 1);
+                    m = 2 * std::max(full, 1);
                     const int k = h.inner_iter - 1;  // index of the last inner residual evaluated
                     if (k >= 1 && h.rel_in > 0.0 && h.rel_in < 1.0) {
                         const double rate = std::pow(h.rel_in, 1.0 / k);
@@ -295,11 +300,11 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
                     }
                 } else {
                     all_pass &= h.rel * h.rel_in <= 0.5 * h.tol;
-                    m = h.inner_last;
+                    m = h.inner_last - first;
                 }
                 need = std::max(need, m);
             }
-            chunk = all_pass ? 0 : std::clamp(need, 1, prm.max_chunk);
+            full = all_pass ? 0 : std::clamp(need, 1, prm.max_chunk);
         }
     }
     if ((e = launch_fixup(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
@@ -548,11 +553,13 @@ int poisson_time_sweep(poisson_t h, int sweep, int fp32, const double* rho, cons
     if ((e = launch_setup_finalize(h->g, h->geo, h->d_slot, 1, h->stream)) != hipSuccess) return hip_status(e);
     // the inner sweeps run in stage 1, which the outer residual opens; the
     // outer residual sweep itself in stage 0
-    if (fp32 && sweep != 6 && (e = launch_outer_residual(h->g, h->geo, h->d_slot, 1, h->stream)) != hipSuccess)
+    if (fp32 && sweep != 6 &&
+        (e = launch_outer_residual(h->g, h->geo, h->tables.t, h->d_slot, 1, h->stream, nullptr)) != hipSuccess)
         return hip_status(e);
     auto one = [&]() {
-        return sweep == 6 ? launch_outer_resid_sweep(h->g, h->d_slot, 1, h->stream, nullptr)
-                          : launch_sweep(h->g, h->tables.t, h->d_slot, 1, fp32 != 0, sweep, h->stream);
+        if (sweep != 6) return launch_sweep(h->g, h->tables.t, h->d_slot, 1, fp32 != 0, sweep, h->stream);
+        return outer_fusable(h->g) ? launch_outer_fused(h->g, h->tables.t, h->d_slot, 1, h->stream, nullptr)
+                                   : launch_outer_resid_sweep(h->g, h->d_slot, 1, h->stream, nullptr);
     };
     if ((e = one()) != hipSuccess) return hip_status(e);  // warm
     if ((e = hipEventRecord(h->ev0, h->stream)) != hipSuccess) return hip_status(e);

@@ -10,6 +10,7 @@ namespace pois {
 constexpr int kHistCap = 256;      // residual-history entries kept per solve
 constexpr int kPartialStride = 8;  // doubles of per-block partial sums per block
 constexpr int kMaxSetupBlocks = 4096;
+constexpr int kStageTail = 3;  // see SolveState::stage
 constexpr int kMaxInnerPerStep = 1 << 20;  // FP32 inner sweeps per refinement step: bounded by max_iter
 
 // Grid description passed by value to every kernel.  Uniform over a batch:
@@ -53,8 +54,10 @@ struct SolveState {
     double p_sumsq;
     int p_fixed;        // p_shift already removed
     // FP32 inner iteration.  stage: 0 the next FP64 outer residual is due, 1 inner
-    // FP32 sweeps run, 2 the FP64 update is due; each kernel acts only on the
-    // solves in its stage, so solves at different stages share one launch sequence
+    // FP32 sweeps run, 2 the FP64 update is due, 3 (kStageTail) the rest of the
+    // first inner sweep is due after an outer residual that also produced that
+    // sweep's transformed weighted residual; each kernel acts only on the solves
+    // in its stage, so solves at different stages share one launch sequence
     int stage;
     int inner_iter;     // inner iteration within the current outer step
     int inner_done;
@@ -135,14 +138,23 @@ hipError_t launch_sweep(const GridArgs& g, const Tables& t, const Slot* slots, i
 // sweep (FP64).  *nunits (may be NULL) receives the number of partial sums P1
 // wrote.  `share`: fraction of the resident blocks the persistent sweeps take.
 hipError_t launch_sweep_mode(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32, int which,
-                             int mode, hipStream_t s, int* nunits, float share = 1.0f);
+                             int mode, hipStream_t s, int* nunits, float share = 1.0f, int stage = 1);
 unsigned sweep_groups_x(const GridArgs& g);
+// FP32_REFINE: whether rows of this length take the outer residual fused with
+// the first inner sweep's residual (one marching column per thread), and that
+// sweep alone (no decision); *nunits receives the number of partial sums.
+bool outer_fusable(const GridArgs& g);
+hipError_t launch_outer_fused(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, hipStream_t s,
+                              int* nunits, float share = 1.0f);
 // FP32_REFINE outer step pieces.
 // the FP64 outer residual sweep alone (no decision); *nunits (may be NULL)
 // receives the number of partial sums it wrote
 hipError_t launch_outer_resid_sweep(const GridArgs& g, const Slot* slots, int nslots, hipStream_t s, int* nunits);
-hipError_t launch_outer_residual(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,
-                                 hipStream_t s);
+// The FP64 outer residual of a refinement step and its decision; where the
+// rows allow (*fused), fused with the first inner sweep's residual and followed
+// by the rest of that sweep.
+hipError_t launch_outer_residual(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slots,
+                                 int nslots, hipStream_t s, bool* fused);
 hipError_t launch_outer_update(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,
                                hipStream_t s);
 hipError_t launch_fixup(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots, hipStream_t s);

@@ -145,15 +145,23 @@ __global__ void __launch_bounds__(256) k_decide_iter(GridArgs g, const Slot* __r
     else decide_fp64(g, st, sums);
 }
 
-// After the FP64 outer residual of a refinement step.
-__global__ void __launch_bounds__(256) k_decide_outer(GridArgs g, const Slot* __restrict__ slots, int nunits) {
+// After the FP64 outer residual of a refinement step (fused: with the first
+// inner sweep's residual).
+__global__ void __launch_bounds__(256) k_decide_outer(GridArgs g, const Slot* __restrict__ slots, int nunits,
+                                                      int fused) {
     __shared__ double red[(256 / 64) * 5];
     const Slot& s = slots[blockIdx.x];
     SolveState* st = s.st;
     if (st->done || st->stage != 0) return;
     double sums[5];
     sum_units<256, 5>(s.partial, (unsigned)nunits, sums, red);
-    if (threadIdx.x == 0) decide_outer(g, st, sums);
+    if (threadIdx.x == 0) decide_outer(g, st, sums, fused != 0);
+}
+
+// After the rest of a fused first inner sweep: the inner sweeps go on.
+__global__ void __launch_bounds__(64) k_tail_done(const Slot* __restrict__ slots) {
+    SolveState* st = slots[blockIdx.x].st;
+    if (threadIdx.x == 0 && !st->done && st->stage == kStageTail) st->stage = 1;
 }
 
 // ---- pointwise FP64 stencil sweeps -------------------------------------------------
@@ -558,13 +566,26 @@ hipError_t launch_outer_resid_sweep(const GridArgs& g, const Slot* slots, int ns
     });
 }
 
-hipError_t launch_outer_residual(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,
-                                 hipStream_t s) {
-    (void)geo;
+hipError_t launch_outer_residual(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slots,
+                                 int nslots, hipStream_t s, bool* fused) {
     int nu = 0;
-    hipError_t e = launch_outer_resid_sweep(g, slots, nslots, s, &nu);
-    if (e != hipSuccess) return e;
-    k_decide_outer<<<nslots, 256, 0, s>>>(g, slots, nu);
+    hipError_t e;
+    const bool fu = outer_fusable(g);
+    if (fused) *fused = fu;
+    if (fu) {
+        if ((e = launch_outer_fused(g, t, slots, nslots, s, &nu, geo.share)) != hipSuccess) return e;
+    } else if ((e = launch_outer_resid_sweep(g, slots, nslots, s, &nu)) != hipSuccess) {
+        return e;
+    }
+    k_decide_outer<<<nslots, 256, 0, s>>>(g, slots, nu, fu ? 1 : 0);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (!fu) return hipSuccess;
+    // the rest of the first inner sweep: P2, P3, P4, P5 (which stores dp as d32)
+    for (int which : {2, 3, 2, 5})
+        if ((e = launch_sweep_mode(g, t, slots, nslots, true, which, 0, s, nullptr, geo.share, kStageTail)) !=
+            hipSuccess)
+            return e;
+    k_tail_done<<<nslots, 64, 0, s>>>(slots);
     return hipGetLastError();
 }
 

@@ -226,7 +226,8 @@ static int launch_class(poisson_server_s* s, SizeClass* c) {
     } else {
         // one fixed sequence for solves at any stage: each kernel acts only on
         // the solves whose stage it serves
-        if ((e = launch_outer_residual(c->g, c->geo, c->d_slots, n, c->stream)) != hipSuccess) return hip_status(e);
+        if ((e = launch_outer_residual(c->g, c->geo, c->tables.t, c->d_slots, n, c->stream, nullptr)) != hipSuccess)
+            return hip_status(e);
         for (int k = 0; k < s->iters_per_tick; ++k)
             if ((e = launch_iteration(c->g, c->geo, c->tables.t, c->d_slots, n, true, c->stream)) != hipSuccess)
                 return hip_status(e);

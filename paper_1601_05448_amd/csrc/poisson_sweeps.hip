@@ -254,6 +254,116 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     }
 }
 
+// FP32_REFINE: the FP64 outer residual of a refinement step fused with the
+// residual half of its first FP32 inner sweep.  The inner correction starts at
+// zero, so that sweep's weighted residual is q = w r32 with r32 = r s^-1 of the
+// FP64 residual r = b~ - A p: the tile's FP64 residual (z-marching as in P1)
+// gives r32 (stored for the later inner sweeps) and q, whose lines are
+// transformed along x into W32 exactly as the FP32 P1 would.  The mean of r32,
+// which the FP32 P1 removes, is FP64 rounding noise here and is not removed.
+// Per tile: r^2, bt^2, p, p^2, r in FP64.  One column per thread.
+template <int N, int COEF, int WEIGHT>
+__global__ void __launch_bounds__((LineCfg<float, N>::NT), 2)
+k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
+    using C = LineCfg<float, N>;
+    using Z = ZTile<N, C::NT, C::L>;
+    static_assert(Z::CPT == 1, "one marching column per thread");
+    __shared__ cpx<float> lds[C::L * C::LS];
+    __shared__ cpx<float> tw[N];
+    __shared__ double red[(C::NT / 64) * 5];
+    __shared__ double edge[2 * Z::SUB * Z::EDGE];
+    const Slot& s = slots[blockIdx.y];
+    SolveState* st = s.st;
+    if (st->done || st->stage != 0) return;
+    const cpx<float>* twg = twiddles<float>(tb, 0);
+    for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
+    const double bm = st->b_mean, inv_s = st->inv_s, rmax = st->rho_max, rinv = recip(st->rho_max);
+
+    const unsigned nyh = (unsigned)g.ny / 2, nz = (unsigned)g.nz;
+    const unsigned ngj = (nyh + Z::SUB - 1) / Z::SUB, ngk = (nz + Z::KM - 1) / Z::KM;
+    const unsigned ntiles = ngj * ngk;
+    const int sidx = (N >= C::NT) ? 0 : (int)threadIdx.x / N;
+    const unsigned i = (N >= C::NT) ? threadIdx.x : threadIdx.x % N;
+    POIS_GLOBAL float* r32 = gptr(s.r32);
+    POIS_GLOBAL float* W32 = gptr(s.W32);
+    ZMarch<double> zm;
+    zm.p = s.p;
+    zm.rho = s.rho;
+    zm.rhs = s.b;
+    zm.nx = (unsigned)g.nx;
+    zm.nz = nz;
+    zm.sz = (unsigned)g.nx * (unsigned)g.ny;
+    zm.lane = (int)(threadIdx.x & 63);
+    double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+
+    for (unsigned tile = xcd_block(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x) {
+        const unsigned tj = tile % ngj, tk = tile / ngj;
+        const unsigned jp = tj * Z::SUB + sidx;
+        const bool jvalid = jp < nyh;
+        zm.rows_of(jvalid ? jp : 0u, (unsigned)g.ny);
+        const int k0 = (int)(tk * Z::KM);
+        PlaneRows<double> pl[3];
+        PlaneSide<double> sd;
+        zm.load_rows(zm.plane(k0 - 1), i, pl[0]);
+        zm.load_rows(zm.plane(k0), i, pl[1]);
+        zm.load_rows(zm.plane(k0 + 1), i, pl[2]);
+        zm.load_side(zm.plane(k0), i, sd);
+        for (int f = 0; f < Z::KM / Z::KF; ++f) {
+#pragma unroll
+            for (int q = 0; q < Z::KF; ++q) {
+                const int k = k0 + f * Z::KF + q;
+                const bool valid = jvalid && k < (int)nz;
+                PlaneRows<double> nn;
+                PlaneSide<double> ns;
+                zm.load_rows(zm.plane(k + 2), i, nn);
+                zm.load_side(zm.plane(k + 1), i, ns);
+                double* eb = edge + ((q & 1) * Z::SUB + sidx) * Z::EDGE;
+                zm.edge_put(eb, i, pl[1]);
+                __syncthreads();
+                PairIn<double> in;
+                zm.pair(pl[0], pl[1], pl[2], sd, zm.edge_get(eb, i), in);
+                cpx<float> qv = {0.0f, 0.0f};
+                if (valid) {
+                    const PairOut<double> pr = pair_eval<double, COEF, WEIGHT>(g, in, bm, rmax, rinv);
+                    acc[0] += pr.a.r * pr.a.r + pr.b.r * pr.b.r;
+                    acc[1] += pr.a.bt * pr.a.bt + pr.b.bt * pr.b.bt;
+                    acc[2] += pr.a.pc + pr.b.pc;
+                    acc[3] += pr.a.pc * pr.a.pc + pr.b.pc * pr.b.pc;
+                    acc[4] += pr.a.r + pr.b.r;
+                    const float ra = (float)(pr.a.r * inv_s), rb = (float)(pr.b.r * inv_s);
+                    const unsigned a = (unsigned)k * zm.sz + zm.ra + i;
+                    r32[a] = ra;
+                    r32[a + (unsigned)g.nx] = rb;
+                    qv = {(float)pr.a.w * ra, (float)pr.b.w * rb};
+                }
+                lds[(sidx * Z::KF + q) * C::LS + C::pos(i)] = qv;
+                pl[0] = pl[1];
+                pl[1] = pl[2];
+                pl[2] = nn;
+                sd = ns;
+            }
+            __syncthreads();
+            fft_block_lines<float, N>(lds, tw);
+#pragma unroll
+            for (int it = 0; it < C::IT; ++it) {
+                const int e = threadIdx.x + it * C::NT;
+                const int l = e / N, kx = e % N;
+                const unsigned ljp = tj * Z::SUB + l / Z::KF;
+                const unsigned lk = (unsigned)(k0 + f * Z::KF) + l % Z::KF;
+                if (ljp < nyh && lk < nz) {
+                    const unsigned P = lk * nyh + ljp;
+                    const cpx<float> h = hartley(lds[l * C::LS + C::pos(kx)],
+                                                 lds[l * C::LS + C::pos((kx == 0 ? 0 : N - kx))]);
+                    W32[(2 * P) * N + kx] = h.x;
+                    W32[(2 * P + 1) * N + kx] = h.y;
+                }
+            }
+            __syncthreads();  // the next flush overwrites the lines
+        }
+        put_unit_sums<C::NT, 5>(acc, red, s.partial + (unsigned long long)tile * kPartialStride);
+    }
+}
+
 // Rows that fill whole waves, and a register budget for CPT marching columns.
 template <typename T, int N>
 constexpr bool use_zmarch() {
@@ -275,12 +385,12 @@ __device__ __forceinline__ unsigned col_base(const GridArgs& g, unsigned line) {
 
 template <typename T, int N, int AX, int MODE>
 __global__ void __launch_bounds__((LineCfg<T, N>::NT), 2)
-k_dht_cols(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
+k_dht_cols(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) {
     using C = LineCfg<T, N>;
     __shared__ cpx<T> lds[C::L * C::LS];
     __shared__ cpx<T> tw[N];
     const Slot& s = slots[blockIdx.y];
-    if (MODE == 0 && IterView<T>::skip(s.st)) return;
+    if (MODE == 0 && IterView<T>::skip(s.st, stage)) return;
     const cpx<T>* twg = twiddles<T>(tb, AX);
     for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
     POIS_GLOBAL T* Wc = MODE == 0 ? IterView<T>(s).W : (POIS_GLOBAL T*)gptr(s.W);  // complex-indexed
@@ -357,12 +467,12 @@ k_dht_cols(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
 // ---- P3: Hartley along z, divide by n * symbol, Hartley along z ----------------
 template <typename T, int N, int MODE>
 __global__ void __launch_bounds__((LineCfg<T, N>::NT), 2)
-k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
+k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) {
     using C = LineCfg<T, N>;
     __shared__ cpx<T> lds[C::L * C::LS];
     __shared__ cpx<T> tw[N];
     const Slot& s = slots[blockIdx.y];
-    if (MODE == 0 && IterView<T>::skip(s.st)) return;
+    if (MODE == 0 && IterView<T>::skip(s.st, stage)) return;
     const cpx<T>* twg = twiddles<T>(tb, 2);
     for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
     POIS_GLOBAL T* Wc = MODE == 0 ? IterView<T>(s).W : (POIS_GLOBAL T*)gptr(s.W);  // complex-indexed
@@ -477,18 +587,20 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
 }
 
 // ---- P5: Hartley along x, update -----------------------------------------------
-// MODE 0: FP64 p += dp - mean(p) (or FP32 d32 += dp); MODE 1: assign to p (L^+ sweep).
+// MODE 0: FP64 p += dp - mean(p) (or FP32 d32 += dp); MODE 1: assign to p (L^+
+// sweep); MODE 2: FP32 d32 = dp, the first inner sweep after a fused outer
+// residual (d32 holds nothing yet).
 template <typename T, int N, int MODE>
 __global__ void __launch_bounds__((LineCfg<T, N>::NT))
-k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
+k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) {
     using C = LineCfg<T, N>;
     __shared__ cpx<T> lds[C::L * C::LS];
     __shared__ cpx<T> tw[N];
     const Slot& s = slots[blockIdx.y];
-    if (MODE == 0 && IterView<T>::skip(s.st)) return;
+    if (MODE != 1 && IterView<T>::skip(s.st, stage)) return;
     const cpx<T>* twg = twiddles<T>(tb, 0);
     for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
-    const POIS_GLOBAL T* W = (MODE == 0) ? IterView<T>(s).W : (const POIS_GLOBAL T*)gptr(s.W);
+    const POIS_GLOBAL T* W = (MODE != 1) ? IterView<T>(s).W : (const POIS_GLOBAL T*)gptr(s.W);
     POIS_GLOBAL T* out;
     if constexpr (sizeof(T) == 8) out = (POIS_GLOBAL T*)gptr(s.p);
     else out = (POIS_GLOBAL T*)gptr(s.d32);
@@ -592,7 +704,7 @@ static int persistent_grid(const void* kernel, int threads, unsigned ngroups, in
 
 template <typename T, int MODE>
 static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, int which,
-                          hipStream_t s, int* nunits, float share) {
+                          hipStream_t s, int* nunits, float share, int stage) {
     const unsigned rows = (unsigned)(g.ny * g.nz / 2);
     switch (which) {
         case 1:
@@ -622,7 +734,7 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
                 using C = LineCfg<T, N>;
                 const unsigned ng = ((unsigned)(g.nxh * g.nz) + C::L - 1) / C::L;
                 const int nb = persistent_grid((const void*)&k_dht_cols<T, N, 1, MODE>, C::NT, ng, nslots, share);
-                k_dht_cols<T, N, 1, MODE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
+                k_dht_cols<T, N, 1, MODE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t, stage);
                 return hipGetLastError();
             });
         case 3:
@@ -630,7 +742,7 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
                 using C = LineCfg<T, N>;
                 const unsigned ng = ((unsigned)(g.nxh * g.ny) + C::L - 1) / C::L;
                 const int nb = persistent_grid((const void*)&k_dht_z_solve<T, N, MODE>, C::NT, ng, nslots, share);
-                k_dht_z_solve<T, N, MODE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
+                k_dht_z_solve<T, N, MODE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t, stage);
                 return hipGetLastError();
             });
         case 5:
@@ -638,7 +750,13 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
                 using C = LineCfg<T, N>;
                 const unsigned ng = (rows + C::L - 1) / C::L;
                 const int nb = persistent_grid((const void*)&k_dhtx_update<T, N, MODE>, C::NT, ng, nslots, share);
-                k_dhtx_update<T, N, MODE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
+                if constexpr (MODE == 0 && sizeof(T) == 4) {
+                    if (stage == kStageTail) {
+                        k_dhtx_update<T, N, 2><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t, stage);
+                        return hipGetLastError();
+                    }
+                }
+                k_dhtx_update<T, N, MODE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t, stage);
                 return hipGetLastError();
             });
         default:
@@ -647,10 +765,45 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
 }
 
 hipError_t launch_sweep_mode(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32, int which,
-                             int mode, hipStream_t s, int* nunits, float share) {
-    if (mode == 1) return sweep_t<double, 1>(g, t, slots, nslots, which, s, nunits, share);
-    return fp32 ? sweep_t<float, 0>(g, t, slots, nslots, which, s, nunits, share)
-                : sweep_t<double, 0>(g, t, slots, nslots, which, s, nunits, share);
+                             int mode, hipStream_t s, int* nunits, float share, int stage) {
+    if (mode == 1) return sweep_t<double, 1>(g, t, slots, nslots, which, s, nunits, share, 1);
+    return fp32 ? sweep_t<float, 0>(g, t, slots, nslots, which, s, nunits, share, stage)
+                : sweep_t<double, 0>(g, t, slots, nslots, which, s, nunits, share, 1);
+}
+
+template <int N>
+constexpr bool outer_fusable_len() {
+    if constexpr (N % 64 != 0) return false;
+    else return ZTile<N, LineCfg<float, N>::NT, LineCfg<float, N>::L>::CPT == 1;
+}
+
+bool outer_fusable(const GridArgs& g) {
+    bool ok = false;
+    (void)dispatch_len(g.nx, [&]<int N>() {
+        ok = outer_fusable_len<N>();
+        return hipSuccess;
+    });
+    return ok;
+}
+
+hipError_t launch_outer_fused(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, hipStream_t s,
+                              int* nunits, float share) {
+    return dispatch_len(g.nx, [&]<int N>() {
+        if constexpr (outer_fusable_len<N>()) {
+            using C = LineCfg<float, N>;
+            using Z = ZTile<N, C::NT, C::L>;
+            const unsigned nt = (((unsigned)g.ny / 2 + Z::SUB - 1) / Z::SUB) * (((unsigned)g.nz + Z::KM - 1) / Z::KM);
+            if (nunits) *nunits = (int)nt;
+            return dispatch_op(g.coef, g.weight, [&]<int CO, int WE>() {
+                const void* k = (const void*)&k_outer_resid_dhtx<N, CO, WE>;
+                const int nb = persistent_grid(k, C::NT, nt, nslots, share);
+                k_outer_resid_dhtx<N, CO, WE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
+                return hipGetLastError();
+            });
+        } else {
+            return hipErrorInvalidValue;
+        }
+    });
 }
 
 unsigned sweep_groups_x(const GridArgs& g) {

@@ -180,8 +180,8 @@ def test_solve_fp32_refine_ragged_outer_tiles(shape):
 
 @pytest.mark.parametrize("precision", [P.POISSON_FP64, P.POISSON_FP32_REFINE])
 def test_kernel_timer_counts_residual_sweeps(precision):
-    """The event timer brackets every launch of P1 inside a solve; the launches
-    that did work are one per residual evaluation."""
+    """The event timer brackets every launch of P1 inside a solve, and the
+    library counts the launches that did work."""
     announce("kernel timer", precision)
     prob = inputs.workload2(64)
     fp32 = precision == P.POISSON_FP32_REFINE
@@ -194,7 +194,10 @@ def test_kernel_timer_counts_residual_sweeps(precision):
         st2 = s.solve(dev(prob.rho), dev(prob.b), p, 1e-10)
         assert P.poisson_kernel_timer_read(s.h) == (0.0, 0)
     assert st["code"] == P.POISSON_OK
-    want = st["iters"] + (st["outer_iters"] if fp32 else 1)
+    # FP64: one P1 per residual evaluation (iters updates + the final one);
+    # FP32 on 64-cell rows: the outer residual sweep evaluates the first inner
+    # residual of each step, so one P1 per inner update
+    want = st["iters"] if fp32 else st["iters"] + 1
     assert st["p1_sweeps"] == want, st
     assert n >= want and ms > 0.0
     assert st2["code"] == P.POISSON_OK
