@@ -8,7 +8,7 @@
 namespace pois {
 
 constexpr int kHistCap = 256;      // residual-history entries kept per solve
-constexpr int kPartialStride = 8;  // doubles of per-block partial sums per block
+constexpr int kPartialStride = 8;  // doubles per set of partial sums (one set per block or per unit of work)
 constexpr int kMaxSetupBlocks = 4096;
 constexpr int kStageTail = 3;  // see SolveState::stage
 constexpr int kMaxInnerPerStep = 1 << 20;  // FP32 inner sweeps per refinement step: bounded by max_iter
@@ -84,7 +84,7 @@ struct Slot {
     float* r32;
     float* d32;
     float* W32;
-    double* partial;  // per-block partial sums, kPartialStride per block
+    double* partial;  // partial sums: kPartialStride doubles per block or per tile / line group
     SolveState* st;
 };
 
@@ -101,7 +101,7 @@ struct Geometry {
     int blocks_x;      // row-pair line groups of the x sweep (most blocks P1 can use)
     int blocks_pt;     // pointwise kernels
     int blocks_outer;  // FP64 outer residual
-    int max_blocks;    // partial-sum capacity needed
+    int max_blocks;    // capacity of the partial-sum array, in sets
     float share;       // fraction of the chip's resident blocks the persistent sweeps take
 };
 

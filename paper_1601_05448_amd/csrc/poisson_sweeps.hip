@@ -1,9 +1,13 @@
 // The four field sweeps of one iteration of the paper's method (section
 // "Poisson equation", eq. (Pois)), written for gfx950:
-//   P1 k_resid_dhtx   r = b~ - A p, q = w r, partial norms, Hartley along x -> W
+//   P1 k_resid_dhtx_z r = b~ - A p, q = w r, partial norms per tile, Hartley
+//                     along x -> W (z-marching stencil; k_resid_dhtx, a row-pair
+//                     gather, for rows that do not fill whole waves)
 //   P2 k_dht_cols     Hartley along y of W (also P4: the transform is self-inverse)
 //   P3 k_dht_z_solve  Hartley along z, divide by n * symbol, Hartley along z
 //   P5 k_dhtx_update  Hartley along x, p += dp (minus the mean of p)
+// and, for the FP32 refinement, k_outer_resid_dhtx: the FP64 outer residual
+// fused with the first inner sweep's residual.
 //
 // Each block holds L whole lines of its transform direction in LDS.  The LDS a
 // line group needs limits an FP64 sweep to two blocks per CU, too few waves to
@@ -11,11 +15,12 @@
 // software-pipelined: a block loops over line groups, and the global loads of
 // the next group (and, in the FP32 P5, the loads of the values to update) are
 // issued before the FFT of the current group, so that they are in flight while
-// the block works in LDS.  P1 evaluates its stencil one row pair behind its loads for the
-// same reason.
+// the block works in LDS.  The stencil sweeps keep the next plane's loads in
+// flight while they evaluate the current one, for the same reason.
 //
 // blockIdx.y selects the solve (slot) of a batch of equal-size grids; every sweep
-// returns at once for solves that are done.
+// returns at once for solves that are done or, on the FP32 path, not in the
+// stage the sweep serves.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
