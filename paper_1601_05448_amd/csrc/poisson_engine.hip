@@ -254,57 +254,84 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
             chunk = std::clamp(need, 1, prm.max_chunk);
         }
     } else {
-        // Speculative refinement cycles: outer residual, `full` inner sweeps,
-        // update.  Every kernel runs only in its stage of the device state, so
-        // a cycle whose inner sweeps stop early idles through the rest, and one
-        // whose inner sweeps are not done leaves the update and the next outer
-        // residual to idle until they are.  Each cycle moves every unfinished
-        // solve on by at least one stage, so the count of cycles is bounded.
-        // Where the outer residual is fused with the first inner sweep (and
-        // followed by the rest of it), a step needs one full sweep less.
+        // Speculative rounds of refinement steps between host polls.  Every
+        // kernel runs only in its stage of the device state, so inner sweeps
+        // launched after the inner phase stopped idle, and an update or outer
+        // residual launched before the phase stopped idles until a later round.
+        // Each round moves every unfinished solve on by at least one stage, so
+        // the count of rounds is bounded.  Where the outer residual is fused
+        // with the first inner sweep (and followed by the rest of it), a step
+        // needs one full sweep less.
         const int first = outer_fusable(g) ? 1 : 0;
         // sweeps of the first step: a contraction of 0.2 per sweep (typical of
         // the method on smooth densities), plus the one whose residual
         // evaluation stops the sweeps
         const int guess = (int)std::ceil(std::log(prm.inner_tol) / std::log(0.2)) + 1;
         int full = std::clamp(guess - first, 0, prm.max_chunk);
-        const int max_cycles = prm.max_outer + prm.max_iter + 2;
-        for (int cycle = 0; cycle < max_cycles; ++cycle) {
-            if ((e = launch_outer_residual(g, geo, t, d_slots, nslots, s, nullptr)) != hipSuccess)
+        // A refinement step: outer residual (with the tail of its first inner
+        // sweep where fused), `nfull` full inner sweeps, update.
+        auto step = [&](int nfull) -> hipError_t {
+            hipError_t le = launch_outer_residual(g, geo, t, d_slots, nslots, s, nullptr);
+            if (le == hipSuccess) le = iterations(nfull, true);
+            if (le == hipSuccess) le = launch_outer_update(g, geo, d_slots, nslots, s);
+            return le;
+        };
+        int open_full = 0;  // full sweeps that finish an open inner phase (then its update)
+        int steps = 1;      // whole steps after that, then one outer residual to check
+        bool check = false;
+        const int max_rounds = prm.max_outer + prm.max_iter + 2;
+        for (int round = 0; round < max_rounds; ++round) {
+            if (open_full > 0) {
+                if ((e = iterations(open_full, true)) != hipSuccess) return hip_status(e);
+                if ((e = launch_outer_update(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
+            }
+            for (int k = 0; k < steps; ++k)
+                if ((e = step(full)) != hipSuccess) return hip_status(e);
+            if (check && (e = launch_outer_residual(g, geo, t, d_slots, nslots, s, nullptr)) != hipSuccess)
                 return hip_status(e);
-            if ((e = iterations(full, true)) != hipSuccess) return hip_status(e);
-            if ((e = launch_outer_update(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
             const int r = poll();
             if (r < 0) return r;
             if (r == 1) break;
-            // The next cycle's full inner sweeps.  A solve still inside its
-            // inner sweeps: those that bring its inner residual to the inner
-            // tolerance at the contraction it has shown (twice the last count
-            // when it has shown none).  A solve between steps: as many as its
-            // last step used (steps need about the same number), or none when
-            // the next outer residual is predicted to pass the tolerance (last
-            // outer residual times the last inner reduction).
-            int need = 0;
-            bool all_pass = true;
+            // What the next round enqueues, from the state now:
+            //  * a solve inside its inner sweeps: the full sweeps that bring its
+            //    inner residual to the inner tolerance at the contraction it has
+            //    shown (twice the last count when it has shown none), then its
+            //    update;
+            //  * then as many whole steps as the outer residual needs to pass the
+            //    tolerance if every step reduces it as the last one did (the
+            //    inner tolerance for a step still open), each with as many full
+            //    sweeps as the last finished step used, and the outer residual
+            //    that checks the result.
+            // Kernels out of their stage idle, so a short guess costs another
+            // round and a long one a few idle launches.
+            int need_open = 0, need_full = 0, need_steps = 0;
             for (int q = 0; q < nslots; ++q) {
                 const SolveState& h = hdr[q];
                 if (h.done) continue;
-                int m;
+                double red = h.rel_in;  // outer reduction per step
+                double rel = h.rel;     // outer residual before the next outer evaluation
                 if (h.stage != 0) {
-                    all_pass = false;
-                    m = 2 * std::max(full, 1);
+                    int m = 2 * std::max(std::max(full, open_full), 1);
                     const int k = h.inner_iter - 1;  // index of the last inner residual evaluated
                     if (k >= 1 && h.rel_in > 0.0 && h.rel_in < 1.0) {
                         const double rate = std::pow(h.rel_in, 1.0 / k);
                         if (rate < 0.95) m = (int)std::ceil(std::log(h.inner_tol / h.rel_in) / std::log(rate) + 0.25);
                     }
+                    need_open = std::max(need_open, std::max(m, 1));
+                    red = h.inner_tol;
                 } else {
-                    all_pass &= h.rel * h.rel_in <= 0.5 * h.tol;
-                    m = h.inner_last - first;
+                    need_full = std::max(need_full, h.inner_last - first);
                 }
-                need = std::max(need, m);
+                rel *= std::clamp(red, 1e-12, 0.5);
+                int st = 0;
+                if (rel > 0.5 * h.tol)
+                    st = (int)std::ceil(std::log(0.5 * h.tol / rel) / std::log(std::clamp(red, 1e-12, 0.5)));
+                need_steps = std::max(need_steps, std::clamp(st, 0, 8));
             }
-            full = all_pass ? 0 : std::clamp(need, 1, prm.max_chunk);
+            open_full = std::min(need_open, prm.max_chunk);
+            if (need_full > 0) full = std::clamp(need_full, 0, prm.max_chunk);
+            steps = need_steps;
+            check = true;
         }
     }
     if ((e = launch_fixup(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
