@@ -131,15 +131,19 @@ __global__ void __launch_bounds__(256) k_setup_finalize(GridArgs g, const Slot* 
 
 // ---- decisions (one block per solve, after the sweep that wrote the sums) -------------
 
+// One block of kDecideThreads per solve: the units' sums of a residual sweep
+// (up to one per row pair) are read by many threads at once.
+constexpr int kDecideThreads = 1024;
+
 // After P1 of an iteration: FP64 path (fp32 = 0) or an FP32 inner sweep.
-__global__ void __launch_bounds__(256) k_decide_iter(GridArgs g, const Slot* __restrict__ slots, int nunits,
-                                                     int fp32) {
-    __shared__ double red[(256 / 64) * 4];
+__global__ void __launch_bounds__(kDecideThreads) k_decide_iter(GridArgs g, const Slot* __restrict__ slots,
+                                                                int nunits, int fp32) {
+    __shared__ double red[(kDecideThreads / 64) * 4];
     const Slot& s = slots[blockIdx.x];
     SolveState* st = s.st;
     if (fp32 ? (st->done || st->stage != 1 || st->inner_done) : st->done) return;
     double sums[4];
-    sum_units<256, 4>(s.partial, (unsigned)nunits, sums, red);
+    sum_units<kDecideThreads, 4>(s.partial, (unsigned)nunits, sums, red);
     if (threadIdx.x != 0) return;
     if (fp32) decide_inner(st, sums, kMaxInnerPerStep);
     else decide_fp64(g, st, sums);
@@ -147,14 +151,14 @@ __global__ void __launch_bounds__(256) k_decide_iter(GridArgs g, const Slot* __r
 
 // After the FP64 outer residual of a refinement step (fused: with the first
 // inner sweep's residual).
-__global__ void __launch_bounds__(256) k_decide_outer(GridArgs g, const Slot* __restrict__ slots, int nunits,
-                                                      int fused) {
-    __shared__ double red[(256 / 64) * 5];
+__global__ void __launch_bounds__(kDecideThreads) k_decide_outer(GridArgs g, const Slot* __restrict__ slots,
+                                                                 int nunits, int fused) {
+    __shared__ double red[(kDecideThreads / 64) * 5];
     const Slot& s = slots[blockIdx.x];
     SolveState* st = s.st;
     if (st->done || st->stage != 0) return;
     double sums[5];
-    sum_units<256, 5>(s.partial, (unsigned)nunits, sums, red);
+    sum_units<kDecideThreads, 5>(s.partial, (unsigned)nunits, sums, red);
     if (threadIdx.x == 0) decide_outer(g, st, sums, fused != 0);
 }
 
@@ -535,7 +539,7 @@ static hipError_t five_sweeps(const GridArgs& g, const Tables& t, const Slot* sl
     };
     if ((e = sweep(1)) != hipSuccess) return e;
     if (mode == 0) {
-        k_decide_iter<<<nslots, 256, 0, s>>>(g, slots, nunits, fp32 ? 1 : 0);
+        k_decide_iter<<<nslots, kDecideThreads, 0, s>>>(g, slots, nunits, fp32 ? 1 : 0);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if ((e = sweep(2)) != hipSuccess) return e;
@@ -577,7 +581,7 @@ hipError_t launch_outer_residual(const GridArgs& g, const Geometry& geo, const T
     } else if ((e = launch_outer_resid_sweep(g, slots, nslots, s, &nu)) != hipSuccess) {
         return e;
     }
-    k_decide_outer<<<nslots, 256, 0, s>>>(g, slots, nu, fu ? 1 : 0);
+    k_decide_outer<<<nslots, kDecideThreads, 0, s>>>(g, slots, nu, fu ? 1 : 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (!fu) return hipSuccess;
     // the rest of the first inner sweep: P2, P3, P4, P5 (which stores dp as d32)
