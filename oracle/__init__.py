@@ -27,6 +27,8 @@ COEF_RHO_FACE_MEAN = 0  # beta = 2 / (rho_a + rho_b)
 COEF_INVRHO_FACE_MEAN = 1  # beta = (1/rho_a + 1/rho_b) / 2
 WEIGHT_RHO = 0  # w = rho, the multiplier of eq. (Pois)
 WEIGHT_DIAG = 1  # w = 1 / mean of the six face coefficients
+BC_PERIODIC = 0  # periodic in x (and always in y, z)
+BC_WALLS_X = 1  # zero-flux walls at both ends of x: the inflow-outflow duct
 
 
 def build(force: bool = True) -> str:
@@ -70,15 +72,15 @@ def _configure(lib: ctypes.CDLL) -> ctypes.CDLL:
     i, d, pd, pi = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)
     pdd = ctypes.POINTER(ctypes.c_double)
     grid = [i, i, i, d, d, d]
-    lib.oracle_apply.argtypes = grid + [i, pd, pd, pd]
+    lib.oracle_apply_bc.argtypes = grid + [i, i, pd, pd, pd]
     lib.oracle_fft1d.argtypes = [i, pd, pd, i]
-    lib.oracle_lap_pinv.argtypes = grid + [pd, pd]
-    lib.oracle_residual.argtypes = grid + [i, pd, pd, pd, pd, pdd, pdd, pdd]
-    lib.oracle_solve.argtypes = grid + [i, i, pd, pd, pd, d, i, pi, pdd, pdd, pd]
-    lib.oracle_cg.argtypes = grid + [i, pd, pd, pd, d, i, pi, pdd]
-    lib.oracle_dense.argtypes = grid + [i, pd, pd, pd]
-    lib.oracle_error_bound.argtypes = grid + [d, d]
-    lib.oracle_error_bound.restype = d
+    lib.oracle_lap_pinv_bc.argtypes = grid + [i, pd, pd]
+    lib.oracle_residual_bc.argtypes = grid + [i, i, pd, pd, pd, pd, pdd, pdd, pdd]
+    lib.oracle_solve_bc.argtypes = grid + [i, i, i, pd, pd, pd, d, i, pi, pdd, pdd, pd]
+    lib.oracle_cg_bc.argtypes = grid + [i, i, pd, pd, pd, d, i, pi, pdd]
+    lib.oracle_dense_bc.argtypes = grid + [i, i, pd, pd, pd]
+    lib.oracle_error_bound_bc.argtypes = grid + [i, d, d]
+    lib.oracle_error_bound_bc.restype = d
     return lib
 
 
@@ -112,15 +114,17 @@ def _check(rc: int, what: str, allow=(OK,)):
 
 
 def apply(rho: Optional[np.ndarray], p: np.ndarray, lengths=(2 * np.pi,) * 3,
-          coef: int = COEF_RHO_FACE_MEAN) -> np.ndarray:
-    """A p: flux-form second-order div((1/rho) grad p), periodic
-    (section "Poisson equation"; staggered grid of section "Spatial
-    discretization").  rho=None means rho = 1, i.e. the 7-point Laplacian."""
+          coef: int = COEF_RHO_FACE_MEAN, bcx: int = BC_PERIODIC) -> np.ndarray:
+    """A p: flux-form second-order div((1/rho) grad p), periodic, or with
+    zero-flux walls in x (bcx = 1, the duct of section "Boundary and initial
+    conditions") (section "Poisson equation"; staggered grid of section
+    "Spatial discretization").  rho=None means rho = 1, i.e. the 7-point
+    Laplacian."""
     p = np.ascontiguousarray(p, dtype=np.float64)
     shape = p.shape
     rho = None if rho is None else _f64(rho, shape)
     out = np.empty(shape)
-    _check(_load().oracle_apply(*_grid(shape, lengths), coef, _ptr(rho), _ptr(p), _ptr(out)), "apply")
+    _check(_load().oracle_apply_bc(*_grid(shape, lengths), coef, bcx, _ptr(rho), _ptr(p), _ptr(out)), "apply")
     return out
 
 
@@ -133,18 +137,19 @@ def fft1d(x: np.ndarray, sign: int = -1) -> np.ndarray:
     return re + 1j * im
 
 
-def lap_pinv(q: np.ndarray, lengths=(2 * np.pi,) * 3) -> np.ndarray:
-    """L^+ q: zero-mean solution of the constant-coefficient periodic problem,
-    by Fourier transform in the periodic directions (section "Poisson
+def lap_pinv(q: np.ndarray, lengths=(2 * np.pi,) * 3, bcx: int = BC_PERIODIC) -> np.ndarray:
+    """L^+ q: zero-mean solution of the constant-coefficient problem, by
+    Fourier transform in the periodic directions and, with walls in x, a
+    tridiagonal solve along x per (k_y, k_z) mode (section "Poisson
     equation")."""
     q = np.ascontiguousarray(q, dtype=np.float64)
     out = np.empty(q.shape)
-    _check(_load().oracle_lap_pinv(*_grid(q.shape, lengths), _ptr(q), _ptr(out)), "lap_pinv")
+    _check(_load().oracle_lap_pinv_bc(*_grid(q.shape, lengths), bcx, _ptr(q), _ptr(out)), "lap_pinv")
     return out
 
 
 def residual(rho, b, p, lengths=(2 * np.pi,) * 3, coef: int = COEF_RHO_FACE_MEAN,
-             want_field: bool = False):
+             want_field: bool = False, bcx: int = BC_PERIODIC):
     """(b - mean b) - A p and its norms: the O(n) verifier (compatibility
     constant chi of Appendix A removes the mean of the right-hand side).
     Returns dict(b_mean, b_norm, r_norm, rel[, r])."""
@@ -153,7 +158,7 @@ def residual(rho, b, p, lengths=(2 * np.pi,) * 3, coef: int = COEF_RHO_FACE_MEAN
     rho, p = _f64(rho, shape), _f64(p, shape)
     r = np.empty(shape) if want_field else None
     bm, bn, rn = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-    _check(_load().oracle_residual(*_grid(shape, lengths), coef, _ptr(rho), _ptr(b), _ptr(p),
+    _check(_load().oracle_residual_bc(*_grid(shape, lengths), coef, bcx, _ptr(rho), _ptr(b), _ptr(p),
                                    _ptr(r), ctypes.byref(bm), ctypes.byref(bn), ctypes.byref(rn)),
            "residual")
     out = dict(b_mean=bm.value, b_norm=bn.value, r_norm=rn.value,
@@ -165,7 +170,7 @@ def residual(rho, b, p, lengths=(2 * np.pi,) * 3, coef: int = COEF_RHO_FACE_MEAN
 
 def solve(rho, b, p0=None, lengths=(2 * np.pi,) * 3, coef: int = COEF_RHO_FACE_MEAN,
           weight: int = WEIGHT_RHO, tol: float = 1e-13, max_iter: int = 10000,
-          allow_noconv: bool = False):
+          allow_noconv: bool = False, bcx: int = BC_PERIODIC):
     """The paper's iteration (section "Poisson equation", eq. (Pois)):
     r = b~ - A p, q = w r, dp = L^+ q, p += dp, until ||r||/||b~|| <= tol.
     Returns dict(p, iters, rel, b_mean, history, code)."""
@@ -175,7 +180,7 @@ def solve(rho, b, p0=None, lengths=(2 * np.pi,) * 3, coef: int = COEF_RHO_FACE_M
     p = np.zeros(shape) if p0 is None else np.array(p0, dtype=np.float64, order="C", copy=True)
     hist = np.zeros(max_iter + 1)
     it, rel, bm = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
-    rc = _load().oracle_solve(*_grid(shape, lengths), coef, weight, _ptr(rho), _ptr(b), _ptr(p),
+    rc = _load().oracle_solve_bc(*_grid(shape, lengths), coef, bcx, weight, _ptr(rho), _ptr(b), _ptr(p),
                               tol, max_iter, ctypes.byref(it), ctypes.byref(rel), ctypes.byref(bm),
                               _ptr(hist))
     _check(rc, "solve", allow=(OK, ENOCONV) if allow_noconv else (OK,))
@@ -184,7 +189,7 @@ def solve(rho, b, p0=None, lengths=(2 * np.pi,) * 3, coef: int = COEF_RHO_FACE_M
 
 
 def cg(rho, b, lengths=(2 * np.pi,) * 3, coef: int = COEF_RHO_FACE_MEAN, tol: float = 1e-13,
-       max_iter: int = 100000):
+       max_iter: int = 100000, bcx: int = BC_PERIODIC):
     """Conjugate gradients on -A over zero-mean fields: an independent
     algorithm for cross-checking the iteration."""
     b = np.ascontiguousarray(b, dtype=np.float64)
@@ -192,21 +197,21 @@ def cg(rho, b, lengths=(2 * np.pi,) * 3, coef: int = COEF_RHO_FACE_MEAN, tol: fl
     rho = _f64(rho, shape)
     p = np.empty(shape)
     it, rel = ctypes.c_int(), ctypes.c_double()
-    _check(_load().oracle_cg(*_grid(shape, lengths), coef, _ptr(rho), _ptr(b), _ptr(p), tol,
+    _check(_load().oracle_cg_bc(*_grid(shape, lengths), coef, bcx, _ptr(rho), _ptr(b), _ptr(p), tol,
                              max_iter, ctypes.byref(it), ctypes.byref(rel)), "cg")
     return dict(p=p, iters=it.value, rel=rel.value)
 
 
-def dense(rho, b, lengths=(2 * np.pi,) * 3, coef: int = COEF_RHO_FACE_MEAN) -> np.ndarray:
+def dense(rho, b, lengths=(2 * np.pi,) * 3, coef: int = COEF_RHO_FACE_MEAN, bcx: int = BC_PERIODIC) -> np.ndarray:
     """Brute-force bordered dense solve (Gaussian elimination) for tiny grids."""
     b = np.ascontiguousarray(b, dtype=np.float64)
     shape = b.shape
     rho = _f64(rho, shape)
     p = np.empty(shape)
-    _check(_load().oracle_dense(*_grid(shape, lengths), coef, _ptr(rho), _ptr(b), _ptr(p)), "dense")
+    _check(_load().oracle_dense_bc(*_grid(shape, lengths), coef, bcx, _ptr(rho), _ptr(b), _ptr(p)), "dense")
     return p
 
 
-def error_bound(shape, lengths, rho_max: float, r_norm: float) -> float:
+def error_bound(shape, lengths, rho_max: float, r_norm: float, bcx: int = BC_PERIODIC) -> float:
     """Upper bound on ||p - p*||_2 from ||r||_2, valid in both coefficient modes."""
-    return _load().oracle_error_bound(*_grid(shape, lengths), rho_max, r_norm)
+    return _load().oracle_error_bound_bc(*_grid(shape, lengths), bcx, rho_max, r_norm)

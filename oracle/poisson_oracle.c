@@ -14,7 +14,11 @@
  *
  * Conventions (all readings of the paper are listed in the design notes):
  *   - Grid (nx, ny, nz), uniform spacing h_d = L_d / N_d, triply periodic
- *     (section "Boundary and initial conditions", configuration 1).
+ *     (section "Boundary and initial conditions", configuration 1), or, with
+ *     bcx = 1, periodic in y and z and bounded in x by walls through which
+ *     the pressure flux is zero (the inflow-outflow duct of configuration 2;
+ *     the paper gives the convective condition for the flow, and the
+ *     pressure condition read here is the homogeneous Neumann one).
  *   - Scalars (rho, p, f) live at cell centres, fluxes on faces (section
  *     "Spatial discretization", staggered-grid figure).  Storage is
  *     [nz][ny][nx], x fastest: idx = (k*ny + j)*nx + i.
@@ -35,7 +39,9 @@
  *     with w = rho (weight 0, the multiplier of eq. (Pois)) or w = 1/mean of the
  *     six face coefficients (weight 1).  L is the constant-coefficient 7-point
  *     Laplacian, inverted on zero-mean fields through its discrete Fourier
- *     symbol  sum_d -4 sin^2(pi k_d / N_d) / h_d^2.
+ *     symbol  sum_d -4 sin^2(pi k_d / N_d) / h_d^2; with walls in x, by Fourier
+ *     transform in y and z and a tridiagonal solve along x per (k_y, k_z)
+ *     mode, as the paper does in its non-periodic direction.
  *
  * Compiled with -O2 -ffp-contract=off: IEEE double, round to nearest, no FMA
  * contraction, no fast-math.
@@ -67,6 +73,8 @@ static size_t cell(int nx, int ny, int i, int j, int k) {
 
 static int wrap(int i, int n) { return (i % n + n) % n; }
 
+static double mean_of(const double* a, size_t n);
+
 static int is_2a3b(int n) {
     if (n < 1) return 0;
     while (n % 2 == 0) n /= 2;
@@ -90,14 +98,36 @@ static double face_beta(int coef, double ra, double rb) {
 /* operator                                                                 */
 /* ------------------------------------------------------------------------ */
 
-/* out = A p : the second-order flux-form discretisation of div((1/rho) grad p)
- * on the periodic staggered grid.  rho may be NULL, meaning rho = 1 (then A is
- * the constant-coefficient 7-point Laplacian L). */
-int oracle_apply(int nx, int ny, int nz, double hx, double hy, double hz, int coef,
-                 const double* rho, const double* p, double* out) {
-    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || (coef != 0 && coef != 1) || !p || !out)
-        return OR_EINVAL;
+/* Face coefficient of the face between cell c and its neighbour at offset +1
+ * (side = +1) or -1 (side = -1) along direction d; 0 for a wall face (bcx = 1,
+ * d = 0, beyond the first or last cell), else beta of the two densities (1
+ * when rho is NULL). */
+static double face_coef(int nx, int ny, int nz, int coef, int bcx, const double* rho, int i, int j, int k,
+                        int d, int side, size_t* nb) {
     const int n3[3] = {nx, ny, nz};
+    int ii = i, jj = j, kk = k;
+    if (d == 0) ii += side;
+    if (d == 1) jj += side;
+    if (d == 2) kk += side;
+    if (d == 0 && bcx == 1 && (ii < 0 || ii >= nx)) {
+        *nb = cell(nx, ny, i, j, k);
+        return 0.0;
+    }
+    *nb = cell(nx, ny, wrap(ii, n3[0]), wrap(jj, n3[1]), wrap(kk, n3[2]));
+    if (!rho) return 1.0;
+    const size_t c = cell(nx, ny, i, j, k);
+    return side > 0 ? face_beta(coef, rho[c], rho[*nb]) : face_beta(coef, rho[*nb], rho[c]);
+}
+
+/* out = A p : the second-order flux-form discretisation of div((1/rho) grad p)
+ * on the staggered grid, periodic, or with zero-flux walls in x (bcx = 1).
+ * rho may be NULL, meaning rho = 1 (then A is the constant-coefficient 7-point
+ * Laplacian L). */
+int oracle_apply_bc(int nx, int ny, int nz, double hx, double hy, double hz, int coef, int bcx,
+                    const double* rho, const double* p, double* out) {
+    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || (coef != 0 && coef != 1) || (bcx != 0 && bcx != 1) ||
+        !p || !out)
+        return OR_EINVAL;
     const double h2[3] = {hx * hx, hy * hy, hz * hz};
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
@@ -105,19 +135,19 @@ int oracle_apply(int nx, int ny, int nz, double hx, double hy, double hz, int co
                 const size_t c = cell(nx, ny, i, j, k);
                 double acc = 0.0;
                 for (int d = 0; d < 3; ++d) {
-                    int ip = i, jp = j, kp = k, im = i, jm = j, km = k;
-                    if (d == 0) { ip = wrap(i + 1, n3[0]); im = wrap(i - 1, n3[0]); }
-                    if (d == 1) { jp = wrap(j + 1, n3[1]); jm = wrap(j - 1, n3[1]); }
-                    if (d == 2) { kp = wrap(k + 1, n3[2]); km = wrap(k - 1, n3[2]); }
-                    const size_t cp = cell(nx, ny, ip, jp, kp);
-                    const size_t cm = cell(nx, ny, im, jm, km);
-                    const double bp = rho ? face_beta(coef, rho[c], rho[cp]) : 1.0;
-                    const double bm = rho ? face_beta(coef, rho[cm], rho[c]) : 1.0;
+                    size_t cp, cm;
+                    const double bp = face_coef(nx, ny, nz, coef, bcx, rho, i, j, k, d, +1, &cp);
+                    const double bm = face_coef(nx, ny, nz, coef, bcx, rho, i, j, k, d, -1, &cm);
                     acc += (bp * (p[cp] - p[c]) - bm * (p[c] - p[cm])) / h2[d];
                 }
                 out[c] = acc;
             }
     return OR_OK;
+}
+
+int oracle_apply(int nx, int ny, int nz, double hx, double hy, double hz, int coef,
+                 const double* rho, const double* p, double* out) {
+    return oracle_apply_bc(nx, ny, nz, hx, hy, hz, coef, 0, rho, p, out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -251,6 +281,102 @@ int oracle_lap_pinv(int nx, int ny, int nz, double hx, double hy, double hz, con
     return OR_OK;
 }
 
+/* Symbol of the 1-D second difference between zero-flux walls (cell centres,
+ * mirror ghost cells): -4 sin^2(pi k/(2N))/h^2, k = 0..N-1, eigenvectors
+ * cos(pi k (i + 1/2)/N).  Used by the pins and the error bound; the solve below
+ * does not use it. */
+static double symbol_wall_1d(int k, int n, double h) {
+    const double s = sin(OR_PI * (double)k / (2.0 * (double)n));
+    return -4.0 * s * s / (h * h);
+}
+
+/* Solve (D + c) x = q along one x-line, D the wall second difference (tridiagonal:
+ * 1/h^2 off the diagonal, -2/h^2 on it, -1/h^2 at the two ends), c = the y and z
+ * symbols of the mode (c < 0), q complex: the Thomas algorithm (the matrix is
+ * strictly diagonally dominant, no pivoting needed).  For c = 0 the matrix is
+ * singular; then q has zero sum, and the solution with x_0 = 0 follows from the
+ * face fluxes g_{i+1/2} = h sum_{j<=i} q_j (g = 0 at both walls):
+ * x_{i+1} = x_i + h g_{i+1/2}.  dmod: scratch of n doubles. */
+static void tridiag_wall(int n, double h, double c, const cplx* q, double* dmod, cplx* x) {
+    const double a = 1.0 / (h * h);
+    if (c == 0.0) {
+        cplx g = 0.0;
+        x[0] = 0.0;
+        for (int i = 0; i + 1 < n; ++i) {
+            g += h * q[i];
+            x[i + 1] = x[i] + h * g;
+        }
+        return;
+    }
+    for (int i = 0; i < n; ++i) {
+        const double b = ((i == 0 || i == n - 1) ? -a : -2.0 * a) + c;
+        if (i == 0) {
+            dmod[0] = b;
+            x[0] = q[0];
+        } else {
+            const double m = a / dmod[i - 1];
+            dmod[i] = b - m * a;
+            x[i] = q[i] - m * x[i - 1];
+        }
+    }
+    x[n - 1] /= dmod[n - 1];
+    for (int i = n - 2; i >= 0; --i) x[i] = (x[i] - a * x[i + 1]) / dmod[i];
+}
+
+/* delta = L^+ q with zero-flux walls in x: the zero-mean solution of
+ * L delta = q - mean(q).  Forward DFT along y and z, a tridiagonal solve along
+ * x for every (k_y, k_z) mode, backward DFT along z and y, scale 1/(ny nz). */
+static int lap_pinv_wall(int nx, int ny, int nz, double hx, double hy, double hz, const double* q, double* delta) {
+    const size_t n = (size_t)nx * ny * nz;
+    const int nmax = nx > ny ? (nx > nz ? nx : nz) : (ny > nz ? ny : nz);
+    cplx* F = (cplx*)malloc(n * sizeof(cplx));
+    cplx* buf = (cplx*)malloc(3 * (size_t)nmax * sizeof(cplx));
+    cplx* line = (cplx*)malloc(2 * (size_t)nx * sizeof(cplx));
+    double* dmod = (double*)malloc((size_t)nx * sizeof(double));
+    cplx* twy = make_twiddles(ny, -1);
+    cplx* twz = make_twiddles(nz, -1);
+    cplx* twyb = make_twiddles(ny, +1);
+    cplx* twzb = make_twiddles(nz, +1);
+    if (!F || !buf || !line || !dmod || !twy || !twz || !twyb || !twzb) {
+        free(F); free(buf); free(line); free(dmod); free(twy); free(twz); free(twyb); free(twzb);
+        return OR_ENOMEM;
+    }
+    const double qm = mean_of(q, n);
+    for (size_t c = 0; c < n; ++c) F[c] = q[c] - qm;
+    cplx *in = buf, *out = buf + nmax, *scr = buf + 2 * (size_t)nmax;
+    for (int k = 0; k < nz; ++k)
+        for (int i = 0; i < nx; ++i) fft_line(F + cell(nx, ny, i, 0, k), (size_t)nx, ny, twy, in, out, scr);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i)
+            fft_line(F + cell(nx, ny, i, j, 0), (size_t)nx * (size_t)ny, nz, twz, in, out, scr);
+    cplx *rhs = line, *x = line + nx;
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j) {
+            const double c = symbol_1d(j, ny, hy) + symbol_1d(k, nz, hz);
+            for (int i = 0; i < nx; ++i) rhs[i] = F[cell(nx, ny, i, j, k)];
+            tridiag_wall(nx, hx, c, rhs, dmod, x);
+            for (int i = 0; i < nx; ++i) F[cell(nx, ny, i, j, k)] = x[i];
+        }
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i)
+            fft_line(F + cell(nx, ny, i, j, 0), (size_t)nx * (size_t)ny, nz, twzb, in, out, scr);
+    for (int k = 0; k < nz; ++k)
+        for (int i = 0; i < nx; ++i) fft_line(F + cell(nx, ny, i, 0, k), (size_t)nx, ny, twyb, in, out, scr);
+    for (size_t c = 0; c < n; ++c) delta[c] = creal(F[c]) / ((double)ny * (double)nz);
+    const double dm = mean_of(delta, n);
+    for (size_t c = 0; c < n; ++c) delta[c] -= dm;
+    free(F); free(buf); free(line); free(dmod); free(twy); free(twz); free(twyb); free(twzb);
+    return OR_OK;
+}
+
+int oracle_lap_pinv_bc(int nx, int ny, int nz, double hx, double hy, double hz, int bcx, const double* q,
+                       double* delta) {
+    if (bcx == 0) return oracle_lap_pinv(nx, ny, nz, hx, hy, hz, q, delta);
+    if (bcx != 1 || check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || !q || !delta) return OR_EINVAL;
+    if (!is_2a3b(ny) || !is_2a3b(nz)) return OR_EINVAL;
+    return lap_pinv_wall(nx, ny, nz, hx, hy, hz, q, delta);
+}
+
 /* ------------------------------------------------------------------------ */
 /* reductions                                                               */
 /* ------------------------------------------------------------------------ */
@@ -279,15 +405,16 @@ static int check_fields(const double* rho, const double* b, size_t n) {
  * ||b - mean(b)||_2 and ||r||_2.  r may be NULL.  This is the O(n) verifier
  * used on any solution, including ones the full oracle solve would take too
  * long to produce. */
-int oracle_residual(int nx, int ny, int nz, double hx, double hy, double hz, int coef,
-                    const double* rho, const double* b, const double* p, double* r,
-                    double* b_mean, double* b_norm, double* r_norm) {
-    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || (coef != 0 && coef != 1) || !rho || !b || !p)
+int oracle_residual_bc(int nx, int ny, int nz, double hx, double hy, double hz, int coef, int bcx,
+                       const double* rho, const double* b, const double* p, double* r,
+                       double* b_mean, double* b_norm, double* r_norm) {
+    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || (coef != 0 && coef != 1) || (bcx != 0 && bcx != 1) ||
+        !rho || !b || !p)
         return OR_EINVAL;
     const size_t n = (size_t)nx * ny * nz;
     double* Ap = (double*)malloc(n * sizeof(double));
     if (!Ap) return OR_ENOMEM;
-    oracle_apply(nx, ny, nz, hx, hy, hz, coef, rho, p, Ap);
+    oracle_apply_bc(nx, ny, nz, hx, hy, hz, coef, bcx, rho, p, Ap);
     const double bm = mean_of(b, n);
     double sb = 0.0, sr = 0.0;
     for (size_t c = 0; c < n; ++c) {
@@ -304,6 +431,12 @@ int oracle_residual(int nx, int ny, int nz, double hx, double hy, double hz, int
     return OR_OK;
 }
 
+int oracle_residual(int nx, int ny, int nz, double hx, double hy, double hz, int coef,
+                    const double* rho, const double* b, const double* p, double* r,
+                    double* b_mean, double* b_norm, double* r_norm) {
+    return oracle_residual_bc(nx, ny, nz, hx, hy, hz, coef, 0, rho, b, p, r, b_mean, b_norm, r_norm);
+}
+
 /* ------------------------------------------------------------------------ */
 /* the paper's iteration                                                    */
 /* ------------------------------------------------------------------------ */
@@ -311,9 +444,8 @@ int oracle_residual(int nx, int ny, int nz, double hx, double hy, double hz, int
 /* Weight multiplying the residual before the constant-coefficient solve.
  * weight 0: w = rho (the multiplier in eq. (Pois)); weight 1: w = 1 / (mean of
  * the six face coefficients around the cell). */
-static void make_weight(int nx, int ny, int nz, int coef, int weight, const double* rho,
+static void make_weight(int nx, int ny, int nz, int coef, int bcx, int weight, const double* rho,
                         double* w) {
-    const int n3[3] = {nx, ny, nz};
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i) {
@@ -322,14 +454,12 @@ static void make_weight(int nx, int ny, int nz, int coef, int weight, const doub
                     w[c] = rho[c];
                     continue;
                 }
+                /* a wall face counts with coefficient 0 */
                 double s = 0.0;
+                size_t nb;
                 for (int d = 0; d < 3; ++d) {
-                    int ip = i, jp = j, kp = k, im = i, jm = j, km = k;
-                    if (d == 0) { ip = wrap(i + 1, n3[0]); im = wrap(i - 1, n3[0]); }
-                    if (d == 1) { jp = wrap(j + 1, n3[1]); jm = wrap(j - 1, n3[1]); }
-                    if (d == 2) { kp = wrap(k + 1, n3[2]); km = wrap(k - 1, n3[2]); }
-                    s += face_beta(coef, rho[c], rho[cell(nx, ny, ip, jp, kp)]);
-                    s += face_beta(coef, rho[cell(nx, ny, im, jm, km)], rho[c]);
+                    s += face_coef(nx, ny, nz, coef, bcx, rho, i, j, k, d, +1, &nb);
+                    s += face_coef(nx, ny, nz, coef, bcx, rho, i, j, k, d, -1, &nb);
                 }
                 w[c] = 6.0 / s;
             }
@@ -341,11 +471,11 @@ static void make_weight(int nx, int ny, int nz, int coef, int weight, const doub
  * history (may be NULL, length max_iter+1) receives ||r_k|| / ||b~||.
  * Returns OR_OK, OR_ENOCONV (p = last iterate), OR_EDIVERGED (relative residual
  * above 1e8 or not finite), OR_EDOMAIN, OR_EINVAL, OR_ENOMEM. */
-int oracle_solve(int nx, int ny, int nz, double hx, double hy, double hz, int coef, int weight,
-                 const double* rho, const double* b, double* p, double tol, int max_iter,
-                 int* iters_out, double* rel_out, double* b_mean_out, double* history) {
-    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK) return OR_EINVAL;
-    if (!is_2a3b(nx) || !is_2a3b(ny) || !is_2a3b(nz)) return OR_EINVAL;
+int oracle_solve_bc(int nx, int ny, int nz, double hx, double hy, double hz, int coef, int bcx, int weight,
+                    const double* rho, const double* b, double* p, double tol, int max_iter,
+                    int* iters_out, double* rel_out, double* b_mean_out, double* history) {
+    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || (bcx != 0 && bcx != 1)) return OR_EINVAL;
+    if ((bcx == 0 && !is_2a3b(nx)) || !is_2a3b(ny) || !is_2a3b(nz)) return OR_EINVAL;
     if ((coef != 0 && coef != 1) || (weight != 0 && weight != 1)) return OR_EINVAL;
     if (!rho || !b || !p || !(tol > 0.0) || max_iter < 0) return OR_EINVAL;
     const size_t n = (size_t)nx * ny * nz;
@@ -377,9 +507,9 @@ int oracle_solve(int nx, int ny, int nz, double hx, double hy, double hz, int co
         const double pm = mean_of(p, n);
         for (size_t c = 0; c < n; ++c) p[c] -= pm;
     }
-    make_weight(nx, ny, nz, coef, weight, rho, w);
+    make_weight(nx, ny, nz, coef, bcx, weight, rho, w);
     for (it = 0;; ++it) {
-        oracle_apply(nx, ny, nz, hx, hy, hz, coef, rho, p, r);
+        oracle_apply_bc(nx, ny, nz, hx, hy, hz, coef, bcx, rho, p, r);
         for (size_t c = 0; c < n; ++c) r[c] = bt[c] - r[c];
         rel = norm2_of(r, n) / bn;
         if (history) history[it] = rel;
@@ -393,7 +523,7 @@ int oracle_solve(int nx, int ny, int nz, double hx, double hy, double hz, int co
             break;
         }
         for (size_t c = 0; c < n; ++c) r[c] *= w[c];
-        rc = oracle_lap_pinv(nx, ny, nz, hx, hy, hz, r, dp);
+        rc = oracle_lap_pinv_bc(nx, ny, nz, hx, hy, hz, bcx, r, dp);
         if (rc != OR_OK) break;
         for (size_t c = 0; c < n; ++c) p[c] += dp[c];
     }
@@ -404,6 +534,13 @@ done:
     return rc;
 }
 
+int oracle_solve(int nx, int ny, int nz, double hx, double hy, double hz, int coef, int weight,
+                 const double* rho, const double* b, double* p, double tol, int max_iter,
+                 int* iters_out, double* rel_out, double* b_mean_out, double* history) {
+    return oracle_solve_bc(nx, ny, nz, hx, hy, hz, coef, 0, weight, rho, b, p, tol, max_iter, iters_out, rel_out,
+                           b_mean_out, history);
+}
+
 /* ------------------------------------------------------------------------ */
 /* independent cross-checks                                                 */
 /* ------------------------------------------------------------------------ */
@@ -411,10 +548,11 @@ done:
 /* Conjugate gradients on the symmetric positive semi-definite -A, restricted
  * to zero-mean vectors: solves -A p = -(b - mean b) from p = 0.  An algorithm
  * unrelated to the paper's iteration, used to cross-check it. */
-int oracle_cg(int nx, int ny, int nz, double hx, double hy, double hz, int coef,
-              const double* rho, const double* b, double* p, double tol, int max_iter,
-              int* iters_out, double* rel_out) {
-    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || (coef != 0 && coef != 1)) return OR_EINVAL;
+int oracle_cg_bc(int nx, int ny, int nz, double hx, double hy, double hz, int coef, int bcx,
+                 const double* rho, const double* b, double* p, double tol, int max_iter,
+                 int* iters_out, double* rel_out) {
+    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || (coef != 0 && coef != 1) || (bcx != 0 && bcx != 1))
+        return OR_EINVAL;
     if (!rho || !b || !p || !(tol > 0.0) || max_iter < 0) return OR_EINVAL;
     const size_t n = (size_t)nx * ny * nz;
     if (check_fields(rho, b, n) != OR_OK) return OR_EDOMAIN;
@@ -440,7 +578,7 @@ int oracle_cg(int nx, int ny, int nz, double hx, double hy, double hz, int coef,
             rc = OR_ENOCONV;
             break;
         }
-        oracle_apply(nx, ny, nz, hx, hy, hz, coef, rho, d, Ad);
+        oracle_apply_bc(nx, ny, nz, hx, hy, hz, coef, bcx, rho, d, Ad);
         double dAd = 0.0;
         for (size_t c = 0; c < n; ++c) dAd += d[c] * (-Ad[c]);
         const double alpha = rr / dAd;
@@ -464,14 +602,21 @@ int oracle_cg(int nx, int ny, int nz, double hx, double hy, double hz, int coef,
     return rc;
 }
 
+int oracle_cg(int nx, int ny, int nz, double hx, double hy, double hz, int coef,
+              const double* rho, const double* b, double* p, double tol, int max_iter,
+              int* iters_out, double* rel_out) {
+    return oracle_cg_bc(nx, ny, nz, hx, hy, hz, coef, 0, rho, b, p, tol, max_iter, iters_out, rel_out);
+}
+
 /* Brute force for tiny grids: assemble the n x n matrix of A column by column
  * from oracle_apply, border it with the constraint sum(p) = 0,
  *      [ A   1 ] [p]   [b - mean b]
  *      [ 1^T 0 ] [c] = [    0     ]
  * and solve by Gaussian elimination with partial pivoting. */
-int oracle_dense(int nx, int ny, int nz, double hx, double hy, double hz, int coef,
-                 const double* rho, const double* b, double* p) {
-    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || (coef != 0 && coef != 1)) return OR_EINVAL;
+int oracle_dense_bc(int nx, int ny, int nz, double hx, double hy, double hz, int coef, int bcx,
+                    const double* rho, const double* b, double* p) {
+    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || (coef != 0 && coef != 1) || (bcx != 0 && bcx != 1))
+        return OR_EINVAL;
     if (!rho || !b || !p) return OR_EINVAL;
     const size_t n = (size_t)nx * ny * nz;
     if (n > 4096) return OR_EINVAL;
@@ -486,7 +631,7 @@ int oracle_dense(int nx, int ny, int nz, double hx, double hy, double hz, int co
     }
     for (size_t jc = 0; jc < n; ++jc) {
         e[jc] = 1.0;
-        oracle_apply(nx, ny, nz, hx, hy, hz, coef, rho, e, col);
+        oracle_apply_bc(nx, ny, nz, hx, hy, hz, coef, bcx, rho, e, col);
         e[jc] = 0.0;
         for (size_t ir = 0; ir < n; ++ir) M[ir * m + jc] = col[ir];
     }
@@ -535,17 +680,30 @@ int oracle_dense(int nx, int ny, int nz, double hx, double hy, double hz, int co
     return rc;
 }
 
+int oracle_dense(int nx, int ny, int nz, double hx, double hy, double hz, int coef,
+                 const double* rho, const double* b, double* p) {
+    return oracle_dense_bc(nx, ny, nz, hx, hy, hz, coef, 0, rho, b, p);
+}
+
 /* A-posteriori error bound.  Every face coefficient is >= 1/rho_max in both
- * coefficient modes, so -A >= (-L)/rho_max on zero-mean fields and
- *     ||p - p*||_2 <= rho_max ||r||_2 / min_d (4 sin^2(pi/N_d) / h_d^2).
+ * coefficient modes (wall faces are 0 in A and in L alike), so -A >= (-L)/rho_max
+ * on zero-mean fields and ||p - p*||_2 <= rho_max ||r||_2 / lambda_min(-L), with
+ * lambda_min = min_d 4 sin^2(pi/N_d) / h_d^2 (4 sin^2(pi/(2 N_x)) / h_x^2 along x
+ * between walls).
  * Returns the bound on the absolute 2-norm error given ||r||_2. */
-double oracle_error_bound(int nx, int ny, int nz, double hx, double hy, double hz,
-                          double rho_max, double r_norm) {
-    double lmin = -symbol_1d(1, nx, hx);
+double oracle_error_bound_bc(int nx, int ny, int nz, double hx, double hy, double hz, int bcx,
+                             double rho_max, double r_norm) {
+    /* smallest nonzero eigenvalue of -L: the lowest mode of one direction */
+    double lmin = bcx ? -symbol_wall_1d(1, nx, hx) : -symbol_1d(1, nx, hx);
     const double ly = -symbol_1d(1, ny, hy), lz = -symbol_1d(1, nz, hz);
     if (ly < lmin) lmin = ly;
     if (lz < lmin) lmin = lz;
     return rho_max * r_norm / lmin;
 }
 
-int oracle_abi_version(void) { return 1; }
+double oracle_error_bound(int nx, int ny, int nz, double hx, double hy, double hz,
+                          double rho_max, double r_norm) {
+    return oracle_error_bound_bc(nx, ny, nz, hx, hy, hz, 0, rho_max, r_norm);
+}
+
+int oracle_abi_version(void) { return 2; }

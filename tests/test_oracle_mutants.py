@@ -20,20 +20,15 @@ MUTANTS = {
     "face coefficient halved": ("return 2.0 / (ra + rb);", "return 1.0 / (ra + rb);"),
     "flux difference sign": ("acc += (bp * (p[cp] - p[c]) - bm * (p[c] - p[cm])) / h2[d];",
                              "acc += (bp * (p[cp] - p[c]) + bm * (p[c] - p[cm])) / h2[d];"),
-    "minus-face uses plus neighbour": ("const double bm = rho ? face_beta(coef, rho[cm], rho[c]) : 1.0;",
-                                       "const double bm = rho ? face_beta(coef, rho[cp], rho[c]) : 1.0;"),
+    "minus face uses the centre density twice": (
+        "face_beta(coef, rho[c], rho[*nb]) : face_beta(coef, rho[*nb], rho[c]);",
+        "face_beta(coef, rho[c], rho[*nb]) : face_beta(coef, rho[c], rho[c]);"),
     "spacings swapped y<->z": ("const double h2[3] = {hx * hx, hy * hy, hz * hz};",
                                "const double h2[3] = {hx * hx, hz * hz, hy * hy};"),
-    "x minus neighbour wrong": ("if (d == 0) { ip = wrap(i + 1, n3[0]); im = wrap(i - 1, n3[0]); }\n"
-                                "                    if (d == 1) { jp = wrap(j + 1, n3[1]); jm = wrap(j - 1, n3[1]); }\n"
-                                "                    if (d == 2) { kp = wrap(k + 1, n3[2]); km = wrap(k - 1, n3[2]); }\n"
-                                "                    const size_t cp",
-                                "if (d == 0) { ip = wrap(i + 1, n3[0]); im = wrap(i - 2, n3[0]); }\n"
-                                "                    if (d == 1) { jp = wrap(j + 1, n3[1]); jm = wrap(j - 1, n3[1]); }\n"
-                                "                    if (d == 2) { kp = wrap(k + 1, n3[2]); km = wrap(k - 1, n3[2]); }\n"
-                                "                    const size_t cp"),
-    "symbol factor": ("return -4.0 * s * s / (h * h);", "return -2.0 * s * s / (h * h);"),
-    "symbol axes transposed": ("symbol_1d(j, ny, hy)", "symbol_1d(j, ny, hx)"),
+    "x minus neighbour wrong": ("if (d == 0) ii += side;", "if (d == 0) ii += (side < 0 ? 2 * side : side);"),
+    "symbol factor": ("return -4.0 * s * s / (h * h);\n}\n\n/* delta = L^+ q : the zero-mean",
+                      "return -2.0 * s * s / (h * h);\n}\n\n/* delta = L^+ q : the zero-mean"),
+    "symbol axes transposed": ("symbol_1d(i, nx, hx) + symbol_1d(j, ny, hy)", "symbol_1d(i, nx, hx) + symbol_1d(j, ny, hx)"),
     "zero mode kept": ("                    F[c] = 0.0;\n                    continue;",
                        "                    continue;"),
     "weight inverted": ("w[c] = rho[c];", "w[c] = 1.0 / rho[c];"),
@@ -44,6 +39,12 @@ MUTANTS = {
     "radix-3 combine index": ("const long t = ((long)q * (long)K) % n;", "const long t = ((long)q * (long)(K % m)) % n;"),
     "gauge not fixed": ("for (size_t c = 0; c < n; ++c) p[c] -= pm;\n    }\n    make_weight",
                         "(void)pm;\n    }\n    make_weight"),
+    "wall face kept": ("if (d == 0 && bcx == 1 && (ii < 0 || ii >= nx)) {",
+                       "if (d == 0 && bcx == 1 && (ii < 0 || ii >= nx) && 0) {"),
+    "wall end of the tridiagonal": ("const double b = ((i == 0 || i == n - 1) ? -a : -2.0 * a) + c;",
+                                    "const double b = -2.0 * a + c;"),
+    "tridiagonal back substitution": ("x[i] = (x[i] - a * x[i + 1]) / dmod[i];",
+                                      "x[i] = (x[i] + a * x[i + 1]) / dmod[i];"),
 }
 
 

@@ -473,6 +473,121 @@ def test_residual_verifier_definition():
     assert abs(res["b_norm"] - np.linalg.norm(prob.b - prob.b.mean())) <= 1e-12 * res["b_norm"]
 
 
+# --------------------------------------------------------------------------
+# zero-flux walls in x (the inflow-outflow duct of section "Boundary and
+# initial conditions"; the constant-coefficient inverse then takes Fourier
+# transforms in y, z and a tridiagonal solve along x)
+# --------------------------------------------------------------------------
+
+
+def pin_wall_modes():
+    """cos(pi m (i+1/2)/Nx) times a Fourier mode in y and z is an eigenvector of
+    the wall Laplacian with eigenvalue -4 sin^2(pi m/(2 Nx))/hx^2 + the y and z
+    symbols: A of that mode, L^+ of it, and one iteration of the solve at
+    constant density reproduce the closed forms."""
+    shape, L = (6, 8, 10), (3.0, 2.0, 5.0)
+    nz, ny, nx = shape
+    hx, hy, hz = _lengths_h(shape, L)
+    i = np.arange(nx)[None, None, :]
+    j = np.arange(ny)[None, :, None]
+    k = np.arange(nz)[:, None, None]
+    for (m, ly, lz) in ((0, 1, 0), (3, 0, 0), (1, 2, 1), (nx - 1, 3, 2), (4, 0, 3)):
+        f = np.cos(np.pi * m * (i + 0.5) / nx) * np.cos(2 * np.pi * (ly * j / ny + lz * k / nz) + 0.3)
+        f = np.ascontiguousarray(np.broadcast_to(f, shape))
+        lam = (-4 * np.sin(np.pi * m / (2 * nx)) ** 2 / hx ** 2 - 4 * np.sin(np.pi * ly / ny) ** 2 / hy ** 2
+               - 4 * np.sin(np.pi * lz / nz) ** 2 / hz ** 2)
+        for coef in (0, 1):
+            Af = oracle.apply(np.full(shape, 2.5), f, L, coef, bcx=1)
+            assert np.max(np.abs(Af - lam / 2.5 * f)) <= 1e-12 * abs(lam) / 2.5
+        d = oracle.lap_pinv(f, L, bcx=1)
+        assert np.max(np.abs(d - f / lam)) <= 1e-12 * np.max(np.abs(f / lam))
+        res = oracle.solve(np.full(shape, 0.7), f, lengths=L, tol=1e-13, bcx=1)
+        assert res["iters"] <= 1
+        assert np.max(np.abs(res["p"] - 0.7 * f / lam)) <= 1e-11 * np.max(np.abs(0.7 * f / lam))
+
+
+def test_wall_cosine_modes():
+    pin_wall_modes()
+
+
+def pin_wall_flux1d():
+    """rho(x), b(x) between walls: the face fluxes vanish at both walls, so
+    g_{i+1/2} = h sum_{j<=i} (b_j - mean b) and p_{i+1} - p_i = h g_{i+1/2} /
+    beta_{i+1/2}; the 3-D solve reproduces it for both coefficient modes."""
+    rng = np.random.default_rng(21)
+    shape, L = (4, 6, 14), (2.5, 2.0, 3.0)
+    hx = L[0] / shape[2]
+    for coef in (0, 1):
+        rho1 = np.exp(rng.uniform(-1.0, 1.0, shape[2]))
+        b1 = rng.standard_normal(shape[2])
+        beta = 2.0 / (rho1[:-1] + rho1[1:]) if coef == 0 else 0.5 * (1 / rho1[:-1] + 1 / rho1[1:])
+        g = hx * np.cumsum(b1 - b1.mean())[:-1]
+        want1 = np.concatenate([[0.0], np.cumsum(hx * g / beta)])
+        want1 -= want1.mean()
+        rho = np.ascontiguousarray(np.broadcast_to(rho1, shape))
+        b = np.ascontiguousarray(np.broadcast_to(b1, shape))
+        for weight in _weights(coef):
+            got = oracle.solve(rho, b, lengths=L, coef=coef, weight=weight, tol=1e-13, bcx=1)["p"]
+            assert np.max(np.abs(got - want1)) <= 1e-11 * max(1.0, np.max(np.abs(want1))), coef
+
+
+def test_wall_flux_form_1d_closed_form():
+    pin_wall_flux1d()
+
+
+def pin_wall_matrix():
+    """The wall operator is symmetric, annihilates constants and only them, is
+    negative semi-definite, and equals the periodic one away from the walls;
+    the iteration, CG and the dense bordered solve agree."""
+    rng = np.random.default_rng(22)
+    shape, L = (4, 4, 6), (3.0, 2.0, 2.5)
+    rho = np.exp(rng.uniform(-1, 1, shape))
+    for coef in (0, 1):
+        M = np.empty((rho.size, rho.size))
+        e = np.zeros(rho.size)
+        for jj in range(rho.size):
+            e[jj] = 1.0
+            M[:, jj] = oracle.apply(rho, e.reshape(shape), L, coef, bcx=1).ravel()
+            e[jj] = 0.0
+        scale = np.max(np.abs(M))
+        assert np.max(np.abs(M - M.T)) <= 1e-14 * scale
+        assert np.max(np.abs(M.sum(axis=1))) <= 1e-12 * scale
+        ev = np.linalg.eigvalsh(-0.5 * (M + M.T))
+        assert ev[0] > -1e-12 * scale and ev[1] > 1e-6 * scale
+        # interior columns x = 1..nx-2 couple exactly as in the periodic operator
+        P = _matrix(rho, L, coef)
+        inner = [c for c in range(rho.size) if 0 < c % shape[2] < shape[2] - 1]
+        assert np.max(np.abs(M[:, inner] - P[:, inner])) <= 1e-14 * scale
+        assert np.max(np.abs(M - P)) > 1e-3 * scale
+    b = rng.standard_normal(shape)
+    pd_ = oracle.dense(rho, b, L, 0, bcx=1)
+    pi_ = oracle.solve(rho, b, lengths=L, tol=1e-13, bcx=1)["p"]
+    pc_ = oracle.cg(rho, b, L, 0, tol=1e-13, bcx=1)["p"]
+    assert np.max(np.abs(pi_ - pd_)) <= 1e-10 * np.max(np.abs(pd_))
+    assert np.max(np.abs(pc_ - pd_)) <= 1e-10 * np.max(np.abs(pd_))
+
+
+def test_wall_matrix_and_cross_checks():
+    pin_wall_matrix()
+
+
+def pin_wall_pinv_dense():
+    """L^+ with walls (FFT in y, z and Thomas along x) against the bordered
+    dense solve of the constant-coefficient wall operator, including rows of odd
+    length and the singular (k_y, k_z) = (0, 0) lines."""
+    rng = np.random.default_rng(23)
+    for shape, L in (((4, 6, 7), (3.0, 2.0, 2.5)), ((6, 4, 5), (1.0, 2.0, 3.0))):
+        q = rng.standard_normal(shape) + 1.0
+        d = oracle.lap_pinv(q, L, bcx=1)
+        want = oracle.dense(np.ones(shape), q, L, 0, bcx=1)  # rho = 1: A = L
+        assert np.max(np.abs(d - want)) <= 1e-11 * np.max(np.abs(want))
+
+
+def test_wall_pinv_against_dense():
+    pin_wall_pinv_dense()
+
+
 ALL_PINS = [pin_fft, pin_symbol, pin_order2, pin_flux1d, pin_matrix, pin_pinv,
             pin_const_one_iteration, pin_discrete_manufactured, pin_dense, pin_cg,
-            pin_equivariance, pin_bound, pin_mean_removal, pin_gauge]
+            pin_equivariance, pin_bound, pin_mean_removal, pin_gauge, pin_wall_modes, pin_wall_flux1d,
+            pin_wall_matrix, pin_wall_pinv_dense]
