@@ -67,6 +67,16 @@ extern "C" {
 #define POISSON_W_RHO 0  /* w = rho, the multiplier of eq. (Pois)                */
 #define POISSON_W_DIAG 1 /* w = 1 / (mean of the six face coefficients of a cell) */
 
+/* Boundary condition along x (y and z are always periodic).  Section
+ * "Boundary and initial conditions": a triply periodic box, or an
+ * inflow-outflow duct, periodic in y-z and bounded in x; for the pressure solve
+ * the duct's x ends are read as walls through which the pressure flux is zero
+ * (homogeneous Neumann).  The paper solves that direction with a tridiagonal
+ * solver; this library uses the cosine transform that diagonalises the same
+ * discrete operator (cos(pi k (i + 1/2)/Nx), symbol -4 sin^2(pi k/(2 Nx))/hx^2). */
+#define POISSON_BC_PERIODIC 0
+#define POISSON_BC_WALLS_X 1
+
 typedef struct poisson_s* poisson_t;
 
 typedef struct {
@@ -84,6 +94,7 @@ typedef struct {
     int use_graphs;       /* nonzero: chunks of iterations are captured once into
                              HIP graphs and replayed; 0: every kernel is launched
                              directly (same kernels, same results)                 */
+    int bc_x;             /* POISSON_BC_PERIODIC or POISSON_BC_WALLS_X             */
 } poisson_opts;
 
 typedef struct {

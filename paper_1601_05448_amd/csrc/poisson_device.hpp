@@ -149,12 +149,20 @@ __device__ __forceinline__ void pair_fetch(const GridArgs& g, const POIS_GLOBAL 
     in.bb = rhs[b];
 }
 
+// Walls in x (bcx = 1): the faces x = 0 and x = Lx carry no flux.  Bit 0: the
+// cell's x- face is a wall (i = 0), bit 1: its x+ face is (i = nx - 1).  The
+// neighbour values across a wall are still read (the periodic wrap) but are
+// multiplied by a zero coefficient.
+__device__ __forceinline__ unsigned x_walls(const GridArgs& g, unsigned i) {
+    return g.bcx ? ((i == 0 ? 1u : 0u) | (i + 1 == (unsigned)g.nx ? 2u : 0u)) : 0u;
+}
+
 // Residual b~ - A p and weight w of the pair; its 11 faces (a x-, a x+, a y-,
 // a|b, a z-, a z+, b x-, b x+, b y+, b z-, b z+) share one batched reciprocal.
-// rmax = max rho, rinv = 1 / rmax.
+// rmax = max rho, rinv = 1 / rmax; `walls` from x_walls for the pair's column.
 template <typename T, int COEF, int WEIGHT>
 __device__ __forceinline__ PairOut<T> pair_eval(const GridArgs& g, const PairIn<T>& in, T rhs_mean, T rmax,
-                                                T rinv) {
+                                                T rinv, unsigned walls) {
     const T* r = in.r;
     const T* q = in.q;
     T be[11];
@@ -178,6 +186,10 @@ __device__ __forceinline__ PairOut<T> pair_eval(const GridArgs& g, const PairIn<
         be[6] = c * (v[4] + v[1]);  be[7] = c * (v[1] + v[5]);  be[8] = c * (v[1] + v[7]);
         be[9] = c * (v[10] + v[1]); be[10] = c * (v[1] + v[11]);
     }
+    be[0] = (walls & 1u) ? T(0) : be[0];
+    be[6] = (walls & 1u) ? T(0) : be[6];
+    be[1] = (walls & 2u) ? T(0) : be[1];
+    be[7] = (walls & 2u) ? T(0) : be[7];
     const T pa = q[0], pb = q[1];
     const T hx = T(g.ihx2), hy = T(g.ihy2), hz = T(g.ihz2);
     const T gy = be[3] * (pb - pa);  // flux through the shared face
@@ -404,7 +416,9 @@ __device__ __forceinline__ CellOut<T> cell_residual(const GridArgs& g, const POI
     const unsigned czm = (k == 0) ? c + (nz - 1) * sz : c - sz;
     const unsigned czp = (k + 1 == g.nz) ? c - (nz - 1) * sz : c + sz;
     const T rc = rho[c];
-    const T bxm = face_beta<T>(g.coef, rho[cxm], rc), bxp = face_beta<T>(g.coef, rc, rho[cxp]);
+    const unsigned walls = x_walls(g, (unsigned)i);
+    const T bxm = (walls & 1u) ? T(0) : face_beta<T>(g.coef, rho[cxm], rc);
+    const T bxp = (walls & 2u) ? T(0) : face_beta<T>(g.coef, rc, rho[cxp]);
     const T bym = face_beta<T>(g.coef, rho[cym], rc), byp = face_beta<T>(g.coef, rc, rho[cyp]);
     const T bzm = face_beta<T>(g.coef, rho[czm], rc), bzp = face_beta<T>(g.coef, rc, rho[czp]);
     CellOut<T> o;
@@ -513,6 +527,56 @@ __device__ __forceinline__ const double* symbol<double>(const Tables& t, int axi
 template <>
 __device__ __forceinline__ const float* symbol<float>(const Tables& t, int axis) {
     return axis == 0 ? t.lamx32 : axis == 1 ? t.lamy32 : t.lamz32;
+}
+
+// ---- cosine transform along x between walls ---------------------------------------
+// With walls in x the constant-coefficient operator is diagonalised by
+// cos(pi k (i + 1/2) / N) instead of the Fourier modes.  Both the forward
+// transform X_k = sum_i q_i cos(pi k (i + 1/2) / N) and its N-scaled inverse
+// y_i = X_0 + 2 sum_{k>0} X_k cos(pi k (i + 1/2) / N) (= N q_i) take one length-N
+// complex FFT of a reordered line (Makhoul's even/odd reordering): x index i
+// sits at slot i/2 (i even) or N - 1 - (i-1)/2 (i odd).  Two real lines a, b
+// travel as one complex line a + i b, like the Hartley pairs.
+__device__ __forceinline__ unsigned x_slot(unsigned i, unsigned n, int bcx) {
+    return bcx ? ((i & 1u) ? n - 1u - (i >> 1) : (i >> 1)) : i;
+}
+
+// forward: Z = FFT of the reordered pair line; (X^a_k, X^b_k) from Z_k, Z_{N-k} and
+// w_k = exp(-i pi k / (2N))
+template <typename T>
+__device__ __forceinline__ cpx<T> dct_out(cpx<T> zk, cpx<T> zm, cpx<T> w) {
+    const T ax = w.x * zk.x - w.y * zk.y, ay = w.x * zk.y + w.y * zk.x;    // w Z_k
+    const T bx = w.x * zm.x + w.y * zm.y, by = w.y * zm.x - w.x * zm.y;    // w conj(Z_{N-k})
+    return {T(0.5) * (ax + bx), T(0.5) * (ay - by)};
+}
+
+// inverse, step 1: c_k = X^a_k + i X^b_k and c_{N-k} (zero for k = 0) give the
+// FFT input conj(U_k), U_k = conj(w_k) ((c_k.x + c_{N-k}.y) + i (c_k.y - c_{N-k}.x));
+// step 2: R = FFT(conj U); slot s holds y^a = R_s.x and y^b = -R_s.y
+template <typename T>
+__device__ __forceinline__ cpx<T> idct_in(cpx<T> c, cpx<T> cm, cpx<T> w) {
+    const T sx = c.x + cm.y, sy = cm.x - c.y;  // conj of the bracket
+    return {w.x * sx - w.y * sy, w.x * sy + w.y * sx};
+}
+
+template <typename T>
+__device__ __forceinline__ const cpx<T>* dct_twiddles(const Tables& t);
+template <>
+__device__ __forceinline__ const cpx<double>* dct_twiddles<double>(const Tables& t) {
+    return reinterpret_cast<const cpx<double>*>(t.twcx);
+}
+template <>
+__device__ __forceinline__ const cpx<float>* dct_twiddles<float>(const Tables& t) {
+    return reinterpret_cast<const cpx<float>*>(t.twcx32);
+}
+
+// Output k of a forward transform along x of one LDS line: the Hartley pair
+// (periodic) or the cosine pair (walls).
+template <typename T, int N>
+__device__ __forceinline__ cpx<T> x_forward_out(const cpx<T>* line, int k, int bcx, const cpx<T>* twc) {
+    using C = LineCfg<T, N>;
+    const cpx<T> zk = line[C::pos(k)], zm = line[C::pos(k == 0 ? 0 : N - k)];
+    return bcx ? dct_out(zk, zm, twc[k]) : hartley(zk, zm);
 }
 
 // 1 / (n (lx + ly + lz)), 0 for the constant mode (the zero-mean gauge)

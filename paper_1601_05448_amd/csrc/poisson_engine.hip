@@ -32,7 +32,7 @@ bool valid_lengths(double lx, double ly, double lz) {
     return std::isfinite(lx) && std::isfinite(ly) && std::isfinite(lz) && lx > 0 && ly > 0 && lz > 0;
 }
 
-GridArgs make_grid(int nx, int ny, int nz, double lx, double ly, double lz, int coef, int weight) {
+GridArgs make_grid(int nx, int ny, int nz, double lx, double ly, double lz, int coef, int weight, int bcx) {
     GridArgs g{};
     g.nx = nx; g.ny = ny; g.nz = nz;
     g.nxh = nx / 2;
@@ -43,16 +43,19 @@ GridArgs make_grid(int nx, int ny, int nz, double lx, double ly, double lz, int 
     g.ihz2 = 1.0 / (hz * hz);
     g.coef = coef;
     g.weight = weight;
+    g.bcx = bcx;
     return g;
 }
 
-// Smallest nonzero eigenvalue magnitude of -L: min_d 4 sin^2(pi/N_d)/h_d^2.
+// Smallest nonzero eigenvalue magnitude of -L: min_d 4 sin^2(pi/N_d)/h_d^2, with
+// 4 sin^2(pi/(2 Nx))/hx^2 along x between walls.
 double min_symbol(const GridArgs& g) {
-    auto one = [](int n, double ih2) {
-        const double s = std::sin(kPi / n);
+    auto one = [](double arg, double ih2) {
+        const double s = std::sin(arg);
         return 4.0 * s * s * ih2;
     };
-    return std::min(one(g.nx, g.ihx2), std::min(one(g.ny, g.ihy2), one(g.nz, g.ihz2)));
+    const double ax = g.bcx ? kPi / (2.0 * g.nx) : kPi / g.nx;
+    return std::min(one(ax, g.ihx2), std::min(one(kPi / g.ny, g.ihy2), one(kPi / g.nz, g.ihz2)));
 }
 
 // ---- per-grid tables ---------------------------------------------------------------
@@ -60,7 +63,8 @@ double min_symbol(const GridArgs& g) {
 int GridTables::build(const GridArgs& g) {
     const int ns[3] = {g.nx, g.ny, g.nz};
     const double ih2[3] = {g.ihx2, g.ihy2, g.ihz2};
-    // layout first: four 256-byte aligned arrays per direction
+    // layout first: four 256-byte aligned arrays per direction, and the cosine
+    // transform's twiddles along x
     size_t off = 0;
     auto take = [&](size_t bytes) {
         off = (off + 255) & ~(size_t)255;
@@ -75,6 +79,7 @@ int GridTables::build(const GridArgs& g) {
         at[d][2] = take((size_t)ns[d] * 8);   // FP64 symbol
         at[d][3] = take((size_t)ns[d] * 4);   // FP32 symbol
     }
+    const size_t at_c = take((size_t)g.nx * 16), at_c32 = take((size_t)g.nx * 8);
     const size_t total = off;
     if (hipMalloc(&mem, total) != hipSuccess) {
         mem = nullptr;
@@ -88,15 +93,27 @@ int GridTables::build(const GridArgs& g) {
         float* tw32 = reinterpret_cast<float*>(host.data() + at[d][1]);
         double* lam = reinterpret_cast<double*>(host.data() + at[d][2]);
         float* lam32 = reinterpret_cast<float*>(host.data() + at[d][3]);
+        const bool wall = d == 0 && g.bcx == 1;
         for (int t = 0; t < n; ++t) {
             const double ang = 2.0 * kPi * (double)t / (double)n;
             tw[2 * t] = std::cos(ang);
             tw[2 * t + 1] = -std::sin(ang);
             tw32[2 * t] = (float)tw[2 * t];
             tw32[2 * t + 1] = (float)tw[2 * t + 1];
-            const double s = std::sin(kPi * (double)t / (double)n);
+            const double s = std::sin(kPi * (double)t / (wall ? 2.0 * n : (double)n));
             lam[t] = -4.0 * s * s * ih2[d];
             lam32[t] = (float)lam[t];
+        }
+    }
+    {
+        double* c = reinterpret_cast<double*>(host.data() + at_c);
+        float* c32 = reinterpret_cast<float*>(host.data() + at_c32);
+        for (int t = 0; t < g.nx; ++t) {
+            const double ang = kPi * (double)t / (2.0 * g.nx);
+            c[2 * t] = std::cos(ang);
+            c[2 * t + 1] = -std::sin(ang);
+            c32[2 * t] = (float)c[2 * t];
+            c32[2 * t + 1] = (float)c[2 * t + 1];
         }
     }
     if (hipMemcpy(mem, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) return POISSON_EHIP;
@@ -109,6 +126,8 @@ int GridTables::build(const GridArgs& g) {
     t.lamz = static_cast<const double*>(ptr(2, 2));
     t.lamx32 = static_cast<const float*>(ptr(0, 3)); t.lamy32 = static_cast<const float*>(ptr(1, 3));
     t.lamz32 = static_cast<const float*>(ptr(2, 3));
+    t.twcx = reinterpret_cast<const double2*>(base + at_c);
+    t.twcx32 = reinterpret_cast<const float2*>(base + at_c32);
     return POISSON_OK;
 }
 
@@ -430,6 +449,7 @@ int poisson_create(const poisson_opts* o, poisson_t* out) {
     if (o->precision != POISSON_FP64 && o->precision != POISSON_FP32_REFINE) return POISSON_EINVAL;
     if (o->coef != POISSON_COEF_RHO_FACE_MEAN && o->coef != POISSON_COEF_INVRHO_FACE_MEAN) return POISSON_EINVAL;
     if (o->weight != POISSON_W_RHO && o->weight != POISSON_W_DIAG) return POISSON_EINVAL;
+    if (o->bc_x != POISSON_BC_PERIODIC && o->bc_x != POISSON_BC_WALLS_X) return POISSON_EINVAL;
     poisson_s* h = new (std::nothrow) poisson_s();
     if (!h) return POISSON_ENOMEM;
     h->o = *o;
@@ -440,7 +460,7 @@ int poisson_create(const poisson_opts* o, poisson_t* out) {
         delete h;
         return POISSON_EHIP;
     }
-    h->g = make_grid(o->nx, o->ny, o->nz, o->lx, o->ly, o->lz, o->coef, o->weight);
+    h->g = make_grid(o->nx, o->ny, o->nz, o->lx, o->ly, o->lz, o->coef, o->weight, o->bc_x);
     h->geo = make_geometry(h->g);
     int rc = h->tables.build(h->g);
     if (rc == POISSON_OK) rc = h->ws.allocate(h->g, h->geo, o->precision);

@@ -81,7 +81,7 @@ struct GraphCache {
 
 int hip_status(hipError_t e);
 bool valid_lengths(double lx, double ly, double lz);
-GridArgs make_grid(int nx, int ny, int nz, double lx, double ly, double lz, int coef, int weight);
+GridArgs make_grid(int nx, int ny, int nz, double lx, double ly, double lz, int coef, int weight, int bcx = 0);
 double min_symbol(const GridArgs& g);
 size_t workspace_bytes(const GridArgs& g, const Geometry& geo, int precision);
 int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* d_slots, int nslots,

@@ -22,6 +22,7 @@ struct GridArgs {
     double ihx2, ihy2, ihz2;  // 1 / h_d^2
     int coef;          // face-coefficient mode
     int weight;        // residual multiplier mode
+    int bcx;           // 0 periodic in x; 1 zero-flux walls at both ends of x
 };
 
 // Per-solve state, resident in device memory.  Written only by the one-block
@@ -92,8 +93,11 @@ struct Slot {
 struct Tables {
     const double2* twx; const double2* twy; const double2* twz;  // exp(-2 pi i t/N), FP64
     const float2* twx32; const float2* twy32; const float2* twz32;
-    const double* lamx; const double* lamy; const double* lamz;  // -4 sin^2(pi k/N)/h^2
+    // symbols: -4 sin^2(pi k/N)/h^2; along x between walls -4 sin^2(pi k/(2N))/h^2
+    const double* lamx; const double* lamy; const double* lamz;
     const float* lamx32; const float* lamy32; const float* lamz32;
+    // walls in x: exp(-i pi k/(2 Nx)), the twiddles of the cosine transform
+    const double2* twcx; const float2* twcx32;
 };
 
 // Launch geometry of the sweeps of one grid (host side).

@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(256) k_outer_resid(GridArgs g, const Slot* __r
                 PairIn<double> in;
                 zm.pair(pl[c][0], pl[c][1], pl[c][2], sd[c], zm.edge_get(eb, i), in);
                 if (valid) {
-                    const PairOut<double> pr = pair_eval<double, COEF, WEIGHT>(g, in, bm, rmax, rinv);
+                    const PairOut<double> pr = pair_eval<double, COEF, WEIGHT>(g, in, bm, rmax, rinv, x_walls(g, i));
                     const unsigned a = (unsigned)k * zm.sz + zm.ra + i, b = a + (unsigned)g.nx;
                     acc[0] += pr.a.r * pr.a.r + pr.b.r * pr.b.r;
                     acc[1] += pr.a.bt * pr.a.bt + pr.b.bt * pr.b.bt;
@@ -369,7 +369,7 @@ __global__ void __launch_bounds__(kPtThreads) k_outer_resid_rows(GridArgs g, con
         const int l = e / N, i = e % N;
         const unsigned P = pair0 + l;
         if (e >= RPB * N || P >= npairs) return;
-        const PairOut<double> pr = pair_eval<double, COEF, WEIGHT>(g, in, bm, rmax, rinv);
+        const PairOut<double> pr = pair_eval<double, COEF, WEIGHT>(g, in, bm, rmax, rinv, x_walls(g, i));
         const unsigned a = (2 * P) * N + i, b = a + N;
         acc[0] += pr.a.r * pr.a.r + pr.b.r * pr.b.r;
         acc[1] += pr.a.bt * pr.a.bt + pr.b.bt * pr.b.bt;

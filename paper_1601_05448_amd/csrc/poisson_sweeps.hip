@@ -6,6 +6,8 @@
 //   P2 k_dht_cols     Hartley along y of W (also P4: the transform is self-inverse)
 //   P3 k_dht_z_solve  Hartley along z, divide by n * symbol, Hartley along z
 //   P5 k_dhtx_update  Hartley along x, p += dp (minus the mean of p)
+// With walls in x (GridArgs::bcx) P1 and P5 take the cosine transform along x
+// instead of the Hartley transform; P2-P4 are the same.
 // and, for the FP32 refinement, k_outer_resid_dhtx: the FP64 outer residual
 // fused with the first inner sweep's residual.
 //
@@ -44,6 +46,7 @@ k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     const Slot& s = slots[blockIdx.y];
     if (MODE == 0 && IterView<T>::skip(s.st)) return;
     const cpx<T>* twg = twiddles<T>(tb, 0);
+    const cpx<T>* twc = dct_twiddles<T>(tb);
     for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
 
     const unsigned nlines = (unsigned)(g.ny * g.nz / 2);
@@ -73,14 +76,14 @@ k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
         const int l = e / N, i = e % N;
         cpx<T> qv = {T(0), T(0)};
         if (grp * C::L + l < nlines) {
-            const PairOut<T> o = pair_eval<T, COEF, WEIGHT>(g, in, v.rhs_mean, v.rmax, v.rinv);
+            const PairOut<T> o = pair_eval<T, COEF, WEIGHT>(g, in, v.rhs_mean, v.rmax, v.rinv, x_walls(g, i));
             qv = {o.a.w * o.a.r, o.b.w * o.b.r};
             acc[0] += (double)o.a.r * o.a.r + (double)o.b.r * o.b.r;
             acc[1] += (double)o.a.bt * o.a.bt + (double)o.b.bt * o.b.bt;
             acc[2] += (double)o.a.pc + (double)o.b.pc;
             acc[3] += (double)o.a.pc * o.a.pc + (double)o.b.pc * o.b.pc;
         }
-        lds[l * C::LS + C::pos(i)] = qv;
+        lds[l * C::LS + C::pos(x_slot(i, N, g.bcx))] = qv;
     };
 
     unsigned grp = blockIdx.x;
@@ -104,8 +107,8 @@ k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                 const int l = e / N, i = e % N;
                 const unsigned P = grp * C::L + l;
                 const POIS_GLOBAL double* q = gptr(s.b);
-                lds[l * C::LS + C::pos(i)] = (P < nlines) ? cpx<T>{T(q[(2 * P) * N + i]), T(q[(2 * P + 1) * N + i])}
-                                                  : cpx<T>{T(0), T(0)};
+                lds[l * C::LS + C::pos(x_slot(i, N, g.bcx))] =
+                    (P < nlines) ? cpx<T>{T(q[(2 * P) * N + i]), T(q[(2 * P + 1) * N + i])} : cpx<T>{T(0), T(0)};
             }
         }
         __syncthreads();
@@ -116,7 +119,7 @@ k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
             const int l = e / N, k = e % N;
             const unsigned P = grp * C::L + l;
             if (P < nlines) {
-                const cpx<T> h = hartley(lds[l * C::LS + C::pos(k)], lds[l * C::LS + C::pos((k == 0 ? 0 : N - k))]);
+                const cpx<T> h = x_forward_out<T, N>(lds + l * C::LS, k, g.bcx, twc);
                 W[(2 * P) * N + k] = h.x;
                 W[(2 * P + 1) * N + k] = h.y;
             }
@@ -145,6 +148,7 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     const Slot& s = slots[blockIdx.y];
     if (IterView<T>::skip(s.st)) return;
     const cpx<T>* twg = twiddles<T>(tb, 0);
+    const cpx<T>* twc = dct_twiddles<T>(tb);
     for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
     const IterView<T> v(s);
 
@@ -209,7 +213,7 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                     zm.pair(pl[c][0], pl[c][1], pl[c][2], sd[c], zm.edge_get(eb, i), in);
                     cpx<T> qv = {T(0), T(0)};
                     if (valid) {
-                        const PairOut<T> o = pair_eval<T, COEF, WEIGHT>(g, in, v.rhs_mean, v.rmax, v.rinv);
+                        const PairOut<T> o = pair_eval<T, COEF, WEIGHT>(g, in, v.rhs_mean, v.rmax, v.rinv, x_walls(g, i));
                         qv = {o.a.w * o.a.r, o.b.w * o.b.r};
                         if constexpr (sizeof(T) == 8) {
                             acc[0] += o.a.r * o.a.r + o.b.r * o.b.r;
@@ -223,7 +227,7 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                             tacc[1] += o.a.bt * o.a.bt + o.b.bt * o.b.bt;
                         }
                     }
-                    lds[(sidx * Z::KF + q) * C::LS + C::pos(i)] = qv;
+                    lds[(sidx * Z::KF + q) * C::LS + C::pos(x_slot(i, N, g.bcx))] = qv;
                 }
 #pragma unroll
                 for (int c = 0; c < Z::CPT; ++c) {
@@ -247,8 +251,7 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                 const unsigned lk = (unsigned)(k0 + f * Z::KF) + l % Z::KF;
                 if (ljp < nyh && lk < nz) {
                     const unsigned P = lk * nyh + ljp;  // row pair index, rows 2P and 2P + 1
-                    const cpx<T> h = hartley(lds[l * C::LS + C::pos(k)],
-                                             lds[l * C::LS + C::pos((k == 0 ? 0 : N - k))]);
+                    const cpx<T> h = x_forward_out<T, N>(lds + l * C::LS, k, g.bcx, twc);
                     v.W[(2 * P) * N + k] = h.x;
                     v.W[(2 * P + 1) * N + k] = h.y;
                 }
@@ -281,6 +284,7 @@ k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     SolveState* st = s.st;
     if (st->done || st->stage != 0) return;
     const cpx<float>* twg = twiddles<float>(tb, 0);
+    const cpx<float>* twc = dct_twiddles<float>(tb);
     for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
     const double bm = st->b_mean, inv_s = st->inv_s, rmax = st->rho_max, rinv = recip(st->rho_max);
 
@@ -329,7 +333,7 @@ k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                 zm.pair(pl[0], pl[1], pl[2], sd, zm.edge_get(eb, i), in);
                 cpx<float> qv = {0.0f, 0.0f};
                 if (valid) {
-                    const PairOut<double> pr = pair_eval<double, COEF, WEIGHT>(g, in, bm, rmax, rinv);
+                    const PairOut<double> pr = pair_eval<double, COEF, WEIGHT>(g, in, bm, rmax, rinv, x_walls(g, i));
                     acc[0] += pr.a.r * pr.a.r + pr.b.r * pr.b.r;
                     acc[1] += pr.a.bt * pr.a.bt + pr.b.bt * pr.b.bt;
                     acc[2] += pr.a.pc + pr.b.pc;
@@ -341,7 +345,7 @@ k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                     r32[a + (unsigned)g.nx] = rb;
                     qv = {(float)pr.a.w * ra, (float)pr.b.w * rb};
                 }
-                lds[(sidx * Z::KF + q) * C::LS + C::pos(i)] = qv;
+                lds[(sidx * Z::KF + q) * C::LS + C::pos(x_slot(i, N, g.bcx))] = qv;
                 pl[0] = pl[1];
                 pl[1] = pl[2];
                 pl[2] = nn;
@@ -357,8 +361,7 @@ k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                 const unsigned lk = (unsigned)(k0 + f * Z::KF) + l % Z::KF;
                 if (ljp < nyh && lk < nz) {
                     const unsigned P = lk * nyh + ljp;
-                    const cpx<float> h = hartley(lds[l * C::LS + C::pos(kx)],
-                                                 lds[l * C::LS + C::pos((kx == 0 ? 0 : N - kx))]);
+                    const cpx<float> h = x_forward_out<float, N>(lds + l * C::LS, kx, g.bcx, twc);
                     W32[(2 * P) * N + kx] = h.x;
                     W32[(2 * P + 1) * N + kx] = h.y;
                 }
@@ -604,6 +607,7 @@ k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
     const Slot& s = slots[blockIdx.y];
     if (MODE != 1 && IterView<T>::skip(s.st, stage)) return;
     const cpx<T>* twg = twiddles<T>(tb, 0);
+    const cpx<T>* twc = dct_twiddles<T>(tb);
     for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
     const POIS_GLOBAL T* W = (MODE != 1) ? IterView<T>(s).W : (const POIS_GLOBAL T*)gptr(s.W);
     POIS_GLOBAL T* out;
@@ -630,6 +634,24 @@ k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
         for (int it = 0; it < C::IT; ++it) {
             const int e = threadIdx.x + it * C::NT;
             lds[(e / N) * C::LS + C::pos(e % N)] = wb[it];
+        }
+        if (g.bcx) {
+            // cosine transform between walls: the FFT input pairs coefficient k
+            // with coefficient N - k of the same line
+            __syncthreads();
+#pragma unroll
+            for (int it = 0; it < C::IT; ++it) {
+                const int e = threadIdx.x + it * C::NT;
+                const int l = e / N, k = e % N;
+                const cpx<T> cm = (k == 0) ? cpx<T>{T(0), T(0)} : lds[l * C::LS + C::pos(N - k)];
+                wb[it] = idct_in(wb[it], cm, twc[k]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int it = 0; it < C::IT; ++it) {
+                const int e = threadIdx.x + it * C::NT;
+                lds[(e / N) * C::LS + C::pos(e % N)] = wb[it];
+            }
         }
         // FP32: the values to update are loaded now and are in flight during the
         // FFT; FP64 has no registers to spare for them and loads them after it
@@ -661,7 +683,13 @@ k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
             const int l = e / N, k = e % N;
             const unsigned P = grp * C::L + l;
             if (P < nlines) {
-                const cpx<T> h = hartley(lds[l * C::LS + C::pos(k)], lds[l * C::LS + C::pos((k == 0 ? 0 : N - k))]);
+                cpx<T> h;
+                if (g.bcx) {
+                    const cpx<T> r = lds[l * C::LS + C::pos(x_slot(k, N, 1))];
+                    h = {r.x, -r.y};
+                } else {
+                    h = hartley(lds[l * C::LS + C::pos(k)], lds[l * C::LS + C::pos((k == 0 ? 0 : N - k))]);
+                }
                 const unsigned a = (2 * P) * N + k, b = a + N;
                 if (MODE == 0) {
                     out[a] = pb[it].x + h.x - shift;

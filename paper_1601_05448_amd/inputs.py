@@ -23,6 +23,10 @@ the gas, hot gas is light, section "Motivation and objectives"):
      lognormal band-limited with contrast R ~ U[2,8], b band-limited.
   5  1024x512x512 on [0,4pi)x[0,2pi)^2, rho = 1/(1 + 19 f/max f), f = sum of
      10^5 periodic Gaussian blobs of width 2 cells; b band-limited.
+  6  duct: 2N x N x N on [0,4pi)x[0,2pi)^2 (the inflow-outflow domain, twice as
+     long in x as the box that feeds it), rho lognormal band-limited with
+     max/min = 4, b band-limited; solved with zero-flux walls at the x ends.
+     The fields are drawn as periodic ones; the walls only change the operator.
 """
 from __future__ import annotations
 
@@ -254,6 +258,16 @@ def workload5(shape=(512, 512, 1024), blobs: int = 10**5, ratio: float = 20.0,
     rho = 1.0 / (1.0 + (ratio - 1.0) * f / f.max())
     b = bandlim(shape, L, kmax, rng)
     return Problem(f"hot-blob-rho {nx}x{ny}x{nz} ratio {ratio:g}", tuple(shape), L, rho, b)
+
+
+def workload_duct(n: int = 256, ratio: float = 4.0, kmax: float = 8.0) -> Problem:
+    rng = np.random.default_rng(workload_seed(6))
+    shape = (n, n, 2 * n)
+    L = (2.0 * TWO_PI, TWO_PI, TWO_PI)
+    s = bandlim(shape, L, kmax, rng)
+    rho = contrast_exp(s, ratio)
+    b = bandlim(shape, L, kmax, rng)
+    return Problem(f"duct lognormal-rho {2 * n}x{n}x{n} ratio {ratio:g}", shape, L, rho, b)
 
 
 SERVE_SIZES = (64, 96, 128, 192)

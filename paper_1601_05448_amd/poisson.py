@@ -35,6 +35,8 @@ POISSON_COEF_RHO_FACE_MEAN = 0
 POISSON_COEF_INVRHO_FACE_MEAN = 1
 POISSON_W_RHO = 0
 POISSON_W_DIAG = 1
+POISSON_BC_PERIODIC = 0
+POISSON_BC_WALLS_X = 1
 
 
 class poisson_opts(ctypes.Structure):
@@ -42,7 +44,7 @@ class poisson_opts(ctypes.Structure):
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
                 ("precision", ctypes.c_int), ("coef", ctypes.c_int), ("weight", ctypes.c_int),
                 ("max_iter", ctypes.c_int), ("stream", ctypes.c_void_p), ("inner_tol", ctypes.c_double),
-                ("use_graphs", ctypes.c_int)]
+                ("use_graphs", ctypes.c_int), ("bc_x", ctypes.c_int)]
 
 
 class poisson_stats(ctypes.Structure):
@@ -132,12 +134,14 @@ def _stream_ptr(stream) -> Optional[int]:
 
 def poisson_create(shape: Sequence[int], lengths: Sequence[float], precision: int = POISSON_FP64,
                    coef: int = POISSON_COEF_RHO_FACE_MEAN, weight: int = POISSON_W_RHO,
-                   max_iter: int = 0, stream=None, inner_tol: float = 0.0, use_graphs: bool = False) -> int:
-    """Handle for grid `shape` = (nz, ny, nx) on box `lengths` = (lx, ly, lz)."""
+                   max_iter: int = 0, stream=None, inner_tol: float = 0.0, use_graphs: bool = False,
+                   bc_x: int = POISSON_BC_PERIODIC) -> int:
+    """Handle for grid `shape` = (nz, ny, nx) on box `lengths` = (lx, ly, lz);
+    `bc_x` = POISSON_BC_WALLS_X for zero-flux walls at both ends of x."""
     nz, ny, nx = (int(v) for v in shape)
     o = poisson_opts(nx, ny, nz, float(lengths[0]), float(lengths[1]), float(lengths[2]),
                      precision, coef, weight, max_iter, _stream_ptr(stream), float(inner_tol),
-                     1 if use_graphs else 0)
+                     1 if use_graphs else 0, int(bc_x))
     h = ctypes.c_void_p()
     rc = load().poisson_create(ctypes.byref(o), ctypes.byref(h))
     if rc != POISSON_OK:
@@ -278,10 +282,11 @@ class Solver:
     stream: object = None
     inner_tol: float = 0.0
     use_graphs: bool = False
+    bc_x: int = POISSON_BC_PERIODIC
 
     def __post_init__(self):
         self.h = poisson_create(self.shape, self.lengths, self.precision, self.coef, self.weight,
-                                self.max_iter, self.stream, self.inner_tol, self.use_graphs)
+                                self.max_iter, self.stream, self.inner_tol, self.use_graphs, self.bc_x)
 
     def solve(self, rho, b, p, tol: float = 1e-10) -> dict:
         rc = poisson_solve(self.h, rho, b, p, tol)

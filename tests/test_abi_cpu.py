@@ -34,7 +34,7 @@ def _create(**kw):
 
 @pytest.mark.parametrize("kw", [dict(nx=5), dict(ny=7), dict(nz=2), dict(nx=2048), dict(nx=9), dict(nx=3),
                                 dict(lx=0.0), dict(ly=-1.0), dict(lz=float("nan")), dict(precision=2),
-                                dict(coef=5), dict(weight=-1)])
+                                dict(coef=5), dict(weight=-1), dict(bc_x=2), dict(bc_x=-1)])
 def test_create_rejects_invalid_options(kw):
     rc, h = _create(**kw)
     assert rc == P.POISSON_EINVAL and h is None

@@ -1,0 +1,224 @@
+"""GPU parity of the walls-in-x variant against the FP64 CPU oracle, through the
+C ABI.
+
+Paper: Pouransari, Mortazavi & Mani (arXiv:1601.05448), section "Boundary and
+initial conditions" (the inflow-outflow duct: periodic in y and z, bounded in
+x) and section "Poisson equation" (Fourier transforms in the periodic
+directions, a tridiagonal solve in the other one).  The pressure flux through
+the two x ends is zero.  The oracle solves the x direction with the Thomas
+algorithm, as the paper states; the library diagonalises the same discrete
+operator with a cosine transform, so the two share no algorithm.
+
+Tolerances:
+  * operator and residual sweeps (FP64, same arithmetic up to rounding order):
+    1e-12 relative to the largest magnitude of the oracle's field;
+  * L^+ with walls: the Thomas recurrences amplify rounding by up to the
+    condition number of the slowest x mode, about (2 Nx / pi)^2, so the bound is
+    1e-15 (2 Nx / pi)^2 + 1e-12; cosine modes, whose exact image is known, are
+    held to 1e-12;
+  * solves: as in the periodic tests (relative residual <= 1e-10 evaluated by
+    the oracle on the GPU's p, error below the reported a-posteriori bound and
+    1e-8); FP64 histories equal to the oracle's to 1e-6 relative or 1e-14
+    absolute (in units of ||b~||): the cosine-transform and Thomas iterates
+    differ by rounding, about 1e-14 of max |p|, which moves the last residuals
+    (near 1e-10) by about 1e-16.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import announce, dev, host, rel_l2
+from paper_1601_05448_amd import inputs
+from paper_1601_05448_amd import poisson as P
+
+pytestmark = pytest.mark.gpu
+TWO_PI = 2.0 * math.pi
+LENGTHS = [4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024]
+W = P.POISSON_BC_WALLS_X
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    P.load()
+    yield
+
+
+def _pinv_tol(nx):
+    return 1e-15 * (2.0 * nx / math.pi) ** 2 + 1e-12
+
+
+# (nz, ny, nx): row-pair gather rows (nx not a multiple of 64) and z-marching
+# rows with one, two and four columns per thread
+@pytest.mark.parametrize("shape", [(4, 4, 4), (8, 6, 12), (16, 12, 24), (12, 8, 64), (6, 4, 256), (4, 4, 1024)])
+@pytest.mark.parametrize("coef", [0, 1])
+def test_apply_walls_matches_oracle(shape, coef):
+    announce("apply walls", shape, coef)
+    rng = np.random.default_rng(31)
+    L = (5.0, 3.0, TWO_PI)
+    rho = np.exp(rng.uniform(-1.0, 1.0, shape))
+    p = rng.standard_normal(shape)
+    want = oracle.apply(rho, p, L, coef, bcx=oracle.BC_WALLS_X)
+    h = P.poisson_create(shape, L, coef=coef, bc_x=W)
+    try:
+        out = dev(np.zeros(shape))
+        P.poisson_apply(h, dev(rho), dev(p), out)
+    finally:
+        P.poisson_destroy(h)
+    assert np.max(np.abs(host(out) - want)) <= 1e-12 * np.max(np.abs(want))
+
+
+def test_residual_walls_matches_oracle():
+    announce("residual walls")
+    prob = inputs.small_problem(shape=(12, 8, 48))
+    p = np.random.default_rng(5).standard_normal(prob.shape)
+    want = oracle.residual(prob.rho, prob.b, p, prob.lengths, want_field=True, bcx=oracle.BC_WALLS_X)
+    h = P.poisson_create(prob.shape, prob.lengths, bc_x=W)
+    try:
+        r = dev(np.zeros(prob.shape))
+        rn, bn = P.poisson_residual(h, dev(prob.rho), dev(prob.b), dev(p), r)
+    finally:
+        P.poisson_destroy(h)
+    assert np.max(np.abs(host(r) - want["r"])) <= 1e-12 * np.max(np.abs(want["r"]))
+    assert abs(rn - want["r_norm"]) <= 1e-12 * want["r_norm"]
+    assert abs(bn - want["b_norm"]) <= 1e-12 * want["b_norm"]
+
+
+@pytest.mark.parametrize("nx", LENGTHS)
+def test_lap_pinv_walls_every_length(nx):
+    """Every supported length along x, where the cosine transform runs."""
+    shape = (6, 4, nx)
+    announce("lap_pinv walls", shape)
+    rng = np.random.default_rng(nx)
+    L = (3.0, 2.5, 4.0)
+    q = rng.standard_normal(shape) + 0.7
+    want = oracle.lap_pinv(q, L, bcx=oracle.BC_WALLS_X)
+    h = P.poisson_create(shape, L, bc_x=W)
+    try:
+        out = dev(np.zeros(shape))
+        P.poisson_lap_pinv(h, dev(q), out)
+    finally:
+        P.poisson_destroy(h)
+    got = host(out)
+    assert np.max(np.abs(got - want)) <= _pinv_tol(nx) * np.max(np.abs(want)), shape
+
+
+@pytest.mark.parametrize("shape", [(8, 6, 24), (4, 8, 128), (6, 4, 512)])
+def test_lap_pinv_walls_cosine_modes(shape):
+    """q = cos(pi kx (i + 1/2)/Nx) cos(2 pi ky j/Ny + 0.3) cos(2 pi kz k/Nz - 0.2) is an
+    eigenvector of the discrete operator with walls in x; L^+ q = q / lambda
+    exactly, lambda = -sum_d 4 sin^2(theta_d / 2) / h_d^2 with theta_x = pi kx/Nx,
+    theta_y = 2 pi ky/Ny, theta_z = 2 pi kz/Nz.  The transforms' rounding is
+    relative to the input (|q| <= 1) and leaks into every mode, the slowest of
+    which divides it by the smallest nonzero |lambda|, so the error is held to
+    1e-12 / lambda_min (for a fast mode that is well above |q / lambda|)."""
+    nz, ny, nx = shape
+    L = (3.0, 2.0, 5.0)
+    h = [L[0] / nx, L[1] / ny, L[2] / nz]
+    lam_min = min(4.0 * math.sin(math.pi / (2 * nx)) ** 2 / h[0] ** 2,
+                  4.0 * math.sin(math.pi / ny) ** 2 / h[1] ** 2, 4.0 * math.sin(math.pi / nz) ** 2 / h[2] ** 2)
+    announce("lap_pinv walls cosine modes", shape)
+    hd = P.poisson_create(shape, L, bc_x=W)
+    try:
+        for kx, ky, kz in [(1, 0, 0), (nx - 1, 1, 2), (nx // 2, ny // 2, 1), (3, 2, nz // 2)]:
+            i, j, k = np.arange(nx), np.arange(ny), np.arange(nz)
+            q = (np.cos(2.0 * math.pi * kz * k / nz - 0.2)[:, None, None] *
+                 np.cos(2.0 * math.pi * ky * j / ny + 0.3)[None, :, None] *
+                 np.cos(math.pi * kx * (i + 0.5) / nx)[None, None, :])
+            lam = -sum(4.0 * math.sin(t / 2.0) ** 2 / hh ** 2 for t, hh in
+                       ((math.pi * kx / nx, h[0]), (2 * math.pi * ky / ny, h[1]), (2 * math.pi * kz / nz, h[2])))
+            out = dev(np.zeros(shape))
+            P.poisson_lap_pinv(hd, dev(q), out)
+            want = q / lam
+            assert np.max(np.abs(host(out) - want)) <= 1e-12 / lam_min, (kx, ky, kz)
+    finally:
+        P.poisson_destroy(hd)
+
+
+def _solve_gpu(prob, precision=P.POISSON_FP64, coef=0, weight=0, tol=1e-10, max_iter=0):
+    h = P.poisson_create(prob.shape, prob.lengths, precision=precision, coef=coef, weight=weight,
+                         max_iter=max_iter, bc_x=W)
+    try:
+        p = dev(np.zeros(prob.shape))
+        rc = P.poisson_solve(h, dev(prob.rho), dev(prob.b), p, tol)
+        st = P.poisson_get_stats(h)
+        hist = P.poisson_get_history(h)
+    finally:
+        P.poisson_destroy(h)
+    st["code"] = rc
+    return host(p), st, hist
+
+
+def _check(prob, p, st, ref, coef=0, tol=1e-10, ref_bound=0.0):
+    res = oracle.residual(prob.rho, prob.b, p, prob.lengths, coef, bcx=oracle.BC_WALLS_X)
+    assert st["code"] == P.POISSON_OK, st
+    assert res["rel"] <= tol, res
+    assert abs(st["rel_resid"] - res["rel"]) <= 1e-3 * res["rel"] + 1e-15
+    err = rel_l2(p, ref)
+    assert err <= st["err_bound_rel"] * (1 + 1e-6) + ref_bound + 1e-14, (err, st["err_bound_rel"], ref_bound)
+    assert err <= 1e-8
+    assert abs(p.mean()) <= 1e-12 * np.max(np.abs(p))
+
+
+@pytest.mark.parametrize("coef,weight", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("shape", [(24, 12, 48), (12, 8, 64)])
+def test_solve_walls_fp64_matches_oracle(shape, coef, weight):
+    """Same iterates as the oracle's Thomas-based iteration: equal iteration
+    counts and residual histories."""
+    announce("solve walls fp64", shape, coef, weight)
+    prob = inputs.small_problem(shape=shape, lengths=(5.0, 3.0, TWO_PI))
+    b = oracle.BC_WALLS_X
+    ref = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, coef=coef, weight=weight, tol=1e-13, bcx=b)
+    lit = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, coef=coef, weight=weight, tol=1e-10, bcx=b)
+    p, st, hist = _solve_gpu(prob, coef=coef, weight=weight)
+    _check(prob, p, st, ref["p"], coef)
+    assert st["iters"] == lit["iters"]
+    assert np.allclose(hist, lit["history"], rtol=1e-6, atol=1e-14)
+
+
+@pytest.mark.parametrize("shape", [(12, 8, 48), (24, 12, 64), (16, 8, 128), (8, 6, 256), (6, 4, 512)])
+def test_solve_walls_fp32_refine_matches_oracle(shape):
+    """FP32 sweeps with FP64 refinement, through the fused outer residual (rows
+    of 64, 128, 256), the z-marching outer residual (512) and the gather (48)."""
+    announce("solve walls fp32", shape)
+    prob = inputs.small_problem(shape=shape, lengths=(5.0, 3.0, TWO_PI), ratio=4.0)
+    b = oracle.BC_WALLS_X
+    ref = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, tol=1e-14, max_iter=60, allow_noconv=True, bcx=b)
+    rr = oracle.residual(prob.rho, prob.b, ref["p"], prob.lengths, bcx=b)
+    ref_bound = oracle.error_bound(prob.shape, prob.lengths, float(prob.rho.max()), rr["r_norm"], bcx=b) / \
+        np.linalg.norm(ref["p"])
+    p, st, _ = _solve_gpu(prob, precision=P.POISSON_FP32_REFINE)
+    _check(prob, p, st, ref["p"], ref_bound=ref_bound)
+
+
+def test_walls_and_periodic_differ():
+    """The flag reaches the kernels: the same fields give different answers."""
+    announce("walls vs periodic")
+    prob = inputs.small_problem(shape=(8, 8, 64), lengths=(TWO_PI,) * 3)
+    pw, stw, _ = _solve_gpu(prob)
+    h = P.poisson_create(prob.shape, prob.lengths)
+    try:
+        pp = dev(np.zeros(prob.shape))
+        assert P.poisson_solve(h, dev(prob.rho), dev(prob.b), pp, 1e-10) == P.POISSON_OK
+    finally:
+        P.poisson_destroy(h)
+    assert stw["code"] == P.POISSON_OK
+    assert rel_l2(host(pp), pw) > 1e-3
+
+
+@pytest.mark.parametrize("precision", [P.POISSON_FP64, P.POISSON_FP32_REFINE])
+def test_full_size_duct(precision):
+    """The 512x256x256 duct at full size: the oracle's O(n) residual of the GPU
+    answer <= 1e-10 and the a-posteriori bound on the error."""
+    announce("full size duct 512x256x256", precision)
+    prob = inputs.workload_duct(256)
+    p, st, _ = _solve_gpu(prob, precision=precision)
+    res = oracle.residual(prob.rho, prob.b, p, prob.lengths, bcx=oracle.BC_WALLS_X)
+    assert st["code"] == P.POISSON_OK
+    assert res["rel"] <= 1e-10
+    assert abs(st["rel_resid"] - res["rel"]) <= 1e-3 * res["rel"]
+    assert st["err_bound_rel"] < 1e-8
