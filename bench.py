@@ -55,7 +55,7 @@ def percentile(xs, q):
     return xs[f] + (xs[c] - xs[f]) * (k - f)
 
 
-def time_path(P, torch, prob, precision, steps, warmup, tol):
+def time_path(P, torch, prob, precision, steps, warmup, tol, bc_x=0):
     """Warm up, then time `steps` solves from p = 0.  Inside the timed region
     every launch of the path's residual sweep P1 (the dominant kernel) is
     bracketed by HIP events on the solver's stream (poisson_kernel_timer)."""
@@ -63,7 +63,7 @@ def time_path(P, torch, prob, precision, steps, warmup, tol):
     rho = torch.from_numpy(prob.rho).cuda()
     b = torch.from_numpy(prob.b).cuda()
     p = torch.zeros(prob.shape, dtype=torch.float64, device="cuda")
-    s = P.Solver(prob.shape, prob.lengths, precision=precision)
+    s = P.Solver(prob.shape, prob.lengths, precision=precision, bc_x=bc_x)
     stats = None
     for _ in range(warmup):
         p.zero_()
@@ -259,6 +259,15 @@ def main():
         "paths": {"fp64": fp64, "fp32_refine": fp32},
         "roofline": roofline,
     }
+    # the inflow-outflow duct: zero-flux walls at the x ends, cosine transform along x
+    duct = inputs.workload_duct(args.size)
+    dsteps, dwarm = max(5, args.steps // 5), max(1, args.warmup // 2)
+    line["duct"] = {"workload": f"{2 * args.size}x{args.size}x{args.size} duct, walls in x, lognormal rho "
+                                f"(max/min 4), band-limited b, tol {args.tol:g}",
+                    "fp64": time_path(P, torch, duct, P.POISSON_FP64, dsteps, dwarm, args.tol, P.POISSON_BC_WALLS_X),
+                    "fp32_refine": time_path(P, torch, duct, P.POISSON_FP32_REFINE, dsteps, dwarm, args.tol,
+                                             P.POISSON_BC_WALLS_X)}
+    del duct
     if args.large:
         big = inputs.workload3(512)
         line["large"] = {"workload": "512^3 particle-deposit rho (ratio 10), band-limited b, tol 1e-10",

@@ -3,6 +3,7 @@
 calibrates the HBM byte counters.
 
     python -m paper_1601_05448_amd.profile_driver --size 256 --reps 5
+    python -m paper_1601_05448_amd.profile_driver --size 256 --duct   # 2N x N x N, walls in x
 """
 import argparse
 import os
@@ -20,6 +21,8 @@ def main():
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--paths", default="fp64,fp32")
     ap.add_argument("--inner-tols", default="", help="comma list: extra FP32+refine solves at these inner tolerances")
+    ap.add_argument("--duct", action="store_true", help="the duct workload with walls in x instead of the cube")
+    ap.add_argument("--periodic", action="store_true", help="with --duct: periodic in x instead of walls")
     args = ap.parse_args()
 
     import torch
@@ -28,13 +31,14 @@ def main():
     from paper_1601_05448_amd import poisson as P
 
     torch.cuda.set_device(0)
-    prob = inputs.workload2(args.size)
+    prob = inputs.workload_duct(args.size) if args.duct else inputs.workload2(args.size)
+    bc_x = P.POISSON_BC_WALLS_X if args.duct and not args.periodic else P.POISSON_BC_PERIODIC
     rho = torch.from_numpy(prob.rho).cuda()
     b = torch.from_numpy(prob.b).cuda()
     p = torch.zeros(prob.shape, dtype=torch.float64, device="cuda")
     for name in args.paths.split(","):
         prec = P.POISSON_FP64 if name == "fp64" else P.POISSON_FP32_REFINE
-        with P.Solver(prob.shape, prob.lengths, precision=prec) as s:
+        with P.Solver(prob.shape, prob.lengths, precision=prec, bc_x=bc_x) as s:
             fp32 = prec == P.POISSON_FP32_REFINE
             for sw in (1, 2, 3, 5, 6) if fp32 else (1, 2, 3, 5):
                 ms = P.poisson_time_sweep(s.h, sw, fp32 and sw != 6, rho, b, p, args.reps)
@@ -43,7 +47,7 @@ def main():
             st = s.solve(rho, b, p, 1e-10)
             print(f"{name} solve: {st['ms']:.3f} ms iters {st['iters']} outer {st['outer_iters']}", flush=True)
     for it in (float(v) for v in args.inner_tols.split(",") if v):
-        with P.Solver(prob.shape, prob.lengths, precision=P.POISSON_FP32_REFINE, inner_tol=it) as s:
+        with P.Solver(prob.shape, prob.lengths, precision=P.POISSON_FP32_REFINE, inner_tol=it, bc_x=bc_x) as s:
             for _ in range(3):
                 p.zero_()
                 st = s.solve(rho, b, p, 1e-10)
