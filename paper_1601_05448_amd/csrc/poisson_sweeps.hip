@@ -5,6 +5,7 @@
 //                     gather, for rows that do not fill whole waves)
 //   P2 k_dht_cols     Hartley along y of W (also P4: the transform is self-inverse)
 //   P3 k_dht_z_solve  Hartley along z, divide by n * symbol, Hartley along z
+//                     (taken as FFT, scaling of the separated spectra, inverse FFT)
 //   P5 k_dhtx_update  Hartley along x, p += dp (minus the mean of p)
 // With walls in x (GridArgs::bcx) P1 and P5 take the cosine transform along x
 // instead of the Hartley transform; P2-P4 are the same.
@@ -473,16 +474,33 @@ k_dht_cols(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) {
 }
 
 // ---- P3: Hartley along z, divide by n * symbol, Hartley along z ----------------
+// The z symbol is even in k_z, so Hartley-scale-Hartley equals an FFT, a scaling
+// of each packed row's spectrum, and an inverse FFT: the two rows of a pair
+// (x wavenumbers 2m and 2m+1, symbols s_a and s_b) are separated as
+// A_k = (Z_k + conj Z_{N-k})/2 and i B_k = (Z_k - conj Z_{N-k})/2, so the scaled
+// spectrum is Z'_k = (s_a + s_b)/2 Z_k + (s_a - s_b)/2 conj Z_{N-k}; the inverse is
+// taken as conj(FFT(conj Z')), which needs no exchange of (k, N-k) partners.
+template <typename T>
+__device__ __forceinline__ cpx<T> scaled_conj(cpx<T> zk, cpx<T> zm, T sa, T sb) {
+    const T hp = T(0.5) * (sa + sb), hm = T(0.5) * (sa - sb);
+    return {hp * zk.x + hm * zm.x, hm * zm.y - hp * zk.y};  // conj(hp Z_k + hm conj Z_{N-k})
+}
+
 template <typename T, int N, int MODE>
 __global__ void __launch_bounds__((LineCfg<T, N>::NT), 2)
 k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) {
     using C = LineCfg<T, N>;
     __shared__ cpx<T> lds[C::L * C::LS];
     __shared__ cpx<T> tw[N];
+    // the z symbol of the register path, in LDS: a global load of it after the
+    // next group's prefetch would make the wait for it a wait for the prefetch
+    __shared__ T lzs[N == 256 ? N : 1];
     const Slot& s = slots[blockIdx.y];
     if (MODE == 0 && IterView<T>::skip(s.st, stage)) return;
     const cpx<T>* twg = twiddles<T>(tb, 2);
     for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
+    if constexpr (N == 256)
+        for (int e = threadIdx.x; e < N; e += C::NT) lzs[e] = symbol<T>(tb, 2)[e];
     POIS_GLOBAL T* Wc = MODE == 0 ? IterView<T>(s).W : (POIS_GLOBAL T*)gptr(s.W);  // complex-indexed
     const unsigned nlines = (unsigned)(g.nxh * g.ny);
     const unsigned ngroups = (nlines + C::L - 1) / C::L;
@@ -528,22 +546,18 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
 #pragma unroll
             for (int b = 0; b < 16; ++b) {
                 const int k = e0 + 16 * b;
-                cpx<T> h = hartley(v[b], ln[C::pos((N - k) & (N - 1))]);
-                const T lzk = lamz[k];
-                h.x *= inv_symbol(lxe, lyj, lzk, nn);
-                h.y *= inv_symbol(lxo, lyj, lzk, nn);
-                v[b] = h;  // the second transform's input x[e0 + 16 b]
+                const T lzk = lzs[k];
+                // the second transform's input x[e0 + 16 b]
+                v[b] = scaled_conj(v[b], ln[C::pos((N - k) & (N - 1))], inv_symbol(lxe, lyj, lzk, nn),
+                                   inv_symbol(lxo, lyj, lzk, nn));
             }
             __syncthreads();
             fft256_regs<T>(v, ln, e0, tw);
-#pragma unroll
-            for (int b = 0; b < 16; ++b) ln[C::pos(e0 + 16 * b)] = v[b];
-            __syncthreads();
             if (cur_valid) {
 #pragma unroll
                 for (int b = 0; b < 16; ++b) {
                     const int k = e0 + 16 * b;
-                    gstore_c(Wc, cur_base + (unsigned)k * se, hartley(v[b], ln[C::pos((N - k) & (N - 1))]));
+                    gstore_c(Wc, cur_base + (unsigned)k * se, cpx<T>{v[b].x, -v[b].y});
                 }
             }
             grp = ng;
@@ -565,18 +579,15 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
         if (ng < ngroups) load(ng, valid, base);  // in flight during the two FFTs
         __syncthreads();
         fft_block_lines<T, N>(lds, tw);
-        // Hartley coefficients of the pairs (k, N-k) of this thread's line, scaled by 1/(n lambda)
+        // scaled spectra of the pairs (k, N-k) of this thread's line (the symbol is
+        // even in k), conjugated for the inverse
         for (int k = e0; k <= N / 2; k += C::TT) {
             const int km = (k == 0) ? 0 : N - k;
             const cpx<T> zk = lds[l * C::LS + C::pos(k)], zm = lds[l * C::LS + C::pos(km)];
-            cpx<T> hk = hartley(zk, zm), hm = hartley(zm, zk);
-            const T lzk = lamz[k], lzm = lamz[km];
-            hk.x *= inv_symbol(lxe, lyj, lzk, nn);
-            hk.y *= inv_symbol(lxo, lyj, lzk, nn);
-            hm.x *= inv_symbol(lxe, lyj, lzm, nn);
-            hm.y *= inv_symbol(lxo, lyj, lzm, nn);
-            lds[l * C::LS + C::pos(k)] = hk;
-            lds[l * C::LS + C::pos(km)] = hm;
+            const T lzk = lamz[k];
+            const T sa = inv_symbol(lxe, lyj, lzk, nn), sb = inv_symbol(lxo, lyj, lzk, nn);
+            lds[l * C::LS + C::pos(k)] = scaled_conj(zk, zm, sa, sb);
+            lds[l * C::LS + C::pos(km)] = scaled_conj(zm, zk, sa, sb);
         }
         __syncthreads();
         fft_block_lines<T, N>(lds, tw);
@@ -584,8 +595,8 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
 #pragma unroll
             for (int it = 0; it < C::IT; ++it) {
                 const int idx = e0 + it * C::TT;
-                gstore_c(Wc, cur_base + (unsigned)idx * se,
-                         hartley(lds[l * C::LS + C::pos(idx)], lds[l * C::LS + C::pos((idx == 0 ? 0 : N - idx))]));
+                const cpx<T> r = lds[l * C::LS + C::pos(idx)];
+                gstore_c(Wc, cur_base + (unsigned)idx * se, cpx<T>{r.x, -r.y});
             }
         }
         grp = ng;
