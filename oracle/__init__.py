@@ -81,6 +81,8 @@ def _configure(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_dense_bc.argtypes = grid + [i, i, pd, pd, pd]
     lib.oracle_error_bound_bc.argtypes = grid + [i, d, d]
     lib.oracle_error_bound_bc.restype = d
+    lib.oracle_divergence.argtypes = grid + [i, pd, pd, pd, pd, pd]
+    lib.oracle_project.argtypes = grid + [i, i, pd, pd, pd, pd, pd, d, pd, d, i, pi, pdd, pdd]
     return lib
 
 
@@ -215,3 +217,39 @@ def dense(rho, b, lengths=(2 * np.pi,) * 3, coef: int = COEF_RHO_FACE_MEAN, bcx:
 def error_bound(shape, lengths, rho_max: float, r_norm: float, bcx: int = BC_PERIODIC) -> float:
     """Upper bound on ||p - p*||_2 from ||r||_2, valid in both coefficient modes."""
     return _load().oracle_error_bound_bc(*_grid(shape, lengths), bcx, rho_max, r_norm)
+
+
+def divergence(rho, mx, my, mz, lengths=(2 * np.pi,) * 3, coef: int = COEF_RHO_FACE_MEAN) -> np.ndarray:
+    """div(u) of face momentum m (m_d[c] on the face between c and c + e_d),
+    u = m / rho_face with 1/rho_face the operator's face coefficient; periodic
+    (appendix A, the divergence of the predicted momentum over rho)."""
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    shape = rho.shape
+    ms = [_f64(m, shape) for m in (mx, my, mz)]
+    out = np.empty(shape)
+    _check(_load().oracle_divergence(*_grid(shape, lengths), coef, _ptr(rho), *(_ptr(m) for m in ms), _ptr(out)),
+           "divergence")
+    return out
+
+
+def project(rho, mx, my, mz, rhs_div, c_dt: float, p0=None, lengths=(2 * np.pi,) * 3,
+            coef: int = COEF_RHO_FACE_MEAN, weight: int = WEIGHT_RHO, tol: float = 1e-13,
+            max_iter: int = 10000):
+    """One pressure projection (appendix A): RHS^Pois from the predicted face
+    momentum and the divergence target, chi from its mean, the solve, and the
+    momentum correction -C dt grad p.  Returns dict(p, mx, my, mz, chi, iters,
+    rel, code); the inputs are not modified."""
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    shape = rho.shape
+    ms = [np.array(m, dtype=np.float64, order="C", copy=True) for m in (mx, my, mz)]
+    for m in ms:
+        if m.shape != shape:
+            raise ValueError("momentum shape")
+    rd = _f64(rhs_div, shape)
+    p = np.zeros(shape) if p0 is None else np.array(p0, dtype=np.float64, order="C", copy=True)
+    it, rel, chi = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+    rc = _load().oracle_project(*_grid(shape, lengths), coef, weight, _ptr(rho), *(_ptr(m) for m in ms), _ptr(rd),
+                                float(c_dt), _ptr(p), tol, max_iter, ctypes.byref(it), ctypes.byref(rel),
+                                ctypes.byref(chi))
+    _check(rc, "project", allow=(OK, ENOCONV))
+    return dict(p=p, mx=ms[0], my=ms[1], mz=ms[2], chi=chi.value, iters=it.value, rel=rel.value, code=rc)

@@ -706,4 +706,84 @@ double oracle_error_bound(int nx, int ny, int nz, double hx, double hy, double h
     return oracle_error_bound_bc(nx, ny, nz, hx, hy, hz, 0, rho_max, r_norm);
 }
 
-int oracle_abi_version(void) { return 2; }
+/* ------------------------------------------------------------------------ */
+/* the projection step around the solve (appendix A)                        */
+/* ------------------------------------------------------------------------ */
+
+/* Face momentum m_d lives on the staggered faces (section "Spatial
+ * discretization"): m_d[c] is the normal momentum on the face between cell c
+ * and its neighbour c + e_d.  The face velocity is u = m / rho_face with
+ * 1 / rho_face = beta, the face coefficient of the operator, so that the
+ * divergence of beta times the face gradient of p is exactly A p.
+ *
+ * out = div(u):  out_c = sum_d ( beta_{c+1/2} m_d[c] - beta_{c-1/2} m_d[c-e_d] ) / h_d,
+ * periodic. */
+int oracle_divergence(int nx, int ny, int nz, double hx, double hy, double hz, int coef, const double* rho,
+                      const double* mx, const double* my, const double* mz, double* out) {
+    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || (coef != 0 && coef != 1) || !rho || !mx || !my || !mz ||
+        !out)
+        return OR_EINVAL;
+    const double h[3] = {hx, hy, hz};
+    const double* m[3] = {mx, my, mz};
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const size_t c = cell(nx, ny, i, j, k);
+                double acc = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    size_t cp, cm;
+                    const double bp = face_coef(nx, ny, nz, coef, 0, rho, i, j, k, d, +1, &cp);
+                    const double bm = face_coef(nx, ny, nz, coef, 0, rho, i, j, k, d, -1, &cm);
+                    acc += (bp * m[d][c] - bm * m[d][cm]) / h[d];
+                }
+                out[c] = acc;
+            }
+    return OR_OK;
+}
+
+/* One pressure projection of the time advance (appendix A), periodic box:
+ *   1. RHS^Pois = ( div(m~ / rho_face) - RHS^div ) / (C dt)
+ *   2. chi' = -mean(RHS^Pois), reported as chi = C dt chi' (the paper's chi)
+ *   3. solve div(beta grad p) = RHS^Pois + chi' with the paper's iteration
+ *      (oracle_solve_bc; p in/out, the previous pressure as the estimate p_g)
+ *   4. m_d <- m~_d - C dt (p_{c+e_d} - p_c) / h_d on every face
+ * Afterwards div(m / rho_face) = RHS^div - chi up to C dt times the residual
+ * of the solve.  c_dt is the product C_RK4^pre[k] dt.  mx, my, mz are in/out.
+ * Returns the solve's status (OR_OK, OR_ENOCONV, ...). */
+int oracle_project(int nx, int ny, int nz, double hx, double hy, double hz, int coef, int weight,
+                   const double* rho, double* mx, double* my, double* mz, const double* rhs_div, double c_dt,
+                   double* p, double tol, int max_iter, int* iters_out, double* rel_out, double* chi_out) {
+    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || !rho || !mx || !my || !mz || !rhs_div || !p ||
+        !(c_dt > 0.0) || !isfinite(c_dt))
+        return OR_EINVAL;
+    const size_t n = (size_t)nx * ny * nz;
+    double* b = malloc(n * sizeof(double));
+    if (!b) return OR_ENOMEM;
+    int rc = oracle_divergence(nx, ny, nz, hx, hy, hz, coef, rho, mx, my, mz, b);
+    if (rc != OR_OK) {
+        free(b);
+        return rc;
+    }
+    for (size_t c = 0; c < n; ++c) b[c] = (b[c] - rhs_div[c]) / c_dt;
+    if (chi_out) *chi_out = -c_dt * mean_of(b, n);
+    double bm;
+    rc = oracle_solve_bc(nx, ny, nz, hx, hy, hz, coef, 0, weight, rho, b, p, tol, max_iter, iters_out, rel_out, &bm,
+                         NULL);
+    free(b);
+    if (rc != OR_OK && rc != OR_ENOCONV) return rc;
+    const double h[3] = {hx, hy, hz};
+    double* m[3] = {mx, my, mz};
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const size_t c = cell(nx, ny, i, j, k);
+                for (int d = 0; d < 3; ++d) {
+                    size_t cp;
+                    (void)face_coef(nx, ny, nz, coef, 0, NULL, i, j, k, d, +1, &cp);
+                    m[d][c] -= c_dt * (p[cp] - p[c]) / h[d];
+                }
+            }
+    return rc;
+}
+
+int oracle_abi_version(void) { return 3; }

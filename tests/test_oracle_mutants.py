@@ -45,6 +45,12 @@ MUTANTS = {
                                     "const double b = -2.0 * a + c;"),
     "tridiagonal back substitution": ("x[i] = (x[i] - a * x[i + 1]) / dmod[i];",
                                       "x[i] = (x[i] + a * x[i + 1]) / dmod[i];"),
+    "divergence minus face": ("acc += (bp * m[d][c] - bm * m[d][cm]) / h[d];",
+                              "acc += (bp * m[d][c] - bm * m[d][cp]) / h[d];"),
+    "divergence target dropped": ("b[c] = (b[c] - rhs_div[c]) / c_dt;", "b[c] = b[c] / c_dt;"),
+    "chi sign": ("*chi_out = -c_dt * mean_of(b, n);", "*chi_out = c_dt * mean_of(b, n);"),
+    "momentum correction sign": ("m[d][c] -= c_dt * (p[cp] - p[c]) / h[d];",
+                                 "m[d][c] += c_dt * (p[cp] - p[c]) / h[d];"),
 }
 
 

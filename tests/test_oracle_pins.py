@@ -22,6 +22,12 @@ force:
   cg        conjugate gradients == iteration
   equivar   scaling rho -> c rho gives p -> c p; shifts; axis permutation
   bound     ||p - p*|| <= rho_max ||r|| / min_d 4 sin^2(pi/N_d)/h_d^2
+  walls     cosine modes, 1-D flux form, matrix invariants, dense (walls in x)
+  div       uniform velocity: 0; sine velocity: closed-form face difference;
+            div(beta grad p) == A p
+  project   chi == mean(RHS^div); div u_new == RHS^div - chi to the solve's
+            residual; correction == -C dt grad p; projecting twice changes
+            nothing; divergence-free input: p = 0
 """
 import math
 
@@ -587,7 +593,92 @@ def test_wall_pinv_against_dense():
     pin_wall_pinv_dense()
 
 
+# --------------------------------------------------------------------------
+# the projection step around the solve (appendix A)
+# --------------------------------------------------------------------------
+# Face momentum m_d[c] on the face between c and c + e_d; face velocity
+# u = beta m with beta the operator's face coefficient (1/rho_face).
+
+
+def _face_beta(rho, axis, coef=0):
+    """beta on the + faces along `axis` (numpy axis: 2 = x, 1 = y, 0 = z)."""
+    rn = np.roll(rho, -1, axis=axis)
+    return 2.0 / (rho + rn) if coef == 0 else 0.5 * (1.0 / rho + 1.0 / rn)
+
+
+def pin_divergence():
+    shape, L = (6, 8, 12), (5.0, 3.0, 2.0)
+    hx, hy, hz = _lengths_h(shape, L)
+    rng = np.random.default_rng(41)
+    rho = np.exp(rng.uniform(-1.0, 1.0, shape))
+    bx, by, bz = (_face_beta(rho, a) for a in (2, 1, 0))
+    # a uniform face velocity has no divergence, whatever rho
+    d = oracle.divergence(rho, 0.7 / bx, -1.3 / by, 2.1 / bz, L)
+    assert np.max(np.abs(d)) <= 1e-13 * (0.7 / hx + 1.3 / hy + 2.1 / hz)
+    # a sine velocity along each axis: the face difference is the closed form
+    # (sin(k x_{i+1/2}) - sin(k x_{i-1/2})) / h = 2 cos(k x_i) sin(k h / 2) / h
+    x, y, z = _coords(shape, L)
+    for axis, (c, h, Ld, beta) in {2: (x, hx, L[0], bx), 1: (y, hy, L[1], by), 0: (z, hz, L[2], bz)}.items():
+        kw = 2.0 * math.pi * 2 / Ld
+        u = np.broadcast_to(np.sin(kw * (c + 0.5 * h)), shape)
+        ms = [np.zeros(shape), np.zeros(shape), np.zeros(shape)]
+        ms[2 - axis] = u / beta
+        d = oracle.divergence(rho, *ms, L)
+        want = np.broadcast_to(2.0 * np.cos(kw * c) * math.sin(kw * h / 2.0) / h, shape)
+        assert np.max(np.abs(d - want)) <= 1e-12 * np.max(np.abs(want)), axis
+    # the divergence of beta times the face gradient of p is the operator A p
+    p = rng.standard_normal(shape)
+    g = [(np.roll(p, -1, axis=a) - p) / h for a, h in ((2, hx), (1, hy), (0, hz))]
+    for coef in (0, 1):
+        d = oracle.divergence(rho, *g, L, coef=coef)
+        a = oracle.apply(rho, p, L, coef)
+        assert np.max(np.abs(d - a)) <= 1e-12 * np.max(np.abs(a)), coef
+
+
+def test_divergence_closed_forms():
+    pin_divergence()
+
+
+def pin_project():
+    shape, L = (8, 6, 12), (5.0, 3.0, TWO_PI)
+    hx, hy, hz = _lengths_h(shape, L)
+    rng = np.random.default_rng(43)
+    rho = np.exp(rng.uniform(-0.8, 0.8, shape))
+    mx, my, mz, rd = (rng.standard_normal(shape) for _ in range(4))
+    c_dt, tol = 0.02, 1e-13
+    r = oracle.project(rho, mx, my, mz, rd, c_dt, lengths=L, tol=tol)
+    # chi: mean(div) = 0 on the periodic box (the face sums telescope), so
+    # chi = -C dt mean(RHS^Pois) = mean(RHS^div)
+    assert abs(r["chi"] - rd.mean()) <= 1e-12 * np.max(np.abs(rd))
+    # the corrected velocity meets the divergence target up to C dt times the
+    # solve's residual: || div u - (RHS^div - chi) || = C dt || b~ - A p ||
+    d = oracle.divergence(rho, r["mx"], r["my"], r["mz"], L)
+    b = (oracle.divergence(rho, mx, my, mz, L) - rd) / c_dt
+    bt = b - b.mean()
+    assert np.linalg.norm(d - (rd - r["chi"])) <= c_dt * 10 * tol * np.linalg.norm(bt)
+    # the correction is -C dt times the face gradient of the returned p
+    p = r["p"]
+    for m0, m1, a, h in ((mx, r["mx"], 2, hx), (my, r["my"], 1, hy), (mz, r["mz"], 0, hz)):
+        want = m0 - c_dt * (np.roll(p, -1, axis=a) - p) / h
+        assert np.max(np.abs(m1 - want)) <= 1e-13 * np.max(np.abs(want))
+    # projecting the projected field again: nothing left to correct
+    r2 = oracle.project(rho, r["mx"], r["my"], r["mz"], rd, c_dt, lengths=L, tol=tol)
+    assert np.max(np.abs(r2["p"])) <= 1e-9 * np.max(np.abs(p))
+    assert abs(r2["chi"] - r["chi"]) <= 1e-12 * np.max(np.abs(rd))
+    # a divergence-free prediction and a uniform target: p = 0, m unchanged
+    # (rho = 1, so that beta = 1 and every value is exact)
+    one = np.ones(shape)
+    u = [np.full(shape, v) for v in (0.5, 0.25, -1.0)]
+    r3 = oracle.project(one, *u, np.full(shape, 3.0), c_dt, lengths=L, tol=tol)
+    assert r3["iters"] == 0 and np.max(np.abs(r3["p"])) == 0.0 and r3["chi"] == 3.0
+    assert all(np.array_equal(r3[k], v) for k, v in zip(("mx", "my", "mz"), u))
+
+
+def test_projection_step():
+    pin_project()
+
+
 ALL_PINS = [pin_fft, pin_symbol, pin_order2, pin_flux1d, pin_matrix, pin_pinv,
             pin_const_one_iteration, pin_discrete_manufactured, pin_dense, pin_cg,
             pin_equivariance, pin_bound, pin_mean_removal, pin_gauge, pin_wall_modes, pin_wall_flux1d,
-            pin_wall_matrix, pin_wall_pinv_dense]
+            pin_wall_matrix, pin_wall_pinv_dense, pin_divergence, pin_project]
