@@ -183,6 +183,55 @@ def serve_mixed(P, torch, count, budget_gb):
     return out
 
 
+PROJ_CDT = 5e-4
+
+
+def time_projection(P, torch, prob, precision, steps, warmup, tol):
+    """The projection step around the solve (RHS from the divergence of the
+    predicted momentum, the solve from the previous pressure, momentum
+    correction): `steps` projections, each from the same predicted momentum and
+    p = 0, timed on the host around poisson_project (which blocks); the copy
+    that restores the predicted momentum is outside the timed calls."""
+    from paper_1601_05448_amd import inputs
+
+    rho = torch.from_numpy(prob.rho).cuda()
+    m_np = inputs.momentum_fields(prob.shape, prob.lengths)
+    m0 = [torch.from_numpy(x).cuda() for x in m_np[:3]]
+    rd = torch.from_numpy(m_np[3]).cuda()
+    m = [x.clone() for x in m0]
+    p = torch.zeros(prob.shape, dtype=torch.float64, device="cuda")
+    out = torch.empty_like(p)
+    with P.Solver(prob.shape, prob.lengths, precision=precision) as s:
+        total, lat, st = 0.0, [], None
+        for it in range(warmup + steps):
+            for a, b in zip(m, m0):
+                a.copy_(b)
+            p.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rc, chi = P.poisson_project(s.h, rho, *m, rd, PROJ_CDT, p, tol)
+            dt = time.perf_counter() - t0
+            st = P.poisson_get_stats(s.h)
+            if it >= warmup:
+                total += dt
+                lat.append(dt * 1e3)
+        # the divergence kernel alone: 32 B/cell read (rho and three momentum
+        # components), 8 B/cell written
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        P.poisson_divergence(s.h, rho, *m, out)
+        e0.record()
+        reps = 10
+        for _ in range(reps):
+            P.poisson_divergence(s.h, rho, *m, out)
+        e1.record()
+        torch.cuda.synchronize()
+        div_ms = e0.elapsed_time(e1) / reps
+    return dict(projections_per_s=steps / total, ms_per_projection=total * 1e3 / steps,
+                p50_ms=percentile(lat, 0.5), p99_ms=percentile(lat, 0.99), iters=st["iters"],
+                outer_iters=st["outer_iters"], solve_ms=st["ms"], chi=chi,
+                divergence_kernel=dict(ms=div_ms, bytes=40 * prob.n, gbs=40 * prob.n / div_ms / 1e6))
+
+
 def cpu_baseline(prob, fp64_iters):
     """The oracle (single-threaded C, FP64) on a bounded sample of the same
     workload: one residual evaluation plus one iteration, scaled to the
@@ -259,6 +308,13 @@ def main():
         "paths": {"fp64": fp64, "fp32_refine": fp32},
         "roofline": roofline,
     }
+    # the projection step around the solve (same density), both paths
+    psteps, pwarm = max(5, args.steps // 5), max(1, args.warmup // 2)
+    line["projection"] = {"workload": f"{args.size}^3 lognormal rho, band-limited face momentum and divergence "
+                                      f"target, C dt {PROJ_CDT:g}, tol {args.tol:g}",
+                          "fp64": time_projection(P, torch, prob, P.POISSON_FP64, psteps, pwarm, args.tol),
+                          "fp32_refine": time_projection(P, torch, prob, P.POISSON_FP32_REFINE, psteps, pwarm,
+                                                         args.tol)}
     # the inflow-outflow duct: zero-flux walls at the x ends, cosine transform along x
     duct = inputs.workload_duct(args.size)
     dsteps, dwarm = max(5, args.steps // 5), max(1, args.warmup // 2)

@@ -185,6 +185,41 @@ int poisson_lap_pinv(poisson_t h, const double* q, double* delta);
 int poisson_time_sweep(poisson_t h, int sweep, int fp32, const double* rho, const double* b, double* p, int reps,
                        double* avg_ms);
 
+/* ---- the projection step around the solve ---------------------------------
+ * Appendix A, time advance: the momentum predicted without the pressure
+ * gradient is divided by the new density, its divergence gives the right-hand
+ * side of the variable-coefficient Poisson equation (with the consistency
+ * constant chi from its mean), and after the solve the momentum is corrected
+ * by the pressure gradient.  Periodic box only (a handle with
+ * POISSON_BC_WALLS_X gets POISSON_EINVAL).
+ *
+ * Face momentum: mx, my, mz are device FP64 arrays [nz][ny][nx] like the
+ * cell fields; m_d[c] is the normal momentum on the face between cell c and
+ * its neighbour c + e_d (periodic).  The face velocity is u = beta m, with
+ * beta the handle's face coefficient (the 1/rho_face of the operator), so
+ * that the divergence of beta times the face gradient of p is A p. */
+
+/* out_c = sum_d ( beta_{c+1/2} m_d[c] - beta_{c-1/2} m_d[c - e_d] ) / h_d:
+ * the divergence of the face velocity.  All pointers device FP64 fields;
+ * out must not alias the inputs.  Blocks until done. */
+int poisson_divergence(poisson_t h, const double* rho, const double* mx, const double* my, const double* mz,
+                       double* out);
+
+/* One pressure projection.  c_dt = C_RK4^pre[k] * dt > 0 of the substep;
+ * rhs_div = RHS^div, the divergence the new velocity must have (cell field).
+ *   RHS^Pois = ( div(beta m) - RHS^div ) / c_dt
+ *   solve A p = RHS^Pois - mean(RHS^Pois) as poisson_solve does (p in/out:
+ *     the previous pressure is the estimate p_g; tol as in poisson_solve)
+ *   m_d <- m_d - c_dt (p_{c+e_d} - p_c) / h_d     (mx, my, mz in/out)
+ * *chi (host pointer, may be NULL) receives chi = -c_dt mean(RHS^Pois), so
+ * that afterwards div(beta m) = RHS^div - chi up to c_dt times the solve's
+ * residual.  Returns the solve's status; on POISSON_OK and POISSON_ENOCONV the
+ * momentum is corrected, on any other status it and p are untouched.
+ * poisson_get_stats describes the solve.  The six fields must not overlap.
+ * The first call allocates one cell field of workspace in the handle. */
+int poisson_project(poisson_t h, const double* rho, double* mx, double* my, double* mz, const double* rhs_div,
+                    double c_dt, double* p, double tol, double* chi);
+
 /* ---- serving: many independent solves of different sizes -----------------
  * A server keeps each admitted request's rho, b, p and iteration state on the
  * device, groups requests of equal grid size into batches that advance

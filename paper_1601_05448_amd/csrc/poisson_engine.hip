@@ -403,6 +403,7 @@ struct poisson_s {
     SweepTimer timer;            // events around one sweep kind inside solves
     double timer_ms = 0.0;       // summed bracketed time since the timer was set
     long long timer_launches = 0;
+    double* proj_b = nullptr;    // right-hand side built by poisson_project (allocated at its first call)
 };
 
 extern "C" {
@@ -437,6 +438,7 @@ void poisson_destroy(poisson_t h) {
     if (h->run) (void)hipStreamDestroy(h->run);
     h->ws.release();
     h->tables.release();
+    if (h->proj_b) (void)hipFree(h->proj_b);
     delete h;
 }
 
@@ -640,6 +642,40 @@ int poisson_kernel_timer_read(poisson_t h, double* total_ms, long long* launches
     *total_ms = h->timer_ms;
     *launches = h->timer_launches;
     return POISSON_OK;
+}
+
+int poisson_divergence(poisson_t h, const double* rho, const double* mx, const double* my, const double* mz,
+                       double* out) {
+    if (!h || !rho || !mx || !my || !mz || !out || h->g.bcx != 0) return POISSON_EINVAL;
+    int rc = hip_status(launch_divergence(h->g, rho, mx, my, mz, nullptr, 1.0, out, h->stream));
+    if (rc != POISSON_OK) return rc;
+    return hip_status(hipStreamSynchronize(h->stream));
+}
+
+int poisson_project(poisson_t h, const double* rho, double* mx, double* my, double* mz, const double* rhs_div,
+                    double c_dt, double* p, double tol, double* chi) {
+    if (!h || !rho || !mx || !my || !mz || !rhs_div || !p || h->g.bcx != 0) return POISSON_EINVAL;
+    if (!(c_dt > 0.0) || !std::isfinite(c_dt) || !(tol > 0.0) || !std::isfinite(tol)) return POISSON_EINVAL;
+    const size_t bytes = (size_t)h->g.n * sizeof(double);
+    const void* f[7] = {rho, mx, my, mz, rhs_div, p, nullptr};
+    for (int a = 0; a < 6; ++a)
+        for (int b = a + 1; b < 6; ++b)
+            if (overlaps(f[a], f[b], bytes)) return POISSON_EINVAL;
+    if (!h->proj_b && hipMalloc(&h->proj_b, bytes) != hipSuccess) {
+        h->proj_b = nullptr;
+        return POISSON_ENOMEM;
+    }
+    // RHS^Pois on the caller's stream; the solve orders itself after it
+    int rc = hip_status(launch_divergence(h->g, rho, mx, my, mz, rhs_div, c_dt, h->proj_b, h->stream));
+    if (rc != POISSON_OK) return rc;
+    rc = poisson_solve(h, rho, h->proj_b, p, tol);
+    if (rc != POISSON_OK && rc != POISSON_ENOCONV) return rc;  // momentum untouched
+    if (chi) *chi = -c_dt * h->stats.b_mean_removed;
+    // the solve has finished (poisson_solve waits for it): correct the momentum
+    const int rc2 = hip_status(launch_correct(h->g, p, mx, my, mz, c_dt, h->stream));
+    if (rc2 != POISSON_OK) return rc2;
+    const int rc3 = hip_status(hipStreamSynchronize(h->stream));
+    return rc3 != POISSON_OK ? rc3 : rc;
 }
 
 int poisson_lap_pinv(poisson_t h, const double* q, double* delta) {

@@ -171,4 +171,11 @@ hipError_t launch_residual(const GridArgs& g, const Geometry& geo, const Slot* s
 hipError_t launch_lap_pinv(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slot,
                            hipStream_t s);
 
+// The projection step around the solve (poisson_project.hip): out = div(beta m)
+// (rhs == nullptr) or (div(beta m) - rhs) / c_dt; m_d -= c_dt grad_d p.
+hipError_t launch_divergence(const GridArgs& g, const double* rho, const double* mx, const double* my,
+                             const double* mz, const double* rhs, double c_dt, double* out, hipStream_t s);
+hipError_t launch_correct(const GridArgs& g, const double* p, double* mx, double* my, double* mz, double c_dt,
+                          hipStream_t s);
+
 }  // namespace pois

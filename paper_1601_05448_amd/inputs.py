@@ -27,6 +27,9 @@ the gas, hot gas is light, section "Motivation and objectives"):
      long in x as the box that feeds it), rho lognormal band-limited with
      max/min = 4, b band-limited; solved with zero-flux walls at the x ends.
      The fields are drawn as periodic ones; the walls only change the operator.
+  7  projection step: the predicted face momentum (three band-limited fields,
+     |k| <= 8) and the divergence target (band-limited, scaled by 0.1) on the
+     grid and density of the workload it accompanies; C dt = 5e-4.
 """
 from __future__ import annotations
 
@@ -268,6 +271,17 @@ def workload_duct(n: int = 256, ratio: float = 4.0, kmax: float = 8.0) -> Proble
     rho = contrast_exp(s, ratio)
     b = bandlim(shape, L, kmax, rng)
     return Problem(f"duct lognormal-rho {2 * n}x{n}x{n} ratio {ratio:g}", shape, L, rho, b)
+
+
+def momentum_fields(shape: Sequence[int], lengths: Sequence[float], kmax: float = 8.0,
+                    target_scale: float = 0.1, seed: int = 7):
+    """Inputs of one pressure projection: the predicted face momentum (three
+    band-limited fields, one per face direction) and the divergence target
+    RHS^div (band-limited, scaled by `target_scale`)."""
+    rng = np.random.default_rng(workload_seed(7) * 1000 + seed)
+    mx, my, mz = (bandlim(shape, lengths, kmax, rng) for _ in range(3))
+    rhs_div = target_scale * bandlim(shape, lengths, kmax, rng)
+    return mx, my, mz, rhs_div
 
 
 SERVE_SIZES = (64, 96, 128, 192)

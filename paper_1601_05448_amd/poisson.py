@@ -96,6 +96,8 @@ def load() -> ctypes.CDLL:
     lib.poisson_time_sweep.argtypes = [vp, i, i, vp, vp, vp, i, pd]
     lib.poisson_kernel_timer.argtypes = [vp, i, i]
     lib.poisson_kernel_timer_read.argtypes = [vp, pd, ctypes.POINTER(ll)]
+    lib.poisson_divergence.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.poisson_project.argtypes = [vp, vp, vp, vp, vp, vp, d, vp, d, pd]
     if hasattr(lib, "poisson_server_create"):
         lib.poisson_server_create.argtypes = [ctypes.c_size_t, i, i, i, i, i, vp, ctypes.POINTER(vp)]
         lib.poisson_server_submit.argtypes = [vp, i, i, i, d, d, d, vp, vp, vp, d, ctypes.POINTER(ll)]
@@ -196,6 +198,23 @@ def poisson_lap_pinv(h: int, q, delta) -> None:
     rc = load().poisson_lap_pinv(h, _ptr(q), _ptr(delta))
     if rc != POISSON_OK:
         raise PoissonError(rc, "poisson_lap_pinv")
+
+
+def poisson_divergence(h: int, rho, mx, my, mz, out) -> None:
+    rc = load().poisson_divergence(h, _ptr(rho), _ptr(mx), _ptr(my), _ptr(mz), _ptr(out))
+    if rc != POISSON_OK:
+        raise PoissonError(rc, "poisson_divergence")
+
+
+def poisson_project(h: int, rho, mx, my, mz, rhs_div, c_dt: float, p, tol: float) -> tuple:
+    """One pressure projection; mx, my, mz and p in/out.  Returns (status, chi):
+    POISSON_OK or POISSON_ENOCONV (momentum corrected); other codes raise."""
+    chi = ctypes.c_double()
+    rc = load().poisson_project(h, _ptr(rho), _ptr(mx), _ptr(my), _ptr(mz), _ptr(rhs_div), float(c_dt), _ptr(p),
+                                float(tol), ctypes.byref(chi))
+    if rc not in (POISSON_OK, POISSON_ENOCONV):
+        raise PoissonError(rc, "poisson_project")
+    return rc, chi.value
 
 
 def poisson_time_sweep(h: int, sweep: int, fp32: bool, rho, b, p, reps: int) -> float:
