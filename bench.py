@@ -232,6 +232,60 @@ def time_projection(P, torch, prob, precision, steps, warmup, tol):
                 divergence_kernel=dict(ms=div_ms, bytes=40 * prob.n, gbs=40 * prob.n / div_ms / 1e6))
 
 
+def warm_chain_leg(P, torch, n, steps, tol):
+    """A chain of `steps` dependent solves with slowly evolving rho and b
+    (advected density, rotating right-hand side), each step from p = 0 (cold)
+    or from the previous solution (warm), both paths.  Inputs are generated on
+    the device before the timed region."""
+    from paper_1601_05448_amd import inputs
+
+    shape, L, fields = inputs.advected_chain_device(n, steps)
+    out = {}
+    for name, prec in (("fp64", P.POISSON_FP64), ("fp32_refine", P.POISSON_FP32_REFINE)):
+        res = {}
+        with P.Solver(shape, L, precision=prec) as s:
+            p = torch.zeros(shape, dtype=torch.float64, device="cuda")
+            s.solve(fields[0][0], fields[0][1], p, tol)  # warm-up
+            for warm in (False, True):
+                p.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                its = []
+                for rho, b in fields:
+                    if not warm:
+                        p.zero_()
+                    st = s.solve(rho, b, p, tol)
+                    its.append(st["iters"])
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                res["warm" if warm else "cold"] = dict(ms_per_solve=dt * 1e3 / steps, iters=its,
+                                                       mean_iters_after_first=sum(its[1:]) / max(1, steps - 1))
+        res["speedup"] = res["cold"]["ms_per_solve"] / res["warm"]["ms_per_solve"]
+        out[name] = res
+    del fields
+    return out
+
+
+def served_chains_leg(P, torch, n, chains, steps, tol):
+    """`chains` chains of `steps` solves each served at once through the
+    server (one request in flight per chain, the next submitted when the
+    previous is done), warm against cold; FP64."""
+    from paper_1601_05448_amd import inputs, serve
+
+    fields = [inputs.advected_chain_device(n, steps, chain=c) for c in range(chains)]
+    out = {}
+    for warm in (False, True):
+        cs = [serve.Chain(shape, L, st, torch.zeros(shape, dtype=torch.float64, device="cuda"), tol=tol, warm=warm)
+              for shape, L, st in fields]
+        with serve.Server(16 << 30, 64) as srv:
+            r = serve.run_chains(srv, cs)
+        its = [s["iters"] for ch in r.stats for s in ch[1:]]
+        out["warm" if warm else "cold"] = dict(solves_per_s=r.solves() / r.wall_s, wall_s=r.wall_s,
+                                               mean_iters_after_first=sum(its) / max(1, len(its)))
+    out["speedup"] = out["warm"]["solves_per_s"] / out["cold"]["solves_per_s"]
+    return out
+
+
 def cpu_baseline(prob, fp64_iters):
     """The oracle (single-threaded C, FP64) on a bounded sample of the same
     workload: one residual evaluation plus one iteration, scaled to the
@@ -315,6 +369,12 @@ def main():
                           "fp64": time_projection(P, torch, prob, P.POISSON_FP64, psteps, pwarm, args.tol),
                           "fp32_refine": time_projection(P, torch, prob, P.POISSON_FP32_REFINE, psteps, pwarm,
                                                          args.tol)}
+    # warm-start chains: slowly evolving rho and b, each solve from the previous answer
+    line["warm_chain"] = {"workload": f"{args.size}^3 chain of 12 solves, rho advected by half a cell per step, "
+                                      f"b rotating slowly, tol {args.tol:g}",
+                          **warm_chain_leg(P, torch, args.size, 12, args.tol)}
+    line["warm_chain"]["served"] = {"workload": "8 chains x 6 steps at 128^3 through the server, FP64",
+                                    **served_chains_leg(P, torch, 128, 8, 6, args.tol)}
     # the inflow-outflow duct: zero-flux walls at the x ends, cosine transform along x
     duct = inputs.workload_duct(args.size)
     dsteps, dwarm = max(5, args.steps // 5), max(1, args.warmup // 2)

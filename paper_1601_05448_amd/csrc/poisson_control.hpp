@@ -92,6 +92,12 @@ __device__ inline void decide_outer(const GridArgs& g, SolveState* st, const dou
         st->status = POISSON_ENOCONV;
     } else {
         st->rhs_mean32 = sums[4] * st->inv_s / (double)g.n;
+        // The update leaves an outer residual of about rel times the inner
+        // relative residual, so a step needs no more than tol / rel from its
+        // inner sweeps (with a margin of 3 for the FP32 evaluation); a step
+        // that starts close to the tolerance, as after a warm start, stops
+        // early instead of running to the inner tolerance.
+        st->inner_goal = fmax(st->inner_tol, 0.3 * st->tol / rel);
         st->stage = 1;
         st->inner_iter = 0;
         st->inner_done = 0;
@@ -120,7 +126,7 @@ __device__ inline void decide_inner(SolveState* st, const double* sums, int max_
     st->rel_in = rel;
     bool stop = false;
     if (!(rel < 1e8)) stop = true;  // non-finite or blown up: let the FP64 step judge
-    if (rel <= st->inner_tol) stop = true;
+    if (rel <= st->inner_goal) stop = true;
     if (rel < 0.9 * st->best_in) {
         st->best_in = rel;
         st->since_best = 0;

@@ -334,10 +334,10 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
                     const int k = h.inner_iter - 1;  // index of the last inner residual evaluated
                     if (k >= 1 && h.rel_in > 0.0 && h.rel_in < 1.0) {
                         const double rate = std::pow(h.rel_in, 1.0 / k);
-                        if (rate < 0.95) m = (int)std::ceil(std::log(h.inner_tol / h.rel_in) / std::log(rate) + 0.25);
+                        if (rate < 0.95) m = (int)std::ceil(std::log(h.inner_goal / h.rel_in) / std::log(rate) + 0.25);
                     }
                     need_open = std::max(need_open, std::max(m, 1));
-                    red = h.inner_tol;
+                    red = h.inner_goal;
                 } else {
                     need_full = std::max(need_full, h.inner_last - first);
                 }

@@ -33,6 +33,7 @@ struct SolveState {
     // parameters (init kernel)
     double tol;
     double inner_tol;
+    double inner_goal;  // inner stop of the current refinement step (decide_outer)
     int max_iter;
     int max_outer;
     int precision;

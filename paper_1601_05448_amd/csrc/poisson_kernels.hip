@@ -43,6 +43,7 @@ __global__ void __launch_bounds__(256) k_init(const Slot* __restrict__ slots, do
     if (threadIdx.x != 0) return;
     st->tol = slots[blockIdx.x].tol;
     st->inner_tol = inner_tol;
+    st->inner_goal = inner_tol;
     st->max_iter = max_iter;
     st->max_outer = max_outer;
     st->precision = precision;

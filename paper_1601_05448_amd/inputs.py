@@ -27,6 +27,9 @@ the gas, hot gas is light, section "Motivation and objectives"):
      long in x as the box that feeds it), rho lognormal band-limited with
      max/min = 4, b band-limited; solved with zero-flux walls at the x ends.
      The fields are drawn as periodic ones; the walls only change the operator.
+  8  warm-start chains: rho_t = exp(c s(x - U t)) with s band-limited and U half
+     a cell per step in x and a quarter in y, b_t = cos(0.02 t) b1 + sin(0.02 t) b2;
+     each solve of a chain starts from the previous solution.
   7  projection step: the predicted face momentum (three band-limited fields,
      |k| <= 8) and the divergence target (band-limited, scaled by 0.1) on the
      grid and density of the workload it accompanies; C dt = 5e-4.
@@ -57,8 +60,11 @@ def centres(n: int, length: float) -> np.ndarray:
 
 
 def _bandlim_spectrum(shape: Sequence[int], lengths: Sequence[float], kmax: float,
-                      rng: np.random.Generator):
-    """Random coefficients and 1-D synthesis factors of a band-limited field."""
+                      rng: np.random.Generator, shift: Optional[Sequence[float]] = None):
+    """Random coefficients and 1-D synthesis factors of a band-limited field;
+    `shift` = (sx, sy, sz) evaluates the same field at x - s (the coefficients
+    times exp(-i k.s)), so that fields drawn from equal seeds with growing shifts
+    are one field carried along by a uniform flow."""
     nz, ny, nx = shape
     lx, ly, lz = lengths
     mx = int(math.floor(kmax * lx / TWO_PI))
@@ -71,6 +77,8 @@ def _bandlim_spectrum(shape: Sequence[int], lengths: Sequence[float], kmax: floa
     kk = kx * kx + ky * ky + kz * kz
     mask = (kk <= kmax * kmax * (1 + 1e-12)) & (kk > 0)
     coef = (rng.standard_normal(mask.shape) + 1j * rng.standard_normal(mask.shape)) * mask
+    if shift is not None:
+        coef = coef * np.exp(-1j * (kx * shift[0] + ky * shift[1] + kz * shift[2]))
     ex = np.exp(1j * np.outer(TWO_PI * ax / lx, centres(nx, lx)))  # (2mx+1, nx)
     ey = np.exp(1j * np.outer(TWO_PI * ay / ly, centres(ny, ly)))  # (2my+1, ny)
     ez = np.exp(1j * np.outer(TWO_PI * az / lz, centres(nz, lz)))  # (2mz+1, nz)
@@ -106,7 +114,7 @@ def bandlim(shape: Sequence[int], lengths: Sequence[float], kmax: float,
 
 
 def bandlim_device(shape: Sequence[int], lengths: Sequence[float], kmax: float,
-                   rng: np.random.Generator, device="cuda"):
+                   rng: np.random.Generator, device="cuda", shift: Optional[Sequence[float]] = None):
     """bandlim with the same random draws, its last synthesis step (the z
     contraction, the only large one) done as a float64 torch matmul on
     `device`; returns a torch tensor.  Values agree with bandlim up to the
@@ -114,7 +122,7 @@ def bandlim_device(shape: Sequence[int], lengths: Sequence[float], kmax: float,
     import torch
 
     nz, ny, nx = shape
-    t2, ez = _bandlim_spectrum(shape, lengths, kmax, rng)
+    t2, ez = _bandlim_spectrum(shape, lengths, kmax, rng, shift)
     t2r = torch.from_numpy(np.ascontiguousarray(t2.real)).to(device)
     t2i = torch.from_numpy(np.ascontiguousarray(t2.imag)).to(device)
     ezr = torch.from_numpy(ez.real.T.copy()).to(device)
@@ -282,6 +290,37 @@ def momentum_fields(shape: Sequence[int], lengths: Sequence[float], kmax: float 
     mx, my, mz = (bandlim(shape, lengths, kmax, rng) for _ in range(3))
     rhs_div = target_scale * bandlim(shape, lengths, kmax, rng)
     return mx, my, mz, rhs_div
+
+
+def advected_chain_device(n: int = 256, steps: int = 12, ratio: float = 4.0, kmax: float = 8.0,
+                          shift_cells: Sequence[float] = (0.5, 0.25, 0.0), omega: float = 0.02,
+                          chain: int = 0, device="cuda"):
+    """A time series of solves whose inputs evolve slowly (workload 8): rho_t =
+    exp(c s(x - U t)), s band-limited (|k| <= kmax) and carried by a uniform
+    velocity U of `shift_cells` cells per step, c fixed by max/min rho_0 =
+    `ratio`; b_t = cos(omega t) b1 + sin(omega t) b2 with b1, b2 band-limited.
+    Generated on `device` (the last synthesis step as a matmul, see
+    bandlim_device).  Returns (shape, lengths, [(rho_t, b_t)]) as torch tensors."""
+    import torch
+
+    shape, L = (n, n, n), (TWO_PI,) * 3
+    h = TWO_PI / n
+    seed = workload_seed(8) * 1000 + chain
+    s0 = bandlim_device(shape, L, kmax, np.random.default_rng(seed), device)
+    c = math.log(ratio) / float(s0.max() - s0.min())
+    del s0
+    rng_b = np.random.default_rng(seed + 500)
+    b1 = bandlim_device(shape, L, kmax, rng_b, device)
+    b2 = bandlim_device(shape, L, kmax, rng_b, device)
+    out = []
+    for t in range(steps):
+        sh = tuple(v * h * t for v in shift_cells)
+        s = bandlim_device(shape, L, kmax, np.random.default_rng(seed), device, shift=sh)
+        rho = torch.exp(s * c).contiguous()
+        del s
+        b = (math.cos(omega * t) * b1 + math.sin(omega * t) * b2).contiguous()
+        out.append((rho, b))
+    return shape, L, out
 
 
 SERVE_SIZES = (64, 96, 128, 192)

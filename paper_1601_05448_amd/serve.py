@@ -116,3 +116,65 @@ def replay(server: Server, jobs: Sequence[Job], realtime: bool = True,
                 on_done(out)
     res.wall_s = time.perf_counter() - t0
     return res
+
+
+@dataclass
+class Chain:
+    """A time series of dependent solves on one grid: step t+1 starts from the
+    solution of step t (p is one device field, updated in place by each step;
+    warm=False zeroes it before every step instead)."""
+    shape: Sequence[int]
+    lengths: Sequence[float]
+    steps: Sequence[tuple]  # (rho_t, b_t) device fields
+    p: object
+    tol: float = 1e-10
+    warm: bool = True
+
+
+@dataclass
+class ChainResult:
+    stats: List[List[dict]] = field(default_factory=list)  # per chain, per step
+    wall_s: float = 0.0
+    ticks: int = 0
+
+    def solves(self) -> int:
+        return sum(len(s) for s in self.stats)
+
+
+def run_chains(server: Server, chains: Sequence[Chain]) -> ChainResult:
+    """Serve several chains at once: every chain has at most one request in
+    flight, and its next step is submitted as soon as the previous one is done
+    (with the same p, so the server starts it from the previous solution)."""
+    res = ChainResult(stats=[[] for _ in chains])
+    nxt = [0] * len(chains)
+    inflight: Dict[int, int] = {}
+
+    def submit(c: int) -> None:
+        ch = chains[c]
+        rho, b = ch.steps[nxt[c]]
+        if not ch.warm:
+            import torch
+
+            ch.p.zero_()
+            torch.cuda.current_stream().synchronize()  # the server reads p on its own streams
+        rid = server.submit(ch.shape, ch.lengths, rho, b, ch.p, ch.tol)
+        inflight[rid] = c
+        nxt[c] += 1
+
+    t0 = time.perf_counter()
+    for c in range(len(chains)):
+        if chains[c].steps:
+            submit(c)
+    while inflight:
+        server.tick()
+        res.ticks += 1
+        for rid in list(inflight):
+            st = server.poll(rid)
+            if st is None:
+                continue
+            c = inflight.pop(rid)
+            res.stats[c].append(st)
+            if nxt[c] < len(chains[c].steps):
+                submit(c)
+    res.wall_s = time.perf_counter() - t0
+    return res
