@@ -83,6 +83,8 @@ def _configure(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_error_bound_bc.restype = d
     lib.oracle_divergence.argtypes = grid + [i, pd, pd, pd, pd, pd]
     lib.oracle_project.argtypes = grid + [i, i, pd, pd, pd, pd, pd, d, pd, d, i, pi, pdd, pdd]
+    lib.oracle_deposit.argtypes = grid + [i, pd, pd, pd]
+    lib.oracle_interpolate.argtypes = grid + [i, pd, pd, pd]
     return lib
 
 
@@ -253,3 +255,28 @@ def project(rho, mx, my, mz, rhs_div, c_dt: float, p0=None, lengths=(2 * np.pi,)
                                 ctypes.byref(chi))
     _check(rc, "project", allow=(OK, ENOCONV))
     return dict(p=p, mx=ms[0], my=ms[1], mz=ms[2], chi=chi.value, iters=it.value, rel=rel.value, code=rc)
+
+
+def deposit(shape, pos, q=None, lengths=(2 * np.pi,) * 3) -> np.ndarray:
+    """P(q): particle values projected to the cell centres per unit volume with
+    trilinear (cloud-in-cell) weights, periodic (section "Physical model").
+    pos: (n_p, 3) positions (x, y, z); q: (n_p,) or None for ones."""
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    qq = None if q is None else np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+    if qq is not None and qq.size != pos.shape[0]:
+        raise ValueError("q length")
+    out = np.empty(tuple(shape))
+    _check(_load().oracle_deposit(*_grid(tuple(shape), lengths), pos.shape[0], _ptr(pos), _ptr(qq), _ptr(out)),
+           "deposit")
+    return out
+
+
+def interpolate(field, pos, lengths=(2 * np.pi,) * 3) -> np.ndarray:
+    """I(field)(x_p): trilinear interpolation of a cell-centred field at the
+    particle positions, periodic (section "Physical model")."""
+    field = np.ascontiguousarray(field, dtype=np.float64)
+    pos = np.ascontiguousarray(pos, dtype=np.float64).reshape(-1, 3)
+    out = np.empty(pos.shape[0])
+    _check(_load().oracle_interpolate(*_grid(field.shape, lengths), pos.shape[0], _ptr(pos), _ptr(field),
+                                      _ptr(out)), "interpolate")
+    return out

@@ -786,4 +786,73 @@ int oracle_project(int nx, int ny, int nz, double hx, double hy, double hz, int 
     return rc;
 }
 
-int oracle_abi_version(void) { return 3; }
+/* ------------------------------------------------------------------------ */
+/* particles and the grid: the linear projection P and interpolation I       */
+/* ------------------------------------------------------------------------ */
+
+/* The 1-D linear weights of a point x on a periodic line of n cells of width
+ * h, cell centres at (i + 1/2) h: with s = x/h - 1/2, i0 = floor(s), f = s - i0,
+ * the point gives weight 1 - f to cell i0 and f to cell i0 + 1 (both wrapped). */
+static void linear_weights(double x, int n, double h, int* i0, int* i1, double* w0, double* w1) {
+    const double s = x / h - 0.5;
+    const double fl = floor(s);
+    const double f = s - fl;
+    long long a = (long long)fl % n;
+    if (a < 0) a += n;
+    *i0 = (int)a;
+    *i1 = (int)((a + 1) % n);
+    *w0 = 1.0 - f;
+    *w1 = f;
+}
+
+/* out = P(q): the particles' values projected to the grid per unit volume
+ * (section "Physical model": P takes data from particle locations to the
+ * fluid grid, by a linear approximation; here the trilinear, cloud-in-cell,
+ * weights of the eight cells around each particle), periodic:
+ *     out_c = sum_p q_p W_x W_y W_z / (hx hy hz).
+ * pos: n_p rows (x, y, z) in physical units, any real value (wrapped);
+ * q: n_p values, or NULL for q = 1.  Particles are added in index order. */
+int oracle_deposit(int nx, int ny, int nz, double hx, double hy, double hz, int np, const double* pos,
+                   const double* q, double* out) {
+    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || np < 0 || (np > 0 && !pos) || !out) return OR_EINVAL;
+    const size_t n = (size_t)nx * ny * nz;
+    memset(out, 0, n * sizeof(double));
+    const double inv_v = 1.0 / (hx * hy * hz);
+    for (int p = 0; p < np; ++p) {
+        int ix[2], iy[2], iz[2];
+        double wx[2], wy[2], wz[2];
+        linear_weights(pos[3 * (size_t)p + 0], nx, hx, &ix[0], &ix[1], &wx[0], &wx[1]);
+        linear_weights(pos[3 * (size_t)p + 1], ny, hy, &iy[0], &iy[1], &wy[0], &wy[1]);
+        linear_weights(pos[3 * (size_t)p + 2], nz, hz, &iz[0], &iz[1], &wz[0], &wz[1]);
+        const double qp = q ? q[p] : 1.0;
+        for (int c = 0; c < 2; ++c)
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a)
+                    out[cell(nx, ny, ix[a], iy[b], iz[c])] += qp * wx[a] * wy[b] * wz[c] * inv_v;
+    }
+    return OR_OK;
+}
+
+/* out_p = I(field)(x_p): trilinear interpolation of a cell-centred field at the
+ * particle positions (section "Physical model", the linear interpolation I),
+ * periodic, with the same weights as P. */
+int oracle_interpolate(int nx, int ny, int nz, double hx, double hy, double hz, int np, const double* pos,
+                       const double* field, double* out) {
+    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || np < 0 || (np > 0 && (!pos || !out)) || !field)
+        return OR_EINVAL;
+    for (int p = 0; p < np; ++p) {
+        int ix[2], iy[2], iz[2];
+        double wx[2], wy[2], wz[2];
+        linear_weights(pos[3 * (size_t)p + 0], nx, hx, &ix[0], &ix[1], &wx[0], &wx[1]);
+        linear_weights(pos[3 * (size_t)p + 1], ny, hy, &iy[0], &iy[1], &wy[0], &wy[1]);
+        linear_weights(pos[3 * (size_t)p + 2], nz, hz, &iz[0], &iz[1], &wz[0], &wz[1]);
+        double acc = 0.0;
+        for (int c = 0; c < 2; ++c)
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a) acc += wx[a] * wy[b] * wz[c] * field[cell(nx, ny, ix[a], iy[b], iz[c])];
+        out[p] = acc;
+    }
+    return OR_OK;
+}
+
+int oracle_abi_version(void) { return 4; }

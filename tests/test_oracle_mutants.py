@@ -49,6 +49,10 @@ MUTANTS = {
                               "acc += (bp * m[d][c] - bm * m[d][cp]) / h[d];"),
     "divergence target dropped": ("b[c] = (b[c] - rhs_div[c]) / c_dt;", "b[c] = b[c] / c_dt;"),
     "chi sign": ("*chi_out = -c_dt * mean_of(b, n);", "*chi_out = c_dt * mean_of(b, n);"),
+    "deposit weights swapped": ("    *w0 = 1.0 - f;\n    *w1 = f;", "    *w0 = f;\n    *w1 = 1.0 - f;"),
+    "deposit upper neighbour": ("*i1 = (int)((a + 1) % n);", "*i1 = (int)((a + n - 1) % n);"),
+    "deposit not per unit volume": ("const double inv_v = 1.0 / (hx * hy * hz);", "const double inv_v = 1.0 / (hx * hy);"),
+    "interpolation drops a corner": ("for (int a = 0; a < 2; ++a) acc += wx[a]", "for (int a = 0; a < 1; ++a) acc += wx[a]"),
     "momentum correction sign": ("m[d][c] -= c_dt * (p[cp] - p[c]) / h[d];",
                                  "m[d][c] += c_dt * (p[cp] - p[c]) / h[d];"),
 }

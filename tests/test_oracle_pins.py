@@ -28,6 +28,10 @@ force:
   project   chi == mean(RHS^div); div u_new == RHS^div - chi to the solve's
             residual; correction == -C dt grad p; projecting twice changes
             nothing; divergence-free input: p = 0
+  deposit   brute-force hat functions; conservation; first moment; a particle
+            on a cell centre
+  interp    brute-force hat functions; adjoint of the deposit; affine fields
+            and constants reproduced
 """
 import math
 
@@ -678,7 +682,82 @@ def test_projection_step():
     pin_project()
 
 
+# --------------------------------------------------------------------------
+# particles and the grid: the linear projection P and interpolation I
+# --------------------------------------------------------------------------
+
+
+def _hat_weights(shape, lengths, x):
+    """Brute force: the weight of every cell for one particle, as the product of
+    1-D hat functions max(0, 1 - |x_c - x_p| / h) with the periodic distance."""
+    nz, ny, nx = shape
+    w = []
+    for n, L, xp in ((nx, lengths[0], x[0]), (ny, lengths[1], x[1]), (nz, lengths[2], x[2])):
+        h = L / n
+        xc = (np.arange(n) + 0.5) * h
+        dist = np.abs(((xc - xp) + L / 2) % L - L / 2)
+        w.append(np.maximum(0.0, 1.0 - dist / h))
+    return w[2][:, None, None] * w[1][None, :, None] * w[0][None, None, :]
+
+
+def pin_deposit():
+    shape, L = (6, 8, 12), (5.0, 3.0, 2.0)
+    hx, hy, hz = _lengths_h(shape, L)
+    V = hx * hy * hz
+    rng = np.random.default_rng(51)
+    pos = rng.uniform(-4.0, 9.0, (40, 3))  # beyond the box too: wrapped
+    q = rng.standard_normal(40)
+    d = oracle.deposit(shape, pos, q, L)
+    # brute force with hat functions
+    want = sum(qp * _hat_weights(shape, L, x) for qp, x in zip(q, pos)) / V
+    assert np.max(np.abs(d - want)) <= 1e-12 * np.max(np.abs(want))
+    # conservation: the grid holds the particles' total
+    assert abs(d.sum() * V - q.sum()) <= 1e-12 * np.abs(q).sum()
+    # first moment, for particles at least a cell away from the box faces
+    inner = rng.uniform(1.5, 4.0, (30, 3)) * np.array([1.0, 0.5, 0.3])
+    qi = rng.uniform(0.5, 1.5, 30)
+    di = oracle.deposit(shape, inner, qi, L)
+    x, y, z = _coords(shape, L)
+    for c, col in ((x, 0), (y, 1), (z, 2)):
+        assert abs((np.broadcast_to(c, shape) * di).sum() * V - (qi * inner[:, col]).sum()) <= 1e-12 * qi.sum() * 5
+    # a particle on a cell centre lands in that cell alone
+    one = oracle.deposit(shape, np.array([[2.5 * hx, 3.5 * hy, 1.5 * hz]]), np.array([2.0]), L)
+    assert one[1, 3, 2] == 2.0 / V and np.count_nonzero(one) == 1
+
+
+def test_deposit_brute_force_and_moments():
+    pin_deposit()
+
+
+def pin_interpolate():
+    shape, L = (6, 8, 12), (5.0, 3.0, 2.0)
+    hx, hy, hz = _lengths_h(shape, L)
+    V = hx * hy * hz
+    rng = np.random.default_rng(53)
+    pos = rng.uniform(-4.0, 9.0, (40, 3))
+    g = rng.standard_normal(shape)
+    got = oracle.interpolate(g, pos, L)
+    # brute force with hat functions
+    want = np.array([(g * _hat_weights(shape, L, x)).sum() for x in pos])
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(g))
+    # adjoint of P: sum_c g_c P(q)_c V = sum_p q_p I(g)(x_p)
+    q = rng.standard_normal(40)
+    lhs = (g * oracle.deposit(shape, pos, q, L)).sum() * V
+    assert abs(lhs - (q * got).sum()) <= 1e-12 * np.abs(q).sum() * np.max(np.abs(g))
+    # affine fields are reproduced away from the wrap, constants everywhere
+    x, y, z = _coords(shape, L)
+    f = np.broadcast_to(0.3 + 2.0 * x - 1.0 * y + 0.5 * z, shape)
+    inner = rng.uniform(1.5, 4.0, (30, 3)) * np.array([1.0, 0.5, 0.3])
+    assert np.max(np.abs(oracle.interpolate(f, inner, L) -
+                         (0.3 + 2.0 * inner[:, 0] - inner[:, 1] + 0.5 * inner[:, 2]))) <= 1e-12 * 10
+    assert np.max(np.abs(oracle.interpolate(np.full(shape, 1.75), pos, L) - 1.75)) <= 1e-14
+
+
+def test_interpolate_brute_force_adjoint_affine():
+    pin_interpolate()
+
+
 ALL_PINS = [pin_fft, pin_symbol, pin_order2, pin_flux1d, pin_matrix, pin_pinv,
             pin_const_one_iteration, pin_discrete_manufactured, pin_dense, pin_cg,
             pin_equivariance, pin_bound, pin_mean_removal, pin_gauge, pin_wall_modes, pin_wall_flux1d,
-            pin_wall_matrix, pin_wall_pinv_dense, pin_divergence, pin_project]
+            pin_wall_matrix, pin_wall_pinv_dense, pin_divergence, pin_project, pin_deposit, pin_interpolate]
