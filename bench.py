@@ -286,6 +286,28 @@ def served_chains_leg(P, torch, n, chains, steps, tol):
     return out
 
 
+def deposit_leg(P, torch, n, reps):
+    """The particle-to-grid projection P of workload 3 (10^6 uniform particles
+    onto n^3, unit values): `reps` calls of poisson_deposit (each blocks),
+    positions resident on the device; algorithmic bytes = the grid written once
+    (8 B/cell) + the positions read once (24 B/particle)."""
+    from paper_1601_05448_amd import inputs
+
+    pos = torch.from_numpy(inputs.workload3_particles()).cuda()
+    shape, L = (n, n, n), (2.0 * math.pi,) * 3
+    out = torch.empty(shape, dtype=torch.float64, device="cuda")
+    with P.Solver(shape, L) as s:
+        P.poisson_deposit(s.h, pos, None, out)  # warm-up (grows the particle buffers)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            P.poisson_deposit(s.h, pos, None, out)
+        dt = (time.perf_counter() - t0) / reps
+    nbytes = 8 * n ** 3 + 24 * pos.shape[0]
+    return dict(ms=dt * 1e3, particles=int(pos.shape[0]), particles_per_s=pos.shape[0] / dt,
+                bytes=nbytes, gbs=nbytes / dt / 1e9)
+
+
 def cpu_baseline(prob, fp64_iters):
     """The oracle (single-threaded C, FP64) on a bounded sample of the same
     workload: one residual evaluation plus one iteration, scaled to the
@@ -375,6 +397,10 @@ def main():
                           **warm_chain_leg(P, torch, args.size, 12, args.tol)}
     line["warm_chain"]["served"] = {"workload": "8 chains x 6 steps at 128^3 through the server, FP64",
                                     **served_chains_leg(P, torch, 128, 8, 6, args.tol)}
+    # the particle-to-grid projection that builds the 512^3 workload's density
+    line["deposit"] = {"workload": "10^6 uniform particles onto 512^3, trilinear weights per unit volume "
+                                   "(the density of the 512^3 particle workload)",
+                       **deposit_leg(P, torch, 512, 10)}
     # the inflow-outflow duct: zero-flux walls at the x ends, cosine transform along x
     duct = inputs.workload_duct(args.size)
     dsteps, dwarm = max(5, args.steps // 5), max(1, args.warmup // 2)

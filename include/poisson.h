@@ -220,6 +220,31 @@ int poisson_divergence(poisson_t h, const double* rho, const double* mx, const d
 int poisson_project(poisson_t h, const double* rho, double* mx, double* my, double* mz, const double* rhs_div,
                     double c_dt, double* p, double tol, double* chi);
 
+/* ---- particles and the grid -----------------------------------------------
+ * Section "Physical model": the operator P projects particle data to the
+ * fluid grid per unit volume, and I interpolates grid data to the particle
+ * positions, both by a linear approximation.  Here: trilinear (cloud-in-cell)
+ * weights on the cell centres, periodic.  For a particle at x, per direction
+ * s = x/h - 1/2, i0 = floor(s), f = s - i0: weight 1 - f to cell i0 and f to
+ * cell i0 + 1 (wrapped); the eight cells around it get the products.
+ * pos: device FP64 array of n_particles rows (x, y, z) in the box's physical
+ * units, any value within 2^30 cells of the box (wrapped).  Periodic handles
+ * only (POISSON_BC_WALLS_X gives POISSON_EINVAL); POISSON_EDOMAIN for a
+ * position that is not finite or too far out (outputs then undefined). */
+
+/* out = P(q): out_c = sum_p q_p W_p(c) / (hx hy hz).  q: n_particles device
+ * values, or NULL for q = 1 (then out is the particle number density).
+ * Deterministic (no atomics: the particles are sorted by cell, and every cell
+ * adds its contributions in a fixed order).  Uses the handle's transform buffer
+ * as scratch (no solve may run on the handle meanwhile) and keeps particle
+ * buffers in the handle, grown as needed.  Blocks until done. */
+int poisson_deposit(poisson_t h, int n_particles, const double* pos, const double* q, double* out);
+
+/* out_p = I(field)(x_p): trilinear interpolation of a device FP64 cell field at
+ * the particle positions (the adjoint of P up to the factor 1/(hx hy hz)).
+ * out: n_particles device values.  Blocks until done. */
+int poisson_interpolate(poisson_t h, int n_particles, const double* pos, const double* field, double* out);
+
 /* ---- serving: many independent solves of different sizes -----------------
  * A server keeps each admitted request's rho, b, p and iteration state on the
  * device, groups requests of equal grid size into batches that advance

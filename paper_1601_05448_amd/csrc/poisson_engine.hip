@@ -404,6 +404,8 @@ struct poisson_s {
     double timer_ms = 0.0;       // summed bracketed time since the timer was set
     long long timer_launches = 0;
     double* proj_b = nullptr;    // right-hand side built by poisson_project (allocated at its first call)
+    void* part_ws = nullptr;     // particle buffers of poisson_deposit / poisson_interpolate (grown on demand)
+    size_t part_ws_bytes = 0;
 };
 
 extern "C" {
@@ -439,6 +441,7 @@ void poisson_destroy(poisson_t h) {
     h->ws.release();
     h->tables.release();
     if (h->proj_b) (void)hipFree(h->proj_b);
+    if (h->part_ws) (void)hipFree(h->part_ws);
     delete h;
 }
 
@@ -487,6 +490,12 @@ int poisson_create(const poisson_opts* o, poisson_t* out) {
 static bool overlaps(const void* a, const void* b, size_t bytes) {
     const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
     return x < y + bytes && y < x + bytes;
+}
+
+// [a, a + na) and [b, b + nb) share a byte
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return na > 0 && nb > 0 && x < y + nb && y < x + na;
 }
 
 static int set_slot(poisson_t h, const Slot& s, hipStream_t st) {
@@ -676,6 +685,47 @@ int poisson_project(poisson_t h, const double* rho, double* mx, double* my, doub
     if (rc2 != POISSON_OK) return rc2;
     const int rc3 = hip_status(hipStreamSynchronize(h->stream));
     return rc3 != POISSON_OK ? rc3 : rc;
+}
+
+static int particle_ws(poisson_t h, size_t bytes) {
+    bytes = std::max<size_t>(bytes, 256);
+    if (h->part_ws_bytes >= bytes) return POISSON_OK;
+    if (h->part_ws) (void)hipFree(h->part_ws);
+    h->part_ws = nullptr;
+    h->part_ws_bytes = 0;
+    if (hipMalloc(&h->part_ws, bytes) != hipSuccess) {
+        h->part_ws = nullptr;
+        return POISSON_ENOMEM;
+    }
+    h->part_ws_bytes = bytes;
+    return POISSON_OK;
+}
+
+int poisson_deposit(poisson_t h, int n_particles, const double* pos, const double* q, double* out) {
+    if (!h || n_particles < 0 || (n_particles > 0 && !pos) || !out || h->g.bcx != 0) return POISSON_EINVAL;
+    const size_t fb = (size_t)h->g.n * sizeof(double), pb = (size_t)n_particles * 3 * sizeof(double);
+    if (overlaps(out, fb, pos, pb) || (q && overlaps(out, fb, q, (size_t)n_particles * sizeof(double))))
+        return POISSON_EINVAL;
+    int rc = particle_ws(h, particle_workspace_bytes(h->g, n_particles));
+    if (rc != POISSON_OK) return rc;
+    int bad = 0;
+    rc = hip_status(launch_deposit(h->g, n_particles, pos, q, out, reinterpret_cast<unsigned*>(h->ws.W), h->part_ws,
+                                   h->part_ws_bytes, &bad, h->stream));
+    if (rc != POISSON_OK) return rc;
+    if (bad) return POISSON_EDOMAIN;
+    return hip_status(hipStreamSynchronize(h->stream));
+}
+
+int poisson_interpolate(poisson_t h, int n_particles, const double* pos, const double* field, double* out) {
+    if (!h || n_particles < 0 || (n_particles > 0 && (!pos || !out)) || !field || h->g.bcx != 0)
+        return POISSON_EINVAL;
+    int rc = particle_ws(h, 256);
+    if (rc != POISSON_OK) return rc;
+    int bad = 0;
+    rc = hip_status(launch_interpolate(h->g, n_particles, pos, field, out, static_cast<int*>(h->part_ws), &bad,
+                                       h->stream));
+    if (rc != POISSON_OK) return rc;
+    return bad ? POISSON_EDOMAIN : POISSON_OK;
 }
 
 int poisson_lap_pinv(poisson_t h, const double* q, double* delta) {

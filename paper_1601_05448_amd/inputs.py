@@ -247,6 +247,13 @@ def workload2(n: int = 256, ratio: float = 4.0, kmax: float = 8.0) -> Problem:
     return Problem(f"lognormal-rho {n}^3 ratio {ratio:g}", (n, n, n), L, rho, b)
 
 
+def workload3_particles(particles: int = 10**6) -> np.ndarray:
+    """The particle positions of workload 3, (particles, 3) as (x, y, z), the
+    same draws workload3 uses."""
+    rng = np.random.default_rng(workload_seed(3))
+    return rng.uniform(0.0, TWO_PI, size=(particles, 3))
+
+
 def workload3(n: int = 512, particles: int = 10**6, ratio: float = 10.0,
               kmax: float = 8.0) -> Problem:
     rng = np.random.default_rng(workload_seed(3))

@@ -98,6 +98,8 @@ def load() -> ctypes.CDLL:
     lib.poisson_kernel_timer_read.argtypes = [vp, pd, ctypes.POINTER(ll)]
     lib.poisson_divergence.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.poisson_project.argtypes = [vp, vp, vp, vp, vp, vp, d, vp, d, pd]
+    lib.poisson_deposit.argtypes = [vp, i, vp, vp, vp]
+    lib.poisson_interpolate.argtypes = [vp, i, vp, vp, vp]
     if hasattr(lib, "poisson_server_create"):
         lib.poisson_server_create.argtypes = [ctypes.c_size_t, i, i, i, i, i, vp, ctypes.POINTER(vp)]
         lib.poisson_server_submit.argtypes = [vp, i, i, i, d, d, d, vp, vp, vp, d, ctypes.POINTER(ll)]
@@ -215,6 +217,21 @@ def poisson_project(h: int, rho, mx, my, mz, rhs_div, c_dt: float, p, tol: float
     if rc not in (POISSON_OK, POISSON_ENOCONV):
         raise PoissonError(rc, "poisson_project")
     return rc, chi.value
+
+
+def poisson_deposit(h: int, pos, q, out) -> None:
+    """out = P(q): pos (n_p, 3) device positions, q (n_p,) or None."""
+    n = int(pos.shape[0]) if pos is not None else 0
+    rc = load().poisson_deposit(h, n, _ptr(pos), _ptr(q), _ptr(out))
+    if rc != POISSON_OK:
+        raise PoissonError(rc, "poisson_deposit")
+
+
+def poisson_interpolate(h: int, pos, field, out) -> None:
+    n = int(pos.shape[0]) if pos is not None else 0
+    rc = load().poisson_interpolate(h, n, _ptr(pos), _ptr(field), _ptr(out))
+    if rc != POISSON_OK:
+        raise PoissonError(rc, "poisson_interpolate")
 
 
 def poisson_time_sweep(h: int, sweep: int, fp32: bool, rho, b, p, reps: int) -> float:
