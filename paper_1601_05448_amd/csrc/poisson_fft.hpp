@@ -172,9 +172,18 @@ constexpr int pick_radix(int rem) {
 // the banks.
 constexpr int line_stride(int n) { return n >= 16 ? ((n + n / 16) | 1) : (n | 1); }
 
+// Lines of 512 elements (and FP32 lines of 1024) take 512 threads' worth of
+// lines (one block of 8 waves per CU, up to 150000 bytes of LDS), so that the
+// column sweeps read runs of 8 or 16 complex values per row and the z-marching
+// stencil has one column per thread; other lines take 256 (or 192) threads, two
+// blocks per CU (82000 bytes of LDS each).  (FP64 lines of 1024 in 512-thread
+// blocks would leave their update sweep too few registers.)  The budget halves
+// the lines where needed.
 constexpr int lines_per_block(int tt, int n, int elem_bytes) {
-    int l = (256 % tt == 0) ? 256 / tt : 192 / tt;
-    while (l * line_stride(n) * elem_bytes > 82000 && ((l / 2) * tt) % 64 == 0) l /= 2;
+    const bool big = tt >= 32 && 512 % tt == 0 && (n <= 512 || elem_bytes <= 8);
+    int l = big ? 512 / tt : (256 % tt == 0) ? 256 / tt : 192 / tt;
+    const int budget = big ? 150000 : 82000;
+    while (l * line_stride(n) * elem_bytes > budget && ((l / 2) * tt) % 64 == 0) l /= 2;
     return l;
 }
 
@@ -188,6 +197,9 @@ struct LineCfg {
     static constexpr int NT = L * TT;
     static constexpr int IT = N / TT;  // elements per thread when a block walks its L lines
     static constexpr int LS = line_stride(N);
+    // blocks per CU the register budget of a sweep is sized for: two blocks of
+    // up to 256 threads, one block of 512 (both 8 waves per CU)
+    static constexpr int MINB = NT > 256 ? 1 : 2;
     static_assert(NT % 64 == 0, "block must be whole wavefronts");
     static __device__ __forceinline__ constexpr int pos(int e) { return N >= 16 ? e + e / 16 : e; }
 };

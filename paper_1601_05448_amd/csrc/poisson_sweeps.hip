@@ -138,7 +138,7 @@ k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
 // Within a flush, line l = s KF + q is row pair jp = tj SUB + s of plane
 // k = tk KM + f KF + q.
 template <typename T, int N, int COEF, int WEIGHT>
-__global__ void __launch_bounds__((LineCfg<T, N>::NT), 2)
+__global__ void __launch_bounds__((LineCfg<T, N>::NT), (LineCfg<T, N>::MINB))
 k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     using C = LineCfg<T, N>;
     using Z = ZTile<N, C::NT, C::L>;
@@ -272,7 +272,7 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
 // which the FP32 P1 removes, is FP64 rounding noise here and is not removed.
 // Per tile: r^2, bt^2, p, p^2, r in FP64.  One column per thread.
 template <int N, int COEF, int WEIGHT>
-__global__ void __launch_bounds__((LineCfg<float, N>::NT), 2)
+__global__ void __launch_bounds__((LineCfg<float, N>::NT), (LineCfg<float, N>::MINB))
 k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     using C = LineCfg<float, N>;
     using Z = ZTile<N, C::NT, C::L>;
@@ -393,7 +393,7 @@ __device__ __forceinline__ unsigned col_base(const GridArgs& g, unsigned line) {
 }
 
 template <typename T, int N, int AX, int MODE>
-__global__ void __launch_bounds__((LineCfg<T, N>::NT), 2)
+__global__ void __launch_bounds__((LineCfg<T, N>::NT), (LineCfg<T, N>::MINB))
 k_dht_cols(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) {
     using C = LineCfg<T, N>;
     __shared__ cpx<T> lds[C::L * C::LS];
@@ -487,7 +487,7 @@ __device__ __forceinline__ cpx<T> scaled_conj(cpx<T> zk, cpx<T> zm, T sa, T sb) 
 }
 
 template <typename T, int N, int MODE>
-__global__ void __launch_bounds__((LineCfg<T, N>::NT), 2)
+__global__ void __launch_bounds__((LineCfg<T, N>::NT), (LineCfg<T, N>::MINB))
 k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) {
     using C = LineCfg<T, N>;
     __shared__ cpx<T> lds[C::L * C::LS];
