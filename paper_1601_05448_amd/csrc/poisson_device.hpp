@@ -381,19 +381,28 @@ __device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
 // threads: SUB strips (row pairs) of N threads each when N < NT, or CPT columns
 // per thread when N >= NT.  A tile marches KM planes; every KF planes its L = SUB
 // KF lines are full and are transformed and written out ("flushed"), so that the
-// two z halo planes a tile reads are shared by KM >= 16 planes however few
+// two z halo planes a tile reads are shared by KM >= KMIN planes however few
 // lines the transform's LDS holds.
-template <int N, int NT, int L>
+template <int N, int NT, int L, int KMIN = 16>
 struct ZTile {
     static constexpr int CPT = N >= NT ? N / NT : 1;
     static constexpr int SUB = N >= NT ? 1 : NT / N;
     static constexpr int KF = L / SUB;
-    static constexpr int KM = KF >= 16 ? KF : 16;
+    static constexpr int KM = KF >= KMIN ? KF : KMIN;
     static constexpr int EDGE = (N / 64) * 2 * 4;  // edge values per strip and buffer
     static_assert(N % 64 == 0, "columns must fill whole waves");
     static_assert(SUB * KF == L && (N >= NT ? N % NT == 0 : NT % N == 0), "tile shape");
     static_assert(KM % KF == 0 && KF % 2 == 0, "flushes");
 };
+
+// Tiles of the residual sweep P1 and of the fused FP32 outer residual: 32
+// planes (halo planes shared by twice as many) wherever the kernel's registers
+// allow it; the FP32 sweep on rows of fewer than 512 cells keeps 16, which keeps
+// it within 128 registers (four waves per SIMD).
+template <typename T, int N>
+using P1Tile = ZTile<N, LineCfg<T, N>::NT, LineCfg<T, N>::L, (sizeof(T) == 8 || N >= 512) ? 32 : 16>;
+template <int N>
+using OuterTile = ZTile<N, LineCfg<float, N>::NT, LineCfg<float, N>::L, 32>;
 
 // One cell, plain IEEE divisions: the stand-alone operator and residual sweeps
 // (parity checks), which need no state and are off the iteration's path.

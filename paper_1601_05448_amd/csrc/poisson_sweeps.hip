@@ -141,7 +141,7 @@ template <typename T, int N, int COEF, int WEIGHT>
 __global__ void __launch_bounds__((LineCfg<T, N>::NT), (LineCfg<T, N>::MINB))
 k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     using C = LineCfg<T, N>;
-    using Z = ZTile<N, C::NT, C::L>;
+    using Z = P1Tile<T, N>;
     __shared__ cpx<T> lds[C::L * C::LS];
     __shared__ cpx<T> tw[N];
     __shared__ double red[(C::NT / 64) * 4];
@@ -275,7 +275,7 @@ template <int N, int COEF, int WEIGHT>
 __global__ void __launch_bounds__((LineCfg<float, N>::NT), (LineCfg<float, N>::MINB))
 k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     using C = LineCfg<float, N>;
-    using Z = ZTile<N, C::NT, C::L>;
+    using Z = OuterTile<N>;
     static_assert(Z::CPT == 1, "one marching column per thread");
     __shared__ cpx<float> lds[C::L * C::LS];
     __shared__ cpx<float> tw[N];
@@ -757,7 +757,7 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
                 const unsigned ng = (rows + C::L - 1) / C::L;
                 return dispatch_op(MODE == 1 ? 0 : g.coef, MODE == 1 ? 0 : g.weight, [&]<int CO, int WE>() {
                     if constexpr (MODE == 0 && use_zmarch<T, N>()) {
-                        using Z = ZTile<N, C::NT, C::L>;
+                        using Z = P1Tile<T, N>;
                         const unsigned nt = (((unsigned)g.ny / 2 + Z::SUB - 1) / Z::SUB) *
                                             (((unsigned)g.nz + Z::KM - 1) / Z::KM);
                         const void* k = (const void*)&k_resid_dhtx_z<T, N, CO, WE>;
@@ -818,7 +818,7 @@ hipError_t launch_sweep_mode(const GridArgs& g, const Tables& t, const Slot* slo
 template <int N>
 constexpr bool outer_fusable_len() {
     if constexpr (N % 64 != 0) return false;
-    else return ZTile<N, LineCfg<float, N>::NT, LineCfg<float, N>::L>::CPT == 1;
+    else return OuterTile<N>::CPT == 1;
 }
 
 bool outer_fusable(const GridArgs& g) {
@@ -835,7 +835,7 @@ hipError_t launch_outer_fused(const GridArgs& g, const Tables& t, const Slot* sl
     return dispatch_len(g.nx, [&]<int N>() {
         if constexpr (outer_fusable_len<N>()) {
             using C = LineCfg<float, N>;
-            using Z = ZTile<N, C::NT, C::L>;
+            using Z = OuterTile<N>;
             const unsigned nt = (((unsigned)g.ny / 2 + Z::SUB - 1) / Z::SUB) * (((unsigned)g.nz + Z::KM - 1) / Z::KM);
             if (nunits) *nunits = (int)nt;
             return dispatch_op(g.coef, g.weight, [&]<int CO, int WE>() {
