@@ -282,10 +282,11 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
         // with the first inner sweep (and followed by the rest of it), a step
         // needs one full sweep less.
         const int first = outer_fusable(g) ? 1 : 0;
-        // sweeps of the first step: a contraction of 0.2 per sweep (typical of
-        // the method on smooth densities), plus the one whose residual
-        // evaluation stops the sweeps
-        const int guess = (int)std::ceil(std::log(prm.inner_tol) / std::log(0.2)) + 1;
+        // sweeps of the first step: a contraction of 0.1 per sweep (the method
+        // on smooth densities: 0.05 on the 256^3 lognormal density of ratio 4),
+        // plus the one whose residual evaluation stops the sweeps; rougher
+        // densities take another round
+        const int guess = (int)std::ceil(std::log(prm.inner_tol) / std::log(0.1)) + 1;
         int full = std::clamp(guess - first, 0, prm.max_chunk);
         // A refinement step: outer residual (with the tail of its first inner
         // sweep where fused), `nfull` full inner sweeps, update.
@@ -297,6 +298,7 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
         };
         int open_full = 0;  // full sweeps that finish an open inner phase (then its update)
         int steps = 1;      // whole steps after that, then one outer residual to check
+        int full_last = full;  // full sweeps of the last of those steps
         bool check = false;
         const int max_rounds = prm.max_outer + prm.max_iter + 2;
         for (int round = 0; round < max_rounds; ++round) {
@@ -305,7 +307,7 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
                 if ((e = launch_outer_update(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
             }
             for (int k = 0; k < steps; ++k)
-                if ((e = step(full)) != hipSuccess) return hip_status(e);
+                if ((e = step(k + 1 == steps ? full_last : full)) != hipSuccess) return hip_status(e);
             if (check && (e = launch_outer_residual(g, geo, t, d_slots, nslots, s, nullptr)) != hipSuccess)
                 return hip_status(e);
             const int r = poll();
@@ -319,11 +321,13 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
             //  * then as many whole steps as the outer residual needs to pass the
             //    tolerance if every step reduces it as the last one did (the
             //    inner tolerance for a step still open), each with as many full
-            //    sweeps as the last finished step used, and the outer residual
-            //    that checks the result.
+            //    sweeps as the last finished step used (the last of them as many
+            //    as its smaller inner goal, max(inner tol, 0.8 tol / rel), needs
+            //    at the contraction per sweep of the last finished step), and the
+            //    outer residual that checks the result.
             // Kernels out of their stage idle, so a short guess costs another
             // round and a long one a few idle launches.
-            int need_open = 0, need_full = 0, need_steps = 0;
+            int need_open = 0, need_full = 0, need_steps = 0, need_last = 0;
             for (int q = 0; q < nslots; ++q) {
                 const SolveState& h = hdr[q];
                 if (h.done) continue;
@@ -341,14 +345,26 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
                 } else {
                     need_full = std::max(need_full, h.inner_last - first);
                 }
-                rel *= std::clamp(red, 1e-12, 0.5);
+                const double redc = std::clamp(red, 1e-12, 0.5);
+                rel *= redc;
                 int st = 0;
-                if (rel > 0.5 * h.tol)
-                    st = (int)std::ceil(std::log(0.5 * h.tol / rel) / std::log(std::clamp(red, 1e-12, 0.5)));
-                need_steps = std::max(need_steps, std::clamp(st, 0, 8));
+                if (rel > 0.5 * h.tol) st = (int)std::ceil(std::log(0.5 * h.tol / rel) / std::log(redc));
+                st = std::clamp(st, 0, 8);
+                need_steps = std::max(need_steps, st);
+                // the last predicted step: from rel redc^(st-1), it needs the
+                // inner reduction max(inner tol, 0.8 tol / that)
+                int last = h.inner_last - first;
+                if (h.stage == 0 && st >= 1 && h.inner_last >= 2 && h.rel_in > 0.0 && h.rel_in < 1.0) {
+                    const double rate = std::pow(h.rel_in, 1.0 / (h.inner_last - 1));
+                    const double goal = std::max(h.inner_tol, 0.8 * h.tol / (rel * std::pow(redc, st - 1)));
+                    if (rate < 0.95 && goal < 1.0)
+                        last = (int)std::ceil(std::log(goal) / std::log(rate)) + 1 - first;
+                }
+                need_last = std::max(need_last, last);
             }
             open_full = std::min(need_open, prm.max_chunk);
             if (need_full > 0) full = std::clamp(need_full, 0, prm.max_chunk);
+            full_last = need_last > 0 ? std::clamp(need_last, 1, full) : full;
             steps = need_steps;
             check = true;
         }
