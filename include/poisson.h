@@ -260,14 +260,16 @@ typedef struct poisson_server_s* poisson_server_t;
 int poisson_server_create(size_t budget_bytes, int max_slots, int precision, int coef, int weight,
                           int max_iter, void* stream, poisson_server_t* out);
 
-/* Queue a request.  rho, b, p: device FP64 fields of the request's grid that
+/* Queue a request on grid (nx, ny, nz), box (lx, ly, lz), boundary condition
+ * bc_x (POISSON_BC_PERIODIC or POISSON_BC_WALLS_X; requests batch together only
+ * with equal grid, box and condition).  rho, b, p: device FP64 fields of the request's grid that
  * the server uses in place: rho and b must stay valid and unchanged, and p
  * must not be touched, until poisson_server_poll reports the request done.  p
  * is in/out like in poisson_solve.  The request's resident footprint (its
  * three fields plus the solver workspace) counts against the budget while it
  * is admitted.  Does not block.  Returns the id through *id.
  * POISSON_ETOOBIG if the request could never fit the budget. */
-int poisson_server_submit(poisson_server_t s, int nx, int ny, int nz, double lx, double ly, double lz,
+int poisson_server_submit(poisson_server_t s, int nx, int ny, int nz, double lx, double ly, double lz, int bc_x,
                           const double* rho, const double* b, double* p, double tol, long long* id);
 
 /* Run one scheduling tick: retire the finished requests of every batch whose

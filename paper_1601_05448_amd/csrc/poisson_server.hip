@@ -44,6 +44,7 @@ struct Request {
     long long id;
     int nx, ny, nz;
     double lx, ly, lz;
+    int bc_x;
     const double* rho;
     const double* b;
     double* p;
@@ -51,7 +52,7 @@ struct Request {
     double t_submit;
 };
 
-using ClassKey = std::tuple<int, int, int, double, double, double>;
+using ClassKey = std::tuple<int, int, int, double, double, double, int>;
 
 struct Resident {
     Request req;
@@ -114,14 +115,14 @@ struct poisson_server_s {
 static size_t field_bytes(long long cells) { return (size_t)cells * 3 * sizeof(double); }
 
 static int class_for(poisson_server_s* s, const Request& r, SizeClass** out) {
-    const ClassKey key{r.nx, r.ny, r.nz, r.lx, r.ly, r.lz};
+    const ClassKey key{r.nx, r.ny, r.nz, r.lx, r.ly, r.lz, r.bc_x};
     auto it = s->classes.find(key);
     if (it != s->classes.end()) {
         *out = it->second.get();
         return POISSON_OK;
     }
     auto c = std::make_unique<SizeClass>();
-    c->g = make_grid(r.nx, r.ny, r.nz, r.lx, r.ly, r.lz, s->coef, s->weight);
+    c->g = make_grid(r.nx, r.ny, r.nz, r.lx, r.ly, r.lz, s->coef, s->weight, r.bc_x);
     c->geo = make_geometry(c->g);
     c->cells = c->g.n;
     c->ws_bytes = workspace_bytes(c->g, c->geo, s->prm.precision);
@@ -140,7 +141,7 @@ static int class_for(poisson_server_s* s, const Request& r, SizeClass** out) {
 }
 
 static size_t request_footprint(poisson_server_s* s, const Request& r) {
-    const GridArgs g = make_grid(r.nx, r.ny, r.nz, r.lx, r.ly, r.lz, s->coef, s->weight);
+    const GridArgs g = make_grid(r.nx, r.ny, r.nz, r.lx, r.ly, r.lz, s->coef, s->weight, r.bc_x);
     return workspace_bytes(g, make_geometry(g), s->prm.precision) + field_bytes(g.n);
 }
 
@@ -324,9 +325,10 @@ void poisson_server_destroy(poisson_server_t s) {
     delete s;
 }
 
-int poisson_server_submit(poisson_server_t s, int nx, int ny, int nz, double lx, double ly, double lz,
+int poisson_server_submit(poisson_server_t s, int nx, int ny, int nz, double lx, double ly, double lz, int bc_x,
                           const double* rho, const double* b, double* p, double tol, long long* id) {
     if (!s || !id || !rho || !b || !p || !(tol > 0.0) || !std::isfinite(tol)) return POISSON_EINVAL;
+    if (bc_x != POISSON_BC_PERIODIC && bc_x != POISSON_BC_WALLS_X) return POISSON_EINVAL;
     if (!length_supported(nx) || !length_supported(ny) || !length_supported(nz)) return POISSON_EINVAL;
     if (!valid_lengths(lx, ly, lz)) return POISSON_EINVAL;
     const size_t bytes = (size_t)nx * ny * nz * sizeof(double);
@@ -335,7 +337,7 @@ int poisson_server_submit(poisson_server_t s, int nx, int ny, int nz, double lx,
         return a < c + bytes && c < a + bytes;
     };
     if (overlaps(rho, b) || overlaps(rho, p) || overlaps(b, p)) return POISSON_EINVAL;
-    Request r{s->next_id, nx, ny, nz, lx, ly, lz, rho, b, p, tol, now_ms()};
+    Request r{s->next_id, nx, ny, nz, lx, ly, lz, bc_x, rho, b, p, tol, now_ms()};
     if (request_footprint(s, r) > s->budget) return POISSON_ETOOBIG;
     s->queue.push_back(r);
     *id = s->next_id++;

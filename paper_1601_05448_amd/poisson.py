@@ -102,7 +102,7 @@ def load() -> ctypes.CDLL:
     lib.poisson_interpolate.argtypes = [vp, i, vp, vp, vp]
     if hasattr(lib, "poisson_server_create"):
         lib.poisson_server_create.argtypes = [ctypes.c_size_t, i, i, i, i, i, vp, ctypes.POINTER(vp)]
-        lib.poisson_server_submit.argtypes = [vp, i, i, i, d, d, d, vp, vp, vp, d, ctypes.POINTER(ll)]
+        lib.poisson_server_submit.argtypes = [vp, i, i, i, d, d, d, i, vp, vp, vp, d, ctypes.POINTER(ll)]
         lib.poisson_server_tick.argtypes = [vp]
         lib.poisson_server_poll.argtypes = [vp, ll, ctypes.POINTER(poisson_stats)]
         lib.poisson_server_destroy.argtypes = [vp]
@@ -276,11 +276,11 @@ def poisson_server_create(budget_bytes: int, max_slots: int, precision: int = PO
 
 
 def poisson_server_submit(s: int, shape: Sequence[int], lengths: Sequence[float], rho, b, p,
-                          tol: float) -> int:
+                          tol: float, bc_x: int = POISSON_BC_PERIODIC) -> int:
     nz, ny, nx = (int(v) for v in shape)
     rid = ctypes.c_longlong()
     rc = load().poisson_server_submit(s, nx, ny, nz, float(lengths[0]), float(lengths[1]), float(lengths[2]),
-                                      _ptr(rho), _ptr(b), _ptr(p), float(tol), ctypes.byref(rid))
+                                      int(bc_x), _ptr(rho), _ptr(b), _ptr(p), float(tol), ctypes.byref(rid))
     if rc != POISSON_OK:
         raise PoissonError(rc, "poisson_server_submit")
     return rid.value

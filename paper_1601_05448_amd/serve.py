@@ -22,8 +22,8 @@ class Server:
                  max_iter: int = 0, stream=None):
         self.h = P.poisson_server_create(budget_bytes, max_slots, precision, coef, weight, max_iter, stream)
 
-    def submit(self, shape, lengths, rho, b, p, tol: float) -> int:
-        return P.poisson_server_submit(self.h, shape, lengths, rho, b, p, tol)
+    def submit(self, shape, lengths, rho, b, p, tol: float, bc_x: int = P.POISSON_BC_PERIODIC) -> int:
+        return P.poisson_server_submit(self.h, shape, lengths, rho, b, p, tol, bc_x)
 
     def tick(self) -> int:
         return P.poisson_server_tick(self.h)
@@ -61,6 +61,7 @@ class Job:
     p: object
     tol: float = 1e-10
     tag: object = None
+    bc_x: int = P.POISSON_BC_PERIODIC
 
 
 @dataclass
@@ -93,7 +94,7 @@ def replay(server: Server, jobs: Sequence[Job], realtime: bool = True,
         now = time.perf_counter() - t0
         while nxt < len(order) and (not realtime or jobs[order[nxt]].arrival_s <= now):
             j = jobs[order[nxt]]
-            rid = server.submit(j.shape, j.lengths, j.rho, j.b, j.p, j.tol)
+            rid = server.submit(j.shape, j.lengths, j.rho, j.b, j.p, j.tol, j.bc_x)
             inflight[rid] = (j, time.perf_counter() - t0)
             nxt += 1
         if not inflight:
@@ -129,6 +130,7 @@ class Chain:
     p: object
     tol: float = 1e-10
     warm: bool = True
+    bc_x: int = P.POISSON_BC_PERIODIC
 
 
 @dataclass
@@ -157,7 +159,7 @@ def run_chains(server: Server, chains: Sequence[Chain]) -> ChainResult:
 
             ch.p.zero_()
             torch.cuda.current_stream().synchronize()  # the server reads p on its own streams
-        rid = server.submit(ch.shape, ch.lengths, rho, b, ch.p, ch.tol)
+        rid = server.submit(ch.shape, ch.lengths, rho, b, ch.p, ch.tol, ch.bc_x)
         inflight[rid] = c
         nxt[c] += 1
 

@@ -161,3 +161,44 @@ def test_poisson_arrival_stream_of_served_sizes():
     o = res.outcomes[0]
     chk = oracle.residual(host(o.job.rho), host(o.job.b), host(o.job.p), o.job.lengths)
     assert chk["rel"] <= 1e-10
+
+
+@pytest.mark.parametrize("precision", [P.POISSON_FP64, P.POISSON_FP32_REFINE])
+def test_duct_and_box_requests_in_one_mix(precision):
+    """Requests with walls in x (the duct) and periodic ones of the same grid
+    are separate classes; each is served with its own condition and gives the
+    same bits as a solve of that request alone (checked by the oracle with the
+    matching condition)."""
+    announce("serve duct and box", precision)
+    W = P.POISSON_BC_WALLS_X
+    probs = [inputs.small_problem(shape=(16, 16, 64), lengths=(TWO_PI,) * 3, ratio=2.0 + k, seed=500 + k)
+             for k in range(6)]
+    bcs = [W if k % 2 else P.POISSON_BC_PERIODIC for k in range(6)]
+    jobs = [serve.Job(0.0, pr.shape, pr.lengths, dev(pr.rho), dev(pr.b), dev(np.zeros(pr.shape)), tag=k,
+                      bc_x=bcs[k]) for k, pr in enumerate(probs)]
+    with serve.Server(1 << 33, 16, precision=precision) as s:
+        res = serve.replay(s, jobs, realtime=False)
+    assert len(res.outcomes) == len(probs)
+    for o in res.outcomes:
+        k = o.job.tag
+        pr = probs[k]
+        h = P.poisson_create(pr.shape, pr.lengths, precision=precision, bc_x=bcs[k])
+        try:
+            p = dev(np.zeros(pr.shape))
+            P.poisson_solve(h, dev(pr.rho), dev(pr.b), p, 1e-10)
+            st = P.poisson_get_stats(h)
+        finally:
+            P.poisson_destroy(h)
+        assert o.stats["status"] == 0 and st["status"] == 0
+        assert o.stats["iters"] == st["iters"]
+        assert np.array_equal(host(o.job.p), host(p)), k
+        assert oracle.residual(pr.rho, pr.b, host(p), pr.lengths, bcx=bcs[k])["rel"] <= 1e-10
+
+
+def test_server_rejects_unknown_boundary_condition():
+    announce("serve bad bc")
+    pr = inputs.small_problem(shape=(8, 8, 16), lengths=(TWO_PI,) * 3)
+    with serve.Server(1 << 30, 4) as s:
+        with pytest.raises(P.PoissonError) as e:
+            s.submit(pr.shape, pr.lengths, dev(pr.rho), dev(pr.b), dev(np.zeros(pr.shape)), 1e-10, bc_x=3)
+        assert e.value.code == P.POISSON_EINVAL
