@@ -620,6 +620,14 @@ inline hipError_t dispatch_len(int n, F&& f) {
     }
 }
 
+// Calls f.template operator()<BCX>() for the runtime boundary condition in x
+// (0 periodic, 1 walls): the hot sweeps are compiled for each, so that the
+// periodic ones carry no wall logic.
+template <typename F>
+inline hipError_t dispatch_bc(int bcx, F&& f) {
+    return bcx ? f.template operator()<1>() : f.template operator()<0>();
+}
+
 // Calls f.template operator()<COEF, WEIGHT>() for the runtime modes.
 template <typename F>
 inline hipError_t dispatch_op(int coef, int weight, F&& f) {

@@ -137,7 +137,7 @@ k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
 // every KF planes the tile's L lines are transformed along x and written out.
 // Within a flush, line l = s KF + q is row pair jp = tj SUB + s of plane
 // k = tk KM + f KF + q.
-template <typename T, int N, int COEF, int WEIGHT>
+template <typename T, int N, int COEF, int WEIGHT, int BCX>
 __global__ void __launch_bounds__((LineCfg<T, N>::NT), (LineCfg<T, N>::MINB))
 k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     using C = LineCfg<T, N>;
@@ -214,7 +214,7 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                     zm.pair(pl[c][0], pl[c][1], pl[c][2], sd[c], zm.edge_get(eb, i), in);
                     cpx<T> qv = {T(0), T(0)};
                     if (valid) {
-                        const PairOut<T> o = pair_eval<T, COEF, WEIGHT>(g, in, v.rhs_mean, v.rmax, v.rinv, x_walls(g, i));
+                        const PairOut<T> o = pair_eval<T, COEF, WEIGHT>(g, in, v.rhs_mean, v.rmax, v.rinv, BCX ? x_walls(g, i) : 0u);
                         qv = {o.a.w * o.a.r, o.b.w * o.b.r};
                         if constexpr (sizeof(T) == 8) {
                             acc[0] += o.a.r * o.a.r + o.b.r * o.b.r;
@@ -228,7 +228,7 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                             tacc[1] += o.a.bt * o.a.bt + o.b.bt * o.b.bt;
                         }
                     }
-                    lds[(sidx * Z::KF + q) * C::LS + C::pos(x_slot(i, N, g.bcx))] = qv;
+                    lds[(sidx * Z::KF + q) * C::LS + C::pos(x_slot(i, N, BCX))] = qv;
                 }
 #pragma unroll
                 for (int c = 0; c < Z::CPT; ++c) {
@@ -252,7 +252,7 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                 const unsigned lk = (unsigned)(k0 + f * Z::KF) + l % Z::KF;
                 if (ljp < nyh && lk < nz) {
                     const unsigned P = lk * nyh + ljp;  // row pair index, rows 2P and 2P + 1
-                    const cpx<T> h = x_forward_out<T, N>(lds + l * C::LS, k, g.bcx, twc);
+                    const cpx<T> h = x_forward_out<T, N>(lds + l * C::LS, k, BCX, twc);
                     v.W[(2 * P) * N + k] = h.x;
                     v.W[(2 * P + 1) * N + k] = h.y;
                 }
@@ -271,7 +271,7 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
 // transformed along x into W32 exactly as the FP32 P1 would.  The mean of r32,
 // which the FP32 P1 removes, is FP64 rounding noise here and is not removed.
 // Per tile: r^2, bt^2, p, p^2, r in FP64.  One column per thread.
-template <int N, int COEF, int WEIGHT>
+template <int N, int COEF, int WEIGHT, int BCX>
 __global__ void __launch_bounds__((LineCfg<float, N>::NT), (LineCfg<float, N>::MINB))
 k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     using C = LineCfg<float, N>;
@@ -334,7 +334,7 @@ k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                 zm.pair(pl[0], pl[1], pl[2], sd, zm.edge_get(eb, i), in);
                 cpx<float> qv = {0.0f, 0.0f};
                 if (valid) {
-                    const PairOut<double> pr = pair_eval<double, COEF, WEIGHT>(g, in, bm, rmax, rinv, x_walls(g, i));
+                    const PairOut<double> pr = pair_eval<double, COEF, WEIGHT>(g, in, bm, rmax, rinv, BCX ? x_walls(g, i) : 0u);
                     acc[0] += pr.a.r * pr.a.r + pr.b.r * pr.b.r;
                     acc[1] += pr.a.bt * pr.a.bt + pr.b.bt * pr.b.bt;
                     acc[2] += pr.a.pc + pr.b.pc;
@@ -346,7 +346,7 @@ k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                     r32[a + (unsigned)g.nx] = rb;
                     qv = {(float)pr.a.w * ra, (float)pr.b.w * rb};
                 }
-                lds[(sidx * Z::KF + q) * C::LS + C::pos(x_slot(i, N, g.bcx))] = qv;
+                lds[(sidx * Z::KF + q) * C::LS + C::pos(x_slot(i, N, BCX))] = qv;
                 pl[0] = pl[1];
                 pl[1] = pl[2];
                 pl[2] = nn;
@@ -362,7 +362,7 @@ k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                 const unsigned lk = (unsigned)(k0 + f * Z::KF) + l % Z::KF;
                 if (ljp < nyh && lk < nz) {
                     const unsigned P = lk * nyh + ljp;
-                    const cpx<float> h = x_forward_out<float, N>(lds + l * C::LS, kx, g.bcx, twc);
+                    const cpx<float> h = x_forward_out<float, N>(lds + l * C::LS, kx, BCX, twc);
                     W32[(2 * P) * N + kx] = h.x;
                     W32[(2 * P + 1) * N + kx] = h.y;
                 }
@@ -609,7 +609,7 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
 // MODE 0: FP64 p += dp - mean(p) (or FP32 d32 += dp); MODE 1: assign to p (L^+
 // sweep); MODE 2: FP32 d32 = dp, the first inner sweep after a fused outer
 // residual (d32 holds nothing yet).
-template <typename T, int N, int MODE>
+template <typename T, int N, int MODE, int BCX>
 __global__ void __launch_bounds__((LineCfg<T, N>::NT))
 k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) {
     using C = LineCfg<T, N>;
@@ -646,7 +646,7 @@ k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
             const int e = threadIdx.x + it * C::NT;
             lds[(e / N) * C::LS + C::pos(e % N)] = wb[it];
         }
-        if (g.bcx) {
+        if constexpr (BCX != 0) {
             // cosine transform between walls: the FFT input pairs coefficient k
             // with coefficient N - k of the same line
             __syncthreads();
@@ -695,7 +695,7 @@ k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
             const unsigned P = grp * C::L + l;
             if (P < nlines) {
                 cpx<T> h;
-                if (g.bcx) {
+                if constexpr (BCX != 0) {
                     const cpx<T> r = lds[l * C::LS + C::pos(x_slot(k, N, 1))];
                     h = {r.x, -r.y};
                 } else {
@@ -760,10 +760,13 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
                         using Z = P1Tile<T, N>;
                         const unsigned nt = (((unsigned)g.ny / 2 + Z::SUB - 1) / Z::SUB) *
                                             (((unsigned)g.nz + Z::KM - 1) / Z::KM);
-                        const void* k = (const void*)&k_resid_dhtx_z<T, N, CO, WE>;
-                        const int nb = persistent_grid(k, C::NT, nt, nslots, share);
                         if (nunits) *nunits = (int)nt;
-                        k_resid_dhtx_z<T, N, CO, WE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
+                        return dispatch_bc(g.bcx, [&]<int BC>() {
+                            const void* k = (const void*)&k_resid_dhtx_z<T, N, CO, WE, BC>;
+                            const int nb = persistent_grid(k, C::NT, nt, nslots, share);
+                            k_resid_dhtx_z<T, N, CO, WE, BC><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
+                            return hipGetLastError();
+                        });
                     } else {
                         const void* k = (const void*)&k_resid_dhtx<T, N, MODE, CO, WE>;
                         const int nb = persistent_grid(k, C::NT, ng, nslots, share);
@@ -793,15 +796,18 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
             return dispatch_len(g.nx, [&]<int N>() {
                 using C = LineCfg<T, N>;
                 const unsigned ng = (rows + C::L - 1) / C::L;
-                const int nb = persistent_grid((const void*)&k_dhtx_update<T, N, MODE>, C::NT, ng, nslots, share);
-                if constexpr (MODE == 0 && sizeof(T) == 4) {
-                    if (stage == kStageTail) {
-                        k_dhtx_update<T, N, 2><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t, stage);
-                        return hipGetLastError();
+                return dispatch_bc(g.bcx, [&]<int BC>() {
+                    const int nb =
+                        persistent_grid((const void*)&k_dhtx_update<T, N, MODE, BC>, C::NT, ng, nslots, share);
+                    if constexpr (MODE == 0 && sizeof(T) == 4) {
+                        if (stage == kStageTail) {
+                            k_dhtx_update<T, N, 2, BC><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t, stage);
+                            return hipGetLastError();
+                        }
                     }
-                }
-                k_dhtx_update<T, N, MODE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t, stage);
-                return hipGetLastError();
+                    k_dhtx_update<T, N, MODE, BC><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t, stage);
+                    return hipGetLastError();
+                });
             });
         default:
             return hipErrorInvalidValue;
@@ -839,10 +845,12 @@ hipError_t launch_outer_fused(const GridArgs& g, const Tables& t, const Slot* sl
             const unsigned nt = (((unsigned)g.ny / 2 + Z::SUB - 1) / Z::SUB) * (((unsigned)g.nz + Z::KM - 1) / Z::KM);
             if (nunits) *nunits = (int)nt;
             return dispatch_op(g.coef, g.weight, [&]<int CO, int WE>() {
-                const void* k = (const void*)&k_outer_resid_dhtx<N, CO, WE>;
-                const int nb = persistent_grid(k, C::NT, nt, nslots, share);
-                k_outer_resid_dhtx<N, CO, WE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
-                return hipGetLastError();
+                return dispatch_bc(g.bcx, [&]<int BC>() {
+                    const void* k = (const void*)&k_outer_resid_dhtx<N, CO, WE, BC>;
+                    const int nb = persistent_grid(k, C::NT, nt, nslots, share);
+                    k_outer_resid_dhtx<N, CO, WE, BC><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
+                    return hipGetLastError();
+                });
             });
         } else {
             return hipErrorInvalidValue;
