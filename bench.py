@@ -308,6 +308,24 @@ def deposit_leg(P, torch, n, reps):
                 bytes=nbytes, gbs=nbytes / dt / 1e9)
 
 
+def copy_ceiling(torch, mib=1024, reps=10):
+    """Rate of a plain device-to-device copy of `mib` MiB (read + write bytes per
+    second): the practical HBM ceiling next to the published peak."""
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * n * 8 / ms / 1e6
+
+
 def cpu_baseline(prob, fp64_iters):
     """The oracle (single-threaded C, FP64) on a bounded sample of the same
     workload: one residual evaluation plus one iteration, scaled to the
@@ -365,6 +383,8 @@ def main():
                 "traffic": measured_traffic(dom["kernel"], args.size),
                 "bytes_per_launch": dom["bytes_per_launch"], "avg_launch_us": dom["avg_launch_us"],
                 "launches": dom["launches"], "working_launches": dom["working_launches"]}
+    roofline["copy_ceiling_gbs"] = copy_ceiling(torch)
+    roofline["frac_of_copy"] = dom["gbs"] / roofline["copy_ceiling_gbs"]
 
     line = {
         "metric": METRIC,

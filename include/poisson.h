@@ -242,7 +242,8 @@ int poisson_deposit(poisson_t h, int n_particles, const double* pos, const doubl
 
 /* out_p = I(field)(x_p): trilinear interpolation of a device FP64 cell field at
  * the particle positions (the adjoint of P up to the factor 1/(hx hy hz)).
- * out: n_particles device values.  Blocks until done. */
+ * out: n_particles device values, not overlapping pos or field.  Blocks until
+ * done. */
 int poisson_interpolate(poisson_t h, int n_particles, const double* pos, const double* field, double* out);
 
 /* ---- serving: many independent solves of different sizes -----------------

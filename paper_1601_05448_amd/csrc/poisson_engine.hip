@@ -672,6 +672,9 @@ int poisson_kernel_timer_read(poisson_t h, double* total_ms, long long* launches
 int poisson_divergence(poisson_t h, const double* rho, const double* mx, const double* my, const double* mz,
                        double* out) {
     if (!h || !rho || !mx || !my || !mz || !out || h->g.bcx != 0) return POISSON_EINVAL;
+    const size_t fb = (size_t)h->g.n * sizeof(double);
+    for (const void* f : {(const void*)rho, (const void*)mx, (const void*)my, (const void*)mz})
+        if (overlaps(out, fb, f, fb)) return POISSON_EINVAL;
     int rc = hip_status(launch_divergence(h->g, rho, mx, my, mz, nullptr, 1.0, out, h->stream));
     if (rc != POISSON_OK) return rc;
     return hip_status(hipStreamSynchronize(h->stream));
@@ -734,6 +737,9 @@ int poisson_deposit(poisson_t h, int n_particles, const double* pos, const doubl
 
 int poisson_interpolate(poisson_t h, int n_particles, const double* pos, const double* field, double* out) {
     if (!h || n_particles < 0 || (n_particles > 0 && (!pos || !out)) || !field || h->g.bcx != 0)
+        return POISSON_EINVAL;
+    const size_t ob = (size_t)n_particles * sizeof(double);
+    if (overlaps(out, ob, pos, 3 * ob) || overlaps(out, ob, field, (size_t)h->g.n * sizeof(double)))
         return POISSON_EINVAL;
     int rc = particle_ws(h, 256);
     if (rc != POISSON_OK) return rc;

@@ -486,8 +486,13 @@ __device__ __forceinline__ cpx<T> scaled_conj(cpx<T> zk, cpx<T> zm, T sa, T sb) 
     return {hp * zk.x + hm * zm.x, hm * zm.y - hp * zk.y};  // conj(hp Z_k + hm conj Z_{N-k})
 }
 
+// The FP32 register path at N = 256 is sized for three blocks per CU (LDS
+// would allow four; its registers with the prefetch buffer allow three).
+template <typename T, int N>
+constexpr int z_min_blocks() { return (sizeof(T) == 4 && N == 256) ? 3 : LineCfg<T, N>::MINB; }
+
 template <typename T, int N, int MODE>
-__global__ void __launch_bounds__((LineCfg<T, N>::NT), (LineCfg<T, N>::MINB))
+__global__ void __launch_bounds__((LineCfg<T, N>::NT), (z_min_blocks<T, N>()))
 k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) {
     using C = LineCfg<T, N>;
     __shared__ cpx<T> lds[C::L * C::LS];

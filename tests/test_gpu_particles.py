@@ -99,6 +99,11 @@ def test_deposit_and_interpolate_reject_bad_positions():
             with pytest.raises(P.PoissonError) as e:
                 P.poisson_interpolate(h, dev(p2), dev(np.zeros(shape)), dev(np.zeros(100)))
             assert e.value.code == P.POISSON_EDOMAIN
+        # outputs over inputs
+        dpos = dev(pos)
+        with pytest.raises(P.PoissonError) as e:
+            P.poisson_interpolate(h, dpos, dev(np.zeros(shape)), dpos.view(-1)[:100])
+        assert e.value.code == P.POISSON_EINVAL
         # the handle still works afterwards
         out = dev(np.zeros(shape))
         P.poisson_deposit(h, dev(pos), None, out)

@@ -150,6 +150,9 @@ def test_project_rejects_walls_and_bad_arguments():
                 P.poisson_project(h, rho, *m, rd, c_dt, p, 1e-10)
         with pytest.raises(P.PoissonError):  # p aliases a momentum component
             P.poisson_project(h, rho, m[0], m[1], m[2], rd, C_DT, m[1], 1e-10)
+        with pytest.raises(P.PoissonError) as e:  # the divergence written over its input
+            P.poisson_divergence(h, rho, m[0], m[1], m[2], m[2])
+        assert e.value.code == P.POISSON_EINVAL
     finally:
         P.poisson_destroy(h)
 
