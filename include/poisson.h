@@ -214,7 +214,8 @@ int poisson_divergence(poisson_t h, const double* rho, const double* mx, const d
  * *chi (host pointer, may be NULL) receives chi = -c_dt mean(RHS^Pois), so
  * that afterwards div(beta m) = RHS^div - chi up to c_dt times the solve's
  * residual.  Returns the solve's status; on POISSON_OK and POISSON_ENOCONV the
- * momentum is corrected, on any other status it and p are untouched.
+ * momentum is corrected, on any other status it is untouched (and p is as
+ * poisson_solve leaves it for that status).
  * poisson_get_stats describes the solve.  The six fields must not overlap.
  * The first call allocates one cell field of workspace in the handle. */
 int poisson_project(poisson_t h, const double* rho, double* mx, double* my, double* mz, const double* rhs_div,

@@ -222,3 +222,30 @@ def test_full_size_duct(precision):
     assert res["rel"] <= 1e-10
     assert abs(st["rel_resid"] - res["rel"]) <= 1e-3 * res["rel"]
     assert st["err_bound_rel"] < 1e-8
+
+
+@pytest.mark.parametrize("precision", [P.POISSON_FP64, P.POISSON_FP32_REFINE])
+def test_walls_graph_replays_match_plain_launches(precision):
+    """The captured-graph path runs the wall kernels too: three solves with
+    graphs against plain launches, bitwise equal."""
+    announce("walls graphs", precision)
+    import torch
+
+    prob = inputs.workload_duct(32)
+    rho, b = dev(prob.rho), dev(prob.b)
+    outs = {}
+    for graphs in (False, True):
+        with P.Solver(prob.shape, prob.lengths, precision=precision, use_graphs=graphs, bc_x=W) as s:
+            p = dev(np.zeros(prob.shape))
+            runs = []
+            for rep in range(3):
+                p.zero_()
+                junk = torch.cos(rho) * (rep + 2)  # eager work between replays
+                st = s.solve(rho, b, p, 1e-10)
+                assert float(junk.sum()) != 0.0 and st["code"] == P.POISSON_OK
+                runs.append((host(p).copy(), st["iters"]))
+            outs[graphs] = runs
+    for (pa, ia), (pb, ib) in zip(outs[False], outs[True]):
+        assert ia == ib and np.array_equal(pa, pb)
+    res = oracle.residual(prob.rho, prob.b, outs[True][-1][0], prob.lengths, bcx=oracle.BC_WALLS_X)
+    assert res["rel"] <= 1e-10
