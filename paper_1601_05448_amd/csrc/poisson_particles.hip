@@ -10,11 +10,12 @@
 // key and, within a key, by index; for every occupied cell the thread at the
 // start of its run of sorted particles records that start and adds, over the
 // run in order, the eight corner sums sum_p q_p W_a W_b W_e (a, b, e the offsets
-// 0/1 of the corner cell in x, y, z); then one thread per grid cell adds the
-// matching corner sums of its eight lower neighbours (itself included), in a
-// fixed order.  Every cell is written once, by one thread, with the same sum
-// order in every run, and a cell waits for memory twice (the eight run starts,
-// then the eight sums).  I is a plain gather, one thread per particle.
+// 0/1 of the corner cell in x, y, z); then every grid cell adds the matching
+// corner sums of its eight lower neighbours (itself included), in a fixed
+// order, by one thread that marches along z (four run starts loaded per cell,
+// the next plane's while the current cell adds).  Every cell is written once,
+// by one thread, with the same sum order in every run.  I is a plain gather,
+// one thread per particle.
 #include <hip/hip_runtime.h>
 
 #include <rocprim/device/device_radix_sort.hpp>
@@ -105,32 +106,51 @@ k_part_runs(PartGeom pg, int np, const double* __restrict__ pos, const double* _
 }
 
 // out_c = sum over the lower neighbours c - (a, b, e), a, b, e in {0, 1}, of
-// their runs' corner sums for corner a + 2 b + 4 e, times 1/V.  One thread per
-// cell: blockIdx.z = k, blockIdx.y = j, x across the threads.
+// their runs' corner sums for corner a + 2 b + 4 e, times 1/V.  A thread owns
+// column (i, j) and marches along z through kGatherPlanes cells: the run starts
+// of plane k (four columns: (i, j), (i-1, j), (i, j-1), (i-1, j-1)) serve as the
+// e = 0 corners of cell k and the e = 1 corners of cell k + 1, and the next
+// plane's starts are loaded while the current cell adds its sums.
+constexpr int kGatherPlanes = 16;
+
 __global__ void __launch_bounds__(kPartThreads)
 k_part_gather(PartGeom pg, const unsigned* __restrict__ first, const double* __restrict__ corner,
               double* __restrict__ out) {
     const unsigned nx = pg.nx, ny = pg.ny, nz = pg.nz;
-    const unsigned i = blockIdx.x * kPartThreads + threadIdx.x, j = blockIdx.y, k = blockIdx.z;
+    const unsigned i = blockIdx.x * kPartThreads + threadIdx.x, j = blockIdx.y;
     if (i >= nx) return;
-    const unsigned im = (i == 0) ? nx - 1 : i - 1, jm = (j == 0) ? ny - 1 : j - 1, km = (k == 0) ? nz - 1 : k - 1;
-    // corner q = a + 2 b + 4 e; all eight lookups are issued before any is used,
-    // so that a thread waits for memory once, not once per corner
-    unsigned cc[8], f0[8];
+    const unsigned im = (i == 0) ? nx - 1 : i - 1, jm = (j == 0) ? ny - 1 : j - 1;
+    const unsigned col[4] = {j * nx + i, j * nx + im, jm * nx + i, jm * nx + im};  // a + 2 b
+    const unsigned sz = nx * ny;
+    const unsigned k0 = blockIdx.z * kGatherPlanes;
+    const unsigned k1 = (k0 + kGatherPlanes < nz) ? k0 + kGatherPlanes : nz;
+    unsigned prev[4], cur[4];
+    const unsigned km = (k0 == 0 ? nz - 1 : k0 - 1) * sz;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const unsigned ii = (q & 1) ? im : i, jj = (q & 2) ? jm : j, kk = (q & 4) ? km : k;
-        cc[q] = (kk * ny + jj) * nx + ii;
+    for (int q = 0; q < 4; ++q) prev[q] = first[km + col[q]];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) cur[q] = first[k0 * sz + col[q]];
+    for (unsigned k = k0; k < k1; ++k) {
+        unsigned nxt[4];
+        const unsigned kn = (k + 1 < nz ? k + 1 : 0) * sz;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) nxt[q] = first[kn + col[q]];  // in flight during this cell
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const unsigned f0 = (q & 4) ? prev[q & 3] : cur[q & 3];
+            v[q] = (f0 == kNoParticle) ? 0.0 : corner[8 * (size_t)f0 + q];
+        }
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc += v[q];
+        out[(size_t)k * sz + col[0]] = acc * pg.inv_v;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            prev[q] = cur[q];
+            cur[q] = nxt[q];
+        }
     }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) f0[q] = first[cc[q]];
-    double v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = (f0[q] == kNoParticle) ? 0.0 : corner[8 * (size_t)f0[q] + q];
-    double acc = 0.0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc += v[q];
-    out[((size_t)k * ny + j) * nx + i] = acc * pg.inv_v;
 }
 
 __global__ void __launch_bounds__(kPartThreads)
@@ -227,7 +247,8 @@ hipError_t launch_deposit(const GridArgs& g, int np, const double* pos, const do
     const unsigned fb = (unsigned)std::min<unsigned long long>((n + kPartThreads - 1) / kPartThreads, 65536ull);
     k_part_fill<<<fb, kPartThreads, 0, s>>>(first, n, kNoParticle);
     if (np > 0) k_part_runs<<<pb, kPartThreads, 0, s>>>(pg, np, pos, q, key_s, idx_s, first, corner);
-    const dim3 gg((unsigned)(g.nx + kPartThreads - 1) / kPartThreads, (unsigned)g.ny, (unsigned)g.nz);
+    const dim3 gg((unsigned)(g.nx + kPartThreads - 1) / kPartThreads, (unsigned)g.ny,
+                  (unsigned)(g.nz + kGatherPlanes - 1) / kGatherPlanes);
     k_part_gather<<<gg, kPartThreads, 0, s>>>(pg, first, corner, out);
     return hipGetLastError();
 }
