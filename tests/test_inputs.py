@@ -59,3 +59,49 @@ def test_bandlim_is_band_limited_zero_mean_unit_rms():
     kx = 2 * math.pi * np.fft.fftfreq(nx, 1 / nx) / L[0]
     kk = kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2
     assert np.max(np.abs(F[kk > kmax * kmax * (1 + 1e-9)])) < 1e-9 * np.max(np.abs(F))
+
+
+def test_shifted_bandlim_is_the_same_field_carried_along():
+    """A shift of whole cells (any axis) is a roll of the unshifted field; the
+    same draws with a fractional shift keep the band limit and the RMS."""
+    shape, L, kmax = (12, 10, 16), (2 * math.pi, 2.5, 3.0), 3.0
+    nz, ny, nx = shape
+    h = (L[0] / nx, L[1] / ny, L[2] / nz)
+    base = inputs.bandlim(shape, L, kmax, np.random.default_rng(9))
+
+    def shifted(sh):
+        t2, ez = inputs._bandlim_spectrum(shape, L, kmax, np.random.default_rng(9), sh)
+        f = (ez.real.T @ t2.real - ez.imag.T @ t2.imag).reshape(shape)
+        f -= f.mean()
+        return f / math.sqrt(np.mean(f * f))
+
+    got = shifted((3 * h[0], -2 * h[1], 5 * h[2]))
+    want = np.roll(np.roll(np.roll(base, 3, axis=2), -2, axis=1), 5, axis=0)
+    assert np.max(np.abs(got - want)) < 1e-12
+    half = shifted((0.5 * h[0], 0.25 * h[1], 0.0))
+    assert abs(np.sqrt(np.mean(half * half)) - 1) < 1e-12 and abs(half.mean()) < 1e-14
+
+
+def test_duct_and_projection_inputs():
+    """The duct is 2N x N x N on [0, 4pi) x [0, 2pi)^2 with max/min rho = ratio;
+    the projection inputs are three band-limited momentum fields and a
+    divergence target scaled by 0.1; both are deterministic."""
+    p = inputs.workload_duct(8)
+    assert p.shape == (8, 8, 16) and p.lengths == (4 * math.pi, 2 * math.pi, 2 * math.pi)
+    assert abs(p.rho.max() / p.rho.min() - 4.0) < 1e-12
+    assert np.array_equal(p.rho, inputs.workload_duct(8).rho)
+    mx, my, mz, rd = inputs.momentum_fields((8, 6, 12), (2 * math.pi,) * 3)
+    for m in (mx, my, mz):
+        assert abs(np.sqrt(np.mean(m * m)) - 1) < 1e-12
+    assert abs(np.sqrt(np.mean(rd * rd)) - 0.1) < 1e-12
+    assert not np.array_equal(mx, my)
+    assert np.array_equal(rd, inputs.momentum_fields((8, 6, 12), (2 * math.pi,) * 3)[3])
+
+
+def test_workload3_particles_are_the_workload_draws():
+    """workload3_particles returns the positions workload 3 deposits."""
+    pos = inputs.workload3_particles(500)
+    assert pos.shape == (500, 3) and pos.min() >= 0 and pos.max() < 2 * math.pi
+    d = inputs.cic_deposit((8, 8, 8), (2 * math.pi,) * 3, pos)
+    w = inputs.workload3(8, particles=500)
+    assert np.allclose(w.rho, 1.0 / (1.0 + 9.0 * d / d.max()), rtol=0, atol=1e-15)
