@@ -197,12 +197,16 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                 // counts are the same every step)
                 PlaneRows<T> nn[Z::CPT];
                 PlaneSide<T> ns[Z::CPT];
+                // waves issuing loads go first, so that the memory requests of
+                // all resident waves are out before any spends its step computing
+                __builtin_amdgcn_s_setprio(2);
 #pragma unroll
                 for (int c = 0; c < Z::CPT; ++c) {
                     const unsigned i = col0 + c * C::NT;
                     zm.load_rows(zm.plane(k + 2), i, nn[c]);
                     zm.load_side(zm.plane(k + 1), i, ns[c]);
                 }
+                __builtin_amdgcn_s_setprio(0);
                 T* eb = edge + ((q & 1) * Z::SUB + sidx) * Z::EDGE;
 #pragma unroll
                 for (int c = 0; c < Z::CPT; ++c) zm.edge_put(eb, col0 + c * C::NT, pl[c][1]);
