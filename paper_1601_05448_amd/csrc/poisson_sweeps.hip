@@ -329,8 +329,10 @@ k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                 const bool valid = jvalid && k < (int)nz;
                 PlaneRows<double> nn;
                 PlaneSide<double> ns;
+                __builtin_amdgcn_s_setprio(2);
                 zm.load_rows(zm.plane(k + 2), i, nn);
                 zm.load_side(zm.plane(k + 1), i, ns);
+                __builtin_amdgcn_s_setprio(0);
                 double* eb = edge + ((q & 1) * Z::SUB + sidx) * Z::EDGE;
                 zm.edge_put(eb, i, pl[1]);
                 __syncthreads();
@@ -436,7 +438,9 @@ k_dht_cols(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) {
             const bool cur_valid = valid;
             const unsigned cur_base = base;
             const unsigned ng = grp + gridDim.x;
+            __builtin_amdgcn_s_setprio(2);
             if (ng < ngroups) load(ng, valid, base);  // in flight during the FFT
+            __builtin_amdgcn_s_setprio(0);
             fft256_regs<T>(v, ln, e0, tw);
 #pragma unroll
             for (int b = 0; b < 16; ++b) ln[C::pos(e0 + 16 * b)] = v[b];
@@ -460,7 +464,9 @@ k_dht_cols(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) {
         const bool cur_valid = valid;
         const unsigned cur_base = base;
         const unsigned ng = grp + gridDim.x;
+        __builtin_amdgcn_s_setprio(2);
         if (ng < ngroups) load(ng, valid, base);  // in flight during the FFT
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         fft_block_lines<T, N>(lds, tw);
         if (cur_valid) {
@@ -547,7 +553,9 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
             const unsigned j = cur_valid ? line / (unsigned)g.nxh : 0u, m = cur_valid ? line - j * (unsigned)g.nxh : 0u;
             const T lxe = lamx[2 * m], lxo = lamx[2 * m + 1], lyj = lamy[j];
             const unsigned ng = grp + gridDim.x;
+            __builtin_amdgcn_s_setprio(2);
             if (ng < ngroups) load(ng, valid, base);  // in flight during the two FFTs
+            __builtin_amdgcn_s_setprio(0);
             fft256_regs<T>(v, ln, e0, tw);  // v[b] = X[e0 + 16 b]
 #pragma unroll
             for (int b = 0; b < 16; ++b) ln[C::pos(e0 + 16 * b)] = v[b];
@@ -585,7 +593,9 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
         const unsigned j = cur_valid ? line / (unsigned)g.nxh : 0u, m = cur_valid ? line - j * (unsigned)g.nxh : 0u;
         const T lxe = lamx[2 * m], lxo = lamx[2 * m + 1], lyj = lamy[j];
         const unsigned ng = grp + gridDim.x;
+        __builtin_amdgcn_s_setprio(2);
         if (ng < ngroups) load(ng, valid, base);  // in flight during the two FFTs
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         fft_block_lines<T, N>(lds, tw);
         // scaled spectra of the pairs (k, N-k) of this thread's line (the symbol is
@@ -685,7 +695,9 @@ k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
             }
         }
         const unsigned ng = grp + gridDim.x;
+        __builtin_amdgcn_s_setprio(2);
         if (ng < ngroups) load_w(ng);
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         fft_block_lines<T, N>(lds, tw);
         if (MODE == 0 && sizeof(T) == 8) {
