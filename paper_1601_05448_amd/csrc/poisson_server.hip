@@ -358,10 +358,11 @@ int poisson_server_tick(poisson_server_t s) {
     }
     if ((rc = admit(s)) != POISSON_OK) return rc;
     // A class at least four times larger than the smallest active one takes
-    // half of the chip's resident blocks in its persistent sweeps, so that the
-    // small classes' blocks find room beside it instead of waiting for each of
-    // its sweeps to end (its long lines run one 512-thread block per CU, so
-    // half the blocks is half the CUs).
+    // three quarters of the chip's resident blocks in its persistent sweeps,
+    // one at least 64 times larger half of them, so that the small classes'
+    // blocks find room beside it instead of waiting for each of its sweeps to
+    // end (the long lines of a very large grid run one 512-thread block per
+    // CU, so there the share is a share of the CUs).
     long long smallest = 0;
     for (auto& kv : s->classes)
         if (!kv.second->active.empty() && (smallest == 0 || kv.second->cells < smallest)) smallest = kv.second->cells;
@@ -370,7 +371,7 @@ int poisson_server_tick(poisson_server_t s) {
     for (auto& kv : s->classes) {
         SizeClass* c = kv.second.get();
         if (c->in_flight || c->active.empty()) continue;
-        c->geo.share = (c->cells >= 4 * smallest) ? 0.5f : 1.0f;
+        c->geo.share = (c->cells >= 64 * smallest) ? 0.5f : (c->cells >= 4 * smallest) ? 0.75f : 1.0f;
         if (!forked) {
             if (hipEventRecord(s->fork_ev, s->stream) != hipSuccess) return POISSON_EHIP;
             forked = true;
