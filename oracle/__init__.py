@@ -1,7 +1,7 @@
 """ctypes binding of the FP64 CPU oracle (``oracle/poisson_oracle.c``).
 
 TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU-baseline
-leg of the benchmark use it to judge the GPU library.  The product path never
+leg of the benchmark use it to check the GPU library.  The product path never
 imports it, and this module imports nothing from the product.
 
 Each function cites the part of Pouransari, Mortazavi & Mani (arXiv:1601.05448)

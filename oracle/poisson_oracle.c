@@ -8,7 +8,7 @@
  * turbulence simulation" (arXiv:1601.05448).
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the checker against which the GPU
- * library is judged.  Only the test-suite, the smoke check and the CPU-baseline
+ * library is checked.  Only the test-suite, the smoke check and the CPU-baseline
  * leg of the benchmark may load it.  It shares no code, header, table or
  * constant with the GPU path and includes nothing from it.
  *
