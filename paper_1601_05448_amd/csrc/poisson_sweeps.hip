@@ -137,8 +137,11 @@ k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
 // every KF planes the tile's L lines are transformed along x and written out.
 // Within a flush, line l = s KF + q is row pair jp = tj SUB + s of plane
 // k = tk KM + f KF + q.
+template <typename T, int N>
+constexpr int p1_min_blocks();
+
 template <typename T, int N, int COEF, int WEIGHT, int BCX>
-__global__ void __launch_bounds__((LineCfg<T, N>::NT), (LineCfg<T, N>::MINB))
+__global__ void __launch_bounds__((LineCfg<T, N>::NT), (p1_min_blocks<T, N>()))
 k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     using C = LineCfg<T, N>;
     using Z = P1Tile<T, N>;
@@ -384,7 +387,15 @@ template <typename T, int N>
 constexpr bool use_zmarch() {
     using C = LineCfg<T, N>;
     if constexpr (N % 64 != 0) return false;
-    else return (N >= C::NT ? N / C::NT : 1) * (int)sizeof(T) <= 16;
+    else return (N >= C::NT ? N / C::NT : 1) * (int)sizeof(T) <= 32;
+}
+
+// Blocks per CU the residual sweep's registers are sized for: one where four
+// FP64 marching columns per thread need the accumulation registers too.
+template <typename T, int N>
+constexpr int p1_min_blocks() {
+    using C = LineCfg<T, N>;
+    return (N >= C::NT ? N / C::NT : 1) * (int)sizeof(T) > 16 ? 1 : C::MINB;
 }
 
 // ---- P2 / P4: Hartley along y (AX = 1) of the pair-packed columns -------------

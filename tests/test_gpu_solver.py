@@ -160,6 +160,20 @@ def test_solve_ragged_tiles(shape):
     _check_solution(prob, p, st, ref["p"])
 
 
+@pytest.mark.parametrize("shape", [(48, 6, 768), (32, 4, 1024)])
+def test_solve_fp64_long_rows(shape):
+    """FP64 on rows of 768 and 1024 cells: the residual sweep marches four
+    columns per thread (ragged z tiles: 48 and 32 planes)."""
+    announce("solve fp64 long rows", shape)
+    prob = inputs.small_problem(shape=shape, lengths=(TWO_PI, TWO_PI, TWO_PI), ratio=4.0)
+    ref = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, tol=1e-14, max_iter=40, allow_noconv=True)
+    rr = oracle.residual(prob.rho, prob.b, ref["p"], prob.lengths)
+    ref_bound = oracle.error_bound(prob.shape, prob.lengths, float(prob.rho.max()), rr["r_norm"]) / \
+        np.linalg.norm(ref["p"])
+    p, st, _ = _solve_gpu(prob)
+    _check_solution(prob, p, st, ref["p"], ref_bound=ref_bound)
+
+
 @pytest.mark.parametrize("shape", [(6, 12, 128), (24, 6, 512), (24, 12, 64), (12, 8, 1024)])
 def test_solve_fp32_refine_ragged_outer_tiles(shape):
     """FP32 refinement where the FP64 outer residual's column tiles are ragged:
