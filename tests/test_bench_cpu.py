@@ -1,0 +1,61 @@
+"""Host logic of bench.py (no GPU): the one-GPU guard, the counter record it
+reads for the roofline's `traffic`, and its latency percentiles."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+import bench
+from paper_1601_05448_amd import profile_summary
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""  # no JSON line for a run that did not happen
+
+
+def test_sweep_byte_table():
+    # each sweep's FP32 bytes are half its FP64 bytes (every field it moves is
+    # one value per cell in the sweep's precision)
+    for sw, (b64, b32) in bench.SWEEP_BYTES.items():
+        assert b64 == 2 * b32, sw
+    # P1 reads rho, p and b and writes the transformed weighted residual
+    assert bench.SWEEP_BYTES[1] == (4 * 8, 4 * 4)
+
+
+def test_traffic_record_matches_the_kernel_sources():
+    with open(bench.TRAFFIC_FILE) as f:
+        rec = json.load(f)
+    assert set(rec) >= {"f32:k_resid_dhtx_z@256", "f64:k_resid_dhtx_z@256"}
+    if any(v["source_sha256"] != profile_summary.kernel_source_hash() for v in rec.values()):
+        pytest.skip("the counters predate the current kernel sources (bench reports traffic null)")
+    n = 256 ** 3
+    for key, per_cell in (("f32:k_resid_dhtx_z", 16), ("f64:k_resid_dhtx_z", 32)):
+        t = bench.measured_traffic(key, 256)
+        assert t is not None
+        # measured HBM bytes: at least the algorithmic bytes, and the halo
+        # re-reads of the z-marching tiles well under a quarter more
+        assert per_cell * n <= t < 1.25 * per_cell * n, (key, t / n)
+
+
+def test_traffic_is_null_without_a_valid_record(monkeypatch):
+    assert bench.measured_traffic("f32:k_resid_dhtx_z", 128) is None  # no record at this size
+    assert bench.measured_traffic("f32:no_such_kernel", 256) is None
+    monkeypatch.setattr(profile_summary, "kernel_source_hash", lambda: "0" * 64)
+    assert bench.measured_traffic("f32:k_resid_dhtx_z", 256) is None  # sources changed since
+
+
+def test_percentile():
+    assert bench.percentile([3.0, 1.0, 2.0], 0.5) == 2.0
+    assert bench.percentile([5.0], 0.99) == 5.0
+    xs = [float(i) for i in range(101)]  # 0 .. 100
+    assert bench.percentile(xs, 0.99) == pytest.approx(99.0)
+    assert bench.percentile([0.0, 10.0], 0.25) == pytest.approx(2.5)
+    assert bench.percentile([], 0.5) != bench.percentile([], 0.5)  # NaN
