@@ -81,8 +81,8 @@ def _configure(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_dense_bc.argtypes = grid + [i, i, pd, pd, pd]
     lib.oracle_error_bound_bc.argtypes = grid + [i, d, d]
     lib.oracle_error_bound_bc.restype = d
-    lib.oracle_divergence.argtypes = grid + [i, pd, pd, pd, pd, pd]
-    lib.oracle_project.argtypes = grid + [i, i, pd, pd, pd, pd, pd, d, pd, d, i, pi, pdd, pdd]
+    lib.oracle_divergence_bc.argtypes = grid + [i, i, pd, pd, pd, pd, pd]
+    lib.oracle_project_bc.argtypes = grid + [i, i, i, pd, pd, pd, pd, pd, d, pd, d, i, pi, pdd, pdd]
     lib.oracle_deposit.argtypes = grid + [i, pd, pd, pd]
     lib.oracle_interpolate.argtypes = grid + [i, pd, pd, pd]
     return lib
@@ -221,26 +221,29 @@ def error_bound(shape, lengths, rho_max: float, r_norm: float, bcx: int = BC_PER
     return _load().oracle_error_bound_bc(*_grid(shape, lengths), bcx, rho_max, r_norm)
 
 
-def divergence(rho, mx, my, mz, lengths=(2 * np.pi,) * 3, coef: int = COEF_RHO_FACE_MEAN) -> np.ndarray:
+def divergence(rho, mx, my, mz, lengths=(2 * np.pi,) * 3, coef: int = COEF_RHO_FACE_MEAN,
+               bcx: int = BC_PERIODIC) -> np.ndarray:
     """div(u) of face momentum m (m_d[c] on the face between c and c + e_d),
-    u = m / rho_face with 1/rho_face the operator's face coefficient; periodic
-    (appendix A, the divergence of the predicted momentum over rho)."""
+    u = m / rho_face with 1/rho_face the operator's face coefficient; periodic,
+    or closed at both x ends with walls (appendix A, the divergence of the
+    predicted momentum over rho)."""
     rho = np.ascontiguousarray(rho, dtype=np.float64)
     shape = rho.shape
     ms = [_f64(m, shape) for m in (mx, my, mz)]
     out = np.empty(shape)
-    _check(_load().oracle_divergence(*_grid(shape, lengths), coef, _ptr(rho), *(_ptr(m) for m in ms), _ptr(out)),
-           "divergence")
+    _check(_load().oracle_divergence_bc(*_grid(shape, lengths), coef, bcx, _ptr(rho), *(_ptr(m) for m in ms),
+                                        _ptr(out)), "divergence")
     return out
 
 
 def project(rho, mx, my, mz, rhs_div, c_dt: float, p0=None, lengths=(2 * np.pi,) * 3,
             coef: int = COEF_RHO_FACE_MEAN, weight: int = WEIGHT_RHO, tol: float = 1e-13,
-            max_iter: int = 10000):
+            max_iter: int = 10000, bcx: int = BC_PERIODIC):
     """One pressure projection (appendix A): RHS^Pois from the predicted face
     momentum and the divergence target, chi from its mean, the solve, and the
-    momentum correction -C dt grad p.  Returns dict(p, mx, my, mz, chi, iters,
-    rel, code); the inputs are not modified."""
+    momentum correction -C dt grad p (not across the closed x end faces with
+    walls).  Returns dict(p, mx, my, mz, chi, iters, rel, code); the inputs are
+    not modified."""
     rho = np.ascontiguousarray(rho, dtype=np.float64)
     shape = rho.shape
     ms = [np.array(m, dtype=np.float64, order="C", copy=True) for m in (mx, my, mz)]
@@ -250,9 +253,9 @@ def project(rho, mx, my, mz, rhs_div, c_dt: float, p0=None, lengths=(2 * np.pi,)
     rd = _f64(rhs_div, shape)
     p = np.zeros(shape) if p0 is None else np.array(p0, dtype=np.float64, order="C", copy=True)
     it, rel, chi = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
-    rc = _load().oracle_project(*_grid(shape, lengths), coef, weight, _ptr(rho), *(_ptr(m) for m in ms), _ptr(rd),
-                                float(c_dt), _ptr(p), tol, max_iter, ctypes.byref(it), ctypes.byref(rel),
-                                ctypes.byref(chi))
+    rc = _load().oracle_project_bc(*_grid(shape, lengths), coef, bcx, weight, _ptr(rho), *(_ptr(m) for m in ms),
+                                   _ptr(rd), float(c_dt), _ptr(p), tol, max_iter, ctypes.byref(it), ctypes.byref(rel),
+                                   ctypes.byref(chi))
     _check(rc, "project", allow=(OK, ENOCONV))
     return dict(p=p, mx=ms[0], my=ms[1], mz=ms[2], chi=chi.value, iters=it.value, rel=rel.value, code=rc)
 

@@ -717,11 +717,13 @@ double oracle_error_bound(int nx, int ny, int nz, double hx, double hy, double h
  * divergence of beta times the face gradient of p is exactly A p.
  *
  * out = div(u):  out_c = sum_d ( beta_{c+1/2} m_d[c] - beta_{c-1/2} m_d[c-e_d] ) / h_d,
- * periodic. */
-int oracle_divergence(int nx, int ny, int nz, double hx, double hy, double hz, int coef, const double* rho,
-                      const double* mx, const double* my, const double* mz, double* out) {
-    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || (coef != 0 && coef != 1) || !rho || !mx || !my || !mz ||
-        !out)
+ * periodic, or with walls in x (bcx = 1): the two end faces of every x row are
+ * closed, their beta is 0 (face_coef), so the momentum stored for the face
+ * between the last and the first cell takes no part. */
+int oracle_divergence_bc(int nx, int ny, int nz, double hx, double hy, double hz, int coef, int bcx,
+                         const double* rho, const double* mx, const double* my, const double* mz, double* out) {
+    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || (coef != 0 && coef != 1) || (bcx != 0 && bcx != 1) || !rho ||
+        !mx || !my || !mz || !out)
         return OR_EINVAL;
     const double h[3] = {hx, hy, hz};
     const double* m[3] = {mx, my, mz};
@@ -732,8 +734,8 @@ int oracle_divergence(int nx, int ny, int nz, double hx, double hy, double hz, i
                 double acc = 0.0;
                 for (int d = 0; d < 3; ++d) {
                     size_t cp, cm;
-                    const double bp = face_coef(nx, ny, nz, coef, 0, rho, i, j, k, d, +1, &cp);
-                    const double bm = face_coef(nx, ny, nz, coef, 0, rho, i, j, k, d, -1, &cm);
+                    const double bp = face_coef(nx, ny, nz, coef, bcx, rho, i, j, k, d, +1, &cp);
+                    const double bm = face_coef(nx, ny, nz, coef, bcx, rho, i, j, k, d, -1, &cm);
                     acc += (bp * m[d][c] - bm * m[d][cm]) / h[d];
                 }
                 out[c] = acc;
@@ -741,25 +743,28 @@ int oracle_divergence(int nx, int ny, int nz, double hx, double hy, double hz, i
     return OR_OK;
 }
 
-/* One pressure projection of the time advance (appendix A), periodic box:
+/* One pressure projection of the time advance (appendix A), periodic box or,
+ * with bcx = 1, walls in x (closed end faces, as in oracle_divergence_bc):
  *   1. RHS^Pois = ( div(m~ / rho_face) - RHS^div ) / (C dt)
  *   2. chi' = -mean(RHS^Pois), reported as chi = C dt chi' (the paper's chi)
  *   3. solve div(beta grad p) = RHS^Pois + chi' with the paper's iteration
  *      (oracle_solve_bc; p in/out, the previous pressure as the estimate p_g)
  *   4. m_d <- m~_d - C dt (p_{c+e_d} - p_c) / h_d on every face
  * Afterwards div(m / rho_face) = RHS^div - chi up to C dt times the residual
- * of the solve.  c_dt is the product C_RK4^pre[k] dt.  mx, my, mz are in/out.
- * Returns the solve's status (OR_OK, OR_ENOCONV, ...). */
-int oracle_project(int nx, int ny, int nz, double hx, double hy, double hz, int coef, int weight,
-                   const double* rho, double* mx, double* my, double* mz, const double* rhs_div, double c_dt,
-                   double* p, double tol, int max_iter, int* iters_out, double* rel_out, double* chi_out) {
-    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || !rho || !mx || !my || !mz || !rhs_div || !p ||
-        !(c_dt > 0.0) || !isfinite(c_dt))
+ * of the solve.  c_dt is the product C_RK4^pre[k] dt.  mx, my, mz are in/out;
+ * with walls the momentum of the closed end faces is left as given (the face
+ * gradient across them is not defined).  Returns the solve's status (OR_OK,
+ * OR_ENOCONV, ...). */
+int oracle_project_bc(int nx, int ny, int nz, double hx, double hy, double hz, int coef, int bcx, int weight,
+                      const double* rho, double* mx, double* my, double* mz, const double* rhs_div, double c_dt,
+                      double* p, double tol, int max_iter, int* iters_out, double* rel_out, double* chi_out) {
+    if (check_grid(nx, ny, nz, hx, hy, hz) != OR_OK || (bcx != 0 && bcx != 1) || !rho || !mx || !my || !mz ||
+        !rhs_div || !p || !(c_dt > 0.0) || !isfinite(c_dt))
         return OR_EINVAL;
     const size_t n = (size_t)nx * ny * nz;
     double* b = malloc(n * sizeof(double));
     if (!b) return OR_ENOMEM;
-    int rc = oracle_divergence(nx, ny, nz, hx, hy, hz, coef, rho, mx, my, mz, b);
+    int rc = oracle_divergence_bc(nx, ny, nz, hx, hy, hz, coef, bcx, rho, mx, my, mz, b);
     if (rc != OR_OK) {
         free(b);
         return rc;
@@ -767,8 +772,8 @@ int oracle_project(int nx, int ny, int nz, double hx, double hy, double hz, int 
     for (size_t c = 0; c < n; ++c) b[c] = (b[c] - rhs_div[c]) / c_dt;
     if (chi_out) *chi_out = -c_dt * mean_of(b, n);
     double bm;
-    rc = oracle_solve_bc(nx, ny, nz, hx, hy, hz, coef, 0, weight, rho, b, p, tol, max_iter, iters_out, rel_out, &bm,
-                         NULL);
+    rc = oracle_solve_bc(nx, ny, nz, hx, hy, hz, coef, bcx, weight, rho, b, p, tol, max_iter, iters_out, rel_out,
+                         &bm, NULL);
     free(b);
     if (rc != OR_OK && rc != OR_ENOCONV) return rc;
     const double h[3] = {hx, hy, hz};
@@ -778,8 +783,8 @@ int oracle_project(int nx, int ny, int nz, double hx, double hy, double hz, int 
             for (int i = 0; i < nx; ++i) {
                 const size_t c = cell(nx, ny, i, j, k);
                 for (int d = 0; d < 3; ++d) {
-                    size_t cp;
-                    (void)face_coef(nx, ny, nz, coef, 0, NULL, i, j, k, d, +1, &cp);
+                    size_t cp;  /* a closed face gives cp = c: no correction */
+                    (void)face_coef(nx, ny, nz, coef, bcx, NULL, i, j, k, d, +1, &cp);
                     m[d][c] -= c_dt * (p[cp] - p[c]) / h[d];
                 }
             }
@@ -855,4 +860,4 @@ int oracle_interpolate(int nx, int ny, int nz, double hx, double hy, double hz, 
     return OR_OK;
 }
 
-int oracle_abi_version(void) { return 4; }
+int oracle_abi_version(void) { return 5; }

@@ -55,6 +55,11 @@ MUTANTS = {
     "interpolation drops a corner": ("for (int a = 0; a < 2; ++a) acc += wx[a]", "for (int a = 0; a < 1; ++a) acc += wx[a]"),
     "momentum correction sign": ("m[d][c] -= c_dt * (p[cp] - p[c]) / h[d];",
                                  "m[d][c] += c_dt * (p[cp] - p[c]) / h[d];"),
+    "correction across the closed x face": ("(void)face_coef(nx, ny, nz, coef, bcx, NULL, i, j, k, d, +1, &cp);",
+                                            "(void)face_coef(nx, ny, nz, coef, 0, NULL, i, j, k, d, +1, &cp);"),
+    "divergence ignores the walls": (
+        "int rc = oracle_divergence_bc(nx, ny, nz, hx, hy, hz, coef, bcx, rho, mx, my, mz, b);",
+        "int rc = oracle_divergence_bc(nx, ny, nz, hx, hy, hz, coef, 0, rho, mx, my, mz, b);"),
 }
 
 
