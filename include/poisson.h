@@ -190,12 +190,14 @@ int poisson_time_sweep(poisson_t h, int sweep, int fp32, const double* rho, cons
  * gradient is divided by the new density, its divergence gives the right-hand
  * side of the variable-coefficient Poisson equation (with the consistency
  * constant chi from its mean), and after the solve the momentum is corrected
- * by the pressure gradient.  Periodic box only (a handle with
- * POISSON_BC_WALLS_X gets POISSON_EINVAL).
+ * by the pressure gradient.  Periodic box, or walls in x (POISSON_BC_WALLS_X):
+ * then the two x end faces of every row are closed, the momentum stored for
+ * the face between the last and the first cell takes no part in the
+ * divergence and is not corrected, and p solves the walls problem.
  *
  * Face momentum: mx, my, mz are device FP64 arrays [nz][ny][nx] like the
  * cell fields; m_d[c] is the normal momentum on the face between cell c and
- * its neighbour c + e_d (periodic).  The face velocity is u = beta m, with
+ * its neighbour c + e_d (wrapped).  The face velocity is u = beta m, with
  * beta the handle's face coefficient (the 1/rho_face of the operator), so
  * that the divergence of beta times the face gradient of p is A p. */
 

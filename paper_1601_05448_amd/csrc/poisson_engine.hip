@@ -675,7 +675,7 @@ int poisson_kernel_timer_read(poisson_t h, double* total_ms, long long* launches
 
 int poisson_divergence(poisson_t h, const double* rho, const double* mx, const double* my, const double* mz,
                        double* out) {
-    if (!h || !rho || !mx || !my || !mz || !out || h->g.bcx != 0) return POISSON_EINVAL;
+    if (!h || !rho || !mx || !my || !mz || !out) return POISSON_EINVAL;
     const size_t fb = (size_t)h->g.n * sizeof(double);
     for (const void* f : {(const void*)rho, (const void*)mx, (const void*)my, (const void*)mz})
         if (overlaps(out, fb, f, fb)) return POISSON_EINVAL;
@@ -686,7 +686,7 @@ int poisson_divergence(poisson_t h, const double* rho, const double* mx, const d
 
 int poisson_project(poisson_t h, const double* rho, double* mx, double* my, double* mz, const double* rhs_div,
                     double c_dt, double* p, double tol, double* chi) {
-    if (!h || !rho || !mx || !my || !mz || !rhs_div || !p || h->g.bcx != 0) return POISSON_EINVAL;
+    if (!h || !rho || !mx || !my || !mz || !rhs_div || !p) return POISSON_EINVAL;
     if (!(c_dt > 0.0) || !std::isfinite(c_dt) || !(tol > 0.0) || !std::isfinite(tol)) return POISSON_EINVAL;
     const size_t bytes = (size_t)h->g.n * sizeof(double);
     const void* f[7] = {rho, mx, my, mz, rhs_div, p, nullptr};

@@ -1,7 +1,7 @@
 // The projection step around the pressure solve (appendix A of the paper: the
 // time advance divides the predicted momentum by the new density, takes its
 // divergence, solves the variable-coefficient Poisson equation, and corrects
-// the momentum with the pressure gradient).  Periodic box.
+// the momentum with the pressure gradient).  Periodic box, or walls in x.
 //
 //   k_divergence   out = div(u), u = beta m on the faces (MODE 0), or the right-
 //                  hand side of the pressure equation (div(u) - RHS^div) / (C dt)
@@ -10,7 +10,10 @@
 //
 // m_d[c] is the normal momentum on the face between cell c and c + e_d; beta is
 // the operator's face coefficient (1 / rho_face), so that the divergence of beta
-// times the face gradient of p is exactly the operator A p of the solve.
+// times the face gradient of p is exactly the operator A p of the solve.  With
+// walls in x the two end faces of every x row are closed: the momentum stored
+// for the face between the last and the first cell takes no part in the
+// divergence and is not corrected.
 //
 // Both kernels are single passes over the fields, bound by HBM bandwidth: a
 // thread owns one (i, j) column and marches along z through kProjPlanes planes,
@@ -44,6 +47,7 @@ k_divergence(GridArgs g, const double* __restrict__ rho_in, const double* __rest
     const unsigned oym = (j == 0) ? (ny - 1) * nx : (unsigned)-(int)nx;
     const unsigned oyp = (j + 1 == ny) ? (unsigned)-(int)((ny - 1) * nx) : nx;
     const double rhx = std::sqrt(g.ihx2), rhy = std::sqrt(g.ihy2), rhz = std::sqrt(g.ihz2);  // 1 / h_d
+    const bool closed_m = g.bcx && i == 0, closed_p = g.bcx && i + 1 == nx;  // walls: end faces
     const unsigned k0 = blockIdx.y * kProjPlanes;
     const unsigned k1 = (k0 + kProjPlanes < nz) ? k0 + kProjPlanes : nz;
     unsigned cm = ((k0 + nz - 1) % nz) * sz + col;
@@ -57,8 +61,8 @@ k_divergence(GridArgs g, const double* __restrict__ rho_in, const double* __rest
         const double bym = face_beta<double>(g.coef, rho[c + oym], r_c), byp = face_beta<double>(g.coef, r_c, rho[c + oyp]);
         const double bzm = face_beta<double>(g.coef, r_m, r_c), bzp = face_beta<double>(g.coef, r_c, r_p);
         const double mzc = mz[c];
-        const double d = (bxp * mx[c] - bxm * mx[c + oxm]) * rhx + (byp * my[c] - bym * my[c + oym]) * rhy +
-                         (bzp * mzc - bzm * mz_m) * rhz;
+        const double fxp = closed_p ? 0.0 : bxp * mx[c], fxm = closed_m ? 0.0 : bxm * mx[c + oxm];
+        const double d = (fxp - fxm) * rhx + (byp * my[c] - bym * my[c + oym]) * rhy + (bzp * mzc - bzm * mz_m) * rhz;
         out[c] = (MODE == 0) ? d : (d - rhs_in[c]) * inv_cdt;
         r_m = r_c;
         r_c = r_p;
@@ -80,6 +84,7 @@ k_correct(GridArgs g, const double* __restrict__ p_in, double* __restrict__ mx_i
     const unsigned oxp = (i + 1 == nx) ? (unsigned)-(int)(nx - 1) : 1u;
     const unsigned oyp = (j + 1 == ny) ? (unsigned)-(int)((ny - 1) * nx) : nx;
     const double cx = c_dt * std::sqrt(g.ihx2), cy = c_dt * std::sqrt(g.ihy2), cz = c_dt * std::sqrt(g.ihz2);
+    const bool closed_p = g.bcx && i + 1 == nx;  // walls: the end face keeps its momentum
     const unsigned k0 = blockIdx.y * kProjPlanes;
     const unsigned k1 = (k0 + kProjPlanes < nz) ? k0 + kProjPlanes : nz;
     unsigned c = k0 * sz + col;
@@ -87,7 +92,7 @@ k_correct(GridArgs g, const double* __restrict__ p_in, double* __restrict__ mx_i
     for (unsigned k = k0; k < k1; ++k, c += sz) {
         const unsigned cp = (k + 1 == nz) ? col : c + sz;
         const double p_p = p[cp];
-        mx[c] -= cx * (p[c + oxp] - p_c);
+        if (!closed_p) mx[c] -= cx * (p[c + oxp] - p_c);
         my[c] -= cy * (p[c + oyp] - p_c);
         mz[c] -= cz * (p_p - p_c);
         p_c = p_p;
