@@ -186,7 +186,7 @@ def serve_mixed(P, torch, count, budget_gb):
 PROJ_CDT = 5e-4
 
 
-def time_projection(P, torch, prob, precision, steps, warmup, tol):
+def time_projection(P, torch, prob, precision, steps, warmup, tol, bc_x=0):
     """The projection step around the solve (RHS from the divergence of the
     predicted momentum, the solve from the previous pressure, momentum
     correction): `steps` projections, each from the same predicted momentum and
@@ -201,7 +201,7 @@ def time_projection(P, torch, prob, precision, steps, warmup, tol):
     m = [x.clone() for x in m0]
     p = torch.zeros(prob.shape, dtype=torch.float64, device="cuda")
     out = torch.empty_like(p)
-    with P.Solver(prob.shape, prob.lengths, precision=precision) as s:
+    with P.Solver(prob.shape, prob.lengths, precision=precision, bc_x=bc_x) as s:
         total, lat, st = 0.0, [], None
         for it in range(warmup + steps):
             for a, b in zip(m, m0):
@@ -428,7 +428,10 @@ def main():
                                 f"(max/min 4), band-limited b, tol {args.tol:g}",
                     "fp64": time_path(P, torch, duct, P.POISSON_FP64, dsteps, dwarm, args.tol, P.POISSON_BC_WALLS_X),
                     "fp32_refine": time_path(P, torch, duct, P.POISSON_FP32_REFINE, dsteps, dwarm, args.tol,
-                                             P.POISSON_BC_WALLS_X)}
+                                             P.POISSON_BC_WALLS_X),
+                    # the projection step on the duct (closed x end faces), FP32 sweeps with refinement
+                    "projection_fp32_refine": time_projection(P, torch, duct, P.POISSON_FP32_REFINE, psteps, pwarm,
+                                                              args.tol, P.POISSON_BC_WALLS_X)}
     del duct
     if args.large:
         big = inputs.workload3(512)
