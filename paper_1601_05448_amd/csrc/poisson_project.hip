@@ -47,7 +47,9 @@ k_divergence(GridArgs g, const double* __restrict__ rho_in, const double* __rest
     const unsigned oym = (j == 0) ? (ny - 1) * nx : (unsigned)-(int)nx;
     const unsigned oyp = (j + 1 == ny) ? (unsigned)-(int)((ny - 1) * nx) : nx;
     const double rhx = std::sqrt(g.ihx2), rhy = std::sqrt(g.ihy2), rhz = std::sqrt(g.ihz2);  // 1 / h_d
-    const bool closed_m = g.bcx && i == 0, closed_p = g.bcx && i + 1 == nx;  // walls: end faces
+    // walls: the coefficient of a closed end face is 0 (multiplied in, so that
+    // every load stays unconditional)
+    const double open_m = (g.bcx && i == 0) ? 0.0 : 1.0, open_p = (g.bcx && i + 1 == nx) ? 0.0 : 1.0;
     const unsigned k0 = blockIdx.y * kProjPlanes;
     const unsigned k1 = (k0 + kProjPlanes < nz) ? k0 + kProjPlanes : nz;
     unsigned cm = ((k0 + nz - 1) % nz) * sz + col;
@@ -57,12 +59,13 @@ k_divergence(GridArgs g, const double* __restrict__ rho_in, const double* __rest
     for (unsigned k = k0; k < k1; ++k, c += sz) {
         const unsigned cp = (k + 1 == nz) ? col : c + sz;
         const double r_p = rho[cp];
-        const double bxm = face_beta<double>(g.coef, rho[c + oxm], r_c), bxp = face_beta<double>(g.coef, r_c, rho[c + oxp]);
+        const double bxm = open_m * face_beta<double>(g.coef, rho[c + oxm], r_c);
+        const double bxp = open_p * face_beta<double>(g.coef, r_c, rho[c + oxp]);
         const double bym = face_beta<double>(g.coef, rho[c + oym], r_c), byp = face_beta<double>(g.coef, r_c, rho[c + oyp]);
         const double bzm = face_beta<double>(g.coef, r_m, r_c), bzp = face_beta<double>(g.coef, r_c, r_p);
         const double mzc = mz[c];
-        const double fxp = closed_p ? 0.0 : bxp * mx[c], fxm = closed_m ? 0.0 : bxm * mx[c + oxm];
-        const double d = (fxp - fxm) * rhx + (byp * my[c] - bym * my[c + oym]) * rhy + (bzp * mzc - bzm * mz_m) * rhz;
+        const double d = (bxp * mx[c] - bxm * mx[c + oxm]) * rhx + (byp * my[c] - bym * my[c + oym]) * rhy +
+                         (bzp * mzc - bzm * mz_m) * rhz;
         out[c] = (MODE == 0) ? d : (d - rhs_in[c]) * inv_cdt;
         r_m = r_c;
         r_c = r_p;
@@ -81,10 +84,11 @@ k_correct(GridArgs g, const double* __restrict__ p_in, double* __restrict__ mx_i
     POIS_GLOBAL double* my = gptr(my_in);
     POIS_GLOBAL double* mz = gptr(mz_in);
     const unsigned i = col % nx, j = col / nx;
-    const unsigned oxp = (i + 1 == nx) ? (unsigned)-(int)(nx - 1) : 1u;
+    // walls: the end face's neighbour is the cell itself, so the gradient across
+    // it is 0 and the face keeps its momentum (m - C dt 0 / h == m exactly)
+    const unsigned oxp = (i + 1 == nx) ? (g.bcx ? 0u : (unsigned)-(int)(nx - 1)) : 1u;
     const unsigned oyp = (j + 1 == ny) ? (unsigned)-(int)((ny - 1) * nx) : nx;
     const double cx = c_dt * std::sqrt(g.ihx2), cy = c_dt * std::sqrt(g.ihy2), cz = c_dt * std::sqrt(g.ihz2);
-    const bool closed_p = g.bcx && i + 1 == nx;  // walls: the end face keeps its momentum
     const unsigned k0 = blockIdx.y * kProjPlanes;
     const unsigned k1 = (k0 + kProjPlanes < nz) ? k0 + kProjPlanes : nz;
     unsigned c = k0 * sz + col;
@@ -92,7 +96,7 @@ k_correct(GridArgs g, const double* __restrict__ p_in, double* __restrict__ mx_i
     for (unsigned k = k0; k < k1; ++k, c += sz) {
         const unsigned cp = (k + 1 == nz) ? col : c + sz;
         const double p_p = p[cp];
-        if (!closed_p) mx[c] -= cx * (p[c + oxp] - p_c);
+        mx[c] -= cx * (p[c + oxp] - p_c);
         my[c] -= cy * (p[c + oyp] - p_c);
         mz[c] -= cz * (p_p - p_c);
         p_c = p_p;

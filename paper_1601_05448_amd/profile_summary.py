@@ -1,7 +1,8 @@
 """Short text summaries of rocprofv3 output (its SQLite ``*_results.db``).
 
-    # per-kernel durations of a --kernel-trace run
-    python -m paper_1601_05448_amd.profile_summary stats DIR [--top 20]
+    # per-kernel durations of a --kernel-trace run (optionally only kernels whose
+    # name contains MATCH, and one row per launch grid)
+    python -m paper_1601_05448_amd.profile_summary stats DIR [--top 20] [--match MATCH] [--by-grid]
 
     # HBM bytes per launch of one kernel from a FETCH_SIZE run and a WRITE_SIZE
     # run, each scaled by what the counter reads for a device copy of known size
@@ -46,11 +47,14 @@ def _db(d: str) -> sqlite3.Connection:
     return sqlite3.connect(files[0])
 
 
-def kernel_durations(d: str) -> dict:
-    """kernel name -> list of dispatch durations (ns)."""
+def kernel_durations(d: str, by_grid: bool = False) -> dict:
+    """kernel name (with the launch grid in work-items when by_grid) -> list of
+    dispatch durations (ns)."""
     out: dict = {}
-    for name, dur in _db(d).execute("select name, duration from kernels"):
-        out.setdefault(name, []).append(float(dur))
+    q = "select name, duration, grid_x, grid_y, grid_z from kernels"
+    for name, dur, gx, gy, gz in _db(d).execute(q):
+        key = f"[grid {gx}x{gy}x{gz}] {name}" if by_grid else name
+        out.setdefault(key, []).append(float(dur))
     return out
 
 
@@ -69,9 +73,9 @@ def counter_values(d: str, counter: str) -> dict:
 
 
 def cmd_stats(a) -> None:
-    durs = kernel_durations(a.dir)
+    durs = kernel_durations(a.dir, a.by_grid)
     total = sum(sum(v) for v in durs.values())
-    rows = sorted(durs.items(), key=lambda kv: -sum(kv[1]))[: a.top]
+    rows = sorted(((k, v) for k, v in durs.items() if a.match in k), key=lambda kv: -sum(kv[1]))[: a.top]
     print(f"{'calls':>6} {'total_ms':>9} {'avg_us':>8} {'min_us':>8} {'max_us':>8} {'pct':>6}  kernel")
     for name, v in rows:
         print(f"{len(v):6d} {sum(v) / 1e6:9.3f} {statistics.fmean(v) / 1e3:8.1f} {min(v) / 1e3:8.1f} "
@@ -147,6 +151,8 @@ def main(argv=None) -> None:
     s = sub.add_parser("stats")
     s.add_argument("dir")
     s.add_argument("--top", type=int, default=20)
+    s.add_argument("--match", default="", help="only kernels whose name contains this")
+    s.add_argument("--by-grid", action="store_true", help="one row per kernel and launch grid")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
