@@ -59,3 +59,26 @@ def test_percentile():
     assert bench.percentile(xs, 0.99) == pytest.approx(99.0)
     assert bench.percentile([0.0, 10.0], 0.25) == pytest.approx(2.5)
     assert bench.percentile([], 0.5) != bench.percentile([], 0.5)  # NaN
+
+
+def test_profile_stats_by_grid(tmp_path, capsys):
+    """The duration summary groups dispatches by kernel name, or by name and
+    launch grid, and filters by a name substring."""
+    import argparse
+    import sqlite3
+
+    db = sqlite3.connect(str(tmp_path / "run_results.db"))
+    db.execute("create table kernels (name text, duration integer, grid_x integer, grid_y integer, grid_z integer)")
+    rows = [("k_a", 1000, 64, 1, 1), ("k_a", 3000, 64, 1, 1), ("k_a", 8000, 128, 1, 1), ("k_b", 500, 64, 1, 1)]
+    db.executemany("insert into kernels values (?, ?, ?, ?, ?)", rows)
+    db.commit()
+    db.close()
+    durs = profile_summary.kernel_durations(str(tmp_path))
+    assert sorted(durs["k_a"]) == [1000.0, 3000.0, 8000.0] and durs["k_b"] == [500.0]
+    by = profile_summary.kernel_durations(str(tmp_path), by_grid=True)
+    assert by["[grid 64x1x1] k_a"] == [1000.0, 3000.0] and by["[grid 128x1x1] k_a"] == [8000.0]
+    profile_summary.cmd_stats(argparse.Namespace(dir=str(tmp_path), top=10, match="k_a", by_grid=True))
+    out = capsys.readouterr().out.splitlines()
+    assert len(out) == 3 and "k_b" not in "".join(out)
+    assert out[1].split()[0] == "1" and out[1].endswith("[grid 128x1x1] k_a")  # largest total first
+    assert out[2].split()[:3] == ["2", "0.004", "2.0"]  # calls, total ms, mean us
