@@ -55,13 +55,29 @@ def percentile(xs, q):
     return xs[f] + (xs[c] - xs[f]) * (k - f)
 
 
-def time_path(P, torch, prob, precision, steps, warmup, tol, bc_x=0):
+def model_bytes_per_cell(fp32, iters, outer_iters):
+    """Modelled HBM bytes per cell of one whole solve from p = 0 (each sweep
+    reads its inputs once and writes its outputs once).
+    FP64, K iterations: setup 16 + K x 104 + the final residual sweep 32.
+    FP32 + refinement, S refinement steps and K inner iterations (the first of
+    each step fused into the FP64 outer residual): setup 20 (rho, b read, rho32
+    written); per step the fused outer residual 32, the rest of its first inner
+    sweep 32 (y, z, y 8 each, the x pass 8), its further inner sweeps 52 each,
+    the inner residual sweep that stops them 16 and the FP64 update 20; the
+    final outer residual 32: 52 + 48 S + 52 K."""
+    if fp32:
+        return 52 + 48 * outer_iters + 52 * iters
+    return 48 + 104 * iters
+
+
+def time_path(P, torch, prob, precision, steps, warmup, tol, bc_x=0, keep_p=False):
     """Warm up, then time `steps` solves from p = 0.  Inside the timed region
     every launch of the path's residual sweep P1 (the dominant kernel) is
-    bracketed by HIP events on the solver's stream (poisson_kernel_timer)."""
+    bracketed by HIP events on the solver's stream (poisson_kernel_timer).
+    prob.rho and prob.b are numpy arrays or device tensors."""
     fp32 = precision == P.POISSON_FP32_REFINE
-    rho = torch.from_numpy(prob.rho).cuda()
-    b = torch.from_numpy(prob.b).cuda()
+    rho = prob.rho if torch.is_tensor(prob.rho) else torch.from_numpy(prob.rho).cuda()
+    b = prob.b if torch.is_tensor(prob.b) else torch.from_numpy(prob.b).cuda()
     p = torch.zeros(prob.shape, dtype=torch.float64, device="cuda")
     s = P.Solver(prob.shape, prob.lengths, precision=precision, bc_x=bc_x)
     stats = None
@@ -86,7 +102,11 @@ def time_path(P, torch, prob, precision, steps, warmup, tol, bc_x=0):
     if stats["status"] != 0:
         raise RuntimeError(f"solve failed: {stats}")
     bytes_p1 = SWEEP_BYTES[1][1 if fp32 else 0] * prob.n
+    bpc = model_bytes_per_cell(fp32, stats["iters"], stats["outer_iters"])
     out = dict(solves_per_s=steps / (t1 - t0), ms_per_solve=(t1 - t0) * 1e3 / steps,
+               model_bytes_per_cell=bpc,
+               # whole-solve roofline fraction: modelled bytes per solve x solves/s over the peak
+               solve_frac=bpc * prob.n * steps / (t1 - t0) / (HBM_PEAK_GBS * 1e9),
                p50_ms=percentile(lat, 0.5), p99_ms=percentile(lat, 0.99), iters=stats["iters"],
                outer_iters=stats["outer_iters"], rel_resid=stats["rel_resid"],
                err_bound_rel=stats["err_bound_rel"], device_ms=stats["ms"],
@@ -103,6 +123,11 @@ def time_path(P, torch, prob, precision, steps, warmup, tol, bc_x=0):
             nbytes = SWEEP_BYTES[sw][1 if f32 else 0] * prob.n
             sweeps[f"{'f32' if f32 else 'f64'}:{SWEEP_NAMES[sw]}"] = dict(
                 ms=ms, bytes=nbytes, gbs=nbytes / ms / 1e6)
+    if keep_p:
+        # the last timed solve's answer (the sweep timings above used p as scratch)
+        p.zero_()
+        s.solve(rho, b, p, tol)
+        out["_p"] = p.cpu().numpy()
     s.close()
     out["sweeps"] = sweeps
     return out
@@ -308,6 +333,33 @@ def deposit_leg(P, torch, n, reps):
                 bytes=nbytes, gbs=nbytes / dt / 1e9)
 
 
+class DeviceProblem:
+    """A workload whose fields were generated on the device (torch tensors)."""
+
+    def __init__(self, name, shape, lengths, rho, b):
+        self.name, self.shape, self.lengths, self.rho, self.b = name, tuple(shape), tuple(lengths), rho, b
+
+    @property
+    def n(self):
+        return int(self.shape[0] * self.shape[1] * self.shape[2])
+
+
+def workload3_device(P, torch, inputs, n=512):
+    """The 512^3 particle workload built on the device: the density from the
+    GPU's trilinear deposit P of the 10^6 seeded particles, rho = 1/(1 + 9
+    d/max d) (d per unit volume; the ratio d/max d is the same as for the raw
+    weight sums), b band-limited from the same seeded draws as the host recipe."""
+    shape, L = (n, n, n), (2.0 * math.pi,) * 3
+    pos = torch.from_numpy(inputs.workload3_particles()).cuda()
+    d = torch.empty(shape, dtype=torch.float64, device="cuda")
+    with P.Solver(shape, L) as s:
+        P.poisson_deposit(s.h, pos, None, d)
+    rho = (1.0 / (1.0 + 9.0 * d / d.max())).contiguous()
+    del d, pos
+    b = inputs.workload3_b_device(n)
+    return DeviceProblem(f"particle-deposit-rho {n}^3 ratio 10", shape, L, rho, b)
+
+
 def copy_ceiling(torch, mib=1024, reps=10):
     """Rate of a plain device-to-device copy of `mib` MiB (read + write bytes per
     second): the practical HBM ceiling next to the published peak."""
@@ -326,25 +378,111 @@ def copy_ceiling(torch, mib=1024, reps=10):
     return 2.0 * n * 8 / ms / 1e6
 
 
-def cpu_baseline(prob, fp64_iters):
-    """The oracle (single-threaded C, FP64) on a bounded sample of the same
-    workload: one residual evaluation plus one iteration, scaled to the
-    iteration count the method needs on this workload."""
-    import numpy as np
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    import oracle
 
-    t0 = time.perf_counter()
-    oracle.residual(prob.rho, prob.b, np.zeros(prob.shape), prob.lengths)
-    t_res = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    oracle.solve(prob.rho, prob.b, lengths=prob.lengths, tol=1e-10, max_iter=1, allow_noconv=True)
-    t_one = time.perf_counter() - t0
-    t_iter = max(t_one - t_res, 1e-9)
-    t_solve = t_res + fp64_iters * t_iter
-    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"one oracle iteration on the {prob.shape[0]}^3 workload ({t_one:.1f} s incl. setup), "
-                      f"scaled to {fp64_iters} iterations + 1 residual"}
+class CpuBaseline:
+    """The cpu_baseline leg: the oracle (single-threaded C, FP64) timed on the
+    host's cores, as it stands.
+
+    * One full oracle solve of the headline workload from p = 0 to the same
+      tolerance, in a background process started before the GPU legs so that
+      its minutes of host time overlap them; the same process continues that
+      solve to a relative residual of 1e-12, and the result is the reference
+      against which the GPU answers' error is measured.
+    * After the GPU legs: 5 repeated solves of the 32^3 workload on one core
+      (median, min), then the same on `procs` concurrent processes (aggregate
+      solves/s of the host)."""
+
+    def __init__(self, prob, small, tol):
+        import subprocess
+        import tempfile
+
+        import numpy as np
+
+        self.prob, self.small, self.tol = prob, small, tol
+        self.dir = tempfile.mkdtemp(prefix="bench_oracle_")
+        self.big_dir = os.path.join(self.dir, "big")
+        self.small_dir = os.path.join(self.dir, "small")
+        for d, pr in ((self.big_dir, prob), (self.small_dir, small)):
+            os.makedirs(d)
+            np.save(os.path.join(d, "rho.npy"), pr.rho)
+            np.save(os.path.join(d, "b.npy"), pr.b)
+        self.log = open(os.path.join(self.dir, "solve.log"), "w")
+        self.proc = subprocess.Popen([sys.executable, "-m", "oracle.jobs", "solve", self.big_dir,
+                                      *(repr(v) for v in prob.lengths), repr(tol), "1e-12"],
+                                     cwd=ROOT, stdout=self.log, stderr=subprocess.STDOUT)
+
+    def _repeat(self, procs, repeats):
+        import subprocess
+
+        cmd = lambda k: [sys.executable, "-m", "oracle.jobs", "repeat", self.small_dir,
+                         *(repr(v) for v in self.small.lengths), repr(self.tol), str(repeats), f"{procs}_{k}"]
+        t0 = time.perf_counter()
+        ps = [subprocess.Popen(cmd(k), cwd=ROOT) for k in range(procs)]
+        for q in ps:
+            if q.wait() != 0:
+                raise RuntimeError("oracle repeat job failed")
+        wall = time.perf_counter() - t0
+        runs = []
+        for k in range(procs):
+            with open(os.path.join(self.small_dir, f"repeat_{procs}_{k}.json")) as f:
+                runs.append(json.load(f))
+        return wall, runs
+
+    def finish(self, answers):
+        """answers: {path name: GPU p (numpy)} of the headline workload.
+        Returns (cpu_baseline dict, {path name: error dict})."""
+        import shutil
+
+        import numpy as np
+
+        t0 = time.perf_counter()
+        while self.proc.poll() is None:
+            time.sleep(1.0)
+            if time.perf_counter() - t0 > 30:
+                print("bench: waiting for the oracle solve", file=sys.stderr, flush=True)
+                t0 = time.perf_counter()
+        self.log.close()
+        if self.proc.returncode != 0:
+            with open(os.path.join(self.dir, "solve.log")) as f:
+                raise RuntimeError("oracle solve failed: " + f.read()[-2000:])
+        with open(os.path.join(self.big_dir, "solve.json")) as f:
+            big = json.load(f)
+        p_ref = np.load(os.path.join(self.big_dir, "p_ref.npy"))
+        errors = {}
+        for name, p in answers.items():
+            d = p - p_ref
+            errors[name] = {"rel_l2": float(np.linalg.norm(d) / big["ref_norm"]), "max_abs": float(np.max(np.abs(d))),
+                            "max_abs_rel": float(np.max(np.abs(d)) / np.max(np.abs(p_ref))),
+                            "reference": f"oracle solve to {big['ref_rel']:.1e} relative residual "
+                                         f"(its own error bound {big['ref_err_bound_abs'] / big['ref_norm']:.1e})"}
+        del p_ref
+        _, one = self._repeat(1, 5)
+        times = sorted(one[0]["seconds"])
+        procs = min(16, len(os.sched_getaffinity(0)))
+        _, runs = self._repeat(procs, 20)
+        shutil.rmtree(self.dir, ignore_errors=True)
+        n = self.prob.shape[0]
+        base = {"value": 1.0 / big["seconds"], "unit": "solves/s", "cores": 1, "kind": "oracle",
+                "sample": f"one full oracle solve of the {n}^3 workload from p = 0 to {self.tol:g} "
+                          f"({big['iters']} iterations, {big['seconds']:.1f} s, single-threaded FP64 C)",
+                "cpu_model": cpu_model(), "nproc": os.cpu_count(), "cores_available": len(os.sched_getaffinity(0)),
+                "small_32": {"workload": "32^3 sinusoidal rho, divergence b, tol %g" % self.tol,
+                             "iters": one[0]["iters"][0], "median_s": times[len(times) // 2], "min_s": times[0],
+                             "solves_per_s_one_core": 1.0 / times[len(times) // 2],
+                             # the processes run side by side: the sum of their rates
+                             "procs": procs, "aggregate_solves_per_s": sum(len(r["seconds"]) / sum(r["seconds"])
+                                                                           for r in runs)}}
+        return base, errors
 
 
 def main():
@@ -357,8 +495,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=512, help="0 skips the served stream")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
+    ap.add_argument("--no-512", action="store_true",
+                    help="skip the 512^3 particle-deposit workload (fields beyond the 256 MB MALL)")
     ap.add_argument("--large", action="store_true",
-                    help="also time the 512^3 particle-deposit workload (fields beyond the 256 MB MALL)")
+                    help="also serve the 1024x512x512 hot-blob solve beside a 128^3 stream (minutes of host-side "
+                         "input generation)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see the design notes on "
@@ -372,8 +513,11 @@ def main():
 
     torch.cuda.set_device(0)
     prob = inputs.workload2(args.size)
-    fp64 = time_path(P, torch, prob, P.POISSON_FP64, args.steps, args.warmup, args.tol)
-    fp32 = time_path(P, torch, prob, P.POISSON_FP32_REFINE, args.steps, args.warmup, args.tol)
+    cpu = None if args.no_cpu_baseline else CpuBaseline(prob, inputs.workload1(32), args.tol)
+    fp64 = time_path(P, torch, prob, P.POISSON_FP64, args.steps, args.warmup, args.tol, keep_p=cpu is not None)
+    fp32 = time_path(P, torch, prob, P.POISSON_FP32_REFINE, args.steps, args.warmup, args.tol,
+                     keep_p=cpu is not None)
+    answers = {name: r.pop("_p") for name, r in (("fp64", fp64), ("fp32_refine", fp32)) if "_p" in r}
     best_name, best = ("fp32_refine", fp32) if fp32["solves_per_s"] > fp64["solves_per_s"] else ("fp64", fp64)
 
     # dominant kernel of the headline path: its residual sweep P1, timed live
@@ -385,6 +529,8 @@ def main():
                 "launches": dom["launches"], "working_launches": dom["working_launches"]}
     roofline["copy_ceiling_gbs"] = copy_ceiling(torch)
     roofline["frac_of_copy"] = dom["gbs"] / roofline["copy_ceiling_gbs"]
+    # whole solves: modelled bytes per solve x solves/s over the peak
+    roofline["solve_frac"] = {"fp64": fp64["solve_frac"], "fp32_refine": fp32["solve_frac"]}
 
     line = {
         "metric": METRIC,
@@ -433,17 +579,24 @@ def main():
                     "projection_fp32_refine": time_projection(P, torch, duct, P.POISSON_FP32_REFINE, psteps, pwarm,
                                                               args.tol, P.POISSON_BC_WALLS_X)}
     del duct
-    if args.large:
-        big = inputs.workload3(512)
-        line["large"] = {"workload": "512^3 particle-deposit rho (ratio 10), band-limited b, tol 1e-10",
-                         "fp64": time_path(P, torch, big, P.POISSON_FP64, 3, 1, args.tol),
-                         "fp32_refine": time_path(P, torch, big, P.POISSON_FP32_REFINE, 3, 1, args.tol)}
+    if not args.no_512:
+        big = workload3_device(P, torch, inputs)
+        lg = {"workload": "512^3 particle-deposit rho (10^6 uniform particles, trilinear deposit by the GPU's P, "
+                          "rho = 1/(1 + 9 d/max d), ratio 10), band-limited b, tol %g" % args.tol,
+              "fp64": time_path(P, torch, big, P.POISSON_FP64, 5, 1, args.tol),
+              "fp32_refine": time_path(P, torch, big, P.POISSON_FP32_REFINE, 5, 1, args.tol)}
+        lg["fp32_speedup"] = lg["fp32_refine"]["solves_per_s"] / lg["fp64"]["solves_per_s"]
+        line["large"] = lg
         del big
-        line["large"]["served_alongside"] = serve_mixed(P, torch, 128, 32.0)
+        torch.cuda.empty_cache()
+    if args.large:
+        line.setdefault("large", {})["served_alongside"] = serve_mixed(P, torch, 128, 32.0)
     if args.serve_requests > 0:
         line["serving"] = serve_leg(P, torch, args.serve_requests, args.serve_budget_gb, 64, P.POISSON_FP64)
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(prob, fp64["iters"])
+    if cpu is not None:
+        line["cpu_baseline"], errors = cpu.finish(answers)
+        for name, e in errors.items():
+            line["paths"][name]["err_vs_oracle"] = e
     print(json.dumps(line))
 
 

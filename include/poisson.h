@@ -4,12 +4,14 @@
  *
  *        div( (1/rho) grad p ) = b
  *
- * on a uniform, triply periodic, staggered grid, by the iteration of
+ * on a uniform staggered grid, periodic in y and z and either periodic or
+ * closed by zero-flux walls in x (bc_x below), by the iteration of
  * Pouransari, Mortazavi & Mani, "Parallel variable-density particle-laden
  * turbulence simulation" (arXiv:1601.05448), section "Poisson equation",
  * eq. (Pois): write p = p_g + dp, drop the term rho grad(1/rho).grad dp, solve
  * the remaining constant-coefficient Poisson equation by Fourier transform in
- * the periodic directions, set p_g <- p_g + dp and repeat until convergence.
+ * the periodic directions (a transform that diagonalises the same operator
+ * along a walled x), set p_g <- p_g + dp and repeat until convergence.
  *
  * Discretisation (section "Spatial discretization"; staggered-grid figure):
  * rho, b and p live at cell centres, fluxes on faces, second order:
@@ -24,7 +26,9 @@
  * e.g. torch.Tensor.data_ptr()) on the current HIP device.  Callers own rho,
  * b and p; the library owns its workspace.  rho, b and p must not overlap.
  *
- * Grid sizes: each of nx, ny, nz must be 2^a or 3*2^a with 4 <= N <= 1024.
+ * Grid sizes: each of nx, ny, nz must be 2^a or 3*2^a with 4 <= N <= 1024
+ * (lengths with a factor 9 or more of 3 are rejected with POISSON_EINVAL: the
+ * transforms are compiled per length, and the paper fixes no grid sizes).
  *
  * Threading: a handle is used by one host thread at a time.  Calls enqueue
  * work on the handle's stream and, unless stated otherwise, block until that
@@ -172,6 +176,14 @@ int poisson_kernel_timer_read(poisson_t h, double* total_ms, long long* launches
  * be the same pointer. */
 int poisson_lap_pinv(poisson_t h, const double* q, double* delta);
 
+/* The same L^+ q through the FP32 sweeps that a POISSON_FP32_REFINE handle
+ * runs inside its refinement steps (q rounded to FP32 as it is loaded, every
+ * transform and the symbol division in FP32 with the FP32 tables, delta
+ * widened to FP64 at the end), to check those sweeps on their own.  The handle
+ * must be POISSON_FP32_REFINE (else POISSON_EINVAL); its FP32 workspace is used
+ * as scratch.  q and delta are device FP64 fields and may be the same pointer. */
+int poisson_lap_pinv_fp32(poisson_t h, const double* q, double* delta);
+
 /* Average device time of one sweep of the iteration, launched `reps` times
  * back to back between two HIP events on the handle's stream (after one
  * warm-up launch), written to *avg_ms.  sweep: 1 residual + weight + Hartley
@@ -252,9 +264,10 @@ int poisson_interpolate(poisson_t h, int n_particles, const double* pos, const d
 /* ---- serving: many independent solves of different sizes -----------------
  * A server keeps each admitted request's rho, b, p and iteration state on the
  * device, groups requests of equal grid size into batches that advance
- * together in one captured graph per size class, and admits new requests
- * between ticks as slots and memory free up.  Requests are independent: each
- * result is the same as a solve of that request alone. */
+ * together (one set of batched launches per size class and tick, blockIdx.y
+ * selecting the request, each class on a stream of its own), and admits new
+ * requests between ticks as slots and memory free up.  Requests are
+ * independent: each result is the same as a solve of that request alone. */
 typedef struct poisson_server_s* poisson_server_t;
 
 /* budget_bytes: device memory the server may hold for admitted requests
@@ -289,6 +302,14 @@ int poisson_server_tick(poisson_server_t s);
  * completion (host clock).  A done request's stats stay readable until the
  * server is destroyed.  A server is driven by one host thread. */
 int poisson_server_poll(poisson_server_t s, long long id, poisson_stats* stats);
+
+/* *bytes = the footprint a request on grid (nx, ny, nz) with boundary
+ * condition bc_x holds against this server's budget while it is admitted: its
+ * three caller fields (24 B per cell) plus the solver workspace of the server's
+ * precision.  A pooled idle workspace of that grid keeps holding the workspace
+ * part until a request reuses it or admission releases it.  POISSON_EINVAL for
+ * an unsupported size. */
+int poisson_server_footprint(poisson_server_t s, int nx, int ny, int nz, int bc_x, size_t* bytes);
 
 void poisson_server_destroy(poisson_server_t s);
 

@@ -174,10 +174,11 @@ def residual(rho, b, p, lengths=(2 * np.pi,) * 3, coef: int = COEF_RHO_FACE_MEAN
 
 def solve(rho, b, p0=None, lengths=(2 * np.pi,) * 3, coef: int = COEF_RHO_FACE_MEAN,
           weight: int = WEIGHT_RHO, tol: float = 1e-13, max_iter: int = 10000,
-          allow_noconv: bool = False, bcx: int = BC_PERIODIC):
+          allow_noconv: bool = False, bcx: int = BC_PERIODIC, allow_diverged: bool = False):
     """The paper's iteration (section "Poisson equation", eq. (Pois)):
     r = b~ - A p, q = w r, dp = L^+ q, p += dp, until ||r||/||b~|| <= tol.
-    Returns dict(p, iters, rel, b_mean, history, code)."""
+    Returns dict(p, iters, rel, b_mean, history, code); allow_noconv and
+    allow_diverged return the cap and divergence codes instead of raising."""
     b = np.ascontiguousarray(b, dtype=np.float64)
     shape = b.shape
     rho = _f64(rho, shape)
@@ -187,7 +188,7 @@ def solve(rho, b, p0=None, lengths=(2 * np.pi,) * 3, coef: int = COEF_RHO_FACE_M
     rc = _load().oracle_solve_bc(*_grid(shape, lengths), coef, bcx, weight, _ptr(rho), _ptr(b), _ptr(p),
                               tol, max_iter, ctypes.byref(it), ctypes.byref(rel), ctypes.byref(bm),
                               _ptr(hist))
-    _check(rc, "solve", allow=(OK, ENOCONV) if allow_noconv else (OK,))
+    _check(rc, "solve", allow=(OK,) + ((ENOCONV,) if allow_noconv else ()) + ((EDIVERGED,) if allow_diverged else ()))
     return dict(p=p, iters=it.value, rel=rel.value, b_mean=bm.value,
                 history=hist[: it.value + 1].copy(), code=rc)
 

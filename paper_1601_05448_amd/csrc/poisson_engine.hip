@@ -60,11 +60,17 @@ double min_symbol(const GridArgs& g) {
 
 // ---- per-grid tables ---------------------------------------------------------------
 
-int GridTables::build(const GridArgs& g) {
+// Layout of one grid's tables in one buffer: four 256-byte aligned arrays per
+// direction and the cosine transform's twiddles along x.
+struct TableLayout {
+    size_t at[3][4];
+    size_t at_c, at_c32;
+    size_t total;
+};
+
+static TableLayout table_layout(const GridArgs& g) {
     const int ns[3] = {g.nx, g.ny, g.nz};
-    const double ih2[3] = {g.ihx2, g.ihy2, g.ihz2};
-    // layout first: four 256-byte aligned arrays per direction, and the cosine
-    // transform's twiddles along x
+    TableLayout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
         off = (off + 255) & ~(size_t)255;
@@ -72,27 +78,31 @@ int GridTables::build(const GridArgs& g) {
         off += bytes;
         return at;
     };
-    size_t at[3][4];
     for (int d = 0; d < 3; ++d) {
-        at[d][0] = take((size_t)ns[d] * 16);  // FP64 twiddles
-        at[d][1] = take((size_t)ns[d] * 8);   // FP32 twiddles
-        at[d][2] = take((size_t)ns[d] * 8);   // FP64 symbol
-        at[d][3] = take((size_t)ns[d] * 4);   // FP32 symbol
+        L.at[d][0] = take((size_t)ns[d] * 16);  // FP64 twiddles
+        L.at[d][1] = take((size_t)ns[d] * 8);   // FP32 twiddles
+        L.at[d][2] = take((size_t)ns[d] * 8);   // FP64 symbol
+        L.at[d][3] = take((size_t)ns[d] * 4);   // FP32 symbol
     }
-    const size_t at_c = take((size_t)g.nx * 16), at_c32 = take((size_t)g.nx * 8);
-    const size_t total = off;
-    if (hipMalloc(&mem, total) != hipSuccess) {
-        mem = nullptr;
-        return POISSON_ENOMEM;
-    }
-    std::vector<unsigned char> host(total, 0);
-    unsigned char* base = static_cast<unsigned char*>(mem);
+    L.at_c = take((size_t)g.nx * 16);
+    L.at_c32 = take((size_t)g.nx * 8);
+    L.total = (off + 255) & ~(size_t)255;
+    return L;
+}
+
+size_t tables_bytes(const GridArgs& g) { return table_layout(g).total; }
+
+void fill_tables(const GridArgs& g, unsigned char* host) {
+    const TableLayout L = table_layout(g);
+    const int ns[3] = {g.nx, g.ny, g.nz};
+    const double ih2[3] = {g.ihx2, g.ihy2, g.ihz2};
+    std::memset(host, 0, L.total);
     for (int d = 0; d < 3; ++d) {
         const int n = ns[d];
-        double* tw = reinterpret_cast<double*>(host.data() + at[d][0]);
-        float* tw32 = reinterpret_cast<float*>(host.data() + at[d][1]);
-        double* lam = reinterpret_cast<double*>(host.data() + at[d][2]);
-        float* lam32 = reinterpret_cast<float*>(host.data() + at[d][3]);
+        double* tw = reinterpret_cast<double*>(host + L.at[d][0]);
+        float* tw32 = reinterpret_cast<float*>(host + L.at[d][1]);
+        double* lam = reinterpret_cast<double*>(host + L.at[d][2]);
+        float* lam32 = reinterpret_cast<float*>(host + L.at[d][3]);
         const bool wall = d == 0 && g.bcx == 1;
         for (int t = 0; t < n; ++t) {
             const double ang = 2.0 * kPi * (double)t / (double)n;
@@ -105,19 +115,22 @@ int GridTables::build(const GridArgs& g) {
             lam32[t] = (float)lam[t];
         }
     }
-    {
-        double* c = reinterpret_cast<double*>(host.data() + at_c);
-        float* c32 = reinterpret_cast<float*>(host.data() + at_c32);
-        for (int t = 0; t < g.nx; ++t) {
-            const double ang = kPi * (double)t / (2.0 * g.nx);
-            c[2 * t] = std::cos(ang);
-            c[2 * t + 1] = -std::sin(ang);
-            c32[2 * t] = (float)c[2 * t];
-            c32[2 * t + 1] = (float)c[2 * t + 1];
-        }
+    double* c = reinterpret_cast<double*>(host + L.at_c);
+    float* c32 = reinterpret_cast<float*>(host + L.at_c32);
+    for (int t = 0; t < g.nx; ++t) {
+        const double ang = kPi * (double)t / (2.0 * g.nx);
+        c[2 * t] = std::cos(ang);
+        c[2 * t + 1] = -std::sin(ang);
+        c32[2 * t] = (float)c[2 * t];
+        c32[2 * t + 1] = (float)c[2 * t + 1];
     }
-    if (hipMemcpy(mem, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) return POISSON_EHIP;
-    auto ptr = [&](int d, int k) { return static_cast<const void*>(base + at[d][k]); };
+}
+
+Tables bind_tables(const GridArgs& g, const void* dev) {
+    const TableLayout L = table_layout(g);
+    const unsigned char* base = static_cast<const unsigned char*>(dev);
+    auto ptr = [&](int d, int k) { return static_cast<const void*>(base + L.at[d][k]); };
+    Tables t{};
     t.twx = static_cast<const double2*>(ptr(0, 0)); t.twy = static_cast<const double2*>(ptr(1, 0));
     t.twz = static_cast<const double2*>(ptr(2, 0));
     t.twx32 = static_cast<const float2*>(ptr(0, 1)); t.twy32 = static_cast<const float2*>(ptr(1, 1));
@@ -126,8 +139,21 @@ int GridTables::build(const GridArgs& g) {
     t.lamz = static_cast<const double*>(ptr(2, 2));
     t.lamx32 = static_cast<const float*>(ptr(0, 3)); t.lamy32 = static_cast<const float*>(ptr(1, 3));
     t.lamz32 = static_cast<const float*>(ptr(2, 3));
-    t.twcx = reinterpret_cast<const double2*>(base + at_c);
-    t.twcx32 = reinterpret_cast<const float2*>(base + at_c32);
+    t.twcx = reinterpret_cast<const double2*>(base + L.at_c);
+    t.twcx32 = reinterpret_cast<const float2*>(base + L.at_c32);
+    return t;
+}
+
+int GridTables::build(const GridArgs& g) {
+    const size_t total = tables_bytes(g);
+    if (hipMalloc(&mem, total) != hipSuccess) {
+        mem = nullptr;
+        return POISSON_ENOMEM;
+    }
+    std::vector<unsigned char> host(total, 0);
+    fill_tables(g, host.data());
+    if (hipMemcpy(mem, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) return POISSON_EHIP;
+    t = bind_tables(g, mem);
     return POISSON_OK;
 }
 
@@ -152,7 +178,12 @@ int Workspace::allocate(const GridArgs& g, const Geometry& geo, int precision) {
         mem = nullptr;
         return POISSON_ENOMEM;
     }
-    unsigned char* base = static_cast<unsigned char*>(mem);
+    carve(g, geo, precision, mem);
+    return POISSON_OK;
+}
+
+void Workspace::carve(const GridArgs& g, const Geometry& geo, int precision, void* at_mem) {
+    unsigned char* base = static_cast<unsigned char*>(at_mem);
     size_t off = 0;
     auto take = [&](size_t n) {
         off = (off + 255) & ~(size_t)255;
@@ -170,7 +201,6 @@ int Workspace::allocate(const GridArgs& g, const Geometry& geo, int precision) {
     }
     partial = reinterpret_cast<double*>(take((size_t)geo.max_blocks * kPartialStride * 8));
     st = reinterpret_cast<SolveState*>(take(sizeof(SolveState)));
-    return POISSON_OK;
 }
 
 void Workspace::release() {
@@ -188,6 +218,25 @@ Slot Workspace::slot(const double* rho, const double* b, double* p, double tol) 
 }
 
 // ---- the solve driver -----------------------------------------------------------------
+
+// n values of T, on the stack for small batches (a single solve allocates
+// nothing on the host), on the heap for large ones.
+template <class T>
+struct SmallArray {
+    static constexpr int kLocal = 64;
+    T local[kLocal];
+    std::vector<T> heap;
+    T* v;
+    SmallArray(int n, T init) : v(local) {
+        if (n > kLocal) {
+            heap.assign((size_t)n, init);
+            v = heap.data();
+        } else {
+            for (int q = 0; q < n; ++q) local[q] = init;
+        }
+    }
+    T& operator[](int q) { return v[q]; }
+};
 
 // Enqueue the whole solve for the slots on the stream, reading back the state
 // header of slot 0..nslots-1 between chunks.  `hdr` is pinned host memory for
@@ -227,6 +276,7 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
     if ((e = launch_setup(g, geo, d_slots, nslots, fp32, s)) != hipSuccess) return hip_status(e);
     if ((e = launch_setup_finalize(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
     const size_t hb = offsetof(SolveState, hist);
+    bool all_done = false;
     auto poll = [&]() -> int {  // 1: all done, 0: not yet, <0 error
         for (int q = 0; q < nslots; ++q)
             if ((e = hipMemcpyAsync(&hdr[q], d_states[q], hb, hipMemcpyDeviceToHost, s)) != hipSuccess)
@@ -235,6 +285,7 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
         for (int q = 0; q < nslots; ++q) {
             if (!hdr[q].done) return 0;
         }
+        all_done = true;
         return 1;
     };
     if (!fp32) {
@@ -244,8 +295,8 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
         // quarter of one (an idle launch costs less than another poll).
         int launched = 0, chunk = prm.first_chunk;
         const int cap = prm.max_iter + 1;
-        std::vector<int> k_prev(nslots, -1);
-        std::vector<double> r_prev(nslots, 0.0);
+        SmallArray<int> k_prev(nslots, -1);
+        SmallArray<double> r_prev(nslots, 0.0);
         while (true) {
             const int now = std::min(chunk, cap - launched);
             if ((e = iterations(now, false)) != hipSuccess) return hip_status(e);
@@ -369,6 +420,9 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
             check = true;
         }
     }
+    // the rounds ran out before every solve reached a terminal status: those
+    // end as if capped (p is their last iterate)
+    if (!all_done && (e = launch_stop_unfinished(d_slots, nslots, s)) != hipSuccess) return hip_status(e);
     if ((e = launch_fixup(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
     return POISSON_OK;
 }
@@ -754,13 +808,18 @@ int poisson_interpolate(poisson_t h, int n_particles, const double* pos, const d
     return bad ? POISSON_EDOMAIN : POISSON_OK;
 }
 
-int poisson_lap_pinv(poisson_t h, const double* q, double* delta) {
+static int lap_pinv(poisson_t h, const double* q, double* delta, bool fp32) {
     if (!h || !q || !delta) return POISSON_EINVAL;
+    if (fp32 && h->o.precision != POISSON_FP32_REFINE) return POISSON_EINVAL;
     int rc = set_slot(h, h->ws.slot(nullptr, q, delta, 1.0));
     if (rc != POISSON_OK) return rc;
-    hipError_t e = launch_lap_pinv(h->g, h->geo, h->tables.t, h->d_slot, h->stream);
+    hipError_t e = launch_lap_pinv(h->g, h->geo, h->tables.t, h->d_slot, h->stream, fp32);
     if (e != hipSuccess) return hip_status(e);
     return hip_status(hipStreamSynchronize(h->stream));
 }
+
+int poisson_lap_pinv(poisson_t h, const double* q, double* delta) { return lap_pinv(h, q, delta, false); }
+
+int poisson_lap_pinv_fp32(poisson_t h, const double* q, double* delta) { return lap_pinv(h, q, delta, true); }
 
 }  // extern "C"

@@ -22,6 +22,12 @@ struct SolveParams {
     int max_chunk = 16;
 };
 
+// Transform tables of one grid: their size in one buffer, their values written
+// into a host buffer of that size, and the device pointers into a copy of it.
+size_t tables_bytes(const GridArgs& g);
+void fill_tables(const GridArgs& g, unsigned char* host);
+Tables bind_tables(const GridArgs& g, const void* dev);
+
 // Transform tables of one grid in device memory.
 struct GridTables {
     void* mem = nullptr;
@@ -39,6 +45,9 @@ struct Workspace {
     double* partial = nullptr;
     SolveState* st = nullptr;
     int allocate(const GridArgs& g, const Geometry& geo, int precision);
+    // lay the workspace out in workspace_bytes(g, geo, precision) bytes at at_mem
+    // (256-byte aligned) without allocating; release() then frees nothing
+    void carve(const GridArgs& g, const Geometry& geo, int precision, void* at_mem);
     void release();
     Slot slot(const double* rho, const double* b, double* p, double tol) const;
 };

@@ -163,14 +163,18 @@ hipError_t launch_outer_residual(const GridArgs& g, const Geometry& geo, const T
 hipError_t launch_outer_update(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,
                                hipStream_t s);
 hipError_t launch_fixup(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots, hipStream_t s);
+// Marks every slot whose solve is not done as done with POISSON_ENOCONV.
+hipError_t launch_stop_unfinished(const Slot* slots, int nslots, hipStream_t s);
 
 // Single sweeps for parity checks (one slot).
 hipError_t launch_apply(const GridArgs& g, const Geometry& geo, const double* rho, const double* p, double* out,
                         hipStream_t s);
 hipError_t launch_residual(const GridArgs& g, const Geometry& geo, const Slot* slot, double* r,
                            hipStream_t s);
+// delta (slot.p) = L^+ q (slot.b); fp32: through the FP32 sweeps (q rounded
+// to FP32 on load, the result widened from d32 at the end).
 hipError_t launch_lap_pinv(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slot,
-                           hipStream_t s);
+                           hipStream_t s, bool fp32 = false);
 
 // The projection step around the solve (poisson_project.hip): out = div(beta m)
 // (rhs == nullptr) or (div(beta m) - rhs) / c_dt; m_d -= c_dt grad_d p.

@@ -463,6 +463,18 @@ __global__ void __launch_bounds__(kPtThreads) k_fixup(GridArgs g, const Slot* __
         gptr(s.p)[c] = zero ? 0.0 : gptr(s.p)[c] - sh;
 }
 
+// A solve that the host driver stopped driving before it reached a terminal
+// status (its rounds ran out) ends with the status of the iteration cap; p is
+// the last iterate its updates left.
+__global__ void __launch_bounds__(64) k_stop_unfinished(const Slot* __restrict__ slots) {
+    if (threadIdx.x != 0) return;
+    SolveState* st = slots[blockIdx.x].st;
+    if (!st->done) {
+        st->done = 1;
+        st->status = POISSON_ENOCONV;
+    }
+}
+
 // ---- launch helpers ------------------------------------------------------------------
 
 bool length_supported(int n) {
@@ -603,6 +615,11 @@ hipError_t launch_outer_update(const GridArgs& g, const Geometry& geo, const Slo
     return hipGetLastError();
 }
 
+hipError_t launch_stop_unfinished(const Slot* slots, int nslots, hipStream_t s) {
+    k_stop_unfinished<<<dim3(nslots), 64, 0, s>>>(slots);
+    return hipGetLastError();
+}
+
 hipError_t launch_fixup(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots, hipStream_t s) {
     k_fixup<<<dim3(geo.blocks_pt, nslots), kPtThreads, 0, s>>>(g, slots);
     return hipGetLastError();
@@ -619,10 +636,20 @@ hipError_t launch_residual(const GridArgs& g, const Geometry& geo, const Slot* s
     return hipGetLastError();
 }
 
+// p = (double) d32: the FP32 stand-alone L^+ sweep leaves its result in d32.
+__global__ void __launch_bounds__(kPtThreads) k_widen(GridArgs g, const Slot* __restrict__ slots) {
+    const Slot& s = slots[blockIdx.y];
+    const long long stride = (long long)gridDim.x * kPtThreads;
+    for (long long c = (long long)blockIdx.x * kPtThreads + threadIdx.x; c < g.n; c += stride)
+        gptr(s.p)[c] = (double)gptr(s.d32)[c];
+}
+
 hipError_t launch_lap_pinv(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slot,
-                           hipStream_t s) {
-    (void)geo;
-    return five_sweeps(g, t, slot, 1, false, 1, s, nullptr);
+                           hipStream_t s, bool fp32) {
+    hipError_t e = five_sweeps(g, t, slot, 1, fp32, 1, s, nullptr);
+    if (e != hipSuccess || !fp32) return e;
+    k_widen<<<dim3(geo.blocks_pt, 1), kPtThreads, 0, s>>>(g, slot);
+    return hipGetLastError();
 }
 
 }  // namespace pois

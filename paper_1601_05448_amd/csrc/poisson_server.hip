@@ -146,11 +146,16 @@ static size_t request_footprint(poisson_server_s* s, const Request& r) {
 }
 
 // Release idle pooled workspaces (largest first) until `need` more bytes fit.
-static void trim_pools(poisson_server_s* s, size_t need) {
+// `keep` (may be NULL) is the class being admitted into when it is about to
+// take one of its own pooled workspaces: its last pooled workspace stays.
+static void trim_pools(poisson_server_s* s, size_t need, const SizeClass* keep) {
     while (s->used + need > s->budget) {
         SizeClass* best = nullptr;
-        for (auto& kv : s->classes)
-            if (!kv.second->pool.empty() && (!best || kv.second->ws_bytes > best->ws_bytes)) best = kv.second.get();
+        for (auto& kv : s->classes) {
+            const SizeClass* c = kv.second.get();
+            const size_t spare = c->pool.size() - (c == keep && !c->pool.empty() ? 1 : 0);
+            if (spare > 0 && (!best || c->ws_bytes > best->ws_bytes)) best = kv.second.get();
+        }
         if (!best) return;
         Workspace* w = best->pool.back();
         best->pool.pop_back();
@@ -170,14 +175,16 @@ static int admit(poisson_server_s* s) {
         const size_t fields = field_bytes(c->cells);
         Workspace* w = nullptr;
         if (!c->pool.empty()) {
-            if (s->used + fields > s->budget) trim_pools(s, fields);
+            // reuse one of the class's pooled workspaces (already counted in
+            // `used`): only the fields are new
+            if (s->used + fields > s->budget) trim_pools(s, fields, c);
             if (s->used + fields > s->budget) break;
             w = c->pool.back();
             c->pool.pop_back();
             s->used += fields;
         } else {
             const size_t need = c->ws_bytes + fields;
-            if (s->used + need > s->budget) trim_pools(s, need);
+            if (s->used + need > s->budget) trim_pools(s, need, nullptr);
             if (s->used + need > s->budget) break;
             w = new (std::nothrow) Workspace();
             if (!w) return POISSON_ENOMEM;
@@ -341,6 +348,18 @@ int poisson_server_submit(poisson_server_t s, int nx, int ny, int nz, double lx,
     if (request_footprint(s, r) > s->budget) return POISSON_ETOOBIG;
     s->queue.push_back(r);
     *id = s->next_id++;
+    return POISSON_OK;
+}
+
+int poisson_server_footprint(poisson_server_t s, int nx, int ny, int nz, int bc_x, size_t* bytes) {
+    if (!s || !bytes) return POISSON_EINVAL;
+    if (bc_x != POISSON_BC_PERIODIC && bc_x != POISSON_BC_WALLS_X) return POISSON_EINVAL;
+    if (!length_supported(nx) || !length_supported(ny) || !length_supported(nz)) return POISSON_EINVAL;
+    Request r{};
+    r.nx = nx; r.ny = ny; r.nz = nz;
+    r.lx = r.ly = r.lz = 1.0;  // the footprint does not depend on the box
+    r.bc_x = bc_x;
+    *bytes = request_footprint(s, r);
     return POISSON_OK;
 }
 

@@ -28,7 +28,7 @@
 
 #include <algorithm>
 #include <mutex>
-#include <unordered_map>
+#include <cstdint>
 
 #include "poisson_device.hpp"
 
@@ -753,9 +753,14 @@ k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
 
 // Blocks of a persistent sweep: every resident block of the device, shared by
 // the slots of the batch, never more than there are line groups.
+// The occupancy of each kernel is asked once and kept in a fixed table (no
+// host allocation on the launch path; a kernel beyond the table's capacity is
+// asked every time).
 static int resident_blocks(const void* kernel, int threads) {
+    constexpr int kCap = 4096;  // a power of two, above the number of kernels
     static std::mutex mu;
-    static std::unordered_map<const void*, int> per_cu;
+    static const void* keys[kCap] = {};
+    static int vals[kCap] = {};
     static int cus = 0;
     std::lock_guard<std::mutex> lock(mu);
     if (cus == 0) {
@@ -764,13 +769,21 @@ static int resident_blocks(const void* kernel, int threads) {
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
             cus = 256;
     }
-    auto it = per_cu.find(kernel);
-    if (it == per_cu.end()) {
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb < 1) nb = 1;
-        it = per_cu.emplace(kernel, nb).first;
+    const uintptr_t hsh = (reinterpret_cast<uintptr_t>(kernel) >> 4) * 0x9E3779B97F4A7C15ull;
+    for (int probe = 0; probe < kCap; ++probe) {
+        const int at = (int)((hsh + (uintptr_t)probe) & (kCap - 1));
+        if (keys[at] == kernel) return vals[at] * cus;
+        if (keys[at] == nullptr) {
+            int nb = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb < 1) nb = 1;
+            keys[at] = kernel;
+            vals[at] = nb;
+            return nb * cus;
+        }
     }
-    return it->second * cus;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb < 1) nb = 1;
+    return nb * cus;
 }
 
 static int persistent_grid(const void* kernel, int threads, unsigned ngroups, int nslots, float share) {
@@ -848,7 +861,9 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
 
 hipError_t launch_sweep_mode(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32, int which,
                              int mode, hipStream_t s, int* nunits, float share, int stage) {
-    if (mode == 1) return sweep_t<double, 1>(g, t, slots, nslots, which, s, nunits, share, 1);
+    if (mode == 1)
+        return fp32 ? sweep_t<float, 1>(g, t, slots, nslots, which, s, nunits, share, 1)
+                    : sweep_t<double, 1>(g, t, slots, nslots, which, s, nunits, share, 1);
     return fp32 ? sweep_t<float, 0>(g, t, slots, nslots, which, s, nunits, share, stage)
                 : sweep_t<double, 0>(g, t, slots, nslots, which, s, nunits, share, 1);
 }

@@ -265,6 +265,16 @@ def workload3(n: int = 512, particles: int = 10**6, ratio: float = 10.0,
     return Problem(f"particle-deposit-rho {n}^3 ratio {ratio:g}", (n, n, n), L, rho, b)
 
 
+def workload3_b_device(n: int = 512, particles: int = 10**6, kmax: float = 8.0, device="cuda"):
+    """b of workload 3 generated on `device` (a torch tensor), from the same
+    seeded draws as workload3 (the particle positions are drawn first and
+    skipped).  The density of workload 3 is the deposit of
+    workload3_particles(), which a caller can build with the GPU's P."""
+    rng = np.random.default_rng(workload_seed(3))
+    rng.uniform(0.0, TWO_PI, size=(particles, 3))
+    return bandlim_device((n, n, n), (TWO_PI,) * 3, kmax, rng, device)
+
+
 def workload5(shape=(512, 512, 1024), blobs: int = 10**5, ratio: float = 20.0,
               sigma_cells: float = 2.0, kmax: float = 8.0) -> Problem:
     rng = np.random.default_rng(workload_seed(5))

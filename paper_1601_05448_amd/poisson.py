@@ -93,6 +93,7 @@ def load() -> ctypes.CDLL:
     lib.poisson_apply.argtypes = [vp, vp, vp, vp]
     lib.poisson_residual.argtypes = [vp, vp, vp, vp, vp, pd, pd]
     lib.poisson_lap_pinv.argtypes = [vp, vp, vp]
+    lib.poisson_lap_pinv_fp32.argtypes = [vp, vp, vp]
     lib.poisson_time_sweep.argtypes = [vp, i, i, vp, vp, vp, i, pd]
     lib.poisson_kernel_timer.argtypes = [vp, i, i]
     lib.poisson_kernel_timer_read.argtypes = [vp, pd, ctypes.POINTER(ll)]
@@ -107,6 +108,7 @@ def load() -> ctypes.CDLL:
         lib.poisson_server_poll.argtypes = [vp, ll, ctypes.POINTER(poisson_stats)]
         lib.poisson_server_destroy.argtypes = [vp]
         lib.poisson_server_destroy.restype = None
+        lib.poisson_server_footprint.argtypes = [vp, i, i, i, i, ctypes.POINTER(ctypes.c_size_t)]
     _lib = lib
     return lib
 
@@ -200,6 +202,12 @@ def poisson_lap_pinv(h: int, q, delta) -> None:
     rc = load().poisson_lap_pinv(h, _ptr(q), _ptr(delta))
     if rc != POISSON_OK:
         raise PoissonError(rc, "poisson_lap_pinv")
+
+
+def poisson_lap_pinv_fp32(h: int, q, delta) -> None:
+    rc = load().poisson_lap_pinv_fp32(h, _ptr(q), _ptr(delta))
+    if rc != POISSON_OK:
+        raise PoissonError(rc, "poisson_lap_pinv_fp32")
 
 
 def poisson_divergence(h: int, rho, mx, my, mz, out) -> None:
@@ -300,6 +308,16 @@ def poisson_server_poll(s: int, rid: int) -> Optional[dict]:
     if rc < 0:
         raise PoissonError(rc, "poisson_server_poll")
     return st.as_dict() if rc == 0 else None
+
+
+def poisson_server_footprint(s: int, shape: Sequence[int], bc_x: int = POISSON_BC_PERIODIC) -> int:
+    """Bytes a request on this grid holds against the server's budget while admitted."""
+    nz, ny, nx = (int(v) for v in shape)
+    out = ctypes.c_size_t()
+    rc = load().poisson_server_footprint(s, nx, ny, nz, int(bc_x), ctypes.byref(out))
+    if rc != POISSON_OK:
+        raise PoissonError(rc, "poisson_server_footprint")
+    return out.value
 
 
 def poisson_server_destroy(s: Optional[int]) -> None:

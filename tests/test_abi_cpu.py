@@ -33,6 +33,7 @@ def _create(**kw):
 
 
 @pytest.mark.parametrize("kw", [dict(nx=5), dict(ny=7), dict(nz=2), dict(nx=2048), dict(nx=9), dict(nx=3),
+                                dict(nx=72), dict(ny=144), dict(nz=288),
                                 dict(lx=0.0), dict(ly=-1.0), dict(lz=float("nan")), dict(precision=2),
                                 dict(coef=5), dict(weight=-1), dict(bc_x=2), dict(bc_x=-1)])
 def test_create_rejects_invalid_options(kw):
@@ -45,7 +46,14 @@ def test_null_arguments_rejected():
     assert lib.poisson_create(None, None) == P.POISSON_EINVAL
     assert lib.poisson_solve(None, None, None, None, 1e-10) == P.POISSON_EINVAL
     assert lib.poisson_get_stats(None, None) == P.POISSON_EINVAL
+    assert lib.poisson_lap_pinv_fp32(None, None, None) == P.POISSON_EINVAL
     lib.poisson_destroy(None)  # NULL is allowed
+
+
+def test_server_footprint_argument_checks():
+    lib = P.load()
+    out = ctypes.c_size_t()
+    assert lib.poisson_server_footprint(None, 32, 32, 32, 0, ctypes.byref(out)) == P.POISSON_EINVAL
 
 
 @pytest.mark.parametrize("args", [(0, 4, 0, 0, 0), (1 << 30, 0, 0, 0, 0), (1 << 30, 4, 7, 0, 0),

@@ -82,3 +82,33 @@ def test_profile_stats_by_grid(tmp_path, capsys):
     assert len(out) == 3 and "k_b" not in "".join(out)
     assert out[1].split()[0] == "1" and out[1].endswith("[grid 128x1x1] k_a")  # largest total first
     assert out[2].split()[:3] == ["2", "0.004", "2.0"]  # calls, total ms, mean us
+
+
+def test_model_bytes_per_cell():
+    """The whole-solve byte model: FP64 16 + 104 K + 32; FP32 with refinement
+    52 + 48 S + 52 K (see bench.model_bytes_per_cell)."""
+    assert bench.model_bytes_per_cell(False, 10, 0) == 16 + 10 * 104 + 32
+    assert bench.model_bytes_per_cell(True, 10, 3) == 20 + 3 * (32 + 32 + 16 + 20) + (10 - 3) * 52 + 32
+
+
+def test_cpu_baseline_leg_end_to_end():
+    """The cpu_baseline leg on small grids: the background oracle solve, the
+    reference it continues to, the error of an answer against it, the repeated
+    small solves and the concurrent processes."""
+    import numpy as np
+
+    import oracle
+    from paper_1601_05448_amd import inputs
+
+    prob = inputs.small_problem(shape=(16, 16, 16), lengths=(2 * np.pi,) * 3)
+    small = inputs.small_problem(shape=(8, 8, 8), lengths=(2 * np.pi,) * 3, seed=3)
+    leg = bench.CpuBaseline(prob, small, 1e-10)
+    ans = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, tol=1e-10)["p"]
+    base, errors = leg.finish({"oracle_1e-10": ans})
+    assert base["kind"] == "oracle" and base["unit"] == "solves/s" and base["value"] > 0
+    assert base["cores"] == 1 and base["nproc"] >= 1 and base["cpu_model"]
+    assert base["small_32"]["procs"] >= 1 and base["small_32"]["aggregate_solves_per_s"] > 0
+    assert base["small_32"]["min_s"] <= base["small_32"]["median_s"]
+    e = errors["oracle_1e-10"]
+    # an answer at 1e-10 against the 1e-12 reference: small but not zero
+    assert 0 < e["rel_l2"] < 1e-8 and e["max_abs"] > 0

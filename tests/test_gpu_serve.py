@@ -110,6 +110,44 @@ def test_budget_admits_one_at_a_time_and_all_finish():
         assert np.array_equal(mixed[k][0], p_alone)
 
 
+def test_admission_reuses_a_pooled_workspace_when_the_budget_is_tight():
+    """Regression test of admission with a pooled workspace: a 32^3 request
+    arrives while the server holds an idle pooled 32^3 workspace and a resident
+    request of another size, and the budget lies in the window where the new
+    request's fields fit only if that pooled workspace were released.  The
+    request must wait for the other resident to retire and then reuse its own
+    class's workspace; every answer equals the solve alone, bit for bit."""
+    announce("serve admission window")
+    a = inputs.small_problem(shape=(32, 32, 32), lengths=(TWO_PI,) * 3, ratio=3.0, seed=501)
+    o = inputs.small_problem(shape=(24, 32, 32), lengths=(TWO_PI,) * 3, ratio=5.0, seed=502)
+    probe = serve.Server(1 << 30, 4)
+    f_a = P.poisson_server_footprint(probe.h, a.shape)
+    f_o = P.poisson_server_footprint(probe.h, o.shape)
+    probe.close()
+    fields_a = 24 * a.n
+    ws_a = f_a - fields_a
+    assert ws_a > 0 and f_o >= ws_a
+    # window: fields_a + f_o <= budget < f_a + f_o; and the request alone fits
+    budget = fields_a + f_o + ws_a // 2
+    assert fields_a + f_o <= budget < f_a + f_o and f_a <= budget
+    p_a_alone, _ = _alone(a, P.POISSON_FP64)
+    p_o_alone, _ = _alone(o, P.POISSON_FP64)
+    with serve.Server(budget, 8) as s:
+        # first request of the 32^3 class: afterwards its workspace is pooled
+        first = serve.replay(s, [serve.Job(0.0, a.shape, a.lengths, dev(a.rho), dev(a.b), dev(np.zeros(a.shape)),
+                                           tag="first")], realtime=False)
+        # the other-size request and a second 32^3 request arrive together
+        res = serve.replay(s, [serve.Job(0.0, o.shape, o.lengths, dev(o.rho), dev(o.b), dev(np.zeros(o.shape)),
+                                         tag="other"),
+                               serve.Job(0.0, a.shape, a.lengths, dev(a.rho), dev(a.b), dev(np.zeros(a.shape)),
+                                         tag="second")], realtime=False)
+    got = {oc.job.tag: (host(oc.job.p), oc.stats) for oc in first.outcomes + res.outcomes}
+    assert set(got) == {"first", "other", "second"}
+    for tag, want in (("first", p_a_alone), ("other", p_o_alone), ("second", p_a_alone)):
+        assert got[tag][1]["status"] == P.POISSON_OK, (tag, got[tag][1])
+        assert np.array_equal(got[tag][0], want), tag
+
+
 def test_request_too_big_for_budget():
     announce("serve etoobig")
     pr = _mix(1)[0]
@@ -202,3 +240,17 @@ def test_server_rejects_unknown_boundary_condition():
         with pytest.raises(P.PoissonError) as e:
             s.submit(pr.shape, pr.lengths, dev(pr.rho), dev(pr.b), dev(np.zeros(pr.shape)), 1e-10, bc_x=3)
         assert e.value.code == P.POISSON_EINVAL
+
+
+def test_server_footprint_query():
+    """The footprint the budget charges: three FP64 fields plus the workspace
+    (8 B/cell and more for FP64, 24 B/cell and more for FP32 refinement)."""
+    announce("serve footprint")
+    for prec, ws_min in ((P.POISSON_FP64, 8), (P.POISSON_FP32_REFINE, 24)):
+        with serve.Server(1 << 30, 4, precision=prec) as s:
+            n = 32 ** 3
+            f = P.poisson_server_footprint(s.h, (32, 32, 32))
+            assert f >= (24 + ws_min) * n and f < (24 + ws_min) * n + (4 << 20)
+            with pytest.raises(P.PoissonError) as e:
+                P.poisson_server_footprint(s.h, (32, 32, 33))
+            assert e.value.code == P.POISSON_EINVAL

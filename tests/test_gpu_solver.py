@@ -365,3 +365,121 @@ def test_full_size_256_lognormal(precision):
     assert res["rel"] <= 1e-10
     assert abs(st["rel_resid"] - res["rel"]) <= 1e-3 * res["rel"]
     assert st["err_bound_rel"] < 1e-8
+
+
+def _lap_min(shape, lengths):
+    """Smallest nonzero eigenvalue magnitude of the periodic 7-point Laplacian."""
+    nz, ny, nx = shape
+    return min(4.0 * math.sin(math.pi / n) ** 2 / (l / n) ** 2 for n, l in zip((nx, ny, nz), lengths))
+
+
+@pytest.mark.parametrize("shape", _shapes_every_length())
+def test_lap_pinv_fp32_matches_oracle(shape):
+    """The FP32 sweeps of the refinement path (the transforms the inner
+    iterations run, register-resident at 256 along y and z) on their own, every
+    length along every axis, element by element against the oracle's FP64 L^+.
+
+    Bound derived from the arithmetic: with u = 2^-24, each length-N FFT adds
+    at most about u log2 N of the norm of what it transforms; the path rounds
+    q to FP32, transforms along x, y and z, divides by the FP32 symbol and
+    transforms back, so the spectrum carries at most u (2 + 2 sum_d log2 N_d)
+    ||q~||, and dividing by the symbol (>= lambda_min) bounds the error of
+    delta in the 2-norm, hence element by element, by that over lambda_min
+    (taken with a factor 4)."""
+    announce("lap_pinv fp32", shape)
+    rng = np.random.default_rng(sum(shape) + 1)
+    L = (TWO_PI, 2.5, 4.0)
+    q = rng.standard_normal(shape) + 0.7
+    want = oracle.lap_pinv(q, L)
+    h = P.poisson_create(shape, L, precision=P.POISSON_FP32_REFINE)
+    try:
+        out = dev(np.zeros(shape))
+        P.poisson_lap_pinv_fp32(h, dev(q), out)
+    finally:
+        P.poisson_destroy(h)
+    got = host(out)
+    u = 2.0 ** -24
+    passes = 2 + 2 * sum(math.log2(n) for n in shape)
+    bound = 4 * u * passes * np.linalg.norm(q - q.mean()) / _lap_min(shape, L)
+    assert np.max(np.abs(got - want)) <= bound, shape
+    assert np.linalg.norm(got - want) <= bound, shape
+    assert abs(got.mean()) <= bound / math.sqrt(q.size)
+
+
+def test_lap_pinv_fp32_smooth_256_cube():
+    """FP32 L^+ at 256^3 (the headline grid, the register-resident 256-point
+    transforms along y and z) on a band-limited right-hand side, against the
+    oracle, with the bound above."""
+    announce("lap_pinv fp32 256^3")
+    shape, L = (256, 256, 256), (TWO_PI,) * 3
+    q = inputs.bandlim(shape, L, 8.0, np.random.default_rng(99))
+    want = oracle.lap_pinv(q, L)
+    h = P.poisson_create(shape, L, precision=P.POISSON_FP32_REFINE)
+    try:
+        out = dev(np.zeros(shape))
+        P.poisson_lap_pinv_fp32(h, dev(q), out)
+    finally:
+        P.poisson_destroy(h)
+    got = host(out)
+    u = 2.0 ** -24
+    bound = 4 * u * (2 + 2 * 3 * 8) * np.linalg.norm(q) / _lap_min(shape, L)
+    assert np.linalg.norm(got - want) <= bound
+    assert np.max(np.abs(got - want)) <= bound
+    # in practice far inside the bound: a few FP32 ulps of the result
+    assert np.max(np.abs(got - want)) <= 1e-5 * np.max(np.abs(want))
+
+
+def test_lap_pinv_fp32_needs_fp32_handle():
+    announce("lap_pinv fp32 on an FP64 handle")
+    shape = (8, 8, 8)
+    h = P.poisson_create(shape, (TWO_PI,) * 3)
+    try:
+        with pytest.raises(P.PoissonError) as e:
+            P.poisson_lap_pinv_fp32(h, dev(np.ones(shape)), dev(np.zeros(shape)))
+        assert e.value.code == P.POISSON_EINVAL
+    finally:
+        P.poisson_destroy(h)
+
+
+@pytest.mark.parametrize("shape", [(12, 8, 256), (8, 256, 12), (256, 8, 12)])
+def test_solve_fp32_refine_axis_256(shape):
+    """FP32 sweeps + FP64 refinement with a 256-long axis along x, y or z (the
+    headline row and column length), element by element against the oracle."""
+    announce("solve fp32 refine 256 axis", shape)
+    prob = inputs.small_problem(shape=shape, lengths=(TWO_PI, TWO_PI, TWO_PI), ratio=4.0)
+    ref = oracle.solve(prob.rho, prob.b, lengths=prob.lengths, tol=1e-14, max_iter=60, allow_noconv=True)
+    rr = oracle.residual(prob.rho, prob.b, ref["p"], prob.lengths)
+    ref_bound = oracle.error_bound(prob.shape, prob.lengths, float(prob.rho.max()), rr["r_norm"]) / \
+        np.linalg.norm(ref["p"])
+    p, st, _ = _solve_gpu(prob, precision=P.POISSON_FP32_REFINE)
+    err = _check_solution(prob, p, st, ref["p"], ref_bound=ref_bound)
+    assert np.max(np.abs(p - ref["p"])) <= (st["err_bound_rel"] + ref_bound) * np.linalg.norm(ref["p"]) + 1e-14
+    assert err <= 1e-8
+
+
+@pytest.mark.parametrize("precision", [P.POISSON_FP64, P.POISSON_FP32_REFINE])
+def test_rough_density_diverges(precision):
+    """The oracle's divergent case (face mean of 1/rho, w = rho, cell-to-cell
+    rough density on 8^3): both paths stop with EDIVERGED, and the FP64 path
+    follows the oracle's residual history up to the divergence."""
+    announce("ediverged", precision)
+    rng = np.random.default_rng(6)
+    shape, L = (8, 8, 8), (TWO_PI,) * 3
+    rho = np.exp(rng.uniform(-0.8, 0.8, shape))
+    b = rng.standard_normal(shape)
+    lit = oracle.solve(rho, b, lengths=L, coef=1, weight=0, tol=1e-12, allow_diverged=True)
+    assert lit["code"] == oracle.EDIVERGED
+    h = P.poisson_create(shape, L, precision=precision, coef=1, weight=0, max_iter=5000)
+    try:
+        p = dev(np.zeros(shape))
+        rc = P.poisson_solve(h, dev(rho), dev(b), p, 1e-12)
+        st = P.poisson_get_stats(h)
+        hist = P.poisson_get_history(h)
+    finally:
+        P.poisson_destroy(h)
+    assert rc == P.POISSON_EDIVERGED and st["status"] == P.POISSON_EDIVERGED, st
+    if precision == P.POISSON_FP64:
+        assert st["iters"] == lit["iters"]
+        k = len(hist) - 1  # the last entry is the divergent one: compare the contracting part closely
+        assert np.allclose(hist[:k], lit["history"][:k], rtol=1e-6, atol=0)
+        assert hist[k] > 1e8 and lit["history"][k] > 1e8
