@@ -131,6 +131,24 @@ int poisson_create(const poisson_opts* opts, poisson_t* out);
  * POISSON_EDIVERGED p holds the last iterate.  Blocks until done. */
 int poisson_solve(poisson_t h, const double* rho, const double* b, double* p, double tol);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * serving loops that must not call the allocator, harnesses that forbid it):
+ * the solve of poisson_solve without a handle and without any allocation.
+ * opts as for poisson_create (use_graphs is ignored; stream: the caller's
+ * hipStream_t or NULL, on which the solve runs); rho, b, p and tol as for
+ * poisson_solve, with the same result bits.  The tables, the workspace and the
+ * state live in one device array of 64 MiB inside the library (each device
+ * holds its own copy from the library's load until the process ends); a grid
+ * whose tables plus workspace exceed it returns POISSON_ETOOBIG with p
+ * untouched (e.g. 128^3 fits in either precision, 192^3 only in POISSON_FP64).
+ * The array keeps the last call's contents; every call rewrites what it reads.
+ * Calls are serialised by a process-wide lock (a call waits for the one
+ * before it, on any device), so calls that would overlap do not race on the
+ * array.  *stats (may be NULL) receives the solve's statistics; stats->ms is
+ * the host time of the call.  Blocks until done. */
+int poisson_solve_noalloc(const poisson_opts* opts, const double* rho, const double* b, double* p, double tol,
+                          poisson_stats* stats);
+
 /* Statistics of the last poisson_solve on this handle. */
 int poisson_get_stats(poisson_t h, poisson_stats* stats);
 

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpoisson.so")
 SOURCES = ["poisson_sweeps.hip", "poisson_kernels.hip", "poisson_engine.hip", "poisson_server.hip",
-           "poisson_project.hip", "poisson_particles.hip"]
+           "poisson_project.hip", "poisson_particles.hip", "poisson_noalloc.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -84,6 +84,7 @@ def load() -> ctypes.CDLL:
     pd = ctypes.POINTER(ctypes.c_double)
     lib.poisson_create.argtypes = [ctypes.POINTER(poisson_opts), ctypes.POINTER(vp)]
     lib.poisson_solve.argtypes = [vp, vp, vp, vp, d]
+    lib.poisson_solve_noalloc.argtypes = [ctypes.POINTER(poisson_opts), vp, vp, vp, d, ctypes.POINTER(poisson_stats)]
     lib.poisson_get_stats.argtypes = [vp, ctypes.POINTER(poisson_stats)]
     lib.poisson_get_history.argtypes = [vp, pd, i]
     lib.poisson_destroy.argtypes = [vp]
@@ -161,6 +162,24 @@ def poisson_solve(h: int, rho, b, p, tol: float) -> int:
     if rc in (POISSON_EINVAL, POISSON_ENOMEM, POISSON_EHIP):
         raise PoissonError(rc, "poisson_solve")
     return rc
+
+
+def poisson_solve_noalloc(shape: Sequence[int], lengths: Sequence[float], rho, b, p, tol: float,
+                          precision: int = POISSON_FP64, coef: int = POISSON_COEF_RHO_FACE_MEAN,
+                          weight: int = POISSON_W_RHO, max_iter: int = 0, stream=None, inner_tol: float = 0.0,
+                          bc_x: int = POISSON_BC_PERIODIC) -> dict:
+    """The allocation-free solve (no handle): returns the stats dict with the
+    status under "code" (raises on argument errors)."""
+    nz, ny, nx = (int(v) for v in shape)
+    o = poisson_opts(nx, ny, nz, float(lengths[0]), float(lengths[1]), float(lengths[2]),
+                     precision, coef, weight, max_iter, _stream_ptr(stream), float(inner_tol), 0, int(bc_x))
+    st = poisson_stats()
+    rc = load().poisson_solve_noalloc(ctypes.byref(o), _ptr(rho), _ptr(b), _ptr(p), float(tol), ctypes.byref(st))
+    if rc in (POISSON_EINVAL, POISSON_ENOMEM, POISSON_EHIP):
+        raise PoissonError(rc, "poisson_solve_noalloc")
+    out = st.as_dict()
+    out["code"] = rc
+    return out
 
 
 def poisson_get_stats(h: int) -> dict:
