@@ -133,10 +133,14 @@ def time_path(P, torch, prob, precision, steps, warmup, tol, bc_x=0, keep_p=Fals
     return out
 
 
-def serve_leg(P, torch, count, budget_gb, slots, precision):
+def serve_leg(P, torch, count, budget_gb, slots, precision, fracs=(0.3, 0.5, 0.7, 0.9)):
     """The served stream (Poisson arrivals, grids drawn from 64^3..192^3, each
     with its own lognormal rho): first all requests at once to measure the
-    capacity, then in real time at 0.7x that rate; latency = arrival to done."""
+    capacity, then in real time at `fracs` x that rate; latency = arrival to
+    done, split into the wait before submission (the replay loop), the queue
+    (submit to admission) and the rest (admission to done).  Both with direct
+    launches and with each size class's chunks replayed from captured graphs;
+    the headline figures are the 0.7 x capacity point of the faster mode."""
     from paper_1601_05448_amd import inputs, serve
 
     reqs = inputs.request_stream(count)
@@ -148,22 +152,65 @@ def serve_leg(P, torch, count, budget_gb, slots, precision):
                           torch.zeros((r.n,) * 3, dtype=torch.float64, device="cuda"))
                 for r, f in zip(stream, fields)]
 
-    with serve.Server(budget, slots, precision=precision) as srv:
-        serve.replay(srv, jobs_for(reqs[: min(16, count)]), realtime=False)  # warm-up
-        torch.cuda.synchronize()
-        cap = serve.replay(srv, jobs_for(reqs), realtime=False)
-        capacity = len(cap.outcomes) / cap.wall_s
-        rate = 0.7 * capacity
-        stream = inputs.request_stream(count, rate_hz=rate)
-        live = serve.replay(srv, jobs_for(stream), realtime=True)
-    bad = [o for o in live.outcomes if o.stats["status"] != 0 or o.stats["rel_resid"] > 1e-10]
-    if bad or len(live.outcomes) != count:
-        raise RuntimeError(f"served solves failed: {len(bad)} bad of {len(live.outcomes)}")
-    lat = live.latencies()
+    def point(res, rate):
+        bad = [o for o in res.outcomes if o.stats["status"] != 0 or o.stats["rel_resid"] > 1e-10]
+        if bad or len(res.outcomes) != count:
+            raise RuntimeError(f"served solves failed: {len(bad)} bad of {len(res.outcomes)}")
+        lat = res.latencies()
+        queue = [o.stats["queue_ms"] for o in res.outcomes]
+        run = [o.stats["ms"] - o.stats["queue_ms"] for o in res.outcomes]
+        before = [lt - o.stats["ms"] for lt, o in zip(lat, res.outcomes)]
+        p50, p99 = percentile(lat, 0.5), percentile(lat, 0.99)
+        by_size = {}
+        for n in inputs.SERVE_SIZES:
+            ls = [lt for lt, o in zip(lat, res.outcomes) if o.job.shape[0] == n]
+            by_size[str(n)] = {"p50_ms": percentile(ls, 0.5), "p99_ms": percentile(ls, 0.99)}
+        return {"rate_hz": rate, "solves_per_s": len(lat) / res.wall_s, "p50_ms": p50, "p99_ms": p99,
+                "p99_over_p50": p99 / p50, "mean_submit_wait_ms": sum(before) / len(before),
+                "queue_p50_ms": percentile(queue, 0.5), "queue_p99_ms": percentile(queue, 0.99),
+                "run_p50_ms": percentile(run, 0.5), "run_p99_ms": percentile(run, 0.99), "by_size": by_size}
+
+    def solo():
+        """Latency of each size served alone (one request at a time, nothing
+        else resident): the floor under that size's latency in the mix."""
+        out = {}
+        with serve.Server(budget, slots, precision=precision) as srv:
+            for n in inputs.SERVE_SIZES:
+                ks = [k for k, r in enumerate(reqs) if r.n == n][:6]
+                jobs = [serve.Job(0.0, (n,) * 3, (2 * math.pi,) * 3, fields[k][0], fields[k][1],
+                                  torch.zeros((n,) * 3, dtype=torch.float64, device="cuda")) for k in ks]
+                lat = []
+                for j in jobs:
+                    res = serve.replay(srv, [j], realtime=False)
+                    lat.append(res.outcomes[0].latency_ms)
+                out[str(n)] = percentile(lat[1:], 0.5)  # the first one warms the class up
+        return out
+
+    modes = {}
+    capacity = None
+    for graphs in (False, True):
+        with serve.Server(budget, slots, precision=precision, use_graphs=graphs) as srv:
+            serve.replay(srv, jobs_for(reqs[: min(16, count)]), realtime=False)  # warm-up
+            torch.cuda.synchronize()
+            cap = serve.replay(srv, jobs_for(reqs), realtime=False)
+            cap_rate = len(cap.outcomes) / cap.wall_s
+            if capacity is None:
+                capacity = cap_rate  # the direct mode's capacity sets the arrival rates of both
+            sweep = {}
+            for f in (fracs if not graphs else (0.7,)):
+                rate = f * capacity
+                stream = inputs.request_stream(count, rate_hz=rate)
+                sweep[f"{f:g}"] = point(serve.replay(srv, jobs_for(stream), realtime=True), rate)
+        modes["graphs" if graphs else "direct"] = {"capacity_solves_per_s": cap_rate, "load": sweep}
+    solo_ms = solo()
+    best = "graphs" if modes["graphs"]["load"]["0.7"]["p99_ms"] < modes["direct"]["load"]["0.7"]["p99_ms"] \
+        else "direct"
+    head = modes[best]["load"]["0.7"]
     return {"requests": count, "sizes": list(inputs.SERVE_SIZES), "budget_gb": budget_gb, "slots": slots,
             "precision": "fp64" if precision == P.POISSON_FP64 else "fp32_refine", "tol": 1e-10,
-            "capacity_solves_per_s": capacity, "rate_hz": rate, "solves_per_s": len(lat) / live.wall_s,
-            "p50_ms": percentile(lat, 0.5), "p99_ms": percentile(lat, 0.99)}
+            "capacity_solves_per_s": modes[best]["capacity_solves_per_s"], "mode": best,
+            "rate_hz": head["rate_hz"], "solves_per_s": head["solves_per_s"], "p50_ms": head["p50_ms"],
+            "p99_ms": head["p99_ms"], "solo_p50_ms_by_size": solo_ms, "modes": modes}
 
 
 def serve_mixed(P, torch, count, budget_gb):
@@ -331,33 +378,6 @@ def deposit_leg(P, torch, n, reps):
     nbytes = 8 * n ** 3 + 24 * pos.shape[0]
     return dict(ms=dt * 1e3, particles=int(pos.shape[0]), particles_per_s=pos.shape[0] / dt,
                 bytes=nbytes, gbs=nbytes / dt / 1e9)
-
-
-class DeviceProblem:
-    """A workload whose fields were generated on the device (torch tensors)."""
-
-    def __init__(self, name, shape, lengths, rho, b):
-        self.name, self.shape, self.lengths, self.rho, self.b = name, tuple(shape), tuple(lengths), rho, b
-
-    @property
-    def n(self):
-        return int(self.shape[0] * self.shape[1] * self.shape[2])
-
-
-def workload3_device(P, torch, inputs, n=512):
-    """The 512^3 particle workload built on the device: the density from the
-    GPU's trilinear deposit P of the 10^6 seeded particles, rho = 1/(1 + 9
-    d/max d) (d per unit volume; the ratio d/max d is the same as for the raw
-    weight sums), b band-limited from the same seeded draws as the host recipe."""
-    shape, L = (n, n, n), (2.0 * math.pi,) * 3
-    pos = torch.from_numpy(inputs.workload3_particles()).cuda()
-    d = torch.empty(shape, dtype=torch.float64, device="cuda")
-    with P.Solver(shape, L) as s:
-        P.poisson_deposit(s.h, pos, None, d)
-    rho = (1.0 / (1.0 + 9.0 * d / d.max())).contiguous()
-    del d, pos
-    b = inputs.workload3_b_device(n)
-    return DeviceProblem(f"particle-deposit-rho {n}^3 ratio 10", shape, L, rho, b)
 
 
 def copy_ceiling(torch, mib=1024, reps=10):
@@ -580,7 +600,9 @@ def main():
                                                               args.tol, P.POISSON_BC_WALLS_X)}
     del duct
     if not args.no_512:
-        big = workload3_device(P, torch, inputs)
+        from paper_1601_05448_amd import device_inputs
+
+        big = device_inputs.workload3_device(512)
         lg = {"workload": "512^3 particle-deposit rho (10^6 uniform particles, trilinear deposit by the GPU's P, "
                           "rho = 1/(1 + 9 d/max d), ratio 10), band-limited b, tol %g" % args.tol,
               "fp64": time_path(P, torch, big, P.POISSON_FP64, 5, 1, args.tol),

@@ -116,6 +116,7 @@ typedef struct {
                                per residual evaluation; FP32_REFINE, one per inner
                                evaluation except the first of a refinement step where
                                the outer residual sweep produced it                  */
+    double queue_ms;        /* served requests: host time from submit to admission; else 0 */
 } poisson_stats;
 
 /* Create a solver for one grid: validates the options, builds the transform
@@ -267,10 +268,11 @@ int poisson_project(poisson_t h, const double* rho, double* mx, double* my, doub
 
 /* out = P(q): out_c = sum_p q_p W_p(c) / (hx hy hz).  q: n_particles device
  * values, or NULL for q = 1 (then out is the particle number density).
- * Deterministic (no atomics: the particles are sorted by cell, and every cell
- * adds its contributions in a fixed order).  Uses the handle's transform buffer
- * as scratch (no solve may run on the handle meanwhile) and keeps particle
- * buffers in the handle, grown as needed.  Blocks until done. */
+ * Deterministic (no floating-point atomics: the particles are sorted by cell,
+ * and every cell adds its contributions in a fixed order, so repeated calls
+ * give the same bits).  Keeps particle buffers in the handle, grown as needed
+ * (about 80 B per particle); out must not overlap pos or q.  Blocks until
+ * done. */
 int poisson_deposit(poisson_t h, int n_particles, const double* pos, const double* q, double* out);
 
 /* out_p = I(field)(x_p): trilinear interpolation of a device FP64 cell field at
@@ -282,8 +284,9 @@ int poisson_interpolate(poisson_t h, int n_particles, const double* pos, const d
 /* ---- serving: many independent solves of different sizes -----------------
  * A server keeps each admitted request's rho, b, p and iteration state on the
  * device, groups requests of equal grid size into batches that advance
- * together (one set of batched launches per size class and tick, blockIdx.y
- * selecting the request, each class on a stream of its own), and admits new
+ * together (one chunk of batched launches per size class at a time, blockIdx.y
+ * selecting the request, each class on a stream of its own, optionally
+ * replayed from captured graphs: poisson_server_use_graphs), and admits new
  * requests between ticks as slots and memory free up.  Requests are
  * independent: each result is the same as a solve of that request alone. */
 typedef struct poisson_server_s* poisson_server_t;
@@ -320,6 +323,12 @@ int poisson_server_tick(poisson_server_t s);
  * completion (host clock).  A done request's stats stay readable until the
  * server is destroyed.  A server is driven by one host thread. */
 int poisson_server_poll(poisson_server_t s, long long id, poisson_stats* stats);
+
+/* on != 0: each size class's chunk of batched launches is captured once per
+ * (batch size, chunk length, share of the chip) into a HIP graph and replayed
+ * on later ticks (the slot table it reads is rewritten before each replay);
+ * 0 (the default): the same kernels are launched directly.  Same results. */
+int poisson_server_use_graphs(poisson_server_t s, int on);
 
 /* *bytes = the footprint a request on grid (nx, ny, nz) with boundary
  * condition bc_x holds against this server's budget while it is admitted: its

@@ -786,8 +786,7 @@ int poisson_deposit(poisson_t h, int n_particles, const double* pos, const doubl
     int rc = particle_ws(h, particle_workspace_bytes(h->g, n_particles));
     if (rc != POISSON_OK) return rc;
     int bad = 0;
-    rc = hip_status(launch_deposit(h->g, n_particles, pos, q, out, reinterpret_cast<unsigned*>(h->ws.W), h->part_ws,
-                                   h->part_ws_bytes, &bad, h->stream));
+    rc = hip_status(launch_deposit(h->g, n_particles, pos, q, out, h->part_ws, h->part_ws_bytes, &bad, h->stream));
     if (rc != POISSON_OK) return rc;
     if (bad) return POISSON_EDOMAIN;
     return hip_status(hipStreamSynchronize(h->stream));

@@ -197,8 +197,10 @@ struct LineCfg {
     static constexpr int NT = L * TT;
     static constexpr int IT = N / TT;  // elements per thread when a block walks its L lines
     static constexpr int LS = line_stride(N);
-    // blocks per CU the register budget of a sweep is sized for: two blocks of
-    // up to 256 threads, one block of 512 (both 8 waves per CU)
+    // minimum waves per SIMD (the second __launch_bounds__ argument, which caps
+    // the registers per thread) a sweep is sized for: 2 for blocks of up to 256
+    // threads (two blocks per CU); 1 for 512-thread blocks, which hold two waves
+    // per SIMD by themselves (one block per CU)
     static constexpr int MINB = NT > 256 ? 1 : 2;
     static_assert(NT % 64 == 0, "block must be whole wavefronts");
     static __device__ __forceinline__ constexpr int pos(int e) { return N >= 16 ? e + e / 16 : e; }
@@ -280,6 +282,47 @@ __device__ __forceinline__ void fft256_regs(cpx<T> (&v)[16], cpx<T>* ln, int c, 
     for (int a = 0; a < 16; ++a) v[a] = ln[C::pos(16 * c + a)];
     __syncthreads();
     dft16(v);
+}
+
+// Forward DFT of the block's lines for N = 512 = 16 x 32, the line held in
+// registers by its 32 threads.  The thread with column index c (0..31) enters
+// with v[a] = x[c + 32 a] (a = 0..15).  Writing n = c + 32 a and
+// k = k1 + 16 k2 (k1 < 16, k2 < 32),
+//     X[k] = sum_c W32^(c k2) W512^(c k1) sum_a x[c + 32 a] W16^(a k1):
+// a length-16 DFT over a in registers and the twiddles W512^(c k1); one
+// transpose through the line's LDS row, after which thread t takes k1 = t/2
+// and the half h = t mod 2 of the columns, c = 2 c' + h; a length-16 DFT over
+// c' (times W32^(k2') for h = 1) gives the even (h = 0) and odd (h = 1) halves
+// of the length-32 DFT over c, which the two partner threads combine:
+//     X[k1 + 16 k2'] = E[k2'] + O[k2'],  X[k1 + 16 k2' + 256] = E[k2'] - O[k2'].
+// The thread leaves with v[b] = X[k1 + 16 b + 256 h].  The partner of column c
+// is column c ^ 1, whose lane is `partner_xor` away (lanes are lines-fastest:
+// lane = line + L c within the wave).  All threads of the block call it: it
+// holds two barriers, the second one guarding `ln` for its next writer.
+template <typename T, int PARTNER_XOR>
+__device__ __forceinline__ void fft512_regs(cpx<T> (&v)[16], cpx<T>* ln, int c, const cpx<T>* tw) {
+    using C = LineCfg<T, 512>;
+    dft16(v);
+#pragma unroll
+    for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmul(v[k1], tw[c * k1]);
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) ln[C::pos(32 * k1 + c)] = v[k1];
+    __syncthreads();
+    const int k1 = c >> 1, h = c & 1;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = ln[C::pos(32 * k1 + 2 * q + h)];
+    __syncthreads();
+    dft16(v);
+    if (h) {
+#pragma unroll
+        for (int q = 1; q < 16; ++q) v[q] = cmul(v[q], tw[16 * q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const cpx<T> o = {__shfl_xor(v[q].x, PARTNER_XOR), __shfl_xor(v[q].y, PARTNER_XOR)};
+        // h = 0: E = v, O = o -> E + O; h = 1: O = v, E = o -> E - O
+        v[q] = h ? csub(o, v[q]) : cadd(v[q], o);
+    }
 }
 
 // Hartley value of the pair-packed line at k from its DFT Z:

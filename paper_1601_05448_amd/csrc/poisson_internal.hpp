@@ -184,12 +184,12 @@ hipError_t launch_correct(const GridArgs& g, const double* p, double* mx, double
                           hipStream_t s);
 
 // Particles and the grid (poisson_particles.hip): out = P(q) per unit volume
-// (cells2: n unsigned words of scratch; ws: particle_workspace_bytes(g, np)),
-// out_p = I(field)(x_p).  *bad_host = 1 when a position is not finite or too far
-// out (then nothing else is written).
+// (ws: particle_workspace_bytes(g, np) bytes of device scratch), out_p =
+// I(field)(x_p).  *bad_host = 1 when a position is not finite or too far out
+// (then nothing else is written).
 size_t particle_workspace_bytes(const GridArgs& g, int np);
-hipError_t launch_deposit(const GridArgs& g, int np, const double* pos, const double* q, double* out,
-                          unsigned* cells2, void* ws, size_t ws_bytes, int* bad_host, hipStream_t s);
+hipError_t launch_deposit(const GridArgs& g, int np, const double* pos, const double* q, double* out, void* ws,
+                          size_t ws_bytes, int* bad_host, hipStream_t s);
 hipError_t launch_interpolate(const GridArgs& g, int np, const double* pos, const double* field, double* out,
                               int* bad_dev, int* bad_host, hipStream_t s);
 

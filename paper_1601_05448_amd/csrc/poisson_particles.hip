@@ -5,27 +5,30 @@
 // gives weight 1 - f to cell i0 and f to cell i0 + 1; its eight cells get the
 // products of the three directions' weights.
 //
-// P without atomics, deterministic: every particle gets the key of its lower
-// corner cell (i0, j0, k0); a stable radix sort (rocPRIM) orders the particles by
-// key and, within a key, by index; for every occupied cell the thread at the
-// start of its run of sorted particles records that start and adds, over the
-// run in order, the eight corner sums sum_p q_p W_a W_b W_e (a, b, e the offsets
-// 0/1 of the corner cell in x, y, z); then every grid cell adds the matching
-// corner sums of its eight lower neighbours (itself included), in a fixed
-// order, by one thread that marches along z (four run starts loaded per cell,
-// the next plane's while the current cell adds).  Every cell is written once,
-// by one thread, with the same sum order in every run.  I is a plain gather,
-// one thread per particle.
+// P without floating-point atomics, deterministic: every particle gets the key
+// of its lower corner cell (i0, j0, k0); a stable radix sort (least significant
+// digit first, 10-bit digits; within a block the rank of a key among equal
+// digits comes from wave ballots, so equal keys keep their index order) orders
+// the particles by key and, within a key, by index; the run of each occupied
+// cell is summed in pieces of at most kPiece sorted particles (so a cell holding
+// many particles costs a few piece sums, not a long serial loop), and the
+// pieces of a run are added in order into its eight corner sums
+// sum_p q_p W_a W_b W_e (a, b, e the offsets 0/1 of the corner cell in x, y, z).
+// The grid is zeroed, then eight passes, one per parity class of the run's cell,
+// add each run's eight corner sums (over the cell volume) to its 2 x 2 x 2
+// cells: within a pass no two runs touch the same cell, so every cell adds its
+// contributions in the same order in every run.  I is a plain gather, one
+// thread per particle.
 #include <hip/hip_runtime.h>
 
-#include <rocprim/device/device_radix_sort.hpp>
+#include <algorithm>
+#include <utility>
 
 #include "poisson_device.hpp"
 
 namespace pois {
 
 constexpr int kPartThreads = 256;
-constexpr unsigned kNoParticle = 0xffffffffu;
 
 // lower cell index and fraction of a coordinate along one direction; false if
 // the position is not finite or more than 2^30 cells away
@@ -63,93 +66,229 @@ k_part_keys(PartGeom pg, int np, const double* __restrict__ pos, unsigned* __res
     idx[p] = (unsigned)p;
 }
 
-__global__ void __launch_bounds__(kPartThreads) k_part_fill(unsigned* __restrict__ a, unsigned long long n, unsigned v) {
+__global__ void __launch_bounds__(kPartThreads) k_part_zero(double* __restrict__ a, unsigned long long n) {
     for (unsigned long long c = (unsigned long long)blockIdx.x * kPartThreads + threadIdx.x; c < n;
          c += (unsigned long long)gridDim.x * kPartThreads)
-        a[c] = v;
+        a[c] = 0.0;
 }
 
 __global__ void __launch_bounds__(kPartThreads) k_part_flag_clear(int* __restrict__ bad) {
     if (threadIdx.x == 0) bad[0] = 0;
 }
 
-// The thread at the start s of each run of equal keys (one occupied lower
-// corner cell c): first[c] = s, and corner[8 s + q] = the run's sum, in sorted
-// order, of q_p W_a W_b W_e for corner q = a + 2 b + 4 e, with W = 1 - f for
-// offset 0 and f for offset 1.
+// ---- stable LSD radix sort of (key, index) pairs ----------------------------------
+// One pass orders by the digit (key >> shift) & (kDigits - 1), keeping the order
+// of equal digits: per tile of kSortTile pairs a block counts its digits
+// (k_rs_count), one block turns the counts into each (digit, tile)'s first
+// output position (k_rs_scan, digit-major so that lower tiles come first), and
+// every block writes its pairs there in tile order (k_rs_scatter).
+constexpr int kDigitBits = 10;
+constexpr int kDigits = 1 << kDigitBits;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;
+
+__global__ void __launch_bounds__(kSortThreads)
+k_rs_count(int np, const unsigned* __restrict__ key, int shift, unsigned* __restrict__ counts) {
+    __shared__ unsigned hist[kDigits];
+    for (int d = threadIdx.x; d < kDigits; d += kSortThreads) hist[d] = 0u;
+    __syncthreads();
+    const int base = blockIdx.x * kSortTile;
+    for (int it = 0; it < kSortItems; ++it) {
+        const int e = base + it * kSortThreads + (int)threadIdx.x;
+        if (e < np) atomicAdd(&hist[(key[e] >> shift) & (kDigits - 1)], 1u);  // integer: exact in any order
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < kDigits; d += kSortThreads) counts[(size_t)d * gridDim.x + blockIdx.x] = hist[d];
+}
+
+// Exclusive prefix sums of the counts, digit-major: one block per digit scans
+// that digit's per-tile counts in place (chunks of kSortThreads with a carry)
+// and writes the digit's total; then one block turns the totals into each
+// digit's first output position (k_rs_digits).  The scatter adds the two.
+__global__ void __launch_bounds__(kSortThreads) k_rs_scan_tiles(unsigned* __restrict__ counts, int tiles,
+                                                                unsigned* __restrict__ digit_tot) {
+    __shared__ unsigned buf[kSortThreads];
+    unsigned* c = counts + (size_t)blockIdx.x * tiles;
+    unsigned carry = 0u;
+    for (int t0 = 0; t0 < tiles; t0 += kSortThreads) {
+        const int t = t0 + (int)threadIdx.x;
+        const unsigned v = t < tiles ? c[t] : 0u;
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < kSortThreads; off <<= 1) {  // Hillis-Steele inclusive scan
+            const unsigned u = threadIdx.x >= (unsigned)off ? buf[threadIdx.x - off] : 0u;
+            __syncthreads();
+            buf[threadIdx.x] += u;
+            __syncthreads();
+        }
+        if (t < tiles) c[t] = carry + buf[threadIdx.x] - v;
+        carry += buf[kSortThreads - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) digit_tot[blockIdx.x] = carry;
+}
+
+__global__ void __launch_bounds__(kDigits) k_rs_digits(unsigned* __restrict__ digit_tot) {
+    __shared__ unsigned buf[kDigits];
+    const unsigned v = digit_tot[threadIdx.x];
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < kDigits; off <<= 1) {
+        const unsigned u = threadIdx.x >= (unsigned)off ? buf[threadIdx.x - off] : 0u;
+        __syncthreads();
+        buf[threadIdx.x] += u;
+        __syncthreads();
+    }
+    digit_tot[threadIdx.x] = buf[threadIdx.x] - v;  // exclusive
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_rs_scatter(int np, const unsigned* __restrict__ key, const unsigned* __restrict__ idx, int shift,
+             const unsigned* __restrict__ start, const unsigned* __restrict__ digit_base,
+             unsigned* __restrict__ key_out, unsigned* __restrict__ idx_out) {
+    constexpr int kWaves = kSortThreads / 64;
+    __shared__ unsigned run[kDigits];               // pairs of each digit this block has placed so far
+    __shared__ unsigned wcnt[kWaves * kDigits];     // this round's count of each digit per wave
+    for (int d = threadIdx.x; d < kDigits; d += kSortThreads)
+        run[d] = digit_base[d] + start[(size_t)d * gridDim.x + blockIdx.x];
+    for (int q = threadIdx.x; q < kWaves * kDigits; q += kSortThreads) wcnt[q] = 0u;
+    __syncthreads();
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int base = blockIdx.x * kSortTile;
+    for (int it = 0; it < kSortItems; ++it) {
+        const int e = base + it * kSortThreads + (int)threadIdx.x;
+        const bool valid = e < np;
+        const unsigned k = valid ? key[e] : 0u;
+        const unsigned d = (k >> shift) & (kDigits - 1);
+        // lanes of this wave with the same digit: the AND over the digit's bits
+        unsigned long long same = __ballot(valid);
+#pragma unroll
+        for (int bit = 0; bit < kDigitBits; ++bit) {
+            const unsigned long long on = __ballot((d >> bit) & 1u);
+            same &= ((d >> bit) & 1u) ? on : ~on;
+        }
+        const unsigned rank = (unsigned)__popcll(same & below);
+        // the lowest lane of each digit group records the group's size
+        if (valid && rank == 0u) wcnt[wave * kDigits + d] = (unsigned)__popcll(same);
+        __syncthreads();
+        if (valid) {
+            unsigned pos = run[d] + rank;
+            for (int w = 0; w < wave; ++w) pos += wcnt[w * kDigits + d];
+            key_out[pos] = k;
+            idx_out[pos] = idx[e];
+        }
+        __syncthreads();
+        for (int dd = threadIdx.x; dd < kDigits; dd += kSortThreads) {
+            unsigned add = 0u;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) {
+                add += wcnt[w * kDigits + dd];
+                wcnt[w * kDigits + dd] = 0u;
+            }
+            run[dd] += add;
+        }
+        __syncthreads();
+    }
+}
+
+// ---- run sums --------------------------------------------------------------------------
+// Pieces: runs cut at every multiple of kPiece sorted positions.  The thread of
+// positions [kPiece t, kPiece (t + 1)) sums each piece that starts in its range
+// (at a run start or at kPiece t) in sorted order and stores the eight sums at
+// the piece's first position; then the thread at each run start adds the run's
+// pieces in order (its own, then those at the following multiples of kPiece).
+constexpr int kPiece = 16;
+
+__device__ __forceinline__ void corner_weights(const PartGeom& pg, const double* __restrict__ pos,
+                                               const double* __restrict__ q, unsigned p, double (&w)[8]) {
+    int i;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    (void)cell_frac(pos[3 * (size_t)p], pg.inv_hx, pg.nx, i, fx);
+    (void)cell_frac(pos[3 * (size_t)p + 1], pg.inv_hy, pg.ny, i, fy);
+    (void)cell_frac(pos[3 * (size_t)p + 2], pg.inv_hz, pg.nz, i, fz);
+    const double qp = q ? q[p] : 1.0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        w[c] = qp * ((c & 1) ? fx : 1.0 - fx) * ((c & 2) ? fy : 1.0 - fy) * ((c & 4) ? fz : 1.0 - fz);
+}
+
 __global__ void __launch_bounds__(kPartThreads)
-k_part_runs(PartGeom pg, int np, const double* __restrict__ pos, const double* __restrict__ q,
-            const unsigned* __restrict__ key_s, const unsigned* __restrict__ idx_s, unsigned* __restrict__ first,
-            double* __restrict__ corner) {
+k_part_pieces(PartGeom pg, int np, const double* __restrict__ pos, const double* __restrict__ q,
+              const unsigned* __restrict__ key_s, const unsigned* __restrict__ idx_s, double* __restrict__ psum) {
+    const int t = blockIdx.x * kPartThreads + threadIdx.x;
+    const int s0 = t * kPiece;
+    if (s0 >= np) return;
+    const int s1 = min(np, s0 + kPiece);
+    double acc[8];
+    int at = s0;
+    unsigned kprev = key_s[s0];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+    for (int s = s0; s < s1; ++s) {
+        const unsigned k = key_s[s];
+        if (k != kprev) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                psum[8 * (size_t)at + c] = acc[c];
+                acc[c] = 0.0;
+            }
+            at = s;
+            kprev = k;
+        }
+        double w[8];
+        corner_weights(pg, pos, q, idx_s[s], w);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] += w[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) psum[8 * (size_t)at + c] = acc[c];
+}
+
+__global__ void __launch_bounds__(kPartThreads)
+k_part_runs(int np, const unsigned* __restrict__ key_s, double* __restrict__ psum) {
     const int s = blockIdx.x * kPartThreads + threadIdx.x;
     if (s >= np) return;
     const unsigned k = key_s[s];
     if (s > 0 && key_s[s - 1] == k) return;
-    first[k] = (unsigned)s;
+    int nxt = (s / kPiece + 1) * kPiece;
+    if (nxt >= np || key_s[nxt] != k) return;  // a single piece: its sums are the run's
     double acc[8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) acc[c] = 0.0;
-    for (int e = s; e < np && key_s[e] == k; ++e) {
-        const unsigned p = idx_s[e];
-        int i;
-        double fx = 0.0, fy = 0.0, fz = 0.0;
-        (void)cell_frac(pos[3 * (size_t)p], pg.inv_hx, pg.nx, i, fx);
-        (void)cell_frac(pos[3 * (size_t)p + 1], pg.inv_hy, pg.ny, i, fy);
-        (void)cell_frac(pos[3 * (size_t)p + 2], pg.inv_hz, pg.nz, i, fz);
-        const double qp = q ? q[p] : 1.0;
+    for (int c = 0; c < 8; ++c) acc[c] = psum[8 * (size_t)s + c];
+    for (; nxt < np && key_s[nxt] == k; nxt += kPiece) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-            acc[c] += qp * ((c & 1) ? fx : 1.0 - fx) * ((c & 2) ? fy : 1.0 - fy) * ((c & 4) ? fz : 1.0 - fz);
+        for (int c = 0; c < 8; ++c) acc[c] += psum[8 * (size_t)nxt + c];
     }
 #pragma unroll
-    for (int c = 0; c < 8; ++c) corner[8 * (size_t)s + c] = acc[c];
+    for (int c = 0; c < 8; ++c) psum[8 * (size_t)s + c] = acc[c];
 }
 
-// out_c = sum over the lower neighbours c - (a, b, e), a, b, e in {0, 1}, of
-// their runs' corner sums for corner a + 2 b + 4 e, times 1/V.  A thread owns
-// column (i, j) and marches along z through kGatherPlanes cells: the run starts
-// of plane k (four columns: (i, j), (i-1, j), (i, j-1), (i-1, j-1)) serve as the
-// e = 0 corners of cell k and the e = 1 corners of cell k + 1, and the next
-// plane's starts are loaded while the current cell adds its sums.
-constexpr int kGatherPlanes = 16;
-
+// Pass `color` of the eight: the runs whose cell (i, j, k) has parities
+// (i, j, k) mod 2 = color add their eight corner sums (over the cell volume) to
+// the cells (i + a, j + b, k + e), wrapped.  Every length is even, so two runs
+// of one color are two or more cells apart in some direction and their 2 x 2 x 2
+// footprints are disjoint: no two threads of a pass touch one cell, and each
+// cell receives its contributions in the fixed order of the passes.
 __global__ void __launch_bounds__(kPartThreads)
-k_part_gather(PartGeom pg, const unsigned* __restrict__ first, const double* __restrict__ corner,
-              double* __restrict__ out) {
+k_part_scatter(PartGeom pg, int np, const unsigned* __restrict__ key_s, const double* __restrict__ psum, int color,
+               double* __restrict__ out) {
+    const int s = blockIdx.x * kPartThreads + threadIdx.x;
+    if (s >= np) return;
+    const unsigned key = key_s[s];
+    if (s > 0 && key_s[s - 1] == key) return;
     const unsigned nx = pg.nx, ny = pg.ny, nz = pg.nz;
-    const unsigned i = blockIdx.x * kPartThreads + threadIdx.x, j = blockIdx.y;
-    if (i >= nx) return;
-    const unsigned im = (i == 0) ? nx - 1 : i - 1, jm = (j == 0) ? ny - 1 : j - 1;
-    const unsigned col[4] = {j * nx + i, j * nx + im, jm * nx + i, jm * nx + im};  // a + 2 b
-    const unsigned sz = nx * ny;
-    const unsigned k0 = blockIdx.z * kGatherPlanes;
-    const unsigned k1 = (k0 + kGatherPlanes < nz) ? k0 + kGatherPlanes : nz;
-    unsigned prev[4], cur[4];
-    const unsigned km = (k0 == 0 ? nz - 1 : k0 - 1) * sz;
+    const unsigned i = key % nx, j = (key / nx) % ny, k = key / (nx * ny);
+    if ((int)((i & 1u) | ((j & 1u) << 1) | ((k & 1u) << 2)) != color) return;
+    const unsigned i1 = i + 1 == nx ? 0u : i + 1, j1 = j + 1 == ny ? 0u : j + 1, k1 = k + 1 == nz ? 0u : k + 1;
+    double w[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) prev[q] = first[km + col[q]];
+    for (int q = 0; q < 8; ++q) w[q] = psum[8 * (size_t)s + q] * pg.inv_v;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) cur[q] = first[k0 * sz + col[q]];
-    for (unsigned k = k0; k < k1; ++k) {
-        unsigned nxt[4];
-        const unsigned kn = (k + 1 < nz ? k + 1 : 0) * sz;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) nxt[q] = first[kn + col[q]];  // in flight during this cell
-        double v[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const unsigned f0 = (q & 4) ? prev[q & 3] : cur[q & 3];
-            v[q] = (f0 == kNoParticle) ? 0.0 : corner[8 * (size_t)f0 + q];
-        }
-        double acc = 0.0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc += v[q];
-        out[(size_t)k * sz + col[0]] = acc * pg.inv_v;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            prev[q] = cur[q];
-            cur[q] = nxt[q];
-        }
+    for (int q = 0; q < 8; ++q) {
+        const size_t c = ((size_t)((q & 4) ? k1 : k) * ny + ((q & 2) ? j1 : j)) * nx + ((q & 1) ? i1 : i);
+        out[c] += w[q];
     }
 }
 
@@ -202,30 +341,33 @@ static int key_bits(long long n) {
     return b;
 }
 
+static size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static int sort_tiles(int np) { return (np + kSortTile - 1) / kSortTile; }
+
 size_t particle_workspace_bytes(const GridArgs& g, int np) {
-    size_t temp = 0;
-    (void)rocprim::radix_sort_pairs(nullptr, temp, (const unsigned*)nullptr, (unsigned*)nullptr,
-                                    (const unsigned*)nullptr, (unsigned*)nullptr, (unsigned)np, 0,
-                                    key_bits(g.n), (hipStream_t)0);
-    // keys, indices, sorted keys, sorted indices, corner sums, flag, sort temp
-    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    return 4 * up((size_t)np * 4) + up((size_t)np * 64) + 256 + up(temp);
+    (void)g;
+    // keys, indices (two of each for the sort passes), piece and run sums, the
+    // per-(digit, tile) counts, the digit totals, the bad-position flag
+    return 4 * up256((size_t)np * 4) + up256((size_t)np * 64) +
+           up256((size_t)kDigits * std::max(1, sort_tiles(np)) * 4) + up256((size_t)kDigits * 4) + 256;
 }
 
-hipError_t launch_deposit(const GridArgs& g, int np, const double* pos, const double* q, double* out,
-                          unsigned* cells2, void* ws, size_t ws_bytes, int* bad_host, hipStream_t s) {
+hipError_t launch_deposit(const GridArgs& g, int np, const double* pos, const double* q, double* out, void* ws,
+                          size_t ws_bytes, int* bad_host, hipStream_t s) {
+    if (ws_bytes < particle_workspace_bytes(g, np)) return hipErrorInvalidValue;
     const PartGeom pg = part_geom(g);
-    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
     char* w = static_cast<char*>(ws);
+    const size_t kb = up256((size_t)np * 4);
     unsigned* key = reinterpret_cast<unsigned*>(w);
-    unsigned* idx = reinterpret_cast<unsigned*>(w + up((size_t)np * 4));
-    unsigned* key_s = reinterpret_cast<unsigned*>(w + 2 * up((size_t)np * 4));
-    unsigned* idx_s = reinterpret_cast<unsigned*>(w + 3 * up((size_t)np * 4));
-    double* corner = reinterpret_cast<double*>(w + 4 * up((size_t)np * 4));
-    int* bad = reinterpret_cast<int*>(w + 4 * up((size_t)np * 4) + up((size_t)np * 64));
-    void* temp = w + 4 * up((size_t)np * 4) + up((size_t)np * 64) + 256;
-    size_t temp_bytes = ws_bytes - (4 * up((size_t)np * 4) + up((size_t)np * 64) + 256);
-    unsigned* first = cells2;
+    unsigned* idx = reinterpret_cast<unsigned*>(w + kb);
+    unsigned* key2 = reinterpret_cast<unsigned*>(w + 2 * kb);
+    unsigned* idx2 = reinterpret_cast<unsigned*>(w + 3 * kb);
+    double* psum = reinterpret_cast<double*>(w + 4 * kb);
+    unsigned* counts = reinterpret_cast<unsigned*>(w + 4 * kb + up256((size_t)np * 64));
+    const size_t cb = up256((size_t)kDigits * std::max(1, sort_tiles(np)) * 4);
+    unsigned* digit_tot = reinterpret_cast<unsigned*>(w + 4 * kb + up256((size_t)np * 64) + cb);
+    int* bad = reinterpret_cast<int*>(w + 4 * kb + up256((size_t)np * 64) + cb + up256((size_t)kDigits * 4));
     const unsigned long long n = (unsigned long long)g.n;
     const int pb = (np + kPartThreads - 1) / kPartThreads;
     hipError_t e;
@@ -240,16 +382,26 @@ hipError_t launch_deposit(const GridArgs& g, int np, const double* pos, const do
             *bad_host = 1;
             return hipSuccess;
         }
-        if ((e = rocprim::radix_sort_pairs(temp, temp_bytes, key, key_s, idx, idx_s, (unsigned)np, 0, key_bits(g.n),
-                                           s)) != hipSuccess)
-            return e;
+        const int tiles = sort_tiles(np);
+        const int bits = key_bits(g.n);
+        for (int shift = 0; shift < bits; shift += kDigitBits) {
+            k_rs_count<<<tiles, kSortThreads, 0, s>>>(np, key, shift, counts);
+            k_rs_scan_tiles<<<kDigits, kSortThreads, 0, s>>>(counts, tiles, digit_tot);
+            k_rs_digits<<<1, kDigits, 0, s>>>(digit_tot);
+            k_rs_scatter<<<tiles, kSortThreads, 0, s>>>(np, key, idx, shift, counts, digit_tot, key2, idx2);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            std::swap(key, key2);
+            std::swap(idx, idx2);
+        }
     }
-    const unsigned fb = (unsigned)std::min<unsigned long long>((n + kPartThreads - 1) / kPartThreads, 65536ull);
-    k_part_fill<<<fb, kPartThreads, 0, s>>>(first, n, kNoParticle);
-    if (np > 0) k_part_runs<<<pb, kPartThreads, 0, s>>>(pg, np, pos, q, key_s, idx_s, first, corner);
-    const dim3 gg((unsigned)(g.nx + kPartThreads - 1) / kPartThreads, (unsigned)g.ny,
-                  (unsigned)(g.nz + kGatherPlanes - 1) / kGatherPlanes);
-    k_part_gather<<<gg, kPartThreads, 0, s>>>(pg, first, corner, out);
+    const unsigned zb = (unsigned)std::min<unsigned long long>((n + kPartThreads - 1) / kPartThreads, 8192ull);
+    k_part_zero<<<zb, kPartThreads, 0, s>>>(out, n);
+    if (np > 0) {
+        const int nb_pieces = ((np + kPiece - 1) / kPiece + kPartThreads - 1) / kPartThreads;
+        k_part_pieces<<<nb_pieces, kPartThreads, 0, s>>>(pg, np, pos, q, key, idx, psum);
+        k_part_runs<<<pb, kPartThreads, 0, s>>>(np, key, psum);
+        for (int c = 0; c < 8; ++c) k_part_scatter<<<pb, kPartThreads, 0, s>>>(pg, np, key, psum, c, out);
+    }
     return hipGetLastError();
 }
 

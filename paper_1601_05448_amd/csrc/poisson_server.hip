@@ -5,11 +5,15 @@
 //   1. admits queued requests, first come first served, while a slot is free
 //      and the request's resident footprint (its rho, b and p plus the solver
 //      workspace) fits the memory budget; workspaces are recycled per grid size;
-//   2. advances every size class (all resident requests of one grid) by a few
-//      iterations with batched launches: blockIdx.y of every kernel selects the
-//      request, each request keeps its own state, norms and stopping decision on
-//      the device, and the classes run on their own streams so that their work
-//      overlaps on the device;
+//   2. advances every size class (all resident requests of one grid) by a chunk
+//      of iterations with batched launches: blockIdx.y of every kernel selects
+//      the request, each request keeps its own state, norms and stopping
+//      decision on the device, and the classes run on their own streams so that
+//      their work overlaps on the device.  A class's chunk is as long as its
+//      request closest to done needs at the contraction it has shown, so that
+//      requests retire as soon as they finish; with graphs on, each chunk's
+//      launches are captured once per (batch size, chunk, share of the chip)
+//      and replayed, the slot table being rewritten between replays;
 //   3. retires finished requests (their p is final) and frees their slots.
 // A request's arithmetic is exactly that of a solve of it alone: the kernels of
 // one request read only that request's fields and workspace, and every
@@ -50,6 +54,7 @@ struct Request {
     double* p;
     double tol;
     double t_submit;
+    double t_admit;
 };
 
 using ClassKey = std::tuple<int, int, int, double, double, double, int>;
@@ -58,6 +63,8 @@ struct Resident {
     Request req;
     Workspace* ws;
     bool fresh;
+    int k_prev = -1;     // index of the residual evaluated at the previous chunk's end
+    double r_prev = 0.0;  // and its relative residual
 };
 
 struct SizeClass {
@@ -75,6 +82,8 @@ struct SizeClass {
     long long cells = 0;
     bool in_flight = false;  // a chunk of this class is enqueued and not yet retired
     int n_launched = 0;      // active[0, n_launched) are the solves of that chunk
+    int chunk = 4;           // iterations (FP32: inner sweeps) of the next chunk
+    GraphCache graphs;       // captured chunks, keyed by batch size, chunk and share
 
     ~SizeClass() {
         for (Workspace* w : pool) {
@@ -88,6 +97,7 @@ struct SizeClass {
         if (d_slots) (void)hipFree(d_slots);
         if (h_slots) (void)hipHostFree(h_slots);
         if (h_hdr) (void)hipHostFree(h_hdr);
+        graphs.release();
         if (done_ev) (void)hipEventDestroy(done_ev);
         if (stream) (void)hipStreamDestroy(stream);
         tables.release();
@@ -109,7 +119,7 @@ struct poisson_server_s {
     std::map<ClassKey, std::unique_ptr<SizeClass>> classes;
     std::map<long long, poisson_stats> finished;
     int resident = 0;
-    int iters_per_tick = 4;
+    bool use_graphs = false;
 };
 
 static size_t field_bytes(long long cells) { return (size_t)cells * 3 * sizeof(double); }
@@ -194,7 +204,9 @@ static int admit(poisson_server_s* s) {
             }
             s->used += need;
         }
-        c->active.push_back(Resident{r, w, true});
+        Resident res{r, w, true};
+        res.req.t_admit = now_ms();
+        c->active.push_back(res);
         ++s->resident;
         s->queue.pop_front();
     }
@@ -227,20 +239,28 @@ static int launch_class(poisson_server_s* s, SizeClass* c) {
             return hip_status(e);
         for (Resident& r : c->active) r.fresh = false;
     }
-    if (!fp32) {
-        for (int k = 0; k < s->iters_per_tick; ++k)
-            if ((e = launch_iteration(c->g, c->geo, c->tables.t, c->d_slots, n, false, c->stream)) != hipSuccess)
-                return hip_status(e);
+    // FP64: `chunk` iterations.  FP32: one fixed sequence for solves at any
+    // stage (each kernel acts only on the solves whose stage it serves): the
+    // outer residual, `chunk` inner sweeps, the update.
+    const int chunk = c->chunk;
+    auto body = [&]() -> hipError_t {
+        hipError_t le = hipSuccess;
+        if (fp32) le = launch_outer_residual(c->g, c->geo, c->tables.t, c->d_slots, n, c->stream, nullptr);
+        for (int k = 0; k < chunk && le == hipSuccess; ++k)
+            le = launch_iteration(c->g, c->geo, c->tables.t, c->d_slots, n, fp32, c->stream);
+        if (fp32 && le == hipSuccess) le = launch_outer_update(c->g, c->geo, c->d_slots, n, c->stream);
+        return le;
+    };
+    if (s->use_graphs) {
+        // the launch grids depend on the batch size and the share of the chip
+        const int share = c->geo.share < 0.6f ? 0 : c->geo.share < 0.9f ? 1 : 2;
+        const long long key = ((long long)n << 8) | ((long long)chunk << 2) | share;
+        if (c->graphs.exec.size() >= 256) c->graphs.release();
+        e = c->graphs.run(key, c->stream, body);
     } else {
-        // one fixed sequence for solves at any stage: each kernel acts only on
-        // the solves whose stage it serves
-        if ((e = launch_outer_residual(c->g, c->geo, c->tables.t, c->d_slots, n, c->stream, nullptr)) != hipSuccess)
-            return hip_status(e);
-        for (int k = 0; k < s->iters_per_tick; ++k)
-            if ((e = launch_iteration(c->g, c->geo, c->tables.t, c->d_slots, n, true, c->stream)) != hipSuccess)
-                return hip_status(e);
-        if ((e = launch_outer_update(c->g, c->geo, c->d_slots, n, c->stream)) != hipSuccess) return hip_status(e);
+        e = body();
     }
+    if (e != hipSuccess) return hip_status(e);
     const size_t hb = offsetof(SolveState, hist);
     for (int q = 0; q < n; ++q)
         if ((e = hipMemcpyAsync(&c->h_hdr[q], c->active[q].ws->st, hb, hipMemcpyDeviceToHost, c->stream)) !=
@@ -259,8 +279,39 @@ static int retire_class(poisson_server_s* s, SizeClass* c) {
     if ((e = hipEventSynchronize(c->done_ev)) != hipSuccess) return hip_status(e);
     c->in_flight = false;
     std::vector<int> done;
-    for (int q = 0; q < c->n_launched; ++q)
-        if (c->h_hdr[q].done) done.push_back(q);
+    // The next chunk: as many iterations as the request closest to done needs
+    // to pass its tolerance at the contraction it has shown since the previous
+    // chunk (or since its first residual), plus a quarter; 4 while no request
+    // has shown one.  FP32: inner sweeps of the refinement step in progress.
+    int need = 1 << 30;
+    for (int q = 0; q < c->n_launched; ++q) {
+        const SolveState& h = c->h_hdr[q];
+        if (h.done) {
+            done.push_back(q);
+            continue;
+        }
+        Resident& r = c->active[q];
+        if (s->prm.precision == POISSON_FP32_REFINE) {
+            const int k = h.inner_iter - 1;
+            if (h.stage == 1 && k >= 1 && h.rel_in > 0.0 && h.rel_in < 1.0) {
+                const double rate = std::pow(h.rel_in, 1.0 / k);
+                if (rate < 0.95)
+                    need = std::min(need, (int)std::ceil(std::log(h.inner_goal / h.rel_in) / std::log(rate) + 0.25));
+            }
+            continue;
+        }
+        const int k = h.iter - 1;
+        double rate = 1.0;
+        if (r.k_prev >= 0 && k > r.k_prev && r.r_prev > 0.0)
+            rate = std::pow(h.rel / r.r_prev, 1.0 / (k - r.k_prev));
+        else if (k >= 1 && h.rel0 > 0.0)
+            rate = std::pow(h.rel / h.rel0, 1.0 / k);
+        r.k_prev = k;
+        r.r_prev = h.rel;
+        if (rate > 0.0 && rate < 0.95 && h.rel > 0.0)
+            need = std::min(need, (int)std::ceil(std::log(h.tol / h.rel) / std::log(rate) + 0.25));
+    }
+    c->chunk = need == (1 << 30) ? 4 : std::clamp(need, 1, 16);
     c->n_launched = 0;
     if (done.empty()) return POISSON_OK;
     // end-of-solve fix-up (mean of p, b~ = 0) for the finished ones
@@ -284,6 +335,7 @@ static int retire_class(poisson_server_s* s, SizeClass* c) {
             poisson_stats st{};
             fill_stats(c->g, c->h_hdr[q], &st);
             st.ms = t - r.req.t_submit;
+            st.queue_ms = r.req.t_admit - r.req.t_submit;
             s->finished[r.req.id] = st;
             c->pool.push_back(r.ws);
             s->used -= field_bytes(c->cells);
@@ -348,6 +400,12 @@ int poisson_server_submit(poisson_server_t s, int nx, int ny, int nz, double lx,
     if (request_footprint(s, r) > s->budget) return POISSON_ETOOBIG;
     s->queue.push_back(r);
     *id = s->next_id++;
+    return POISSON_OK;
+}
+
+int poisson_server_use_graphs(poisson_server_t s, int on) {
+    if (!s) return POISSON_EINVAL;
+    s->use_graphs = on != 0;
     return POISSON_OK;
 }
 

@@ -390,11 +390,17 @@ constexpr bool use_zmarch() {
     else return (N >= C::NT ? N / C::NT : 1) * (int)sizeof(T) <= 32;
 }
 
-// Blocks per CU the residual sweep's registers are sized for: one where four
-// FP64 marching columns per thread need the accumulation registers too.
+// Minimum waves per SIMD the residual sweep's registers are sized for (the
+// second __launch_bounds__ argument, which caps the registers per thread): one
+// where four FP64 marching columns per thread need the accumulation registers
+// too.  The FP32 sweep on 512-cell rows runs 512-thread blocks whose LDS leaves
+// room for two per CU: asking for four waves per SIMD (128 registers) lets both
+// be resident, 16 waves per CU instead of 8 (6% faster at 512^3; the FP32 y, z
+// and x-update sweeps spill at 128 registers and lose 2x, so they keep one).
 template <typename T, int N>
 constexpr int p1_min_blocks() {
     using C = LineCfg<T, N>;
+    if constexpr (sizeof(T) == 4 && N == 512 && C::NT == 512) return 4;
     return (N >= C::NT ? N / C::NT : 1) * (int)sizeof(T) > 16 ? 1 : C::MINB;
 }
 
@@ -507,10 +513,14 @@ __device__ __forceinline__ cpx<T> scaled_conj(cpx<T> zk, cpx<T> zm, T sa, T sb) 
     return {hp * zk.x + hm * zm.x, hm * zm.y - hp * zk.y};  // conj(hp Z_k + hm conj Z_{N-k})
 }
 
-// The FP32 register path at N = 256 is sized for three blocks per CU (LDS
-// would allow four; its registers with the prefetch buffer allow three).
+// The FP32 register path at N = 256 is sized for three blocks per CU (three
+// waves per SIMD; LDS would allow four, its registers with the prefetch buffer
+// allow three).  At N = 512 one 512-thread block per CU (at 128 registers, for
+// two, the two line transforms spill and the sweep is slower).
 template <typename T, int N>
-constexpr int z_min_blocks() { return (sizeof(T) == 4 && N == 256) ? 3 : LineCfg<T, N>::MINB; }
+constexpr int z_min_blocks() {
+    return (sizeof(T) == 4 && N == 256) ? 3 : LineCfg<T, N>::MINB;
+}
 
 template <typename T, int N, int MODE>
 __global__ void __launch_bounds__((LineCfg<T, N>::NT), (z_min_blocks<T, N>()))
@@ -520,12 +530,12 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
     __shared__ cpx<T> tw[N];
     // the z symbol of the register path, in LDS: a global load of it after the
     // next group's prefetch would make the wait for it a wait for the prefetch
-    __shared__ T lzs[N == 256 ? N : 1];
+    __shared__ T lzs[(N == 256 || N == 512) ? N : 1];
     const Slot& s = slots[blockIdx.y];
     if (MODE == 0 && IterView<T>::skip(s.st, stage)) return;
     const cpx<T>* twg = twiddles<T>(tb, 2);
     for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
-    if constexpr (N == 256)
+    if constexpr (N == 256 || N == 512)
         for (int e = threadIdx.x; e < N; e += C::NT) lzs[e] = symbol<T>(tb, 2)[e];
     POIS_GLOBAL T* Wc = MODE == 0 ? IterView<T>(s).W : (POIS_GLOBAL T*)gptr(s.W);  // complex-indexed
     const unsigned nlines = (unsigned)(g.nxh * g.ny);
@@ -585,6 +595,54 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
 #pragma unroll
                 for (int b = 0; b < 16; ++b) {
                     const int k = e0 + 16 * b;
+                    gstore_c(Wc, cur_base + (unsigned)k * se, cpx<T>{v[b].x, -v[b].y});
+                }
+            }
+            grp = ng;
+            if (grp >= ngroups) break;
+            __syncthreads();
+        }
+        return;
+    }
+    if constexpr (N == 512) {
+        // the line stays in registers (see fft512_regs): thread e0 of a line
+        // holds x[e0 + 32 a]; after each transform it holds X[k] for
+        // k = k1 + 16 b + 256 h (k1 = e0 / 2, h = e0 % 2)
+        static_assert(C::TT == 32 && C::IT == 16, "512-point lines: 32 threads of 16 values");
+        __syncthreads();  // twiddles, symbol
+        cpx<T>* ln = lds + l * C::LS;
+        const int k1 = e0 >> 1, h = e0 & 1;
+        while (true) {
+            cpx<T> v[16];
+#pragma unroll
+            for (int a = 0; a < 16; ++a) v[a] = buf[a];
+            const bool cur_valid = valid;
+            const unsigned cur_base = base;
+            const unsigned line = grp * C::L + l;
+            const unsigned j = cur_valid ? line / (unsigned)g.nxh : 0u, m = cur_valid ? line - j * (unsigned)g.nxh : 0u;
+            const T lxe = lamx[2 * m], lxo = lamx[2 * m + 1], lyj = lamy[j];
+            const unsigned ng = grp + gridDim.x;
+            __builtin_amdgcn_s_setprio(2);
+            if (ng < ngroups) load(ng, valid, base);  // in flight during the two FFTs
+            __builtin_amdgcn_s_setprio(0);
+            fft512_regs<T, C::L>(v, ln, e0, tw);
+#pragma unroll
+            for (int b = 0; b < 16; ++b) ln[C::pos(k1 + 16 * b + 256 * h)] = v[b];
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < 16; ++a) {
+                const int k = e0 + 32 * a;
+                const T lzk = lzs[k];
+                // the second transform's input x[e0 + 32 a]
+                v[a] = scaled_conj(ln[C::pos(k)], ln[C::pos((N - k) & (N - 1))], inv_symbol(lxe, lyj, lzk, nn),
+                                   inv_symbol(lxo, lyj, lzk, nn));
+            }
+            __syncthreads();
+            fft512_regs<T, C::L>(v, ln, e0, tw);
+            if (cur_valid) {
+#pragma unroll
+                for (int b = 0; b < 16; ++b) {
+                    const int k = k1 + 16 * b + 256 * h;
                     gstore_c(Wc, cur_base + (unsigned)k * se, cpx<T>{v[b].x, -v[b].y});
                 }
             }

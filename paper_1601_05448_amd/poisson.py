@@ -51,7 +51,8 @@ class poisson_stats(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int), ("iters", ctypes.c_int), ("outer_iters", ctypes.c_int),
                 ("rel_resid", ctypes.c_double), ("b_mean_removed", ctypes.c_double),
                 ("b_norm", ctypes.c_double), ("rho_min", ctypes.c_double), ("rho_max", ctypes.c_double),
-                ("err_bound_rel", ctypes.c_double), ("ms", ctypes.c_double), ("p1_sweeps", ctypes.c_int)]
+                ("err_bound_rel", ctypes.c_double), ("ms", ctypes.c_double), ("p1_sweeps", ctypes.c_int),
+                ("queue_ms", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -110,6 +111,7 @@ def load() -> ctypes.CDLL:
         lib.poisson_server_destroy.argtypes = [vp]
         lib.poisson_server_destroy.restype = None
         lib.poisson_server_footprint.argtypes = [vp, i, i, i, i, ctypes.POINTER(ctypes.c_size_t)]
+        lib.poisson_server_use_graphs.argtypes = [vp, i]
     _lib = lib
     return lib
 
@@ -327,6 +329,12 @@ def poisson_server_poll(s: int, rid: int) -> Optional[dict]:
     if rc < 0:
         raise PoissonError(rc, "poisson_server_poll")
     return st.as_dict() if rc == 0 else None
+
+
+def poisson_server_use_graphs(s: int, on: bool) -> None:
+    rc = load().poisson_server_use_graphs(s, 1 if on else 0)
+    if rc != POISSON_OK:
+        raise PoissonError(rc, "poisson_server_use_graphs")
 
 
 def poisson_server_footprint(s: int, shape: Sequence[int], bc_x: int = POISSON_BC_PERIODIC) -> int:

@@ -4,6 +4,7 @@ calibrates the HBM byte counters.
 
     python -m paper_1601_05448_amd.profile_driver --size 256 --reps 5
     python -m paper_1601_05448_amd.profile_driver --size 256 --duct   # 2N x N x N, walls in x
+    python -m paper_1601_05448_amd.profile_driver --size 512 --deposit  # the 512^3 particle workload
 """
 import argparse
 import os
@@ -23,6 +24,8 @@ def main():
     ap.add_argument("--inner-tols", default="", help="comma list: extra FP32+refine solves at these inner tolerances")
     ap.add_argument("--duct", action="store_true", help="the duct workload with walls in x instead of the cube")
     ap.add_argument("--periodic", action="store_true", help="with --duct: periodic in x instead of walls")
+    ap.add_argument("--deposit", action="store_true",
+                    help="the particle-deposit workload (density built with the GPU's P) instead of the lognormal cube")
     args = ap.parse_args()
 
     import torch
@@ -31,10 +34,15 @@ def main():
     from paper_1601_05448_amd import poisson as P
 
     torch.cuda.set_device(0)
-    prob = inputs.workload_duct(args.size) if args.duct else inputs.workload2(args.size)
+    if args.deposit:
+        from paper_1601_05448_amd import device_inputs
+
+        prob = device_inputs.workload3_device(args.size)
+    else:
+        prob = inputs.workload_duct(args.size) if args.duct else inputs.workload2(args.size)
     bc_x = P.POISSON_BC_WALLS_X if args.duct and not args.periodic else P.POISSON_BC_PERIODIC
-    rho = torch.from_numpy(prob.rho).cuda()
-    b = torch.from_numpy(prob.b).cuda()
+    rho = prob.rho if torch.is_tensor(prob.rho) else torch.from_numpy(prob.rho).cuda()
+    b = prob.b if torch.is_tensor(prob.b) else torch.from_numpy(prob.b).cuda()
     p = torch.zeros(prob.shape, dtype=torch.float64, device="cuda")
     for name in args.paths.split(","):
         prec = P.POISSON_FP64 if name == "fp64" else P.POISSON_FP32_REFINE

@@ -19,8 +19,10 @@ class Server:
 
     def __init__(self, budget_bytes: int, max_slots: int, precision: int = P.POISSON_FP64,
                  coef: int = P.POISSON_COEF_RHO_FACE_MEAN, weight: int = P.POISSON_W_RHO,
-                 max_iter: int = 0, stream=None):
+                 max_iter: int = 0, stream=None, use_graphs: bool = False):
         self.h = P.poisson_server_create(budget_bytes, max_slots, precision, coef, weight, max_iter, stream)
+        if use_graphs:
+            P.poisson_server_use_graphs(self.h, True)
 
     def submit(self, shape, lengths, rho, b, p, tol: float, bc_x: int = P.POISSON_BC_PERIODIC) -> int:
         return P.poisson_server_submit(self.h, shape, lengths, rho, b, p, tol, bc_x)

@@ -115,3 +115,28 @@ def test_warm_chains_take_fewer_iterations_than_cold():
             out = serve.run_chains(srv, chains)
         tot[warm] = sum(s["iters"] for ch in out.stats for s in ch[1:])
     assert tot[True] < tot[False], tot
+
+
+def test_fp32_warm_chain_saves_inner_sweeps():
+    """FP32 sweeps with refinement on the slowly evolving chain (half a cell
+    of advection per step, the benchmark's chain) at 64^3: the warm start
+    begins within a few percent of the answer, so the refinement steps'
+    adaptive inner stop needs fewer inner sweeps than from zero, on every step
+    after the first."""
+    announce("fp32 warm vs cold 64^3")
+    import torch
+
+    shape, L, steps = inputs.advected_chain_device(64, steps=6)
+    its = {}
+    for warm in (False, True):
+        p = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        its[warm] = []
+        with P.Solver(shape, L, precision=P.POISSON_FP32_REFINE) as s:
+            for rho, b in steps:
+                if not warm:
+                    p.zero_()
+                st = s.solve(rho, b, p, 1e-10)
+                assert st["code"] == P.POISSON_OK
+                its[warm].append(st["iters"])
+    assert its[True][0] == its[False][0], its
+    assert all(w < c for w, c in zip(its[True][1:], its[False][1:])), its

@@ -60,6 +60,27 @@ def test_deposit_matches_oracle(shape, with_q):
     assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("cluster", [17, 5000, 70000])
+def test_deposit_clustered_particles(cluster):
+    """Preferential concentration: `cluster` particles share one cell (runs
+    longer than a summation piece and, at 70000, than a sort tile), among
+    uniform ones and a second, smaller cluster; against the oracle and bitwise
+    repeatable."""
+    announce("deposit clustered", cluster)
+    rng = np.random.default_rng(cluster)
+    shape, L = (16, 12, 24), (5.0, 3.0, TWO_PI)
+    h = (L[0] / shape[2], L[1] / shape[1], L[2] / shape[0])
+    c1 = (np.array([3, 4, 5]) + rng.uniform(0.5, 1.5, (cluster, 3))) * h   # cells (3..4, 4..5, 5..6)
+    c2 = (np.array([10, 2, 7]) + rng.uniform(0.5, 1.5, (cluster // 3 + 1, 3))) * h
+    uni = rng.uniform(0.0, 1.0, (4000, 3)) * np.array(L)
+    pos = np.concatenate([uni[:2000], c1, uni[2000:], c2])
+    q = rng.standard_normal(pos.shape[0])
+    want = oracle.deposit(shape, pos, q, L)
+    a, b = _deposit_gpu(shape, L, pos, q, reps=2)
+    assert np.max(np.abs(a - want)) <= 1e-12 * np.max(np.abs(want))
+    assert np.array_equal(a, b)
+
+
 def test_deposit_degenerate_inputs():
     announce("deposit degenerate")
     shape, L = (8, 8, 16), (TWO_PI,) * 3

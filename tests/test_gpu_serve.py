@@ -52,12 +52,12 @@ def _alone(prob, precision):
     return host(p), st
 
 
-def _served(probs, precision, budget=1 << 33, slots=64, tols=None):
+def _served(probs, precision, budget=1 << 33, slots=64, tols=None, use_graphs=False):
     jobs = []
     for k, pr in enumerate(probs):
         jobs.append(serve.Job(0.0, pr.shape, pr.lengths, dev(pr.rho), dev(pr.b), dev(np.zeros(pr.shape)),
                               tol=1e-10 if tols is None else tols[k], tag=k))
-    with serve.Server(budget, slots, precision=precision) as s:
+    with serve.Server(budget, slots, precision=precision, use_graphs=use_graphs) as s:
         res = serve.replay(s, jobs, realtime=False)
     out = [None] * len(probs)
     for o in res.outcomes:
@@ -254,3 +254,31 @@ def test_server_footprint_query():
             with pytest.raises(P.PoissonError) as e:
                 P.poisson_server_footprint(s.h, (32, 32, 33))
             assert e.value.code == P.POISSON_EINVAL
+
+
+@pytest.mark.parametrize("precision", [P.POISSON_FP64, P.POISSON_FP32_REFINE])
+def test_graph_replays_give_the_same_bits(precision):
+    """Chunks captured once per (batch size, chunk, share) and replayed: every
+    request's answer and iteration counts equal its solve alone, bit for bit,
+    across a stream whose batch sizes change as requests come and go (several
+    replays of the same graphs with the slot table rewritten between them)."""
+    announce("serve graphs", precision)
+    probs = _mix(16)
+    mixed, res = _served(probs, precision, slots=6, use_graphs=True)
+    assert len(res.outcomes) == len(probs)
+    for k, pr in enumerate(probs):
+        p_alone, st_alone = _alone(pr, precision)
+        p_mix, st_mix = mixed[k]
+        assert st_mix["status"] == 0
+        assert (st_mix["iters"], st_mix["outer_iters"]) == (st_alone["iters"], st_alone["outer_iters"])
+        assert np.array_equal(p_mix, p_alone), k
+
+
+def test_served_timing_breakdown():
+    """Served requests report their queue time (submit to admission) within
+    their latency (submit to done)."""
+    announce("serve timing breakdown")
+    mixed, _ = _served(_mix(10), P.POISSON_FP64, slots=2)
+    for _, st in mixed:
+        assert 0.0 <= st["queue_ms"] <= st["ms"]
+    assert max(st["queue_ms"] for _, st in mixed) > 0.0  # with two slots some requests waited
