@@ -55,18 +55,21 @@ def percentile(xs, q):
     return xs[f] + (xs[c] - xs[f]) * (k - f)
 
 
-def model_bytes_per_cell(fp32, iters, outer_iters):
+def model_bytes_per_cell(fp32, iters, outer_iters, p1_sweeps=None):
     """Modelled HBM bytes per cell of one whole solve from p = 0 (each sweep
     reads its inputs once and writes its outputs once).
     FP64, K iterations: setup 16 + K x 104 + the final residual sweep 32.
-    FP32 + refinement, S refinement steps and K inner iterations (the first of
-    each step fused into the FP64 outer residual): setup 20 (rho, b read, rho32
-    written); per step the fused outer residual 32, the rest of its first inner
-    sweep 32 (y, z, y 8 each, the x pass 8), its further inner sweeps 52 each,
-    the inner residual sweep that stops them 16 and the FP64 update 20; the
-    final outer residual 32: 52 + 48 S + 52 K."""
+    FP32 + refinement, S refinement steps, K inner updates and E inner residual
+    sweeps that ran (the first evaluation of each step is fused into the FP64
+    outer residual): setup 20 (rho, b read, rho32 written); per step the fused
+    outer residual 32, the rest of its first inner sweep 32 (y, z, y 8 each,
+    the x pass 8) and the FP64 update 20; 36 per further inner update (y, z, y,
+    x update) and 16 per inner residual sweep; the final outer residual 32:
+    52 + 48 S + 36 K + 16 E, which is 52 + 48 S + 52 K when every step ends
+    with a confirming residual sweep (E = K)."""
     if fp32:
-        return 52 + 48 * outer_iters + 52 * iters
+        e = iters if p1_sweeps is None else p1_sweeps
+        return 52 + 48 * outer_iters + 36 * iters + 16 * e
     return 48 + 104 * iters
 
 
@@ -102,7 +105,7 @@ def time_path(P, torch, prob, precision, steps, warmup, tol, bc_x=0, keep_p=Fals
     if stats["status"] != 0:
         raise RuntimeError(f"solve failed: {stats}")
     bytes_p1 = SWEEP_BYTES[1][1 if fp32 else 0] * prob.n
-    bpc = model_bytes_per_cell(fp32, stats["iters"], stats["outer_iters"])
+    bpc = model_bytes_per_cell(fp32, stats["iters"], stats["outer_iters"], stats["p1_sweeps"])
     out = dict(solves_per_s=steps / (t1 - t0), ms_per_solve=(t1 - t0) * 1e3 / steps,
                model_bytes_per_cell=bpc,
                # whole-solve roofline fraction: modelled bytes per solve x solves/s over the peak
@@ -213,16 +216,16 @@ def serve_leg(P, torch, count, budget_gb, slots, precision, fracs=(0.3, 0.5, 0.7
             "p99_ms": head["p99_ms"], "solo_p50_ms_by_size": solo_ms, "modes": modes}
 
 
-def serve_mixed(P, torch, count, budget_gb):
+def serve_mixed(P, torch, big, count, budget_gb):
     """A stream of 128^3 requests (FP32+refine) served alone, then with the
-    1024x512x512 hot-blob solve admitted at the start of the same stream:
-    p50/p99 of the small requests both ways and the big solve's latency."""
+    1024x512x512 hot-blob solve `big` (device fields) admitted at the start of
+    the same stream: p50/p99 of the small requests both ways and the big
+    solve's latency."""
     from paper_1601_05448_amd import inputs, serve
 
     reqs = inputs.request_stream(count, sizes=(128,))
     fields = [inputs.request_fields_device(r) for r in reqs]
-    big = inputs.workload5()
-    big_rho, big_b = torch.from_numpy(big.rho).cuda(), torch.from_numpy(big.b).cuda()
+    big_rho, big_b = big.rho, big.b
     budget = int(budget_gb * (1 << 30))
 
     def jobs_for(stream):
@@ -517,9 +520,8 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=16.0)
     ap.add_argument("--no-512", action="store_true",
                     help="skip the 512^3 particle-deposit workload (fields beyond the 256 MB MALL)")
-    ap.add_argument("--large", action="store_true",
-                    help="also serve the 1024x512x512 hot-blob solve beside a 128^3 stream (minutes of host-side "
-                         "input generation)")
+    ap.add_argument("--no-blobs", action="store_true",
+                    help="skip the 1024x512x512 hot-blob workload (alone, and served beside a 128^3 stream)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see the design notes on "
@@ -611,8 +613,19 @@ def main():
         line["large"] = lg
         del big
         torch.cuda.empty_cache()
-    if args.large:
-        line.setdefault("large", {})["served_alongside"] = serve_mixed(P, torch, 128, 32.0)
+    if not args.no_blobs:
+        from paper_1601_05448_amd import device_inputs
+
+        blobs = device_inputs.workload5_device()
+        bl = {"workload": "1024x512x512 box [0,4pi)x[0,2pi)^2, 10^5 Gaussian hot blobs (sigma 2 cells), "
+                          "rho = 1/(1 + 19 f/max f) (ratio 20), band-limited b, tol %g" % args.tol,
+              "fp64": time_path(P, torch, blobs, P.POISSON_FP64, 3, 1, args.tol),
+              "fp32_refine": time_path(P, torch, blobs, P.POISSON_FP32_REFINE, 3, 1, args.tol)}
+        bl["fp32_speedup"] = bl["fp32_refine"]["solves_per_s"] / bl["fp64"]["solves_per_s"]
+        bl["served_alongside"] = serve_mixed(P, torch, blobs, 128, 32.0)
+        line["blobs"] = bl
+        del blobs
+        torch.cuda.empty_cache()
     if args.serve_requests > 0:
         line["serving"] = serve_leg(P, torch, args.serve_requests, args.serve_budget_gb, 64, P.POISSON_FP64)
     if cpu is not None:

@@ -115,7 +115,9 @@ typedef struct {
     int p1_sweeps;          /* launches of the residual sweep P1 that did work: FP64, one
                                per residual evaluation; FP32_REFINE, one per inner
                                evaluation except the first of a refinement step where
-                               the outer residual sweep produced it                  */
+                               the outer residual sweep produced it (a step whose end
+                               is predicted from the contraction skips the evaluation
+                               that would only confirm it)                           */
     double queue_ms;        /* served requests: host time from submit to admission; else 0 */
 } poisson_stats;
 

@@ -102,6 +102,7 @@ __device__ inline void decide_outer(const GridArgs& g, SolveState* st, const dou
         st->stage = 1;
         st->inner_iter = 0;
         st->inner_done = 0;
+        st->stop_next = 0;
         st->since_best = 0;
         st->best_in = INFINITY;
         st->rel_in = 1.0;
@@ -120,10 +121,20 @@ __device__ inline void decide_outer(const GridArgs& g, SolveState* st, const dou
 
 // FP32_REFINE, after the FP32 P1 of an inner iteration.  sums: r^2, bt^2.
 __device__ inline void decide_inner(SolveState* st, const double* sums, int max_inner) {
-    st->p1_work += 1;  // runs exactly when P1 did its work
     const int t = st->inner_iter;
+    if (st->stop_next) {
+        // the previous iteration was predicted to be the phase's last: its
+        // update has been applied and this iteration's P1 idled
+        st->stop_next = 0;
+        st->inner_done = 1;
+        st->inner_last = t + 1;
+        st->stage = 2;
+        return;
+    }
+    st->p1_work += 1;  // P1 did its work
     if (t == 0) st->rhs_norm32 = sqrt(sums[1]);
     const double rel = (st->rhs_norm32 > 0.0) ? sqrt(sums[0]) / st->rhs_norm32 : 0.0;
+    const double prev = st->rel_in;  // the previous evaluation of this phase (1 before any)
     st->rel_in = rel;
     bool stop = false;
     if (!(rel < 1e8)) stop = true;  // non-finite or blown up: let the FP64 step judge
@@ -147,6 +158,19 @@ __device__ inline void decide_inner(SolveState* st, const double* sums, int max_
     } else {
         st->inner_iter = t + 1;
         st->inner_total += 1;
+        // Predicted stop: the sweeps contract the inner residual at a steady
+        // rate, so when the contraction since the previous evaluation brings
+        // the residual after this iteration's update below half the goal, the
+        // phase ends after that update and the residual sweep that would only
+        // confirm it is not run (the FP64 outer residual that follows measures
+        // the step anyway; a step that falls short costs another step).
+        if (t >= 1 && prev > 0.0 && rel < prev && t + 1 < max_inner && st->inner_total < st->max_iter) {
+            const double next = rel * (rel / prev);
+            if (next <= 0.5 * st->inner_goal) {
+                st->stop_next = 1;
+                st->rel_in = next;  // what the step is expected to reach (the host's estimate of its reduction)
+            }
+        }
     }
 }
 

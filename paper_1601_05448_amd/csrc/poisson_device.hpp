@@ -500,6 +500,7 @@ struct IterView<double> {
         (void)stage;
         return st->done != 0;
     }
+    static __device__ bool skip_p1(const SolveState* st) { return st->done != 0; }
 };
 
 template <>
@@ -514,6 +515,9 @@ struct IterView<float> {
     static __device__ bool skip(const SolveState* st, int stage = 1) {
         return st->done != 0 || st->stage != stage || st->inner_done != 0;
     }
+    // the inner residual sweep also idles once the phase is known to end after
+    // the iteration in progress (its evaluation is not needed)
+    static __device__ bool skip_p1(const SolveState* st) { return skip(st) || st->stop_next != 0; }
 };
 
 template <typename T>

@@ -476,6 +476,8 @@ struct poisson_s {
     double* proj_b = nullptr;    // right-hand side built by poisson_project (allocated at its first call)
     void* part_ws = nullptr;     // particle buffers of poisson_deposit / poisson_interpolate (grown on demand)
     size_t part_ws_bytes = 0;
+    hipStream_t part_aux = nullptr;  // second stream of poisson_deposit (created at its first call)
+    hipEvent_t part_fork = nullptr, part_join = nullptr;
 };
 
 extern "C" {
@@ -512,6 +514,9 @@ void poisson_destroy(poisson_t h) {
     h->tables.release();
     if (h->proj_b) (void)hipFree(h->proj_b);
     if (h->part_ws) (void)hipFree(h->part_ws);
+    if (h->part_fork) (void)hipEventDestroy(h->part_fork);
+    if (h->part_join) (void)hipEventDestroy(h->part_join);
+    if (h->part_aux) (void)hipStreamDestroy(h->part_aux);
     delete h;
 }
 
@@ -785,8 +790,16 @@ int poisson_deposit(poisson_t h, int n_particles, const double* pos, const doubl
         return POISSON_EINVAL;
     int rc = particle_ws(h, particle_workspace_bytes(h->g, n_particles));
     if (rc != POISSON_OK) return rc;
+    if (!h->part_aux) {
+        // default priority (no priority argument anywhere)
+        if (hipStreamCreateWithFlags(&h->part_aux, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&h->part_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&h->part_join, hipEventDisableTiming) != hipSuccess)
+            return POISSON_EHIP;
+    }
     int bad = 0;
-    rc = hip_status(launch_deposit(h->g, n_particles, pos, q, out, h->part_ws, h->part_ws_bytes, &bad, h->stream));
+    rc = hip_status(launch_deposit(h->g, n_particles, pos, q, out, h->part_ws, h->part_ws_bytes, &bad, h->stream,
+                                   h->part_aux, h->part_fork, h->part_join));
     if (rc != POISSON_OK) return rc;
     if (bad) return POISSON_EDOMAIN;
     return hip_status(hipStreamSynchronize(h->stream));

@@ -67,6 +67,8 @@ struct SolveState {
     int inner_last;     // inner-sweep launches the last finished outer step used
     int p1_work;        // launches of the residual sweep P1 that did their work
     int since_best;
+    int stop_next;      // the inner phase ends after the update of the iteration in progress:
+                        // the next inner residual sweep idles and its decision closes the phase
     double inv_s;       // r32 = r * inv_s (a power of two)
     double rhs_mean32;  // mean of r32, removed inside the inner sweeps
     double rhs_norm32;  // ||r32 - mean||
@@ -184,12 +186,14 @@ hipError_t launch_correct(const GridArgs& g, const double* p, double* mx, double
                           hipStream_t s);
 
 // Particles and the grid (poisson_particles.hip): out = P(q) per unit volume
-// (ws: particle_workspace_bytes(g, np) bytes of device scratch), out_p =
+// (ws: particle_workspace_bytes(g, np) bytes of device scratch; the grid is
+// zeroed on s_aux between the two events while the sort runs on s), out_p =
 // I(field)(x_p).  *bad_host = 1 when a position is not finite or too far out
 // (then nothing else is written).
 size_t particle_workspace_bytes(const GridArgs& g, int np);
 hipError_t launch_deposit(const GridArgs& g, int np, const double* pos, const double* q, double* out, void* ws,
-                          size_t ws_bytes, int* bad_host, hipStream_t s);
+                          size_t ws_bytes, int* bad_host, hipStream_t s, hipStream_t s_aux, hipEvent_t ev_fork,
+                          hipEvent_t ev_join);
 hipError_t launch_interpolate(const GridArgs& g, int np, const double* pos, const double* field, double* out,
                               int* bad_dev, int* bad_host, hipStream_t s);
 

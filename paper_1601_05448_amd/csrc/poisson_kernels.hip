@@ -143,8 +143,8 @@ __global__ void __launch_bounds__(kDecideThreads) k_decide_iter(GridArgs g, cons
     const Slot& s = slots[blockIdx.x];
     SolveState* st = s.st;
     if (fp32 ? (st->done || st->stage != 1 || st->inner_done) : st->done) return;
-    double sums[4];
-    sum_units<kDecideThreads, 4>(s.partial, (unsigned)nunits, sums, red);
+    double sums[4] = {0.0, 0.0, 0.0, 0.0};
+    if (!(fp32 && st->stop_next)) sum_units<kDecideThreads, 4>(s.partial, (unsigned)nunits, sums, red);
     if (threadIdx.x != 0) return;
     if (fp32) decide_inner(st, sums, kMaxInnerPerStep);
     else decide_fp64(g, st, sums);

@@ -48,9 +48,13 @@ struct PartGeom {
     double inv_hx, inv_hy, inv_hz, inv_v;
 };
 
+// The key of a particle: its lower corner cell c = (k ny + j) nx + i, below it
+// the parity class (i, j, k) mod 2 of that cell, so that the sorted particles
+// come in eight contiguous classes (the scatter passes below), each ordered by
+// cell.
 __global__ void __launch_bounds__(kPartThreads)
 k_part_keys(PartGeom pg, int np, const double* __restrict__ pos, unsigned* __restrict__ key,
-            unsigned* __restrict__ idx, int* __restrict__ bad) {
+            unsigned* __restrict__ idx, int* __restrict__ bad, int cell_bits) {
     const int p = blockIdx.x * kPartThreads + threadIdx.x;
     if (p >= np) return;
     int i, j, k;
@@ -62,7 +66,10 @@ k_part_keys(PartGeom pg, int np, const double* __restrict__ pos, unsigned* __res
         bad[0] = 1;  // plain vector store: every writer writes the same value
         i = j = k = 0;
     }
-    key[p] = ((unsigned)k * (unsigned)pg.ny + (unsigned)j) * (unsigned)pg.nx + (unsigned)i;
+    // (grids of more than 2^29 cells leave no room for the class: cell keys alone)
+    const unsigned color = (unsigned)(i & 1) | ((unsigned)(j & 1) << 1) | ((unsigned)(k & 1) << 2);
+    const unsigned cell = ((unsigned)k * (unsigned)pg.ny + (unsigned)j) * (unsigned)pg.nx + (unsigned)i;
+    key[p] = cell_bits <= 29 ? (color << cell_bits) | cell : cell;
     idx[p] = (unsigned)p;
 }
 
@@ -199,7 +206,7 @@ k_rs_scatter(int np, const unsigned* __restrict__ key, const unsigned* __restric
 // (at a run start or at kPiece t) in sorted order and stores the eight sums at
 // the piece's first position; then the thread at each run start adds the run's
 // pieces in order (its own, then those at the following multiples of kPiece).
-constexpr int kPiece = 16;
+constexpr int kPiece = 8;
 
 __device__ __forceinline__ void corner_weights(const PartGeom& pg, const double* __restrict__ pos,
                                                const double* __restrict__ q, unsigned p, double (&w)[8]) {
@@ -265,30 +272,58 @@ k_part_runs(int np, const unsigned* __restrict__ key_s, double* __restrict__ psu
     for (int c = 0; c < 8; ++c) psum[8 * (size_t)s + c] = acc[c];
 }
 
-// Pass `color` of the eight: the runs whose cell (i, j, k) has parities
-// (i, j, k) mod 2 = color add their eight corner sums (over the cell volume) to
-// the cells (i + a, j + b, k + e), wrapped.  Every length is even, so two runs
-// of one color are two or more cells apart in some direction and their 2 x 2 x 2
-// footprints are disjoint: no two threads of a pass touch one cell, and each
-// cell receives its contributions in the fixed order of the passes.
+// First sorted position of each parity class (bound[8] = np): a binary search
+// of the sorted keys per class.
+__global__ void __launch_bounds__(64) k_part_bounds(int np, const unsigned* __restrict__ key_s, int cell_bits,
+                                                   int* __restrict__ bound) {
+    const int c = threadIdx.x;
+    if (c > 8) return;
+    const unsigned lo_key = (unsigned)c << cell_bits;
+    int lo = 0, hi = np;  // first s with key_s[s] >= lo_key
+    if (c == 8) lo = np;
+    while (lo < hi) {
+        const int mid = lo + (hi - lo) / 2;
+        if (key_s[mid] < lo_key) lo = mid + 1;
+        else hi = mid;
+    }
+    bound[c] = lo;
+}
+
+// Pass `color` of the eight: the runs of the cells (i, j, k) with parities
+// (i, j, k) mod 2 = color, the sorted positions [bound[color], bound[color+1]),
+// add their eight corner sums (over the cell volume) to the cells (i + a,
+// j + b, k + e), wrapped.  Every length is even, so two runs of one class are
+// two or more cells apart in some direction and their 2 x 2 x 2 footprints are
+// disjoint: no two threads of a pass touch one cell, and each cell receives its
+// contributions in the fixed order of the passes.
+// (Keys without the class, on grids above 2^29 cells: every pass walks all the
+// runs and takes those of its class.)
 __global__ void __launch_bounds__(kPartThreads)
-k_part_scatter(PartGeom pg, int np, const unsigned* __restrict__ key_s, const double* __restrict__ psum, int color,
-               double* __restrict__ out) {
-    const int s = blockIdx.x * kPartThreads + threadIdx.x;
-    if (s >= np) return;
-    const unsigned key = key_s[s];
-    if (s > 0 && key_s[s - 1] == key) return;
+k_part_scatter(PartGeom pg, int np, const unsigned* __restrict__ key_s, const double* __restrict__ psum,
+               const int* __restrict__ bound, int color, int cell_bits, double* __restrict__ out) {
+    const bool keyed = cell_bits <= 29;
+    const int s0 = keyed ? bound[color] : 0, s1 = keyed ? bound[color + 1] : np;
     const unsigned nx = pg.nx, ny = pg.ny, nz = pg.nz;
-    const unsigned i = key % nx, j = (key / nx) % ny, k = key / (nx * ny);
-    if ((int)((i & 1u) | ((j & 1u) << 1) | ((k & 1u) << 2)) != color) return;
-    const unsigned i1 = i + 1 == nx ? 0u : i + 1, j1 = j + 1 == ny ? 0u : j + 1, k1 = k + 1 == nz ? 0u : k + 1;
-    double w[8];
+    const unsigned cmask = keyed ? (1u << cell_bits) - 1u : 0xffffffffu;
+    for (int s = s0 + (int)(blockIdx.x * kPartThreads + threadIdx.x); s < s1; s += (int)(gridDim.x * kPartThreads)) {
+        const unsigned key = key_s[s];
+        if (s > s0 && key_s[s - 1] == key) continue;
+        const unsigned cell = key & cmask;
+        const unsigned i = cell % nx, j = (cell / nx) % ny, k = cell / (nx * ny);
+        if (!keyed && (int)((i & 1u) | ((j & 1u) << 1) | ((k & 1u) << 2)) != color) continue;
+        const unsigned i1 = i + 1 == nx ? 0u : i + 1, j1 = j + 1 == ny ? 0u : j + 1, k1 = k + 1 == nz ? 0u : k + 1;
+        // the eight cells are distinct (every length is at least 4): all loads
+        // are issued before any store, so the thread waits for memory once
+        size_t c[8];
+        double w[8], o[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) w[q] = psum[8 * (size_t)s + q] * pg.inv_v;
+        for (int q = 0; q < 8; ++q) {
+            c[q] = ((size_t)((q & 4) ? k1 : k) * ny + ((q & 2) ? j1 : j)) * nx + ((q & 1) ? i1 : i);
+            w[q] = psum[8 * (size_t)s + q];
+            o[q] = out[c[q]];
+        }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const size_t c = ((size_t)((q & 4) ? k1 : k) * ny + ((q & 2) ? j1 : j)) * nx + ((q & 1) ? i1 : i);
-        out[c] += w[q];
+        for (int q = 0; q < 8; ++q) out[c[q]] = o[q] + w[q] * pg.inv_v;
     }
 }
 
@@ -354,7 +389,8 @@ size_t particle_workspace_bytes(const GridArgs& g, int np) {
 }
 
 hipError_t launch_deposit(const GridArgs& g, int np, const double* pos, const double* q, double* out, void* ws,
-                          size_t ws_bytes, int* bad_host, hipStream_t s) {
+                          size_t ws_bytes, int* bad_host, hipStream_t s, hipStream_t s_aux, hipEvent_t ev_fork,
+                          hipEvent_t ev_join) {
     if (ws_bytes < particle_workspace_bytes(g, np)) return hipErrorInvalidValue;
     const PartGeom pg = part_geom(g);
     char* w = static_cast<char*>(ws);
@@ -368,12 +404,14 @@ hipError_t launch_deposit(const GridArgs& g, int np, const double* pos, const do
     const size_t cb = up256((size_t)kDigits * std::max(1, sort_tiles(np)) * 4);
     unsigned* digit_tot = reinterpret_cast<unsigned*>(w + 4 * kb + up256((size_t)np * 64) + cb);
     int* bad = reinterpret_cast<int*>(w + 4 * kb + up256((size_t)np * 64) + cb + up256((size_t)kDigits * 4));
+    int* bound = bad + 16;  // nine class bounds after the flag, in the same 256 bytes
     const unsigned long long n = (unsigned long long)g.n;
     const int pb = (np + kPartThreads - 1) / kPartThreads;
+    const int cell_bits = key_bits(g.n);
     hipError_t e;
     k_part_flag_clear<<<1, 64, 0, s>>>(bad);
     if (np > 0) {
-        k_part_keys<<<pb, kPartThreads, 0, s>>>(pg, np, pos, key, idx, bad);
+        k_part_keys<<<pb, kPartThreads, 0, s>>>(pg, np, pos, key, idx, bad, cell_bits);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         int flag = 0;
         if ((e = hipMemcpyAsync(&flag, bad, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
@@ -382,8 +420,18 @@ hipError_t launch_deposit(const GridArgs& g, int np, const double* pos, const do
             *bad_host = 1;
             return hipSuccess;
         }
+    }
+    // the zero fill (bandwidth) runs on the second stream while the sort and the
+    // run sums (latency) run on the first; the scatter passes wait for both
+    const unsigned zb = (unsigned)std::min<unsigned long long>((n + kPartThreads - 1) / kPartThreads, 8192ull);
+    if ((e = hipEventRecord(ev_fork, s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(s_aux, ev_fork, 0)) != hipSuccess) return e;
+    k_part_zero<<<zb, kPartThreads, 0, s_aux>>>(out, n);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev_join, s_aux)) != hipSuccess) return e;
+    if (np > 0) {
         const int tiles = sort_tiles(np);
-        const int bits = key_bits(g.n);
+        const int bits = cell_bits <= 29 ? cell_bits + 3 : cell_bits;
         for (int shift = 0; shift < bits; shift += kDigitBits) {
             k_rs_count<<<tiles, kSortThreads, 0, s>>>(np, key, shift, counts);
             k_rs_scan_tiles<<<kDigits, kSortThreads, 0, s>>>(counts, tiles, digit_tot);
@@ -393,14 +441,17 @@ hipError_t launch_deposit(const GridArgs& g, int np, const double* pos, const do
             std::swap(key, key2);
             std::swap(idx, idx2);
         }
-    }
-    const unsigned zb = (unsigned)std::min<unsigned long long>((n + kPartThreads - 1) / kPartThreads, 8192ull);
-    k_part_zero<<<zb, kPartThreads, 0, s>>>(out, n);
-    if (np > 0) {
         const int nb_pieces = ((np + kPiece - 1) / kPiece + kPartThreads - 1) / kPartThreads;
         k_part_pieces<<<nb_pieces, kPartThreads, 0, s>>>(pg, np, pos, q, key, idx, psum);
         k_part_runs<<<pb, kPartThreads, 0, s>>>(np, key, psum);
-        for (int c = 0; c < 8; ++c) k_part_scatter<<<pb, kPartThreads, 0, s>>>(pg, np, key, psum, c, out);
+        if (cell_bits <= 29) k_part_bounds<<<1, 64, 0, s>>>(np, key, cell_bits, bound);
+    }
+    if ((e = hipStreamWaitEvent(s, ev_join, 0)) != hipSuccess) return e;
+    if (np > 0) {
+        // about a class's share of the particles per pass (at least one block)
+        const int sb = cell_bits <= 29 ? std::max(1, std::min(pb / 8 + 1, 2048)) : std::max(1, std::min(pb, 8192));
+        for (int c = 0; c < 8; ++c)
+            k_part_scatter<<<sb, kPartThreads, 0, s>>>(pg, np, key, psum, bound, c, cell_bits, out);
     }
     return hipGetLastError();
 }

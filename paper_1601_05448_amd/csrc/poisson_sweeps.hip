@@ -45,7 +45,7 @@ k_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     __shared__ cpx<T> tw[N];
     __shared__ double red[(C::NT / 64) * 4];
     const Slot& s = slots[blockIdx.y];
-    if (MODE == 0 && IterView<T>::skip(s.st)) return;
+    if (MODE == 0 && IterView<T>::skip_p1(s.st)) return;
     const cpx<T>* twg = twiddles<T>(tb, 0);
     const cpx<T>* twc = dct_twiddles<T>(tb);
     for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
@@ -150,7 +150,7 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
     __shared__ double red[(C::NT / 64) * 4];
     __shared__ T edge[2 * Z::SUB * Z::EDGE];  // wave-edge columns, double-buffered by step parity
     const Slot& s = slots[blockIdx.y];
-    if (IterView<T>::skip(s.st)) return;
+    if (IterView<T>::skip_p1(s.st)) return;
     const cpx<T>* twg = twiddles<T>(tb, 0);
     const cpx<T>* twc = dct_twiddles<T>(tb);
     for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];

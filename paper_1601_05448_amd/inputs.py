@@ -275,6 +275,20 @@ def workload3_b_device(n: int = 512, particles: int = 10**6, kmax: float = 8.0, 
     return bandlim_device((n, n, n), (TWO_PI,) * 3, kmax, rng, device)
 
 
+def workload5_draws(shape=(512, 512, 1024), blobs: int = 10**5, kmax: float = 8.0, device=None):
+    """The seeded draws of workload 5 without the blob sum: the box lengths, the
+    blob centres (blobs, 3) as (x, y, z), and b (on `device` as a torch tensor
+    when given, else on the host), from the same generator states as
+    workload5."""
+    rng = np.random.default_rng(workload_seed(5))
+    nz, ny, nx = shape
+    h = TWO_PI / ny
+    L = (nx * h, ny * h, nz * h)
+    cen = rng.uniform(0.0, 1.0, size=(blobs, 3)) * np.asarray(L)
+    b = bandlim_device(shape, L, kmax, rng, device) if device is not None else bandlim(shape, L, kmax, rng)
+    return L, cen, b
+
+
 def workload5(shape=(512, 512, 1024), blobs: int = 10**5, ratio: float = 20.0,
               sigma_cells: float = 2.0, kmax: float = 8.0) -> Problem:
     rng = np.random.default_rng(workload_seed(5))

@@ -89,6 +89,8 @@ def test_model_bytes_per_cell():
     52 + 48 S + 52 K (see bench.model_bytes_per_cell)."""
     assert bench.model_bytes_per_cell(False, 10, 0) == 16 + 10 * 104 + 32
     assert bench.model_bytes_per_cell(True, 10, 3) == 20 + 3 * (32 + 32 + 16 + 20) + (10 - 3) * 52 + 32
+    # a step whose end was predicted runs no confirming residual sweep: 16 less
+    assert bench.model_bytes_per_cell(True, 10, 3, 9) == bench.model_bytes_per_cell(True, 10, 3) - 16
 
 
 def test_cpu_baseline_leg_end_to_end():

@@ -81,6 +81,24 @@ def test_deposit_clustered_particles(cluster):
     assert np.array_equal(a, b)
 
 
+def test_deposit_on_a_grid_beyond_2_pow_29_cells():
+    """1024^3 cells leave no room for the parity class in a 32-bit sort key:
+    the deposit then sorts by cell alone and every scatter pass filters its
+    class.  Against the oracle, with clusters and particles on the wrapped
+    faces."""
+    announce("deposit 1024^3 (cell keys only)")
+    rng = np.random.default_rng(29)
+    shape, L = (1024, 1024, 1024), (TWO_PI,) * 3
+    h = TWO_PI / 1024
+    pos = np.concatenate([rng.uniform(-1.0, 8.0, (3000, 3)),
+                          (np.array([1023, 5, 700]) + rng.uniform(0.5, 1.5, (500, 3))) * h])
+    want = oracle.deposit(shape, pos, None, L)
+    (got,) = _deposit_gpu(shape, L, pos)
+    nz = np.flatnonzero(want)
+    assert np.array_equal(np.flatnonzero(got), nz)
+    assert np.max(np.abs(got.reshape(-1)[nz] - want.reshape(-1)[nz])) <= 1e-12 * np.max(want)
+
+
 def test_deposit_degenerate_inputs():
     announce("deposit degenerate")
     shape, L = (8, 8, 16), (TWO_PI,) * 3

@@ -208,12 +208,16 @@ def test_kernel_timer_counts_residual_sweeps(precision):
         st2 = s.solve(dev(prob.rho), dev(prob.b), p, 1e-10)
         assert P.poisson_kernel_timer_read(s.h) == (0.0, 0)
     assert st["code"] == P.POISSON_OK
-    # FP64: one P1 per residual evaluation (iters updates + the final one);
+    # FP64: one P1 per residual evaluation (iters updates + the final one).
     # FP32 on 64-cell rows: the outer residual sweep evaluates the first inner
-    # residual of each step, so one P1 per inner update
-    want = st["iters"] if fp32 else st["iters"] + 1
-    assert st["p1_sweeps"] == want, st
-    assert n >= want and ms > 0.0
+    # residual of each step, so one P1 per inner update, less one for each step
+    # whose end was predicted from the contraction (its confirming P1 idles)
+    if fp32:
+        assert st["iters"] - st["outer_iters"] <= st["p1_sweeps"] <= st["iters"], st
+        assert n >= st["p1_sweeps"] and ms > 0.0
+    else:
+        assert st["p1_sweeps"] == st["iters"] + 1, st
+        assert n >= st["p1_sweeps"] and ms > 0.0
     assert st2["code"] == P.POISSON_OK
 
 

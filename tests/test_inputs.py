@@ -105,3 +105,17 @@ def test_workload3_particles_are_the_workload_draws():
     d = inputs.cic_deposit((8, 8, 8), (2 * math.pi,) * 3, pos)
     w = inputs.workload3(8, particles=500)
     assert np.allclose(w.rho, 1.0 / (1.0 + 9.0 * d / d.max()), rtol=0, atol=1e-15)
+
+
+def test_device_blob_sum_matches_host_recipe():
+    """The torch blob sum used to build the 1024 x 512 x 512 workload on the
+    device equals the host recipe's (bincount) sum up to summation order."""
+    import torch  # noqa: F401
+
+    from paper_1601_05448_amd import device_inputs
+
+    shape = (12, 16, 24)
+    L, cen, _ = inputs.workload5_draws(shape, blobs=40)
+    want = inputs.gaussian_blobs(shape, L, cen, 2.0)
+    got = device_inputs.gaussian_blobs_device(shape, L, cen, 2.0, batch=16, device="cpu").numpy()
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(want)
