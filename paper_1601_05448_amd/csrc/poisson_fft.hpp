@@ -188,22 +188,29 @@ constexpr int lines_per_block(int tt, int n, int elem_bytes) {
 }
 
 // Threads per line TT (one radix-16 butterfly per thread in the first stage),
-// lines per block L (threads a multiple of 64), LDS line stride LS and the LDS
+// LL lines per block (threads a multiple of 64), LDS line stride LS and the LDS
 // position pos(e) of element e within a line (see line_stride).
-template <typename T, int N>
-struct LineCfg {
+template <typename T, int N, int LL>
+struct LineShape {
     static constexpr int TT = N >= 16 ? N / 16 : 1;
-    static constexpr int L = lines_per_block(TT, N, (int)sizeof(cpx<T>));
+    static constexpr int L = LL;
     static constexpr int NT = L * TT;
     static constexpr int IT = N / TT;  // elements per thread when a block walks its L lines
     static constexpr int LS = line_stride(N);
+    static_assert(NT % 64 == 0, "block must be whole wavefronts");
+    static __device__ __forceinline__ constexpr int pos(int e) { return N >= 16 ? e + e / 16 : e; }
+};
+
+// The line shape of the sweeps, L from lines_per_block.
+template <typename T, int N>
+struct LineCfg : LineShape<T, N, lines_per_block(N >= 16 ? N / 16 : 1, N, (int)sizeof(cpx<T>))> {
+    using S = LineShape<T, N, lines_per_block(N >= 16 ? N / 16 : 1, N, (int)sizeof(cpx<T>))>;
+    using S::TT, S::L, S::NT, S::IT, S::LS;
     // minimum waves per SIMD (the second __launch_bounds__ argument, which caps
     // the registers per thread) a sweep is sized for: 2 for blocks of up to 256
     // threads (two blocks per CU); 1 for 512-thread blocks, which hold two waves
     // per SIMD by themselves (one block per CU)
     static constexpr int MINB = NT > 256 ? 1 : 2;
-    static_assert(NT % 64 == 0, "block must be whole wavefronts");
-    static __device__ __forceinline__ constexpr int pos(int e) { return N >= 16 ? e + e / 16 : e; }
 };
 
 // One Stockham stage on a line in LDS (all threads of the block call it).
@@ -323,6 +330,70 @@ __device__ __forceinline__ void fft512_regs(cpx<T> (&v)[16], cpx<T>* ln, int c, 
         // h = 0: E = v, O = o -> E + O; h = 1: O = v, E = o -> E - O
         v[q] = h ? csub(o, v[q]) : cadd(v[q], o);
     }
+}
+
+// Column index of the threads of a line in the register paths (N = 256, 512;
+// 16 lines per block, so a wave holds four columns of each of its 16 lines,
+// lane = line + 16 r): the four columns of wave w are closed under the map
+// that pairs the thread holding X[k] with the one holding X[N - k] after the
+// forward transform, so that the (k, N - k) exchange stays within the wave.
+//   N = 256 (thread c holds X[c + 16 b]; partner column 16 - c, or c for
+//   c = 0, 8): wave w holds {2w, 16 - 2w, 2w + 1, 15 - 2w}, wave 0 {0, 8, 1, 15}.
+//   N = 512 (thread c holds X[c/2 + 16 b + 256 (c mod 2)]; partner column
+//   33 - c, or c ^ 1 for c < 2): wave w holds {2w, 2w + 1, 32 - 2w, 33 - 2w},
+//   wave 0 {0, 1, 16, 17}; the column pairs (c, c ^ 1) of fft512_regs stay
+//   16 lanes apart.
+template <int N>
+__device__ __forceinline__ int reg_col(int q) {
+    const int w = q >> 2, r = q & 3;
+    if constexpr (N == 256) {
+        return r == 0 ? 2 * w : r == 1 ? (w == 0 ? 8 : 16 - 2 * w) : r == 2 ? 2 * w + 1 : 15 - 2 * w;
+    } else {
+        static_assert(N == 512, "register paths: 256 and 512");
+        return r == 0 ? 2 * w : r == 1 ? 2 * w + 1 : r == 2 ? (w == 0 ? 16 : 32 - 2 * w) : (w == 0 ? 17 : 33 - 2 * w);
+    }
+}
+
+// The (k, N - k) exchange after a register transform of a line (N = 256: the
+// thread with column c holds X[k] = X[c + 16 b]; N = 512: X[c/2 + 16 b +
+// 256 (c mod 2)]) goes through the line's LDS row at the positions pos(k),
+// which only the thread's wave writes and reads (reg_col).  X[0] is also
+// written to the row's last padding slot, so that the partner of every b sits
+// at one base position minus 17 b: the addresses take one register and
+// immediate offsets.
+template <typename T, int N>
+__device__ __forceinline__ void exchange_write(cpx<T>* ln, int c, const cpx<T> (&v)[16]) {
+    static_assert(N == 256 || N == 512, "register paths: 256 and 512");
+    cpx<T>* w = ln + (N == 256 ? c : (c >> 1) + 272 * (c & 1));  // pos(k) = that + 17 b
+#pragma unroll
+    for (int b = 0; b < 16; ++b) w[17 * b] = v[b];
+    if (c == 0) ln[N == 256 ? 272 : 544] = v[0];
+}
+
+// Base of the partner values: X[N - k] of the thread's b-th value is at
+// [17 (15 - b)] from the returned pointer (wave order: after exchange_write
+// and wave_lds_sync).
+template <typename T, int N>
+__device__ __forceinline__ const cpx<T>* exchange_partner(const cpx<T>* ln, int c) {
+    int pb;
+    if constexpr (N == 256) {
+        pb = c == 0 ? 272 : 271 - c;
+    } else {
+        const int k1 = c >> 1, h = c & 1;
+        pb = k1 == 0 ? (h == 0 ? 544 : 272) : 271 - k1 + 272 * (1 - h);
+    }
+    return ln + (pb - 255);
+}
+
+// Orders the LDS accesses of one wave: the LDS serves a wave's instructions in
+// issue order, so after this point a lane reads what every lane of its wave
+// wrote before it (the compiler may not move LDS accesses across it).  Other
+// waves are not ordered.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __builtin_amdgcn_sched_barrier(0);
 }
 
 // Hartley value of the pair-packed line at k from its DFT Z:

@@ -429,23 +429,30 @@ k_dht_cols(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) {
     const unsigned nlines = (AX == 1) ? (unsigned)(g.nxh * g.nz) : (unsigned)(g.nxh * g.ny);
     const unsigned ngroups = (nlines + C::L - 1) / C::L;
     const unsigned se = (AX == 1) ? (unsigned)g.nxh : (unsigned)(g.nxh * g.ny);
-    const int l = threadIdx.x % C::L, e0 = threadIdx.x / C::L;
+    constexpr bool kRegs = (N == 256 || N == 512) && C::L == 16;
+    const int l = threadIdx.x % C::L;
+    const int e0 = kRegs ? reg_col<kRegs ? N : 256>((int)threadIdx.x / 16) : (int)threadIdx.x / C::L;
 
+    // element e0 + it TT of a line at base + e0 se + (it TT) se: the lane's part
+    // in one register, the rest wave-uniform (no per-element address registers
+    // live across the transform).  A line past the end (in the last group)
+    // loads line 0 and is not stored: no branch per element.
+    const unsigned lane_off = (unsigned)e0 * se;
     cpx<T> buf[C::IT];
     auto load = [&](unsigned grp, bool& valid, unsigned& base) {
         const unsigned line = grp * C::L + l;
         valid = line < nlines;
         base = valid ? col_base<AX>(g, line) : 0u;
 #pragma unroll
-        for (int it = 0; it < C::IT; ++it)
-            buf[it] = valid ? gload_c(Wc, base + (unsigned)(e0 + it * C::TT) * se) : cpx<T>{T(0), T(0)};
+        for (int it = 0; it < C::IT; ++it) buf[it] = gload_c(Wc, base + lane_off + (unsigned)(it * C::TT) * se);
     };
     unsigned grp = blockIdx.x, base;
     bool valid;
     load(grp, valid, base);
-    if constexpr (N == 256) {
-        // the line stays in registers; LDS only for one transpose and the
-        // exchange of the (k, N-k) partners
+    if constexpr (kRegs) {
+        // the line stays in registers; LDS only for the transpose of the
+        // transform and the exchange of the (k, N-k) partners, which stays
+        // within the wave (reg_col, exchange_write)
         __syncthreads();  // twiddles
         cpx<T>* ln = lds + l * C::LS;
         while (true) {
@@ -458,20 +465,30 @@ k_dht_cols(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) {
             __builtin_amdgcn_s_setprio(2);
             if (ng < ngroups) load(ng, valid, base);  // in flight during the FFT
             __builtin_amdgcn_s_setprio(0);
-            fft256_regs<T>(v, ln, e0, tw);
-#pragma unroll
-            for (int b = 0; b < 16; ++b) ln[C::pos(e0 + 16 * b)] = v[b];
-            __syncthreads();
+            // the column, opaque within each group: the lane-dependent
+            // addresses derived from it are formed here rather than held in
+            // registers across the loop
+            int c = e0;
+            asm volatile("" : "+v"(c));
+            if constexpr (N == 256) fft256_regs<T>(v, ln, c, tw);
+            else fft512_regs<T, 16>(v, ln, c, tw);
+            exchange_write<T, N>(ln, c, v);
+            wave_lds_sync();
             if (cur_valid) {
+                const cpx<T>* pp = exchange_partner<T, N>(ln, c);
+                // k = kb + 16 b
+                const unsigned kb = N == 256 ? (unsigned)c : (unsigned)((c >> 1) + 256 * (c & 1));
+                const unsigned st_base = cur_base + kb * se;
 #pragma unroll
-                for (int b = 0; b < 16; ++b) {
-                    const int k = e0 + 16 * b;
-                    gstore_c(Wc, cur_base + (unsigned)k * se, hartley(v[b], ln[C::pos((N - k) & (N - 1))]));
-                }
+                for (int b = 0; b < 16; ++b)
+                    gstore_c(Wc, st_base + (unsigned)(16 * b) * se, hartley(v[b], pp[17 * (15 - b)]));
             }
             grp = ng;
             if (grp >= ngroups) break;
-            __syncthreads();
+            // N = 256: the next transpose writes this thread's own column, read
+            // only by its wave; N = 512: it writes every wave's positions
+            if constexpr (N == 256) wave_lds_sync();
+            else __syncthreads();
         }
         return;
     }
@@ -513,19 +530,31 @@ __device__ __forceinline__ cpx<T> scaled_conj(cpx<T> zk, cpx<T> zm, T sa, T sb) 
     return {hp * zk.x + hm * zm.x, hm * zm.y - hp * zk.y};  // conj(hp Z_k + hm conj Z_{N-k})
 }
 
-// The FP32 register path at N = 256 is sized for three blocks per CU (three
-// waves per SIMD; LDS would allow four, its registers with the prefetch buffer
-// allow three).  At N = 512 one 512-thread block per CU (at 128 registers, for
-// two, the two line transforms spill and the sweep is slower).
+// Launch shape of the z sweep: ZL lines per block, PF whether the next line
+// group is loaded during this one's transforms, MINW the waves per SIMD its
+// registers are sized for (the second __launch_bounds__ argument).  Measured
+// (MI355X): the FP32 256-point path runs three blocks per CU with the
+// prefetch; the FP32 512-point path runs two 512-thread blocks per CU without
+// it (128 registers, no spills; 14% faster than one block with it); the FP64
+// paths prefetch (no spills at 2 and 1 blocks per CU).
 template <typename T, int N>
 constexpr int z_min_blocks() {
-    return (sizeof(T) == 4 && N == 256) ? 3 : LineCfg<T, N>::MINB;
+    if constexpr (sizeof(T) == 4 && N == 256) return 3;
+    else if constexpr (sizeof(T) == 4 && N == 512) return 4;
+    else return LineCfg<T, N>::MINB;
 }
 
-template <typename T, int N, int MODE>
-__global__ void __launch_bounds__((LineCfg<T, N>::NT), (z_min_blocks<T, N>()))
+template <typename T, int N>
+struct ZCfg {
+    static constexpr int ZL = LineCfg<T, N>::L;
+    static constexpr bool PF = !(sizeof(T) == 4 && N == 512);
+    static constexpr int MINW = z_min_blocks<T, N>();
+};
+
+template <typename T, int N, int MODE, int ZL, bool PF, int MINW>
+__global__ void __launch_bounds__((LineShape<T, N, ZL>::NT), (MINW))
 k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) {
-    using C = LineCfg<T, N>;
+    using C = LineShape<T, N, ZL>;
     __shared__ cpx<T> lds[C::L * C::LS];
     __shared__ cpx<T> tw[N];
     // the z symbol of the register path, in LDS: a global load of it after the
@@ -541,30 +570,36 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
     const unsigned nlines = (unsigned)(g.nxh * g.ny);
     const unsigned ngroups = (nlines + C::L - 1) / C::L;
     const unsigned se = (unsigned)(g.nxh * g.ny);
-    const int l = threadIdx.x % C::L, e0 = threadIdx.x / C::L;
+    constexpr bool kRegs = (N == 256 || N == 512) && C::L == 16;
+    const int l = threadIdx.x % C::L;
+    const int e0 = kRegs ? reg_col<kRegs ? N : 256>((int)threadIdx.x / 16) : (int)threadIdx.x / C::L;
     const T* lamx = symbol<T>(tb, 0);
     const T* lamy = symbol<T>(tb, 1);
     const T* lamz = symbol<T>(tb, 2);
     const T nn = T(g.n);
 
+    // element e0 + it TT of a line at base + e0 se + (it TT) se; a line past
+    // the end loads line 0 and is not stored (see k_dht_cols)
+    const unsigned lane_off = (unsigned)e0 * se;
     cpx<T> buf[C::IT];
     auto load = [&](unsigned grp, bool& valid, unsigned& base) {
         const unsigned line = grp * C::L + l;
         valid = line < nlines;
         base = valid ? col_base<2>(g, line) : 0u;
 #pragma unroll
-        for (int it = 0; it < C::IT; ++it)
-            buf[it] = valid ? gload_c(Wc, base + (unsigned)(e0 + it * C::TT) * se) : cpx<T>{T(0), T(0)};
+        for (int it = 0; it < C::IT; ++it) buf[it] = gload_c(Wc, base + lane_off + (unsigned)(it * C::TT) * se);
     };
     unsigned grp = blockIdx.x, base;
     bool valid;
-    load(grp, valid, base);
-    if constexpr (N == 256) {
+    if constexpr (PF) load(grp, valid, base);
+    if constexpr (N == 256 && kRegs) {
         // the line stays in registers (see fft256_regs); LDS only for the
-        // transposes and the exchange of the (k, N-k) partners
+        // transposes and the exchange of the (k, N-k) partners, which stays
+        // within the wave (reg_col): 4 block barriers per line group
         __syncthreads();  // twiddles
         cpx<T>* ln = lds + l * C::LS;
         while (true) {
+            if constexpr (!PF) load(grp, valid, base);
             cpx<T> v[16];
 #pragma unroll
             for (int a = 0; a < 16; ++a) v[a] = buf[a];
@@ -574,45 +609,52 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
             const unsigned j = cur_valid ? line / (unsigned)g.nxh : 0u, m = cur_valid ? line - j * (unsigned)g.nxh : 0u;
             const T lxe = lamx[2 * m], lxo = lamx[2 * m + 1], lyj = lamy[j];
             const unsigned ng = grp + gridDim.x;
-            __builtin_amdgcn_s_setprio(2);
-            if (ng < ngroups) load(ng, valid, base);  // in flight during the two FFTs
-            __builtin_amdgcn_s_setprio(0);
-            fft256_regs<T>(v, ln, e0, tw);  // v[b] = X[e0 + 16 b]
-#pragma unroll
-            for (int b = 0; b < 16; ++b) ln[C::pos(e0 + 16 * b)] = v[b];
-            __syncthreads();
-#pragma unroll
-            for (int b = 0; b < 16; ++b) {
-                const int k = e0 + 16 * b;
-                const T lzk = lzs[k];
-                // the second transform's input x[e0 + 16 b]
-                v[b] = scaled_conj(v[b], ln[C::pos((N - k) & (N - 1))], inv_symbol(lxe, lyj, lzk, nn),
-                                   inv_symbol(lxo, lyj, lzk, nn));
+            if constexpr (PF) {
+                __builtin_amdgcn_s_setprio(2);
+                if (ng < ngroups) load(ng, valid, base);  // in flight during the two FFTs
+                __builtin_amdgcn_s_setprio(0);
             }
-            __syncthreads();
-            fft256_regs<T>(v, ln, e0, tw);
-            if (cur_valid) {
+            int c = e0;  // opaque within each group (see k_dht_cols)
+            asm volatile("" : "+v"(c));
+            fft256_regs<T>(v, ln, c, tw);  // v[b] = X[c + 16 b]
+            exchange_write<T, N>(ln, c, v);
+            wave_lds_sync();
+            {
+                const cpx<T>* pp = exchange_partner<T, N>(ln, c);
+                const T* lz = lzs + c;  // z symbol at k = c + 16 b
 #pragma unroll
                 for (int b = 0; b < 16; ++b) {
-                    const int k = e0 + 16 * b;
-                    gstore_c(Wc, cur_base + (unsigned)k * se, cpx<T>{v[b].x, -v[b].y});
+                    const T lzk = lz[16 * b];
+                    // the second transform's input x[c + 16 b]
+                    v[b] = scaled_conj(v[b], pp[17 * (15 - b)], inv_symbol(lxe, lyj, lzk, nn),
+                                       inv_symbol(lxo, lyj, lzk, nn));
                 }
+            }
+            wave_lds_sync();  // the partner lanes' reads before this wave's transpose writes
+            fft256_regs<T>(v, ln, c, tw);
+            if (cur_valid) {
+                const unsigned st_base = cur_base + (unsigned)c * se;
+#pragma unroll
+                for (int b = 0; b < 16; ++b)
+                    gstore_c(Wc, st_base + (unsigned)(16 * b) * se, cpx<T>{v[b].x, -v[b].y});
             }
             grp = ng;
             if (grp >= ngroups) break;
-            __syncthreads();
         }
         return;
     }
-    if constexpr (N == 512) {
-        // the line stays in registers (see fft512_regs): thread e0 of a line
-        // holds x[e0 + 32 a]; after each transform it holds X[k] for
-        // k = k1 + 16 b + 256 h (k1 = e0 / 2, h = e0 % 2)
+    if constexpr (N == 512 && kRegs) {
+        // the line stays in registers: thread e0 of a line holds x[e0 + 32 a];
+        // after fft512_regs it holds X[k] for k = k1 + 16 b + 256 h (k1 = e0 / 2,
+        // h = e0 % 2).  The spectrum goes through the line's LDS row once, which
+        // hands each thread its natural-order input of the second transform and
+        // the (k, N-k) partners: 6 block barriers per line group, with the fewest
+        // registers (two 512-thread FP32 blocks per CU).
         static_assert(C::TT == 32 && C::IT == 16, "512-point lines: 32 threads of 16 values");
         __syncthreads();  // twiddles, symbol
         cpx<T>* ln = lds + l * C::LS;
-        const int k1 = e0 >> 1, h = e0 & 1;
         while (true) {
+            if constexpr (!PF) load(grp, valid, base);
             cpx<T> v[16];
 #pragma unroll
             for (int a = 0; a < 16; ++a) v[a] = buf[a];
@@ -622,37 +664,48 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
             const unsigned j = cur_valid ? line / (unsigned)g.nxh : 0u, m = cur_valid ? line - j * (unsigned)g.nxh : 0u;
             const T lxe = lamx[2 * m], lxo = lamx[2 * m + 1], lyj = lamy[j];
             const unsigned ng = grp + gridDim.x;
-            __builtin_amdgcn_s_setprio(2);
-            if (ng < ngroups) load(ng, valid, base);  // in flight during the two FFTs
-            __builtin_amdgcn_s_setprio(0);
-            fft512_regs<T, C::L>(v, ln, e0, tw);
-#pragma unroll
-            for (int b = 0; b < 16; ++b) ln[C::pos(k1 + 16 * b + 256 * h)] = v[b];
-            __syncthreads();
-#pragma unroll
-            for (int a = 0; a < 16; ++a) {
-                const int k = e0 + 32 * a;
-                const T lzk = lzs[k];
-                // the second transform's input x[e0 + 32 a]
-                v[a] = scaled_conj(ln[C::pos(k)], ln[C::pos((N - k) & (N - 1))], inv_symbol(lxe, lyj, lzk, nn),
-                                   inv_symbol(lxo, lyj, lzk, nn));
+            if constexpr (PF) {
+                __builtin_amdgcn_s_setprio(2);
+                if (ng < ngroups) load(ng, valid, base);  // in flight during the two FFTs
+                __builtin_amdgcn_s_setprio(0);
             }
+            int c = e0;  // opaque within each group (see k_dht_cols)
+            asm volatile("" : "+v"(c));
+            fft512_regs<T, 16>(v, ln, c, tw);  // v[b] = X[c/2 + 16 b + 256 (c mod 2)]
+            exchange_write<T, N>(ln, c, v);
+            // the whole spectrum through LDS: the second forward transform
+            // takes its input x[c + 32 a] in natural order, at pos(c + 32 a) =
+            // c + c/16 + 34 a, its partner at pos(N - c - 32 a) = p2 - 34 a
+            // (for c = 0 the padding slot holding X[0] at a = 0)
             __syncthreads();
-            fft512_regs<T, C::L>(v, ln, e0, tw);
-            if (cur_valid) {
+            {
+                const cpx<T>* pk = ln + c + (c >> 4);
+                const int p2 = c == 0 ? 544 : (512 - c) + ((512 - c) >> 4);
+                const cpx<T>* pm = ln + (p2 - 510);
+                const T* lz = lzs + c;  // z symbol at k = c + 32 a
 #pragma unroll
-                for (int b = 0; b < 16; ++b) {
-                    const int k = k1 + 16 * b + 256 * h;
-                    gstore_c(Wc, cur_base + (unsigned)k * se, cpx<T>{v[b].x, -v[b].y});
+                for (int a = 0; a < 16; ++a) {
+                    const T lzk = lz[32 * a];
+                    v[a] = scaled_conj(pk[34 * a], pm[34 * (15 - a)], inv_symbol(lxe, lyj, lzk, nn),
+                                       inv_symbol(lxo, lyj, lzk, nn));
                 }
             }
+            __syncthreads();
+            fft512_regs<T, 16>(v, ln, c, tw);  // v[b] = conj(x'[c/2 + 16 b + 256 (c mod 2)])
+            if (cur_valid) {
+                const unsigned st_base = cur_base + (unsigned)((c >> 1) + 256 * (c & 1)) * se;
+#pragma unroll
+                for (int b = 0; b < 16; ++b)
+                    gstore_c(Wc, st_base + (unsigned)(16 * b) * se, cpx<T>{v[b].x, -v[b].y});
+            }
+            // fft512_regs ends on a barrier: the next group's writes are safe
             grp = ng;
             if (grp >= ngroups) break;
-            __syncthreads();
         }
         return;
     }
     while (true) {
+        if constexpr (!PF) load(grp, valid, base);
 #pragma unroll
         for (int it = 0; it < C::IT; ++it) lds[l * C::LS + C::pos(e0 + it * C::TT)] = buf[it];
         const bool cur_valid = valid;
@@ -662,9 +715,11 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
         const unsigned j = cur_valid ? line / (unsigned)g.nxh : 0u, m = cur_valid ? line - j * (unsigned)g.nxh : 0u;
         const T lxe = lamx[2 * m], lxo = lamx[2 * m + 1], lyj = lamy[j];
         const unsigned ng = grp + gridDim.x;
-        __builtin_amdgcn_s_setprio(2);
-        if (ng < ngroups) load(ng, valid, base);  // in flight during the two FFTs
-        __builtin_amdgcn_s_setprio(0);
+        if constexpr (PF) {
+            __builtin_amdgcn_s_setprio(2);
+            if (ng < ngroups) load(ng, valid, base);  // in flight during the two FFTs
+            __builtin_amdgcn_s_setprio(0);
+        }
         __syncthreads();
         fft_block_lines<T, N>(lds, tw);
         // scaled spectra of the pairs (k, N-k) of this thread's line (the symbol is
@@ -889,10 +944,12 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
             });
         case 3:
             return dispatch_len(g.nz, [&]<int N>() {
-                using C = LineCfg<T, N>;
+                using Z = ZCfg<T, N>;
+                using C = LineShape<T, N, Z::ZL>;
                 const unsigned ng = ((unsigned)(g.nxh * g.ny) + C::L - 1) / C::L;
-                const int nb = persistent_grid((const void*)&k_dht_z_solve<T, N, MODE>, C::NT, ng, nslots, share);
-                k_dht_z_solve<T, N, MODE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t, stage);
+                const void* k = (const void*)&k_dht_z_solve<T, N, MODE, Z::ZL, Z::PF, Z::MINW>;
+                const int nb = persistent_grid(k, C::NT, ng, nslots, share);
+                k_dht_z_solve<T, N, MODE, Z::ZL, Z::PF, Z::MINW><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t, stage);
                 return hipGetLastError();
             });
         case 5:
