@@ -396,11 +396,14 @@ struct ZTile {
 };
 
 // Tiles of the residual sweep P1 and of the fused FP32 outer residual: 32
-// planes (halo planes shared by twice as many) wherever the kernel's registers
-// allow it; the FP32 sweep on rows of fewer than 512 cells keeps 16, which keeps
-// it within 128 registers (four waves per SIMD).
+// planes (halo planes shared by twice as many) for FP64 and for FP32 rows of
+// 1024 cells; the FP32 sweep on shorter rows keeps 16, which keeps it within
+// 128 registers (four waves per SIMD) and, at 512 cells, with two blocks per
+// CU, lets neighbouring tiles stay closer in z, so that more of the y halo rows
+// they read from each other are still in L2 (measured at 512^3: 1.19 instead
+// of 1.38 of the algorithmic bytes, 7% faster).
 template <typename T, int N>
-using P1Tile = ZTile<N, LineCfg<T, N>::NT, LineCfg<T, N>::L, (sizeof(T) == 8 || N >= 512) ? 32 : 16>;
+using P1Tile = ZTile<N, LineCfg<T, N>::NT, LineCfg<T, N>::L, (sizeof(T) == 8 || N >= 1024) ? 32 : 16>;
 template <int N>
 using OuterTile = ZTile<N, LineCfg<float, N>::NT, LineCfg<float, N>::L, 32>;
 

@@ -436,10 +436,11 @@ int poisson_server_tick(poisson_server_t s) {
     if ((rc = admit(s)) != POISSON_OK) return rc;
     // A class at least four times larger than the smallest active one takes
     // three quarters of the chip's resident blocks in its persistent sweeps,
-    // one at least 64 times larger half of them, so that the small classes'
-    // blocks find room beside it instead of waiting for each of its sweeps to
-    // end (the long lines of a very large grid run one 512-thread block per
-    // CU, so there the share is a share of the CUs).
+    // so that the small classes' blocks find room beside it instead of waiting
+    // for each of its sweeps to end; one at least 64 times larger takes half of
+    // the CUs, one block on each that reserves the CU's LDS, so that the small
+    // classes' blocks run on the other half and never share a CU with one of
+    // its long sweeps (see persistent_grid in the sweeps).
     long long smallest = 0;
     for (auto& kv : s->classes)
         if (!kv.second->active.empty() && (smallest == 0 || kv.second->cells < smallest)) smallest = kv.second->cells;

@@ -260,8 +260,12 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                 if (ljp < nyh && lk < nz) {
                     const unsigned P = lk * nyh + ljp;  // row pair index, rows 2P and 2P + 1
                     const cpx<T> h = x_forward_out<T, N>(lds + l * C::LS, k, BCX, twc);
-                    v.W[(2 * P) * N + k] = h.x;
-                    v.W[(2 * P + 1) * N + k] = h.y;
+                    // streaming stores: the transformed lines are not read
+                    // again by this sweep, and left out of L2 they do not push
+                    // out the rows that neighbouring tiles read as y halo
+                    // (FP64 at 512^3: 1.09 -> 1.02 of the algorithmic bytes)
+                    __builtin_nontemporal_store(h.x, &v.W[(2 * P) * N + k]);
+                    __builtin_nontemporal_store(h.y, &v.W[(2 * P + 1) * N + k]);
                 }
             }
             __syncthreads();  // the next flush overwrites the lines
@@ -351,8 +355,8 @@ k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                     acc[4] += pr.a.r + pr.b.r;
                     const float ra = (float)(pr.a.r * inv_s), rb = (float)(pr.b.r * inv_s);
                     const unsigned a = (unsigned)k * zm.sz + zm.ra + i;
-                    r32[a] = ra;
-                    r32[a + (unsigned)g.nx] = rb;
+                    __builtin_nontemporal_store(ra, &r32[a]);  // streaming (see k_resid_dhtx_z)
+                    __builtin_nontemporal_store(rb, &r32[a + (unsigned)g.nx]);
                     qv = {(float)pr.a.w * ra, (float)pr.b.w * rb};
                 }
                 lds[(sidx * Z::KF + q) * C::LS + C::pos(x_slot(i, N, BCX))] = qv;
@@ -372,8 +376,8 @@ k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                 if (ljp < nyh && lk < nz) {
                     const unsigned P = lk * nyh + ljp;
                     const cpx<float> h = x_forward_out<float, N>(lds + l * C::LS, kx, BCX, twc);
-                    W32[(2 * P) * N + kx] = h.x;
-                    W32[(2 * P + 1) * N + kx] = h.y;
+                    __builtin_nontemporal_store(h.x, &W32[(2 * P) * N + kx]);
+                    __builtin_nontemporal_store(h.y, &W32[(2 * P + 1) * N + kx]);
                 }
             }
             __syncthreads();  // the next flush overwrites the lines
@@ -869,19 +873,25 @@ k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
 // The occupancy of each kernel is asked once and kept in a fixed table (no
 // host allocation on the launch path; a kernel beyond the table's capacity is
 // asked every time).
+static int device_cus() {
+    static std::once_flag once;
+    static int cus = 256;
+    std::call_once(once, [] {
+        int dev = 0, n = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n >= 1)
+            cus = n;
+    });
+    return cus;
+}
+
 static int resident_blocks(const void* kernel, int threads) {
     constexpr int kCap = 4096;  // a power of two, above the number of kernels
     static std::mutex mu;
     static const void* keys[kCap] = {};
     static int vals[kCap] = {};
-    static int cus = 0;
+    const int cus = device_cus();
     std::lock_guard<std::mutex> lock(mu);
-    if (cus == 0) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
-            cus = 256;
-    }
     const uintptr_t hsh = (reinterpret_cast<uintptr_t>(kernel) >> 4) * 0x9E3779B97F4A7C15ull;
     for (int probe = 0; probe < kCap; ++probe) {
         const int at = (int)((hsh + (uintptr_t)probe) & (kCap - 1));
@@ -899,8 +909,57 @@ static int resident_blocks(const void* kernel, int threads) {
     return nb * cus;
 }
 
+// A share of at most one half (a very large size class served beside small
+// ones) is a share of the CUs: one block per CU over that share, each block
+// reserving the rest of its CU's LDS (reserve_lds), so that no block of
+// another kernel shares a CU with it and the dispatcher, which spreads blocks
+// over the CUs, leaves the other CUs whole to the small classes.  A larger
+// partial share is a share of the resident blocks on every CU.
+static unsigned reserve_lds(const void* kernel, float share) {
+    if (share > 0.5f) return 0;
+    static std::once_flag once;
+    static int lds_cu = 0, lds_block = 0;
+    std::call_once(once, [] {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return;
+        if (hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
+            lds_cu = 0;
+        if (hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+            lds_block = 0;
+    });
+    constexpr int kCap = 1024;  // a power of two, above the number of kernels launched with a half share
+    static std::mutex mu;
+    static const void* keys[kCap] = {};
+    static unsigned vals[kCap] = {};
+    std::lock_guard<std::mutex> lock(mu);
+    const uintptr_t hsh = (reinterpret_cast<uintptr_t>(kernel) >> 4) * 0x9E3779B97F4A7C15ull;
+    int at = -1;
+    for (int probe = 0; probe < kCap; ++probe) {
+        at = (int)((hsh + (uintptr_t)probe) & (kCap - 1));
+        if (keys[at] == kernel) return vals[at];
+        if (keys[at] == nullptr) break;
+        at = -1;
+    }
+    unsigned pad = 0;
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, kernel) == hipSuccess) {
+        const long long total = std::min(lds_cu, lds_block), own = (long long)fa.sharedSizeBytes;
+        if (total > own &&
+            hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(total - own)) == hipSuccess)
+            pad = (unsigned)(total - own);
+    }
+    (void)hipGetLastError();  // a refused reservation is not an error of the launch
+    if (at >= 0) {
+        keys[at] = kernel;
+        vals[at] = pad;
+    }
+    return pad;
+}
+
 static int persistent_grid(const void* kernel, int threads, unsigned ngroups, int nslots, float share) {
-    const int cap = std::max(1, (int)(resident_blocks(kernel, threads) * share) / std::max(1, nslots));
+    int blocks = resident_blocks(kernel, threads);
+    if (share <= 0.5f) blocks = std::min(blocks, device_cus());
+    const int cap = std::max(1, (int)(blocks * share) / std::max(1, nslots));
     return (int)std::min<unsigned>(ngroups, (unsigned)cap);
 }
 
@@ -922,14 +981,15 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
                         return dispatch_bc(g.bcx, [&]<int BC>() {
                             const void* k = (const void*)&k_resid_dhtx_z<T, N, CO, WE, BC>;
                             const int nb = persistent_grid(k, C::NT, nt, nslots, share);
-                            k_resid_dhtx_z<T, N, CO, WE, BC><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
+                            k_resid_dhtx_z<T, N, CO, WE, BC>
+                                <<<dim3(nb, nslots), C::NT, reserve_lds(k, share), s>>>(g, slots, t);
                             return hipGetLastError();
                         });
                     } else {
                         const void* k = (const void*)&k_resid_dhtx<T, N, MODE, CO, WE>;
                         const int nb = persistent_grid(k, C::NT, ng, nslots, share);
                         if (nunits) *nunits = (int)ng;
-                        k_resid_dhtx<T, N, MODE, CO, WE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
+                        k_resid_dhtx<T, N, MODE, CO, WE><<<dim3(nb, nslots), C::NT, reserve_lds(k, share), s>>>(g, slots, t);
                     }
                     return hipGetLastError();
                 });
@@ -938,8 +998,9 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
             return dispatch_len(g.ny, [&]<int N>() {
                 using C = LineCfg<T, N>;
                 const unsigned ng = ((unsigned)(g.nxh * g.nz) + C::L - 1) / C::L;
-                const int nb = persistent_grid((const void*)&k_dht_cols<T, N, 1, MODE>, C::NT, ng, nslots, share);
-                k_dht_cols<T, N, 1, MODE><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t, stage);
+                const void* k = (const void*)&k_dht_cols<T, N, 1, MODE>;
+                const int nb = persistent_grid(k, C::NT, ng, nslots, share);
+                k_dht_cols<T, N, 1, MODE><<<dim3(nb, nslots), C::NT, reserve_lds(k, share), s>>>(g, slots, t, stage);
                 return hipGetLastError();
             });
         case 3:
@@ -949,7 +1010,8 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
                 const unsigned ng = ((unsigned)(g.nxh * g.ny) + C::L - 1) / C::L;
                 const void* k = (const void*)&k_dht_z_solve<T, N, MODE, Z::ZL, Z::PF, Z::MINW>;
                 const int nb = persistent_grid(k, C::NT, ng, nslots, share);
-                k_dht_z_solve<T, N, MODE, Z::ZL, Z::PF, Z::MINW><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t, stage);
+                k_dht_z_solve<T, N, MODE, Z::ZL, Z::PF, Z::MINW>
+                    <<<dim3(nb, nslots), C::NT, reserve_lds(k, share), s>>>(g, slots, t, stage);
                 return hipGetLastError();
             });
         case 5:
@@ -957,15 +1019,17 @@ static hipError_t sweep_t(const GridArgs& g, const Tables& t, const Slot* slots,
                 using C = LineCfg<T, N>;
                 const unsigned ng = (rows + C::L - 1) / C::L;
                 return dispatch_bc(g.bcx, [&]<int BC>() {
-                    const int nb =
-                        persistent_grid((const void*)&k_dhtx_update<T, N, MODE, BC>, C::NT, ng, nslots, share);
+                    const void* k = (const void*)&k_dhtx_update<T, N, MODE, BC>;
+                    const int nb = persistent_grid(k, C::NT, ng, nslots, share);
                     if constexpr (MODE == 0 && sizeof(T) == 4) {
                         if (stage == kStageTail) {
-                            k_dhtx_update<T, N, 2, BC><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t, stage);
+                            const void* k2 = (const void*)&k_dhtx_update<T, N, 2, BC>;
+                            k_dhtx_update<T, N, 2, BC>
+                                <<<dim3(nb, nslots), C::NT, reserve_lds(k2, share), s>>>(g, slots, t, stage);
                             return hipGetLastError();
                         }
                     }
-                    k_dhtx_update<T, N, MODE, BC><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t, stage);
+                    k_dhtx_update<T, N, MODE, BC><<<dim3(nb, nslots), C::NT, reserve_lds(k, share), s>>>(g, slots, t, stage);
                     return hipGetLastError();
                 });
             });
@@ -1010,7 +1074,7 @@ hipError_t launch_outer_fused(const GridArgs& g, const Tables& t, const Slot* sl
                 return dispatch_bc(g.bcx, [&]<int BC>() {
                     const void* k = (const void*)&k_outer_resid_dhtx<N, CO, WE, BC>;
                     const int nb = persistent_grid(k, C::NT, nt, nslots, share);
-                    k_outer_resid_dhtx<N, CO, WE, BC><<<dim3(nb, nslots), C::NT, 0, s>>>(g, slots, t);
+                    k_outer_resid_dhtx<N, CO, WE, BC><<<dim3(nb, nslots), C::NT, reserve_lds(k, share), s>>>(g, slots, t);
                     return hipGetLastError();
                 });
             });

@@ -13,6 +13,10 @@
     # HBM bytes per cell of every kernel from the same two runs
     python -m paper_1601_05448_amd.profile_summary bytes --fetch DIR --write DIR --cells 16777216
 
+    # per-solve breakdown of a --kernel-trace run (a solve starts at k_init):
+    # span, kernel time, gaps, and launches per kernel with the idle ones apart
+    python -m paper_1601_05448_amd.profile_summary solves DIR [--first K] [--count N] [--min-kernels M]
+
 The traffic record carries a hash of the kernel sources, so that a reader can
 tell counters taken on older code from current ones.
 """
@@ -145,6 +149,39 @@ def cmd_bytes(a) -> None:
               f"  {name[:110]}")
 
 
+SWEEP_KERNELS = ("k_resid_dhtx_z", "k_dht_cols", "k_dht_z_solve", "k_dhtx_update", "k_outer_resid_dhtx",
+                 "k_outer_update")
+
+
+def cmd_solves(a) -> None:
+    """Solves in launch order (each from one k_init to the next): kernels, span
+    from the first start to the last end, time inside kernels, gaps between
+    them, and per kernel the launches and time, a sweep launch shorter than
+    `idle_us` counted apart as idle (its solve was finished or out of stage)."""
+    q = "select name, start, end from kernels order by start"
+    rows = [(n, s, e) for n, s, e in _db(a.dir).execute(q) if "pois::" in n]
+    inits = [i for i, r in enumerate(rows) if "k_init" in r[0]]
+    segs = [(si, rows[i:inits[si + 1] if si + 1 < len(inits) else len(rows)]) for si, i in enumerate(inits)]
+    # solves of at least min_kernels launches (the sweep timings of the profile
+    # driver also start at k_init, with a handful of launches)
+    segs = [(si, seg) for si, seg in segs if len(seg) >= getattr(a, "min_kernels", 0)]
+    for si, seg in segs[a.first:a.first + a.count]:
+        span = (seg[-1][2] - seg[0][1]) / 1e3
+        busy = sum(e - s for _, s, e in seg) / 1e3
+        per: dict = {}
+        for n, s, e in seg:
+            base = n.split("(")[0].replace("void ", "").replace("pois::", "").split("<")[0]
+            idle = base in SWEEP_KERNELS and (e - s) / 1e3 < a.idle_us
+            key = base + (" (idle)" if idle else "")
+            c = per.setdefault(key, [0, 0.0])
+            c[0] += 1
+            c[1] += (e - s) / 1e3
+        print(f"solve {si}: {len(seg)} kernels, span {span:.1f} us, in kernels {busy:.1f} us, "
+              f"gaps {span - busy:.1f} us")
+        for key, (cnt, t) in sorted(per.items(), key=lambda kv: -kv[1][1]):
+            print(f"  {cnt:4d} {t:9.1f} us  {key}")
+
+
 def main(argv=None) -> None:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -161,6 +198,12 @@ def main(argv=None) -> None:
     t.add_argument("--copy-kernel", default="copy", help="substring of the copy kernel's name")
     t.add_argument("--copy-mib", type=int, default=1024)
     t.add_argument("--json", default="")
+    v = sub.add_parser("solves")
+    v.add_argument("dir")
+    v.add_argument("--first", type=int, default=0, help="index of the first solve shown")
+    v.add_argument("--count", type=int, default=4)
+    v.add_argument("--idle-us", type=float, default=6.0)
+    v.add_argument("--min-kernels", type=int, default=0, help="only solves of at least this many launches")
     b = sub.add_parser("bytes")
     b.add_argument("--fetch", required=True)
     b.add_argument("--write", required=True)
@@ -168,7 +211,7 @@ def main(argv=None) -> None:
     b.add_argument("--copy-kernel", default="copy")
     b.add_argument("--copy-mib", type=int, default=1024)
     a = ap.parse_args(argv)
-    {"stats": cmd_stats, "traffic": cmd_traffic, "bytes": cmd_bytes}[a.cmd](a)
+    {"stats": cmd_stats, "traffic": cmd_traffic, "bytes": cmd_bytes, "solves": cmd_solves}[a.cmd](a)
 
 
 if __name__ == "__main__":

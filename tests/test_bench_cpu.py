@@ -84,6 +84,32 @@ def test_profile_stats_by_grid(tmp_path, capsys):
     assert out[2].split()[:3] == ["2", "0.004", "2.0"]  # calls, total ms, mean us
 
 
+def test_profile_solves_breakdown(tmp_path, capsys):
+    """The per-solve breakdown splits the trace at each k_init, reports span,
+    time in kernels and gaps, and counts sweep launches shorter than the idle
+    limit apart."""
+    import argparse
+    import sqlite3
+
+    db = sqlite3.connect(str(tmp_path / "run_results.db"))
+    db.execute("create table kernels (name text, start integer, end integer)")
+    us = 1000
+    rows = [("pois::k_init(x)", 0, 2 * us), ("void pois::k_dht_cols<float, 256, 1, 0>(x)", 3 * us, 23 * us),
+            ("void pois::k_dht_cols<float, 256, 1, 0>(x)", 25 * us, 29 * us),  # idle: 4 us
+            ("pois::k_decide_iter(x)", 30 * us, 37 * us), ("at::other_kernel(x)", 38 * us, 90 * us),
+            ("pois::k_init(x)", 100 * us, 101 * us), ("void pois::k_dhtx_update<float, 256, 0, 0>(x)", 101 * us, 131 * us)]
+    db.executemany("insert into kernels values (?, ?, ?)", rows)
+    db.commit()
+    db.close()
+    profile_summary.cmd_solves(argparse.Namespace(dir=str(tmp_path), first=0, count=4, idle_us=6.0))
+    out = capsys.readouterr().out.splitlines()
+    assert out[0] == "solve 0: 4 kernels, span 37.0 us, in kernels 33.0 us, gaps 4.0 us"
+    rows0 = {line.split("us  ")[1]: (int(line.split()[0]), float(line.split()[1])) for line in out[1:5]}
+    assert rows0 == {"k_dht_cols": (1, 20.0), "k_decide_iter": (1, 7.0), "k_dht_cols (idle)": (1, 4.0),
+                     "k_init": (1, 2.0)}
+    assert out[5] == "solve 1: 2 kernels, span 31.0 us, in kernels 31.0 us, gaps 0.0 us"
+
+
 def test_model_bytes_per_cell():
     """The whole-solve byte model: FP64 16 + 104 K + 32; FP32 with refinement
     52 + 48 S + 52 K (see bench.model_bytes_per_cell)."""

@@ -98,6 +98,26 @@ def test_each_result_same_alone_and_in_the_mix(precision):
         assert oracle.residual(pr.rho, pr.b, p_mix, pr.lengths)["rel"] <= 1e-10
 
 
+@pytest.mark.parametrize("precision", [P.POISSON_FP64, P.POISSON_FP32_REFINE])
+def test_same_bits_when_a_large_class_splits_the_cus(precision):
+    """A 64^3 request with 16^3 requests: 64 times larger, so while both are
+    active the server runs it on one half of the CUs and the small ones on the
+    other (CU-masked streams where available), with other launch grids; every
+    answer is still the same bits as alone."""
+    announce("serve split CUs", precision)
+    probs = [inputs.small_problem(shape=(64, 64, 64), lengths=(TWO_PI,) * 3, ratio=4.0, seed=610)]
+    probs += [inputs.small_problem(shape=(16, 16, 16), lengths=(TWO_PI,) * 3, ratio=2.0 + k, seed=611 + k)
+              for k in range(6)]
+    mixed, res = _served(probs, precision)
+    assert len(res.outcomes) == len(probs)
+    for k, pr in enumerate(probs):
+        p_alone, st_alone = _alone(pr, precision)
+        p_mix, st_mix = mixed[k]
+        assert st_mix["status"] == 0 and st_alone["status"] == 0
+        assert st_mix["iters"] == st_alone["iters"] and st_mix["outer_iters"] == st_alone["outer_iters"]
+        assert np.array_equal(p_mix, p_alone), k
+
+
 def test_budget_admits_one_at_a_time_and_all_finish():
     announce("serve tight budget")
     probs = _mix(6)
