@@ -103,6 +103,7 @@ __device__ inline void decide_outer(const GridArgs& g, SolveState* st, const dou
         st->inner_iter = 0;
         st->inner_done = 0;
         st->stop_next = 0;
+        st->upd_due = 0;
         st->since_best = 0;
         st->best_in = INFINITY;
         st->rel_in = 1.0;
@@ -158,6 +159,7 @@ __device__ inline void decide_inner(SolveState* st, const double* sums, int max_
     } else {
         st->inner_iter = t + 1;
         st->inner_total += 1;
+        st->upd_due = 1;  // this evaluation's update comes next
         // Predicted stop: the sweeps contract the inner residual at a steady
         // rate, so when the contraction since the previous evaluation brings
         // the residual after this iteration's update below half the goal, the

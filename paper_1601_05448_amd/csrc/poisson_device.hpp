@@ -519,8 +519,12 @@ struct IterView<float> {
         return st->done != 0 || st->stage != stage || st->inner_done != 0;
     }
     // the inner residual sweep also idles once the phase is known to end after
-    // the iteration in progress (its evaluation is not needed)
-    static __device__ bool skip_p1(const SolveState* st) { return skip(st) || st->stop_next != 0; }
+    // the iteration in progress (its evaluation is not needed), and while the
+    // update of the last evaluation is still due (a launch sequence may end on
+    // an evaluation and leave that update to the next one)
+    static __device__ bool skip_p1(const SolveState* st) {
+        return skip(st) || st->stop_next != 0 || st->upd_due != 0;
+    }
 };
 
 template <typename T>

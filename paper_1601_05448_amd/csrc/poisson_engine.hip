@@ -339,27 +339,48 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
         // densities take another round
         const int guess = (int)std::ceil(std::log(prm.inner_tol) / std::log(0.1)) + 1;
         int full = std::clamp(guess - first, 0, prm.max_chunk);
+        // n inner sweeps that end on an evaluation: n - 1 full sweeps, then the
+        // residual sweep and decision of the n-th.  The sweep whose evaluation
+        // stops the phase needs no update, so when the guess is right no
+        // transform sweep idles; when the phase goes on, the update of that
+        // evaluation opens the next round (SolveState::upd_due holds the
+        // residual sweeps back until it has run).
+        auto sweeps_to_evaluation = [&](int n) -> hipError_t {
+            if (n <= 0) return hipSuccess;
+            hipError_t le = iterations(n - 1, true);
+            if (le == hipSuccess) le = launch_evaluation(g, geo, t, d_slots, nslots, s, tm);
+            return le;
+        };
         // A refinement step: outer residual (with the tail of its first inner
-        // sweep where fused), `nfull` full inner sweeps, update.
+        // sweep where fused), `nfull` inner sweeps ending on an evaluation, update.
         auto step = [&](int nfull) -> hipError_t {
             hipError_t le = launch_outer_residual(g, geo, t, d_slots, nslots, s, nullptr);
-            if (le == hipSuccess) le = iterations(nfull, true);
+            if (le == hipSuccess) le = sweeps_to_evaluation(nfull);
             if (le == hipSuccess) le = launch_outer_update(g, geo, d_slots, nslots, s);
             return le;
         };
-        int open_full = 0;  // full sweeps that finish an open inner phase (then its update)
+        int open_full = 0;  // evaluations that finish an open inner phase (then its update)
+        bool open_tail = false;    // an open phase's first sweep still needs its transforms
+        bool open_update = false;  // an open phase's last evaluation still needs its update
         int steps = 1;      // whole steps after that, then one outer residual to check
-        int full_last = full;  // full sweeps of the last of those steps
+        int full_last = full;  // inner sweeps of the last of those steps
         bool check = false;
         const int max_rounds = prm.max_outer + prm.max_iter + 2;
         for (int round = 0; round < max_rounds; ++round) {
+            if (open_tail && (e = launch_outer_tail(g, geo, t, d_slots, nslots, s)) != hipSuccess)
+                return hip_status(e);
+            if (open_update && (e = launch_inner_update(g, geo, t, d_slots, nslots, s, tm)) != hipSuccess)
+                return hip_status(e);
             if (open_full > 0) {
-                if ((e = iterations(open_full, true)) != hipSuccess) return hip_status(e);
+                if ((e = sweeps_to_evaluation(open_full)) != hipSuccess) return hip_status(e);
                 if ((e = launch_outer_update(g, geo, d_slots, nslots, s)) != hipSuccess) return hip_status(e);
             }
             for (int k = 0; k < steps; ++k)
                 if ((e = step(k + 1 == steps ? full_last : full)) != hipSuccess) return hip_status(e);
-            if (check && (e = launch_outer_residual(g, geo, t, d_slots, nslots, s, nullptr)) != hipSuccess)
+            // the check: the outer residual alone, without the transforms of
+            // the first inner sweep it would start (due in a later round if
+            // the solve goes on)
+            if (check && (e = launch_outer_residual(g, geo, t, d_slots, nslots, s, nullptr, false)) != hipSuccess)
                 return hip_status(e);
             const int r = poll();
             if (r < 0) return r;
@@ -379,18 +400,27 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
             // Kernels out of their stage idle, so a short guess costs another
             // round and a long one a few idle launches.
             int need_open = 0, need_full = 0, need_steps = 0, need_last = 0;
+            bool need_tail = false, need_update = false;
             for (int q = 0; q < nslots; ++q) {
                 const SolveState& h = hdr[q];
                 if (h.done) continue;
                 double red = h.rel_in;  // outer reduction per step
                 double rel = h.rel;     // outer residual before the next outer evaluation
-                if (h.stage != 0) {
+                if (h.stage == kStageTail) {
+                    // a check that did not pass: its step's first sweep goes on
+                    need_tail = true;
+                    need_open = std::max(need_open, std::max(full, 1));
+                    red = h.inner_goal;
+                } else if (h.stage != 0) {
                     int m = 2 * std::max(std::max(full, open_full), 1);
                     const int k = h.inner_iter - 1;  // index of the last inner residual evaluated
                     if (k >= 1 && h.rel_in > 0.0 && h.rel_in < 1.0) {
                         const double rate = std::pow(h.rel_in, 1.0 / k);
                         if (rate < 0.95) m = (int)std::ceil(std::log(h.inner_goal / h.rel_in) / std::log(rate) + 0.25);
                     }
+                    // the phase ends after the pending update: one evaluation closes it
+                    if (h.stop_next) m = 1;
+                    if (h.stage == 1 && h.upd_due) need_update = true;
                     need_open = std::max(need_open, std::max(m, 1));
                     red = h.inner_goal;
                 } else {
@@ -414,6 +444,8 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
                 need_last = std::max(need_last, last);
             }
             open_full = std::min(need_open, prm.max_chunk);
+            open_tail = need_tail;
+            open_update = need_update;
             if (need_full > 0) full = std::clamp(need_full, 0, prm.max_chunk);
             full_last = need_last > 0 ? std::clamp(need_last, 1, full) : full;
             steps = need_steps;

@@ -69,6 +69,9 @@ struct SolveState {
     int since_best;
     int stop_next;      // the inner phase ends after the update of the iteration in progress:
                         // the next inner residual sweep idles and its decision closes the phase
+    int upd_due;        // the last inner evaluation went on with the phase and its update (the
+                        // y, z, y and x sweeps) has not run yet: the next inner residual sweep
+                        // and its decision idle until it has (the x sweep clears it)
     double inv_s;       // r32 = r * inv_s (a power of two)
     double rhs_mean32;  // mean of r32, removed inside the inner sweeps
     double rhs_norm32;  // ||r32 - mean||
@@ -138,6 +141,14 @@ struct SweepTimer {
 };
 hipError_t launch_iteration(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slots,
                             int nslots, bool fp32, hipStream_t s, SweepTimer* tm = nullptr);
+// FP32_REFINE inner iterations in halves: the residual sweep and its decision
+// (an evaluation), and the four transform sweeps that apply its update; a
+// launch sequence may end on an evaluation and the next start with its update
+// (SolveState::upd_due keeps the order).
+hipError_t launch_evaluation(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slots,
+                             int nslots, hipStream_t s, SweepTimer* tm = nullptr);
+hipError_t launch_inner_update(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slots,
+                               int nslots, hipStream_t s, SweepTimer* tm = nullptr);
 // One sweep alone (1: P1, 2: P2 and P4, 3: P3, 5: P5), for timing.
 hipError_t launch_sweep(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32, int which,
                         hipStream_t s);
@@ -158,10 +169,13 @@ hipError_t launch_outer_fused(const GridArgs& g, const Tables& t, const Slot* sl
 // receives the number of partial sums it wrote
 hipError_t launch_outer_resid_sweep(const GridArgs& g, const Slot* slots, int nslots, hipStream_t s, int* nunits);
 // The FP64 outer residual of a refinement step and its decision; where the
-// rows allow (*fused), fused with the first inner sweep's residual and followed
-// by the rest of that sweep.
+// rows allow (*fused), fused with the first inner sweep's residual and, with
+// `tail`, followed by the rest of that sweep (without, the rest is due in stage
+// kStageTail: launch_outer_tail).
 hipError_t launch_outer_residual(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slots,
-                                 int nslots, hipStream_t s, bool* fused);
+                                 int nslots, hipStream_t s, bool* fused, bool tail = true);
+hipError_t launch_outer_tail(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slots,
+                             int nslots, hipStream_t s);
 hipError_t launch_outer_update(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,
                                hipStream_t s);
 hipError_t launch_fixup(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots, hipStream_t s);

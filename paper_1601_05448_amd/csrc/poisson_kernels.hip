@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(kDecideThreads) k_decide_iter(GridArgs g, cons
     __shared__ double red[(kDecideThreads / 64) * 4];
     const Slot& s = slots[blockIdx.x];
     SolveState* st = s.st;
-    if (fp32 ? (st->done || st->stage != 1 || st->inner_done) : st->done) return;
+    if (fp32 ? (st->done || st->stage != 1 || st->inner_done || st->upd_due) : st->done) return;
     double sums[4] = {0.0, 0.0, 0.0, 0.0};
     if (!(fp32 && st->stop_next)) sum_units<kDecideThreads, 4>(s.partial, (unsigned)nunits, sums, red);
     if (threadIdx.x != 0) return;
@@ -533,8 +533,10 @@ hipError_t launch_setup_finalize(const GridArgs& g, const Geometry& geo, const S
 
 // P1, convergence check, P2, P3, P4 (= P2), P5.  MODE 1 is the stand-alone
 // L^+ q sweep (q in slot.b, result in slot.p), which has no check.
+// parts: 1 the residual sweep and its decision only (an evaluation), 2 the
+// four transform sweeps only (the update of an evaluation), 3 both
 static hipError_t five_sweeps(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, bool fp32,
-                              int mode, hipStream_t s, SweepTimer* tm, float share = 1.0f) {
+                              int mode, hipStream_t s, SweepTimer* tm, float share = 1.0f, int parts = 3) {
     hipError_t e;
     int nunits = 0;
     // one sweep, bracketed by the timer's events when it times this sweep
@@ -550,11 +552,14 @@ static hipError_t five_sweeps(const GridArgs& g, const Tables& t, const Slot* sl
         }
         return hipSuccess;
     };
-    if ((e = sweep(1)) != hipSuccess) return e;
-    if (mode == 0) {
-        k_decide_iter<<<nslots, kDecideThreads, 0, s>>>(g, slots, nunits, fp32 ? 1 : 0);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (parts & 1) {
+        if ((e = sweep(1)) != hipSuccess) return e;
+        if (mode == 0) {
+            k_decide_iter<<<nslots, kDecideThreads, 0, s>>>(g, slots, nunits, fp32 ? 1 : 0);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
     }
+    if (!(parts & 2)) return hipSuccess;
     if ((e = sweep(2)) != hipSuccess) return e;
     if ((e = sweep(3)) != hipSuccess) return e;
     if ((e = sweep(2)) != hipSuccess) return e;
@@ -571,6 +576,16 @@ hipError_t launch_iteration(const GridArgs& g, const Geometry& geo, const Tables
     return five_sweeps(g, t, slots, nslots, fp32, 0, s, tm, geo.share);
 }
 
+hipError_t launch_evaluation(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slots,
+                             int nslots, hipStream_t s, SweepTimer* tm) {
+    return five_sweeps(g, t, slots, nslots, true, 0, s, tm, geo.share, 1);
+}
+
+hipError_t launch_inner_update(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slots,
+                               int nslots, hipStream_t s, SweepTimer* tm) {
+    return five_sweeps(g, t, slots, nslots, true, 0, s, tm, geo.share, 2);
+}
+
 hipError_t launch_outer_resid_sweep(const GridArgs& g, const Slot* slots, int nslots, hipStream_t s, int* nunits) {
     return dispatch_len(g.nx, [&]<int N>() {
         const int nb = blocks_outer<N>(g);
@@ -583,8 +598,19 @@ hipError_t launch_outer_resid_sweep(const GridArgs& g, const Slot* slots, int ns
     });
 }
 
+hipError_t launch_outer_tail(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slots,
+                             int nslots, hipStream_t s) {
+    hipError_t e;
+    for (int which : {2, 3, 2, 5})
+        if ((e = launch_sweep_mode(g, t, slots, nslots, true, which, 0, s, nullptr, geo.share, kStageTail)) !=
+            hipSuccess)
+            return e;
+    k_tail_done<<<nslots, 64, 0, s>>>(slots);
+    return hipGetLastError();
+}
+
 hipError_t launch_outer_residual(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slots,
-                                 int nslots, hipStream_t s, bool* fused) {
+                                 int nslots, hipStream_t s, bool* fused, bool tail) {
     int nu = 0;
     hipError_t e;
     const bool fu = outer_fusable(g);
@@ -596,14 +622,9 @@ hipError_t launch_outer_residual(const GridArgs& g, const Geometry& geo, const T
     }
     k_decide_outer<<<nslots, kDecideThreads, 0, s>>>(g, slots, nu, fu ? 1 : 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (!fu) return hipSuccess;
+    if (!fu || !tail) return hipSuccess;
     // the rest of the first inner sweep: P2, P3, P4, P5 (which stores dp as d32)
-    for (int which : {2, 3, 2, 5})
-        if ((e = launch_sweep_mode(g, t, slots, nslots, true, which, 0, s, nullptr, geo.share, kStageTail)) !=
-            hipSuccess)
-            return e;
-    k_tail_done<<<nslots, 64, 0, s>>>(slots);
-    return hipGetLastError();
+    return launch_outer_tail(g, geo, t, slots, nslots, s);
 }
 
 hipError_t launch_outer_update(const GridArgs& g, const Geometry& geo, const Slot* slots, int nslots,

@@ -764,6 +764,10 @@ k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
     __shared__ cpx<T> tw[N];
     const Slot& s = slots[blockIdx.y];
     if (MODE != 1 && IterView<T>::skip(s.st, stage)) return;
+    // the update of the last inner evaluation is applied here: the next inner
+    // residual sweep may run (no other block of this launch reads the flag)
+    if constexpr (MODE == 0 && sizeof(T) == 4)
+        if (blockIdx.x == 0 && threadIdx.x == 0) s.st->upd_due = 0;
     const cpx<T>* twg = twiddles<T>(tb, 0);
     const cpx<T>* twc = dct_twiddles<T>(tb);
     for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
