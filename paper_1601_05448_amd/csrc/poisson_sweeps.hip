@@ -948,11 +948,16 @@ static unsigned reserve_lds(const void* kernel, float share) {
     hipFuncAttributes fa{};
     if (hipFuncGetAttributes(&fa, kernel) == hipSuccess) {
         const long long total = std::min(lds_cu, lds_block), own = (long long)fa.sharedSizeBytes;
-        if (total > own &&
-            hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(total - own)) == hipSuccess)
-            pad = (unsigned)(total - own);
+        if (total > own) {
+            if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(total - own)) ==
+                hipSuccess)
+                pad = (unsigned)(total - own);
+            else
+                (void)hipGetLastError();  // a refused reservation is not an error of the launch
+        }
+    } else {
+        (void)hipGetLastError();
     }
-    (void)hipGetLastError();  // a refused reservation is not an error of the launch
     if (at >= 0) {
         keys[at] = kernel;
         vals[at] = pad;
