@@ -756,8 +756,17 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
 // MODE 0: FP64 p += dp - mean(p) (or FP32 d32 += dp); MODE 1: assign to p (L^+
 // sweep); MODE 2: FP32 d32 = dp, the first inner sweep after a fused outer
 // residual (d32 holds nothing yet).
+// The FP32 x-update sweep on periodic rows of 256 is sized for four blocks per
+// CU (what its LDS allows; 128 registers, no spills): it then loads the values
+// it updates after the transform, their latency covered by the other blocks
+// instead of a second register buffer.
+template <typename T, int N, int BCX>
+constexpr int update_min_waves() {
+    return (sizeof(T) == 4 && N == 256 && BCX == 0) ? 4 : 1;
+}
+
 template <typename T, int N, int MODE, int BCX>
-__global__ void __launch_bounds__((LineCfg<T, N>::NT))
+__global__ void __launch_bounds__((LineCfg<T, N>::NT), (update_min_waves<T, N, BCX>()))
 k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) {
     using C = LineCfg<T, N>;
     __shared__ cpx<T> lds[C::L * C::LS];
@@ -817,7 +826,8 @@ k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
         }
         // FP32: the values to update are loaded now and are in flight during the
         // FFT; FP64 has no registers to spare for them and loads them after it
-        if (MODE == 0 && sizeof(T) == 4) {
+        constexpr bool kEarly = MODE == 0 && sizeof(T) == 4 && update_min_waves<T, N, BCX>() == 1;
+        if (kEarly) {
 #pragma unroll
             for (int it = 0; it < C::IT; ++it) {
                 const int e = threadIdx.x + it * C::NT;
@@ -832,7 +842,7 @@ k_dhtx_update(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
         __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         fft_block_lines<T, N>(lds, tw);
-        if (MODE == 0 && sizeof(T) == 8) {
+        if (MODE == 0 && !kEarly) {
 #pragma unroll
             for (int it = 0; it < C::IT; ++it) {
                 const int e = threadIdx.x + it * C::NT;
