@@ -303,11 +303,27 @@ __device__ __forceinline__ void fft256_regs(cpx<T> (&v)[16], cpx<T>* ln, int c, 
 // of the length-32 DFT over c, which the two partner threads combine:
 //     X[k1 + 16 k2'] = E[k2'] + O[k2'],  X[k1 + 16 k2' + 256] = E[k2'] - O[k2'].
 // The thread leaves with v[b] = X[k1 + 16 b + 256 h].  The partner of column c
-// is column c ^ 1, whose lane is `partner_xor` away (lanes are lines-fastest:
-// lane = line + L c within the wave).  All threads of the block call it: it
-// holds two barriers, the second one guarding `ln` for its next writer.
+// is column c ^ 1: the lanes of even columns sit in the even rows of 16 lanes of
+// their wave and their partners in the row above (reg_col), so one
+// v_permlane16_swap per 32-bit word hands both threads of a pair the E and the
+// O value.  All threads of the block call it: it holds two barriers, the
+// second one guarding `ln` for its next writer.
+__device__ __forceinline__ void row_pair(float x, float& ev, float& od) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(x), false, false);
+    ev = __uint_as_float(r[0]);  // the value of the pair's even row
+    od = __uint_as_float(r[1]);  // the value of its odd row
+}
+__device__ __forceinline__ void row_pair(double x, double& ev, double& od) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)u, (unsigned)u, false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+    ev = __longlong_as_double((long long)(((unsigned long long)hi[0] << 32) | lo[0]));
+    od = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
+}
+
 template <typename T, int PARTNER_XOR>
 __device__ __forceinline__ void fft512_regs(cpx<T> (&v)[16], cpx<T>* ln, int c, const cpx<T>* tw) {
+    static_assert(PARTNER_XOR == 16, "column pairs in adjacent rows of 16 lanes");
     using C = LineCfg<T, 512>;
     dft16(v);
 #pragma unroll
@@ -320,15 +336,16 @@ __device__ __forceinline__ void fft512_regs(cpx<T> (&v)[16], cpx<T>* ln, int c, 
     for (int q = 0; q < 16; ++q) v[q] = ln[C::pos(32 * k1 + 2 * q + h)];
     __syncthreads();
     dft16(v);
-    if (h) {
-#pragma unroll
-        for (int q = 1; q < 16; ++q) v[q] = cmul(v[q], tw[16 * q]);
-    }
+    // both threads of the pair take E (h = 0) and O (h = 1), apply the odd
+    // half's twiddles W32^q = tw[16 q] to O and keep E + O (h = 0) or E - O
+    const T sg = h ? T(-1) : T(1);
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-        const cpx<T> o = {__shfl_xor(v[q].x, PARTNER_XOR), __shfl_xor(v[q].y, PARTNER_XOR)};
-        // h = 0: E = v, O = o -> E + O; h = 1: O = v, E = o -> E - O
-        v[q] = h ? csub(o, v[q]) : cadd(v[q], o);
+        cpx<T> e, o;
+        row_pair(v[q].x, e.x, o.x);
+        row_pair(v[q].y, e.y, o.y);
+        if (q > 0) o = cmul(o, tw[16 * q]);
+        v[q] = {fma(sg, o.x, e.x), fma(sg, o.y, e.y)};
     }
 }
 

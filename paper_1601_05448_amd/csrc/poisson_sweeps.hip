@@ -529,9 +529,42 @@ k_dht_cols(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) {
 // spectrum is Z'_k = (s_a + s_b)/2 Z_k + (s_a - s_b)/2 conj Z_{N-k}; the inverse is
 // taken as conj(FFT(conj Z')), which needs no exchange of (k, N-k) partners.
 template <typename T>
-__device__ __forceinline__ cpx<T> scaled_conj(cpx<T> zk, cpx<T> zm, T sa, T sb) {
-    const T hp = T(0.5) * (sa + sb), hm = T(0.5) * (sa - sb);
+__device__ __forceinline__ cpx<T> scaled_conj_h(cpx<T> zk, cpx<T> zm, T hp, T hm) {
     return {hp * zk.x + hm * zm.x, hm * zm.y - hp * zk.y};  // conj(hp Z_k + hm conj Z_{N-k})
+}
+template <typename T>
+__device__ __forceinline__ cpx<T> scaled_conj(cpx<T> zk, cpx<T> zm, T sa, T sb) {
+    return scaled_conj_h(zk, zm, T(0.5) * (sa + sb), T(0.5) * (sa - sb));
+}
+
+// The register paths take hp = (s_a + s_b)/2 and hm = (s_a - s_b)/2 with one
+// reciprocal per wavenumber instead of two.  The symbols are scaled by a power
+// of two sc (exact, and the product of two of them then stays in range): with
+// ta = sc lam_a, tb = sc lam_b and kn = n / sc, s_a = 1 / (n lam_a) = 1 / (kn ta)
+// and
+//     hp = (ta + tb) / (2 kn ta tb),   hm = (tb - ta) / (2 kn ta tb).
+// Only the constant mode has a zero symbol; the one value per thread that may
+// hold it takes pair_coefs0, which inverts each symbol on its own (0 for 0).
+template <typename T>
+__device__ __forceinline__ void pair_coefs(T ta, T tb, T dt, T kn2, T& hp, T& hm) {
+    const T r = recip(ta * tb * kn2);
+    hp = (ta + tb) * r;
+    hm = dt * r;
+}
+template <typename T>
+__device__ __forceinline__ void pair_coefs0(T ta, T tb, T kn, T& hp, T& hm) {
+    const T sa = ta == T(0) ? T(0) : recip(kn * ta), sb = tb == T(0) ? T(0) : recip(kn * tb);
+    hp = T(0.5) * (sa + sb);
+    hm = T(0.5) * (sa - sb);
+}
+// sc = 2^-e, with every symbol's magnitude (at most 4 (1/hx^2 + 1/hy^2 + 1/hz^2))
+// below 2^e
+template <typename T>
+__device__ __forceinline__ T symbol_scale(const GridArgs& g) {
+    int e;
+    (void)frexp(4.0 * (g.ihx2 + g.ihy2 + g.ihz2), &e);
+    e = e < -120 ? -120 : (e > 120 ? 120 : e);
+    return T(ldexp(1.0, -e));
 }
 
 // Launch shape of the z sweep: ZL lines per block, PF whether the next line
@@ -568,8 +601,9 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
     if (MODE == 0 && IterView<T>::skip(s.st, stage)) return;
     const cpx<T>* twg = twiddles<T>(tb, 2);
     for (int e = threadIdx.x; e < N; e += C::NT) tw[e] = twg[e];
+    const T sc = symbol_scale<T>(g);
     if constexpr (N == 256 || N == 512)
-        for (int e = threadIdx.x; e < N; e += C::NT) lzs[e] = symbol<T>(tb, 2)[e];
+        for (int e = threadIdx.x; e < N; e += C::NT) lzs[e] = symbol<T>(tb, 2)[e] * sc;
     POIS_GLOBAL T* Wc = MODE == 0 ? IterView<T>(s).W : (POIS_GLOBAL T*)gptr(s.W);  // complex-indexed
     const unsigned nlines = (unsigned)(g.nxh * g.ny);
     const unsigned ngroups = (nlines + C::L - 1) / C::L;
@@ -581,6 +615,7 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
     const T* lamy = symbol<T>(tb, 1);
     const T* lamz = symbol<T>(tb, 2);
     const T nn = T(g.n);
+    const T kn = nn / sc, kn2 = T(2) * kn;  // exact: sc is a power of two
 
     // element e0 + it TT of a line at base + e0 se + (it TT) se; a line past
     // the end loads line 0 and is not stored (see k_dht_cols)
@@ -612,6 +647,7 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
             const unsigned line = grp * C::L + l;
             const unsigned j = cur_valid ? line / (unsigned)g.nxh : 0u, m = cur_valid ? line - j * (unsigned)g.nxh : 0u;
             const T lxe = lamx[2 * m], lxo = lamx[2 * m + 1], lyj = lamy[j];
+            const T ta0 = (lxe + lyj) * sc, tb0 = (lxo + lyj) * sc, dt = (lxo - lxe) * sc;
             const unsigned ng = grp + gridDim.x;
             if constexpr (PF) {
                 __builtin_amdgcn_s_setprio(2);
@@ -625,13 +661,15 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
             wave_lds_sync();
             {
                 const cpx<T>* pp = exchange_partner<T, N>(ln, c);
-                const T* lz = lzs + c;  // z symbol at k = c + 16 b
+                const T* lz = lzs + c;  // sc times the z symbol at k = c + 16 b (zero only for k = 0)
 #pragma unroll
                 for (int b = 0; b < 16; ++b) {
                     const T lzk = lz[16 * b];
+                    T hp, hm;
+                    if (b == 0) pair_coefs0(ta0 + lzk, tb0 + lzk, kn, hp, hm);
+                    else pair_coefs(ta0 + lzk, tb0 + lzk, dt, kn2, hp, hm);
                     // the second transform's input x[c + 16 b]
-                    v[b] = scaled_conj(v[b], pp[17 * (15 - b)], inv_symbol(lxe, lyj, lzk, nn),
-                                       inv_symbol(lxo, lyj, lzk, nn));
+                    v[b] = scaled_conj_h(v[b], pp[17 * (15 - b)], hp, hm);
                 }
             }
             wave_lds_sync();  // the partner lanes' reads before this wave's transpose writes
@@ -667,6 +705,7 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
             const unsigned line = grp * C::L + l;
             const unsigned j = cur_valid ? line / (unsigned)g.nxh : 0u, m = cur_valid ? line - j * (unsigned)g.nxh : 0u;
             const T lxe = lamx[2 * m], lxo = lamx[2 * m + 1], lyj = lamy[j];
+            const T ta0 = (lxe + lyj) * sc, tb0 = (lxo + lyj) * sc, dt = (lxo - lxe) * sc;
             const unsigned ng = grp + gridDim.x;
             if constexpr (PF) {
                 __builtin_amdgcn_s_setprio(2);
@@ -686,12 +725,14 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
                 const cpx<T>* pk = ln + c + (c >> 4);
                 const int p2 = c == 0 ? 544 : (512 - c) + ((512 - c) >> 4);
                 const cpx<T>* pm = ln + (p2 - 510);
-                const T* lz = lzs + c;  // z symbol at k = c + 32 a
+                const T* lz = lzs + c;  // sc times the z symbol at k = c + 32 a (zero only for k = 0)
 #pragma unroll
                 for (int a = 0; a < 16; ++a) {
                     const T lzk = lz[32 * a];
-                    v[a] = scaled_conj(pk[34 * a], pm[34 * (15 - a)], inv_symbol(lxe, lyj, lzk, nn),
-                                       inv_symbol(lxo, lyj, lzk, nn));
+                    T hp, hm;
+                    if (a == 0) pair_coefs0(ta0 + lzk, tb0 + lzk, kn, hp, hm);
+                    else pair_coefs(ta0 + lzk, tb0 + lzk, dt, kn2, hp, hm);
+                    v[a] = scaled_conj_h(pk[34 * a], pm[34 * (15 - a)], hp, hm);
                 }
             }
             __syncthreads();
