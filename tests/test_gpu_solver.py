@@ -445,6 +445,42 @@ def test_lap_pinv_fp32_needs_fp32_handle():
         P.poisson_destroy(h)
 
 
+@pytest.mark.parametrize("scale", [1e-7, 1e10])
+@pytest.mark.parametrize("shape", [(256, 8, 8), (512, 8, 8), (8, 512, 8)])
+def test_lap_pinv_extreme_spacings(shape, scale):
+    """L^+ on boxes 1e7 times smaller and 1e10 times larger than the unit box,
+    with 256- and 512-cell lines along z and y (the register-resident
+    transforms): the z sweep takes the inverse symbols of a row pair from one
+    reciprocal of a product of two symbols, formed after scaling them by a
+    power of two; unscaled, that product (times 2 n) would overflow FP32 at
+    the small box (symbols up to 7e18) and leave FP32's normal range at the
+    large one (symbols down to 2.5e-20).  Element by element against the oracle,
+    with the bounds of the tests above."""
+    announce("lap_pinv extreme spacing", shape, scale)
+    rng = np.random.default_rng(int(math.log10(scale)) + sum(shape))
+    L = (TWO_PI * scale, 2.5 * scale, 4.0 * scale)
+    q = rng.standard_normal(shape) + 0.7
+    want = oracle.lap_pinv(q, L)
+    for precision in (P.POISSON_FP64, P.POISSON_FP32_REFINE):
+        h = P.poisson_create(shape, L, precision=precision)
+        try:
+            out = dev(np.zeros(shape))
+            if precision == P.POISSON_FP64:
+                P.poisson_lap_pinv(h, dev(q), out)
+            else:
+                P.poisson_lap_pinv_fp32(h, dev(q), out)
+        finally:
+            P.poisson_destroy(h)
+        got = host(out)
+        assert np.all(np.isfinite(got)), (shape, scale, precision)
+        if precision == P.POISSON_FP64:
+            assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want)), (shape, scale)
+        else:
+            passes = 2 + 2 * sum(math.log2(n) for n in shape)
+            bound = 4 * 2.0 ** -24 * passes * np.linalg.norm(q - q.mean()) / _lap_min(shape, L)
+            assert np.max(np.abs(got - want)) <= bound, (shape, scale)
+
+
 @pytest.mark.parametrize("shape", [(12, 8, 256), (8, 256, 12), (256, 8, 12)])
 def test_solve_fp32_refine_axis_256(shape):
     """FP32 sweeps + FP64 refinement with a 256-long axis along x, y or z (the
