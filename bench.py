@@ -64,12 +64,13 @@ def model_bytes_per_cell(fp32, iters, outer_iters, p1_sweeps=None):
     outer residual): setup 20 (rho, b read, rho32 written); per step the fused
     outer residual 32, the rest of its first inner sweep 32 (y, z, y 8 each,
     the x pass 8) and the FP64 update 20; 36 per further inner update (y, z, y,
-    x update) and 16 per inner residual sweep; the final outer residual 32:
-    52 + 48 S + 36 K + 16 E, which is 52 + 48 S + 52 K when every step ends
-    with a confirming residual sweep (E = K)."""
+    x update) and 16 per inner residual sweep; the final outer residual, which
+    checks the result and writes nothing on rows that take the fused sweep (all
+    the workloads here), 24: 44 + 48 S + 36 K + 16 E, which is 44 + 48 S + 52 K
+    when every step ends with a confirming residual sweep (E = K)."""
     if fp32:
         e = iters if p1_sweeps is None else p1_sweeps
-        return 52 + 48 * outer_iters + 36 * iters + 16 * e
+        return 44 + 48 * outer_iters + 36 * iters + 16 * e
     return 48 + 104 * iters
 
 

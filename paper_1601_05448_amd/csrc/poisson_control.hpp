@@ -59,7 +59,10 @@ __device__ inline void decide_fp64(const GridArgs& g, SolveState* st, const doub
 // bt^2, p, p^2, r.  fused: the sweep also produced the first inner sweep's
 // transformed residual, whose evaluation (rel 1 against the step's own right-
 // hand side) is taken here; the rest of that sweep is due next (kStageTail).
-__device__ inline void decide_outer(const GridArgs& g, SolveState* st, const double* sums, bool fused) {
+// check: the sweep wrote nothing but its sums; a solve it does not end stays in
+// stage 0 for an outer residual that starts the step (the same sums again).
+__device__ inline void decide_outer(const GridArgs& g, SolveState* st, const double* sums, bool fused,
+                                    bool check = false) {
     const int m = st->iter;
     st->p_sum = sums[2];
     st->p_sumsq = sums[3];
@@ -90,7 +93,7 @@ __device__ inline void decide_outer(const GridArgs& g, SolveState* st, const dou
     } else if (m >= st->max_outer || st->inner_total >= st->max_iter) {
         st->done = 1;
         st->status = POISSON_ENOCONV;
-    } else {
+    } else if (!check) {
         st->rhs_mean32 = sums[4] * st->inv_s / (double)g.n;
         // The update leaves an outer residual of rel times the inner relative
         // residual (up to the FP32 operator's rounding, about 1e-6 of it), so

@@ -377,9 +377,9 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
             }
             for (int k = 0; k < steps; ++k)
                 if ((e = step(k + 1 == steps ? full_last : full)) != hipSuccess) return hip_status(e);
-            // the check: the outer residual alone, without the transforms of
-            // the first inner sweep it would start (due in a later round if
-            // the solve goes on)
+            // the check: the outer residual's sums alone (on rows that take the
+            // fused sweep); a solve it does not end starts its next step with
+            // a full outer residual in the next round
             if (check && (e = launch_outer_residual(g, geo, t, d_slots, nslots, s, nullptr, false)) != hipSuccess)
                 return hip_status(e);
             const int r = poll();
@@ -407,7 +407,9 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
                 double red = h.rel_in;  // outer reduction per step
                 double rel = h.rel;     // outer residual before the next outer evaluation
                 if (h.stage == kStageTail) {
-                    // a check that did not pass: its step's first sweep goes on
+                    // a step's first sweep still open (not left by the launch
+                    // sequences above, which follow every fused outer residual
+                    // with its tail): it goes on
                     need_tail = true;
                     need_open = std::max(need_open, std::max(full, 1));
                     red = h.inner_goal;

@@ -161,17 +161,19 @@ unsigned sweep_groups_x(const GridArgs& g);
 // FP32_REFINE: whether rows of this length take the outer residual fused with
 // the first inner sweep's residual (one marching column per thread), and that
 // sweep alone (no decision); *nunits receives the number of partial sums.
+// write = false: the partial sums alone (no r32, no transformed residual).
 bool outer_fusable(const GridArgs& g);
 hipError_t launch_outer_fused(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, hipStream_t s,
-                              int* nunits, float share = 1.0f);
+                              int* nunits, float share = 1.0f, bool write = true);
 // FP32_REFINE outer step pieces.
 // the FP64 outer residual sweep alone (no decision); *nunits (may be NULL)
 // receives the number of partial sums it wrote
 hipError_t launch_outer_resid_sweep(const GridArgs& g, const Slot* slots, int nslots, hipStream_t s, int* nunits);
 // The FP64 outer residual of a refinement step and its decision; where the
 // rows allow (*fused), fused with the first inner sweep's residual and, with
-// `tail`, followed by the rest of that sweep (without, the rest is due in stage
-// kStageTail: launch_outer_tail).
+// `tail`, followed by the rest of that sweep.  Without `tail` (the final check
+// of a solve) fused rows take the residual's sums alone: a solve it does not
+// end stays in stage 0, and its next outer residual starts the step.
 hipError_t launch_outer_residual(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slots,
                                  int nslots, hipStream_t s, bool* fused, bool tail = true);
 hipError_t launch_outer_tail(const GridArgs& g, const Geometry& geo, const Tables& t, const Slot* slots,

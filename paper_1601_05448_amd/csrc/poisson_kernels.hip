@@ -150,17 +150,18 @@ __global__ void __launch_bounds__(kDecideThreads) k_decide_iter(GridArgs g, cons
     else decide_fp64(g, st, sums);
 }
 
-// After the FP64 outer residual of a refinement step (fused: with the first
-// inner sweep's residual).
+// After the FP64 outer residual of a refinement step.  mode 0: the residual
+// alone (r32 written), 1: fused with the first inner sweep's residual, 2: its
+// sums alone (a check: no step starts from it).
 __global__ void __launch_bounds__(kDecideThreads) k_decide_outer(GridArgs g, const Slot* __restrict__ slots,
-                                                                 int nunits, int fused) {
+                                                                 int nunits, int mode) {
     __shared__ double red[(kDecideThreads / 64) * 5];
     const Slot& s = slots[blockIdx.x];
     SolveState* st = s.st;
     if (st->done || st->stage != 0) return;
     double sums[5];
     sum_units<kDecideThreads, 5>(s.partial, (unsigned)nunits, sums, red);
-    if (threadIdx.x == 0) decide_outer(g, st, sums, fused != 0);
+    if (threadIdx.x == 0) decide_outer(g, st, sums, mode == 1, mode == 2);
 }
 
 // After the rest of a fused first inner sweep: the inner sweeps go on.
@@ -616,11 +617,11 @@ hipError_t launch_outer_residual(const GridArgs& g, const Geometry& geo, const T
     const bool fu = outer_fusable(g);
     if (fused) *fused = fu;
     if (fu) {
-        if ((e = launch_outer_fused(g, t, slots, nslots, s, &nu, geo.share)) != hipSuccess) return e;
+        if ((e = launch_outer_fused(g, t, slots, nslots, s, &nu, geo.share, tail)) != hipSuccess) return e;
     } else if ((e = launch_outer_resid_sweep(g, slots, nslots, s, &nu)) != hipSuccess) {
         return e;
     }
-    k_decide_outer<<<nslots, kDecideThreads, 0, s>>>(g, slots, nu, fu ? 1 : 0);
+    k_decide_outer<<<nslots, kDecideThreads, 0, s>>>(g, slots, nu, fu ? (tail ? 1 : 2) : 0);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (!fu || !tail) return hipSuccess;
     // the rest of the first inner sweep: P2, P3, P4, P5 (which stores dp as d32)

@@ -281,10 +281,12 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
 // gives r32 (stored for the later inner sweeps) and q, whose lines are
 // transformed along x into W32 exactly as the FP32 P1 would.  The mean of r32,
 // which the FP32 P1 removes, is FP64 rounding noise here and is not removed.
-// Per tile: r^2, bt^2, p, p^2, r in FP64.  One column per thread.
+// Per tile: r^2, bt^2, p, p^2, r in FP64.  One column per thread.  write = 0:
+// the sums alone (the final check of a solve, which usually ends it: no r32,
+// no transform, no W32).
 template <int N, int COEF, int WEIGHT, int BCX>
 __global__ void __launch_bounds__((LineCfg<float, N>::NT), (LineCfg<float, N>::MINB))
-k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
+k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb, int write) {
     using C = LineCfg<float, N>;
     using Z = OuterTile<N>;
     static_assert(Z::CPT == 1, "one marching column per thread");
@@ -353,18 +355,21 @@ k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                     acc[2] += pr.a.pc + pr.b.pc;
                     acc[3] += pr.a.pc * pr.a.pc + pr.b.pc * pr.b.pc;
                     acc[4] += pr.a.r + pr.b.r;
-                    const float ra = (float)(pr.a.r * inv_s), rb = (float)(pr.b.r * inv_s);
-                    const unsigned a = (unsigned)k * zm.sz + zm.ra + i;
-                    __builtin_nontemporal_store(ra, &r32[a]);  // streaming (see k_resid_dhtx_z)
-                    __builtin_nontemporal_store(rb, &r32[a + (unsigned)g.nx]);
-                    qv = {(float)pr.a.w * ra, (float)pr.b.w * rb};
+                    if (write) {
+                        const float ra = (float)(pr.a.r * inv_s), rb = (float)(pr.b.r * inv_s);
+                        const unsigned a = (unsigned)k * zm.sz + zm.ra + i;
+                        __builtin_nontemporal_store(ra, &r32[a]);  // streaming (see k_resid_dhtx_z)
+                        __builtin_nontemporal_store(rb, &r32[a + (unsigned)g.nx]);
+                        qv = {(float)pr.a.w * ra, (float)pr.b.w * rb};
+                    }
                 }
-                lds[(sidx * Z::KF + q) * C::LS + C::pos(x_slot(i, N, BCX))] = qv;
+                if (write) lds[(sidx * Z::KF + q) * C::LS + C::pos(x_slot(i, N, BCX))] = qv;
                 pl[0] = pl[1];
                 pl[1] = pl[2];
                 pl[2] = nn;
                 sd = ns;
             }
+            if (!write) continue;  // uniform
             __syncthreads();
             fft_block_lines<float, N>(lds, tw);
 #pragma unroll
@@ -1123,7 +1128,7 @@ bool outer_fusable(const GridArgs& g) {
 }
 
 hipError_t launch_outer_fused(const GridArgs& g, const Tables& t, const Slot* slots, int nslots, hipStream_t s,
-                              int* nunits, float share) {
+                              int* nunits, float share, bool write) {
     return dispatch_len(g.nx, [&]<int N>() {
         if constexpr (outer_fusable_len<N>()) {
             using C = LineCfg<float, N>;
@@ -1134,7 +1139,8 @@ hipError_t launch_outer_fused(const GridArgs& g, const Tables& t, const Slot* sl
                 return dispatch_bc(g.bcx, [&]<int BC>() {
                     const void* k = (const void*)&k_outer_resid_dhtx<N, CO, WE, BC>;
                     const int nb = persistent_grid(k, C::NT, nt, nslots, share);
-                    k_outer_resid_dhtx<N, CO, WE, BC><<<dim3(nb, nslots), C::NT, reserve_lds(k, share), s>>>(g, slots, t);
+                    k_outer_resid_dhtx<N, CO, WE, BC>
+                        <<<dim3(nb, nslots), C::NT, reserve_lds(k, share), s>>>(g, slots, t, write ? 1 : 0);
                     return hipGetLastError();
                 });
             });

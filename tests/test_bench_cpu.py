@@ -112,9 +112,10 @@ def test_profile_solves_breakdown(tmp_path, capsys):
 
 def test_model_bytes_per_cell():
     """The whole-solve byte model: FP64 16 + 104 K + 32; FP32 with refinement
-    52 + 48 S + 52 K (see bench.model_bytes_per_cell)."""
+    44 + 48 S + 52 K (see bench.model_bytes_per_cell)."""
     assert bench.model_bytes_per_cell(False, 10, 0) == 16 + 10 * 104 + 32
-    assert bench.model_bytes_per_cell(True, 10, 3) == 20 + 3 * (32 + 32 + 16 + 20) + (10 - 3) * 52 + 32
+    # the final check reads rho, p and b and writes nothing
+    assert bench.model_bytes_per_cell(True, 10, 3) == 20 + 3 * (32 + 32 + 16 + 20) + (10 - 3) * 52 + 24
     # a step whose end was predicted runs no confirming residual sweep: 16 less
     assert bench.model_bytes_per_cell(True, 10, 3, 9) == bench.model_bytes_per_cell(True, 10, 3) - 16
 
