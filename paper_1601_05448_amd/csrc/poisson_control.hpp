@@ -64,6 +64,7 @@ __device__ inline void decide_fp64(const GridArgs& g, SolveState* st, const doub
 __device__ inline void decide_outer(const GridArgs& g, SolveState* st, const double* sums, bool fused,
                                     bool check = false) {
     const int m = st->iter;
+    st->checked = check ? 1 : 0;
     st->p_sum = sums[2];
     st->p_sumsq = sums[3];
     if (m == 0) {

@@ -429,7 +429,11 @@ int drive_solve(const GridArgs& g, const Geometry& geo, const Tables& t, const S
                     need_full = std::max(need_full, h.inner_last - first);
                 }
                 const double redc = std::clamp(red, 1e-12, 0.5);
-                rel *= redc;
+                // in stage 0 the last update has not been measured yet (one
+                // reduction pending), except after a check that did not end the
+                // solve: its residual is that of the current p, and at least one
+                // more step is due
+                if (!(h.stage == 0 && h.checked)) rel *= redc;
                 int st = 0;
                 if (rel > 0.5 * h.tol) st = (int)std::ceil(std::log(0.5 * h.tol / rel) / std::log(redc));
                 st = std::clamp(st, 0, 8);

@@ -321,9 +321,8 @@ __device__ __forceinline__ void row_pair(double x, double& ev, double& od) {
     od = __longlong_as_double((long long)(((unsigned long long)hi[1] << 32) | lo[1]));
 }
 
-template <typename T, int PARTNER_XOR>
+template <typename T>
 __device__ __forceinline__ void fft512_regs(cpx<T> (&v)[16], cpx<T>* ln, int c, const cpx<T>* tw) {
-    static_assert(PARTNER_XOR == 16, "column pairs in adjacent rows of 16 lanes");
     using C = LineCfg<T, 512>;
     dft16(v);
 #pragma unroll

@@ -72,6 +72,8 @@ struct SolveState {
     int upd_due;        // the last inner evaluation went on with the phase and its update (the
                         // y, z, y and x sweeps) has not run yet: the next inner residual sweep
                         // and its decision idle until it has (the x sweep clears it)
+    int checked;        // the last outer residual was a check (sums alone) that did not end the
+                        // solve: `rel` is the residual of the current p, no update is pending
     double inv_s;       // r32 = r * inv_s (a power of two)
     double rhs_mean32;  // mean of r32, removed inside the inner sweeps
     double rhs_norm32;  // ||r32 - mean||

@@ -480,7 +480,7 @@ k_dht_cols(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) {
             int c = e0;
             asm volatile("" : "+v"(c));
             if constexpr (N == 256) fft256_regs<T>(v, ln, c, tw);
-            else fft512_regs<T, 16>(v, ln, c, tw);
+            else fft512_regs<T>(v, ln, c, tw);
             exchange_write<T, N>(ln, c, v);
             wave_lds_sync();
             if (cur_valid) {
@@ -719,7 +719,7 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
             }
             int c = e0;  // opaque within each group (see k_dht_cols)
             asm volatile("" : "+v"(c));
-            fft512_regs<T, 16>(v, ln, c, tw);  // v[b] = X[c/2 + 16 b + 256 (c mod 2)]
+            fft512_regs<T>(v, ln, c, tw);  // v[b] = X[c/2 + 16 b + 256 (c mod 2)]
             exchange_write<T, N>(ln, c, v);
             // the whole spectrum through LDS: the second forward transform
             // takes its input x[c + 32 a] in natural order, at pos(c + 32 a) =
@@ -741,7 +741,7 @@ k_dht_z_solve(GridArgs g, const Slot* __restrict__ slots, Tables tb, int stage) 
                 }
             }
             __syncthreads();
-            fft512_regs<T, 16>(v, ln, c, tw);  // v[b] = conj(x'[c/2 + 16 b + 256 (c mod 2)])
+            fft512_regs<T>(v, ln, c, tw);  // v[b] = conj(x'[c/2 + 16 b + 256 (c mod 2)])
             if (cur_valid) {
                 const unsigned st_base = cur_base + (unsigned)((c >> 1) + 256 * (c & 1)) * se;
 #pragma unroll

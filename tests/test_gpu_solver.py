@@ -497,6 +497,22 @@ def test_solve_fp32_refine_axis_256(shape):
     assert err <= 1e-8
 
 
+def test_fp32_refine_check_that_does_not_end_the_solve():
+    """The final check of a host round (the outer residual's sums alone) can
+    find the residual still above the tolerance; the solve must then go on
+    with a full refinement step, planned from the residual the check measured.
+    This 128^3 problem at 1e-12 ends its third step at 6e-12 (measured), so its
+    check fails once."""
+    announce("fp32 refine failed check")
+    prob = inputs.small_problem(shape=(128, 128, 128), lengths=(TWO_PI,) * 3, ratio=4.0, seed=9)
+    p, st, _ = _solve_gpu(prob, precision=P.POISSON_FP32_REFINE, tol=1e-12)
+    assert st["code"] == P.POISSON_OK, st
+    assert 4 <= st["outer_iters"] <= 6, st
+    res = oracle.residual(prob.rho, prob.b, p, prob.lengths)
+    assert res["rel"] <= 1e-12, res
+    assert abs(st["rel_resid"] - res["rel"]) <= 1e-3 * res["rel"]
+
+
 @pytest.mark.parametrize("precision", [P.POISSON_FP64, P.POISSON_FP32_REFINE])
 def test_rough_density_diverges(precision):
     """The oracle's divergent case (face mean of 1/rho, w = rho, cell-to-cell
