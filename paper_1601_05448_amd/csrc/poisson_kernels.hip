@@ -58,15 +58,29 @@ k_setup(GridArgs g, const Slot* __restrict__ slots, int write_rho32) {
     const Slot& s = slots[blockIdx.y];
     double sb = 0.0, sb2 = 0.0, mn = INFINITY, mx = -INFINITY, bad = 0.0;
     const long long stride = (long long)gridDim.x * kPtThreads;
-    for (long long c = (long long)blockIdx.x * kPtThreads + threadIdx.x; c < g.n; c += stride) {
-        const double r = gptr(s.rho)[c], b = gptr(s.b)[c];
+    auto cell = [&](long long c, double r, double b) {
         if (!(r > 0.0) || !isfinite(r) || !isfinite(b)) bad += 1.0;
         mn = fmin(mn, r);
         mx = fmax(mx, r);
         sb += b;
         sb2 += b * b;
         if (write_rho32) gptr(s.rho32)[c] = (float)r;
+    };
+    // four cells' loads in flight per thread, the sums taken in the same order
+    // as one cell at a time
+    constexpr int kU = 4;
+    long long c = (long long)blockIdx.x * kPtThreads + threadIdx.x;
+    for (; c + (kU - 1) * stride < g.n; c += kU * stride) {
+        double r[kU], b[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            r[u] = gptr(s.rho)[c + u * stride];
+            b[u] = gptr(s.b)[c + u * stride];
+        }
+#pragma unroll
+        for (int u = 0; u < kU; ++u) cell(c + u * stride, r[u], b[u]);
     }
+    for (; c < g.n; c += stride) cell(c, gptr(s.rho)[c], gptr(s.b)[c]);
     const int w = threadIdx.x / 64, lane = threadIdx.x % 64;
     sb = wave_sum(sb); sb2 = wave_sum(sb2); bad = wave_sum(bad);
     mn = wave_min(mn); mx = wave_max(mx);
