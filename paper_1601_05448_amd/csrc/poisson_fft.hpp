@@ -278,15 +278,19 @@ __device__ __forceinline__ void fft_block_lines(cpx<T>* lds, const cpx<T>* tw) {
 // it holds two barriers, the second one guarding `ln` for its next writer.
 template <typename T>
 __device__ __forceinline__ void fft256_regs(cpx<T> (&v)[16], cpx<T>* ln, int c, const cpx<T>* tw) {
-    using C = LineCfg<T, 256>;
     dft16(v);
 #pragma unroll
     for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmul(v[k1], tw[c * k1]);
+    // the LDS positions pos(e) = e + e/16 in closed form (c < 16), one base
+    // register and immediate offsets: pos(16 k1 + c) = 17 k1 + c, pos(16 c + a) =
+    // 17 c + a
+    cpx<T>* wp = ln + c;
 #pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) ln[C::pos(16 * k1 + c)] = v[k1];
+    for (int k1 = 0; k1 < 16; ++k1) wp[17 * k1] = v[k1];
     __syncthreads();
+    const cpx<T>* rp = ln + 17 * c;
 #pragma unroll
-    for (int a = 0; a < 16; ++a) v[a] = ln[C::pos(16 * c + a)];
+    for (int a = 0; a < 16; ++a) v[a] = rp[a];
     __syncthreads();
     dft16(v);
 }
@@ -323,16 +327,20 @@ __device__ __forceinline__ void row_pair(double x, double& ev, double& od) {
 
 template <typename T>
 __device__ __forceinline__ void fft512_regs(cpx<T> (&v)[16], cpx<T>* ln, int c, const cpx<T>* tw) {
-    using C = LineCfg<T, 512>;
     dft16(v);
 #pragma unroll
     for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmul(v[k1], tw[c * k1]);
+    // the LDS positions pos(e) = e + e/16 in closed form (c < 32), one base
+    // register and immediate offsets: pos(32 k1 + c) = 34 k1 + c + c/16, and
+    // with k1 = c/2, h = c mod 2, pos(32 k1 + 2 q + h) = 34 k1 + h + 2 q + q/8
+    cpx<T>* wp = ln + c + (c >> 4);
 #pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) ln[C::pos(32 * k1 + c)] = v[k1];
+    for (int k1 = 0; k1 < 16; ++k1) wp[34 * k1] = v[k1];
     __syncthreads();
     const int k1 = c >> 1, h = c & 1;
+    const cpx<T>* rp = ln + 34 * k1 + h;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = ln[C::pos(32 * k1 + 2 * q + h)];
+    for (int q = 0; q < 16; ++q) v[q] = rp[2 * q + (q >> 3)];
     __syncthreads();
     dft16(v);
     // both threads of the pair take E (h = 0) and O (h = 1), apply the odd

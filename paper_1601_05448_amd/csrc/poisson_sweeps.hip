@@ -575,13 +575,13 @@ __device__ __forceinline__ T symbol_scale(const GridArgs& g) {
 // Launch shape of the z sweep: ZL lines per block, PF whether the next line
 // group is loaded during this one's transforms, MINW the waves per SIMD its
 // registers are sized for (the second __launch_bounds__ argument).  Measured
-// (MI355X): the FP32 256-point path runs three blocks per CU with the
-// prefetch; the FP32 512-point path runs two 512-thread blocks per CU without
-// it (128 registers, no spills; 14% faster than one block with it); the FP64
-// paths prefetch (no spills at 2 and 1 blocks per CU).
+// (MI355X): the FP32 256-point path runs four blocks per CU with the prefetch
+// (111 registers); the FP32 512-point path runs two 512-thread blocks per CU
+// without it (no spills; 14% faster than one block with it); the FP64 paths
+// prefetch (no spills at 2 and 1 blocks per CU).
 template <typename T, int N>
 constexpr int z_min_blocks() {
-    if constexpr (sizeof(T) == 4 && N == 256) return 3;
+    if constexpr (sizeof(T) == 4 && N == 256) return 4;
     else if constexpr (sizeof(T) == 4 && N == 512) return 4;
     else return LineCfg<T, N>::MINB;
 }
