@@ -279,8 +279,11 @@ __device__ __forceinline__ void fft_block_lines(cpx<T>* lds, const cpx<T>* tw) {
 template <typename T>
 __device__ __forceinline__ void fft256_regs(cpx<T> (&v)[16], cpx<T>* ln, int c, const cpx<T>* tw) {
     dft16(v);
+    // c masked to its range: the twiddle offsets then take full-rate 24-bit
+    // multiplies instead of 32-bit ones
+    const unsigned cm = (unsigned)c & 15u;
 #pragma unroll
-    for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmul(v[k1], tw[c * k1]);
+    for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmul(v[k1], tw[cm * (unsigned)k1]);
     // the LDS positions pos(e) = e + e/16 in closed form (c < 16), one base
     // register and immediate offsets: pos(16 k1 + c) = 17 k1 + c, pos(16 c + a) =
     // 17 c + a
@@ -328,8 +331,9 @@ __device__ __forceinline__ void row_pair(double x, double& ev, double& od) {
 template <typename T>
 __device__ __forceinline__ void fft512_regs(cpx<T> (&v)[16], cpx<T>* ln, int c, const cpx<T>* tw) {
     dft16(v);
+    const unsigned cm = (unsigned)c & 31u;  // as in fft256_regs
 #pragma unroll
-    for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmul(v[k1], tw[c * k1]);
+    for (int k1 = 1; k1 < 16; ++k1) v[k1] = cmul(v[k1], tw[cm * (unsigned)k1]);
     // the LDS positions pos(e) = e + e/16 in closed form (c < 32), one base
     // register and immediate offsets: pos(32 k1 + c) = 34 k1 + c + c/16, and
     // with k1 = c/2, h = c mod 2, pos(32 k1 + 2 q + h) = 34 k1 + h + 2 q + q/8
