@@ -157,16 +157,44 @@ __device__ __forceinline__ unsigned x_walls(const GridArgs& g, unsigned i) {
     return g.bcx ? ((i == 0 ? 1u : 0u) | (i + 1 == (unsigned)g.nx ? 2u : 0u)) : 0u;
 }
 
+// The lower z-face coefficients of both rows of a pair, COEF 0 (the start of a
+// z march; later planes carry them, see pair_eval with ZC).
+template <typename T>
+__device__ __forceinline__ void z_faces_below(const PairIn<T>& in, T rinv, T* zc) {
+    T d[2] = {(in.r[8] + in.r[0]) * rinv, (in.r[10] + in.r[1]) * rinv};
+    scaled_recips(d);
+    const T c = T(2) * rinv;
+    zc[0] = c * d[0];
+    zc[1] = c * d[1];
+}
+
 // Residual b~ - A p and weight w of the pair; its 11 faces (a x-, a x+, a y-,
 // a|b, a z-, a z+, b x-, b x+, b y+, b z-, b z+) share one batched reciprocal.
 // rmax = max rho, rinv = 1 / rmax; `walls` from x_walls for the pair's column.
-template <typename T, int COEF, int WEIGHT>
+// ZC (COEF 0, a z march): the two lower z faces come in through zc and the two
+// upper ones go out through it, 9 faces computed instead of 11.
+template <typename T, int COEF, int WEIGHT, bool ZC = false>
 __device__ __forceinline__ PairOut<T> pair_eval(const GridArgs& g, const PairIn<T>& in, T rhs_mean, T rmax,
-                                                T rinv, unsigned walls) {
+                                                T rinv, unsigned walls, T* zc = nullptr) {
     const T* r = in.r;
     const T* q = in.q;
     T be[11];
-    if constexpr (COEF == 0) {
+    if constexpr (COEF == 0 && ZC) {
+        // the lower z faces of both rows are the upper ones of the plane below
+        // (the same two densities, summed in the same order): taken from zc,
+        // which receives this plane's upper z faces for the plane above
+        T d[9] = {r[2] + r[0], r[0] + r[3], r[6] + r[0], r[0] + r[1], r[0] + r[9],
+                  r[4] + r[1], r[1] + r[5], r[1] + r[7], r[1] + r[11]};
+#pragma unroll
+        for (int f = 0; f < 9; ++f) d[f] *= rinv;
+        scaled_recips(d);
+        const T c = T(2) * rinv;
+        be[0] = c * d[0]; be[1] = c * d[1]; be[2] = c * d[2]; be[3] = c * d[3]; be[4] = zc[0];
+        be[5] = c * d[4]; be[6] = c * d[5]; be[7] = c * d[6]; be[8] = c * d[7]; be[9] = zc[1];
+        be[10] = c * d[8];
+        zc[0] = be[5];
+        zc[1] = be[10];
+    } else if constexpr (COEF == 0) {
         T d[11] = {r[2] + r[0], r[0] + r[3], r[6] + r[0], r[0] + r[1], r[8] + r[0], r[0] + r[9],
                    r[4] + r[1], r[1] + r[5], r[1] + r[7], r[10] + r[1], r[1] + r[11]};
 #pragma unroll

@@ -187,6 +187,10 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
             zm.load_rows(zm.plane(k0 + 1), i, pl[c][2]);
             zm.load_side(zm.plane(k0), i, sd[c]);
         }
+        // the lower z faces of each column's pair, carried from plane to plane
+        // (one marching column per thread: with more, the registers are spoken for)
+        constexpr bool kZC = COEF == 0 && Z::CPT == 1;
+        T zc[Z::CPT][2];
         for (int f = 0; f < Z::KM / Z::KF; ++f) {
             T tacc[2] = {T(0), T(0)};
             // fully unrolled, so that the rotation of the plane registers below
@@ -221,7 +225,10 @@ k_resid_dhtx_z(GridArgs g, const Slot* __restrict__ slots, Tables tb) {
                     zm.pair(pl[c][0], pl[c][1], pl[c][2], sd[c], zm.edge_get(eb, i), in);
                     cpx<T> qv = {T(0), T(0)};
                     if (valid) {
-                        const PairOut<T> o = pair_eval<T, COEF, WEIGHT>(g, in, v.rhs_mean, v.rmax, v.rinv, BCX ? x_walls(g, i) : 0u);
+                        if constexpr (kZC)
+                            if (q == 0 && f == 0) z_faces_below(in, v.rinv, zc[c]);
+                        const PairOut<T> o = pair_eval<T, COEF, WEIGHT, kZC>(g, in, v.rhs_mean, v.rmax, v.rinv,
+                                                                             BCX ? x_walls(g, i) : 0u, zc[c]);
                         qv = {o.a.w * o.a.r, o.b.w * o.b.r};
                         if constexpr (sizeof(T) == 8) {
                             acc[0] += o.a.r * o.a.r + o.b.r * o.b.r;
@@ -331,6 +338,7 @@ k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb, int wr
         zm.load_rows(zm.plane(k0), i, pl[1]);
         zm.load_rows(zm.plane(k0 + 1), i, pl[2]);
         zm.load_side(zm.plane(k0), i, sd);
+        double zc[2];  // the lower z faces of the pair, carried from plane to plane (COEF 0)
         for (int f = 0; f < Z::KM / Z::KF; ++f) {
 #pragma unroll
             for (int q = 0; q < Z::KF; ++q) {
@@ -349,7 +357,10 @@ k_outer_resid_dhtx(GridArgs g, const Slot* __restrict__ slots, Tables tb, int wr
                 zm.pair(pl[0], pl[1], pl[2], sd, zm.edge_get(eb, i), in);
                 cpx<float> qv = {0.0f, 0.0f};
                 if (valid) {
-                    const PairOut<double> pr = pair_eval<double, COEF, WEIGHT>(g, in, bm, rmax, rinv, BCX ? x_walls(g, i) : 0u);
+                    if constexpr (COEF == 0)
+                        if (q == 0 && f == 0) z_faces_below(in, rinv, zc);
+                    const PairOut<double> pr =
+                        pair_eval<double, COEF, WEIGHT, COEF == 0>(g, in, bm, rmax, rinv, BCX ? x_walls(g, i) : 0u, zc);
                     acc[0] += pr.a.r * pr.a.r + pr.b.r * pr.b.r;
                     acc[1] += pr.a.bt * pr.a.bt + pr.b.bt * pr.b.bt;
                     acc[2] += pr.a.pc + pr.b.pc;
